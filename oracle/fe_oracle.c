@@ -26,6 +26,8 @@
  *    functions 1-xi-eta-zeta, xi, eta, zeta; reference prism = unit right
  *    triangle x [-1,1], bottom nodes 0-2 at zeta=-1, top node v+3 above v;
  *  - det J is used signed (no absolute value);
+ *  - the Jacobian is formed from the edge vectors X_r - X_0 (see
+ *    jacobian_terms);
  *  - 3-component problems number unknowns node-major (3 r + alpha); the
  *    isotropic elasticity tensor is C_{i alpha j beta} = lambda d_{i alpha}
  *    d_{j beta} + mu (d_ij d_{alpha beta} + d_{i beta} d_{j alpha}) for the
@@ -197,8 +199,12 @@ typedef struct {
     double *d;     /* scalar: [4][n_q];    elasticity: [4][3][n_q] */
 } scratch_t;
 
-/* Jacobian terms at one point: J[i][k] = dx_i/dxi_k = sum_r X[r][i] dphi_r/dxi_k,
- * det J by cofactor expansion along row 0, inverse = adjugate / det. */
+/* Jacobian terms at one point: J[i][k] = dx_i/dxi_k. Because the reference
+ * derivatives of the shape functions sum to zero, x(xi) = X_0 + sum_r
+ * phi_r(xi) (X_r - X_0) and J[i][k] = sum_r (X[r][i] - X[0][i]) dphi_r/dxi_k
+ * exactly; forming J from these edge vectors instead of absolute coordinates
+ * avoids cancellation on thin elements. det J by cofactor expansion along
+ * row 0, inverse = adjugate / det. */
 static void jacobian_terms(int ns, const double X[6][3], const double dphi[6][3],
                            double *det_out, double Jinv[3][3])
 {
@@ -207,7 +213,7 @@ static void jacobian_terms(int ns, const double X[6][3], const double dphi[6][3]
         for (int k = 0; k < 3; ++k) {
             double s = 0.0;
             for (int r = 0; r < ns; ++r)
-                s += X[r][i] * dphi[r][k];
+                s += (X[r][i] - X[0][i]) * dphi[r][k];
             J[i][k] = s;
         }
     const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];

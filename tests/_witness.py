@@ -153,3 +153,37 @@ def prism_brute_scalar(X, slots, xi, wt):
     K = np.einsum("m,mra,ab,msb->rs", vol, Phi, c, Phi)
     F = np.einsum("m,mra,a->r", vol, Phi, d)
     return K, F, det
+
+
+def prism_extended(X, coeffs_q, xi, w):
+    """Scalar weak-form quadrature sum on one prism in long double (x87
+    extended precision), per-point coefficient slots coeffs_q (n_q, 20):
+    an accuracy reference for thin (sliver) elements."""
+    ld = np.longdouble
+    X = np.asarray(X, dtype=ld)
+    E = X - X[0]
+    K = np.zeros((6, 6), ld)
+    F = np.zeros(6, ld)
+    for q in range(len(w)):
+        phi, dphi = prism_shape_np(np.asarray(xi[q:q + 1], dtype=np.float64))
+        phi, dphi = phi[0].astype(ld), dphi[0].astype(ld)
+        J = np.einsum("ri,rk->ik", E, dphi)
+        c0 = J[1, 1] * J[2, 2] - J[1, 2] * J[2, 1]
+        c1 = J[1, 2] * J[2, 0] - J[1, 0] * J[2, 2]
+        c2 = J[1, 0] * J[2, 1] - J[1, 1] * J[2, 0]
+        det = J[0, 0] * c0 + J[0, 1] * c1 + J[0, 2] * c2
+        adj = np.empty((3, 3), ld)
+        adj[0, 0], adj[1, 0], adj[2, 0] = c0, c1, c2
+        adj[0, 1] = J[0, 2] * J[2, 1] - J[0, 1] * J[2, 2]
+        adj[1, 1] = J[0, 0] * J[2, 2] - J[0, 2] * J[2, 0]
+        adj[2, 1] = J[0, 1] * J[2, 0] - J[0, 0] * J[2, 1]
+        adj[0, 2] = J[0, 1] * J[1, 2] - J[0, 2] * J[1, 1]
+        adj[1, 2] = J[0, 2] * J[1, 0] - J[0, 0] * J[1, 2]
+        adj[2, 2] = J[0, 0] * J[1, 1] - J[0, 1] * J[1, 0]
+        g = dphi @ (adj / det)
+        Phi = np.concatenate([phi[:, None], g], 1)
+        c = np.asarray(coeffs_q[q], dtype=ld)
+        vol = det * ld(w[q])
+        K += vol * Phi @ c[:16].reshape(4, 4) @ Phi.T
+        F += vol * Phi @ c[16:20]
+    return K, F

@@ -464,3 +464,21 @@ def test_inverted_element_uses_signed_determinant():
                               inputs.ALL_SCALAR_MASK, None, wl.coeffs)
     np.testing.assert_allclose(K1, -K0[:, perm][:, :, perm], atol=1e-13 * np.abs(K0).max())
     np.testing.assert_allclose(F1, -F0[:, perm], atol=1e-13 * np.abs(F0).max())
+
+
+def test_sliver_prisms_match_extended_precision():
+    # thin (aspect ~1e3) non-affine prisms with per-point coefficients: the
+    # FP64 oracle stays within 1e-14 (relative Frobenius) of a long-double
+    # evaluation of the same quadrature sum
+    wl = inputs.prism_cdr_qp(9, 8, seed=3)
+    K, F = oracle.integrate_workload(wl)
+    xi, w = oracle.quad_rule("prism6", 6)
+    X = wl.mesh.coords.reshape(6, 3, -1)
+    n_col = 2 * 9 * 9
+    sliver = range(4 * n_col, 5 * n_col, 17)   # layer L // 2
+    for e in list(sliver) + [3, 100]:
+        cq = wl.coeffs[:, e].reshape(20, 6).T
+        Kx, Fx = W.prism_extended(X[:, :, e], cq, xi, w)
+        ek = np.sqrt(((K[e] - Kx) ** 2).sum() / (Kx ** 2).sum())
+        ef = np.sqrt(((F[e] - Fx) ** 2).sum() / (Fx ** 2).sum())
+        assert ek < 1e-14 and ef < 1e-14, (e, float(ek), float(ef))

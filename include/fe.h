@@ -1,0 +1,226 @@
+/*
+ * fe.h -- C ABI of libfe: finite element numerical integration for
+ * first-order approximations on AMD Instinct MI355X (gfx950).
+ *
+ * What the library computes (K. Banas, F. Kruzel, J. Bielanski,
+ * arXiv:1504.01023): for every element e of a batch of elements of one type,
+ * the element stiffness matrix A^e (here K) and load vector b^e (here F) of
+ * the weak form of Sec. 2.1 (eq. "weak_form"), i.e. eqs. "sm_local" and
+ * "lv_local" of Sec. 2.2 with all coefficient terms c^{i;j}, c^{i;0},
+ * c^{0;i}, c^{0;0}, d^i, d^0, evaluated by the change of variables to the
+ * reference element (eq. "change_of_variables") and the quadrature sum of
+ * eq. "quadrature" (Sec. 2.3). Boundary terms are not computed (the paper
+ * neglects them, Sec. 2.1). The inputs mirror the procedure's input list of
+ * Sec. 2.3: element type, quadrature points and weights, per-element geometry
+ * degrees of freedom (vertex coordinates) and problem-dependent coefficient
+ * values; the outputs are stored in device memory for later solution steps
+ * (Sec. 3.1).
+ *
+ * Elements: affine 4-node tetrahedra and 6-node linear prisms. Problems:
+ * scalar convection-diffusion-reaction, and 3-component isotropic linear
+ * elasticity (a vector problem, Sec. 3.3).
+ *
+ * Conventions (readings where the paper is silent):
+ *  - Reference tetrahedron (0,0,0),(1,0,0),(0,1,0),(0,0,1), shape functions
+ *    1-xi-eta-zeta, xi, eta, zeta. Reference prism: unit right triangle in
+ *    (xi, eta) times zeta in [-1, 1]; nodes 0-2 at zeta = -1 in triangle
+ *    order, node v+3 above node v.
+ *  - Coefficient index 0 is the function value, 1..3 the x, y, z
+ *    derivatives (Algorithm 1). The first index of c^{a;b} pairs with the
+ *    test function (row of K), the second with the trial function (column).
+ *  - det J is used signed: inverted elements are integrated as written.
+ *  - Vector problems number unknowns node-major: row 3*r + alpha.
+ *
+ * Memory layout (structure of arrays, element index fastest, so that one
+ * wavefront reads and writes whole cache lines; Sec. 4.2 discusses coalesced
+ * access):
+ *  coords  [(v*3 + d) * ld_in + e]            FP64 always
+ *  coeffs  per element: [j * ld_in + e]
+ *          per point:   [(j * n_q + q) * ld_in + e]
+ *          where j runs over the set bits of coef_mask in increasing slot
+ *          order ("compact" layout); FP64 for FE_FP64, FP32 for FE_FP32_BULK.
+ *  out_K   [k * ld_out + e], k = packed or full entry index (below)
+ *  out_F   [i * ld_out + e]
+ * Full K: k = row * N + col. Packed (symmetric problems only): the upper
+ * triangle row by row, k = row * N - row * (row - 1) / 2 + (col - row) for
+ * col >= row. N = number of shape functions times components.
+ *
+ * Coefficient slots. Scalar problems (20 slots): slot 4*a + b holds c^{a;b}
+ * (a, b in 0..3), slot 16 + a holds d^a. Elasticity (5 slots): E, nu, f_x,
+ * f_y, f_z, with Lame parameters lambda = E nu / ((1+nu)(1-2nu)),
+ * mu = E / (2 (1+nu)) and the body force as d^0 per component. A slot whose
+ * bit is set in coef_mask is read from `coeffs`; every other slot takes the
+ * value problem->uniform[slot] (zero for absent terms). With
+ * FE_COEF_UNIFORM no slot is read from memory.
+ *
+ * Ownership and streams: every device pointer is owned by the caller and must
+ * stay valid until the work enqueued on `stream` has completed. Quadrature
+ * rules are host memory read during the call only. Calls enqueue work on
+ * `stream` and return without synchronising; device faults surface at the
+ * caller's next synchronisation. The library never allocates device memory
+ * in fe_integrate / fe_integrate_ex.
+ *
+ * Errors: every entry point returns FE_OK or a status code; on error nothing
+ * has been enqueued and the outputs are untouched. fe_last_error() returns a
+ * thread-local description of the last failure of the calling thread.
+ * Thread safety: all entry points are reentrant.
+ */
+#ifndef FE_H
+#define FE_H
+
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FE_API __attribute__((visibility("default")))
+
+typedef enum fe_status {
+    FE_OK = 0,
+    FE_ERR_INVALID_ARG = 1,   /* null pointer with n_elem > 0, negative size,
+                                 bad enum, ld < n_elem, bad rule weights */
+    FE_ERR_UNSUPPORTED = 2,   /* n_q outside the supported range, misaligned
+                                 pointer, combination not built */
+    FE_ERR_NOT_SYMMETRIC = 3, /* packed K requested for a non-symmetric problem */
+    FE_ERR_HIP = 4,           /* HIP runtime error; see fe_last_error() */
+    FE_ERR_CAPACITY = 5       /* batch, server or table capacity exceeded */
+} fe_status;
+
+typedef enum fe_elem_type { FE_TET4 = 0, FE_PRISM6 = 1 } fe_elem_type;
+typedef enum fe_problem_kind { FE_SCALAR_CDR = 0, FE_ELASTICITY = 1 } fe_problem_kind;
+
+/* FE_FP32_BULK: coordinates stay FP64 and the Jacobian terms (J, det J, its
+ * inverse), the global derivatives and vol are computed in FP64, then rounded
+ * to FP32; coefficients, accumulation and outputs are FP32. */
+typedef enum fe_precision { FE_FP64 = 0, FE_FP32_BULK = 1 } fe_precision;
+
+/* Coefficients constant over the whole element (Sec. 3.3) or given at each
+ * quadrature point (the paper's "Poisson" right-hand side, Sec. 4.1). */
+typedef enum fe_coef_mode {
+    FE_COEF_UNIFORM = 0,
+    FE_COEF_PER_ELEMENT = 1,
+    FE_COEF_PER_QP = 2
+} fe_coef_mode;
+
+typedef enum fe_k_format { FE_K_FULL = 0, FE_K_SYM_PACKED = 1 } fe_k_format;
+
+typedef struct fe_problem {
+    int32_t kind;        /* fe_problem_kind */
+    int32_t precision;   /* fe_precision */
+    int32_t coef_mode;   /* fe_coef_mode */
+    uint32_t coef_mask;  /* slots read from `coeffs` (ignored for UNIFORM) */
+    int32_t k_format;    /* fe_k_format */
+    int32_t reserved;    /* must be 0 */
+    double uniform[20];  /* values of the slots not read from memory */
+} fe_problem;
+
+/* A quadrature rule on the reference element: n_q points xi[q*3 + k] and
+ * weights w[q] (Sec. 2.3). Host memory. 1 <= n_q <= FE_MAX_QP. */
+#define FE_MAX_QP 8
+typedef struct fe_quad_rule {
+    int32_t n_q;
+    const double *xi;
+    const double *w;
+} fe_quad_rule;
+
+/* Launch variant (the tuning parameters of Sec. 4.3: where reference data
+ * lives, plus GPU launch shape). Zero fields mean "library default". */
+typedef struct fe_variant {
+    int32_t wg_size;           /* 64, 128 or 256 threads */
+    int32_t elems_per_thread;  /* 1 or 2 contiguous elements (tetrahedra) */
+    int32_t ref_in_lds;        /* 1: stage reference tables in LDS; 2: read
+                                  them as wave-uniform kernel arguments */
+    int32_t nontemporal;       /* 1: streaming (non-temporal) loads/stores; 2: off */
+    int32_t blocks;            /* grid size; 0 = one element group per thread */
+} fe_variant;
+
+/* ---------------------------------------------------------------------
+ * Integration (Sec. 2.3, Algorithm 1; the element loop parallelised one
+ * element per GPU thread as in Sec. 3.2).
+ * ------------------------------------------------------------------- */
+
+/* Integrate n_elem elements with leading dimension n_elem for inputs and
+ * outputs. coeffs may be NULL when no slot is read from memory.
+ * n_elem == 0 returns FE_OK without enqueuing anything. */
+FE_API int fe_integrate(const fe_problem *problem, fe_elem_type elem_type, int64_t n_elem,
+                        const double *coords, const void *coeffs, const fe_quad_rule *quad_rule,
+                        void *out_K, void *out_F, hipStream_t stream);
+
+/* As fe_integrate with explicit leading dimensions (ld_in for coords and
+ * coeffs, ld_out for out_K and out_F; both >= n_elem), which lets a caller
+ * integrate a slice of a larger batch in place, and an optional forced
+ * launch variant (NULL = the tuned or default variant). */
+FE_API int fe_integrate_ex(const fe_problem *problem, fe_elem_type elem_type, int64_t n_elem,
+                           const double *coords, const void *coeffs, int64_t ld_in,
+                           const fe_quad_rule *quad_rule, void *out_K, void *out_F, int64_t ld_out,
+                           const fe_variant *variant, hipStream_t stream);
+
+/* ---------------------------------------------------------------------
+ * Sizes and accounting (Sec. 4.1, table "memory_requirements"; Sec. 4.4,
+ * table "accesses_and_operations"). Each returns -1 on invalid input.
+ * ------------------------------------------------------------------- */
+
+/* Rows of out_K per element (N*N full, N(N+1)/2 packed). */
+FE_API int64_t fe_k_entries(const fe_problem *problem, fe_elem_type elem_type);
+/* Rows of out_F per element (N). */
+FE_API int64_t fe_f_entries(const fe_problem *problem, fe_elem_type elem_type);
+/* Rows of coeffs for this problem and rule size (popcount(mask) per element,
+ * times n_q for per-point data; 0 for uniform). */
+FE_API int64_t fe_coeff_entries(const fe_problem *problem, fe_elem_type elem_type, int n_q);
+/* Algorithmic global-memory bytes per element: every input word read once
+ * and every output word written once. */
+FE_API int64_t fe_bytes_per_element(const fe_problem *problem, fe_elem_type elem_type, int n_q);
+/* Storage row of K entry (row, col) in out_K, or -1 when that entry is not
+ * stored (lower triangle of a packed K) or out of range. */
+FE_API int64_t fe_k_index(const fe_problem *problem, fe_elem_type elem_type, int row, int col);
+
+/* Built-in rules: tetrahedron 1 point (centroid) and 4 points (degree 2),
+ * prism 6 points (3-point triangle rule times 2-point Gauss line). Fills *out
+ * with pointers to library-owned static arrays. */
+FE_API int fe_quad_rule_builtin(fe_elem_type elem_type, int n_q, fe_quad_rule *out);
+
+FE_API const char *fe_status_string(int status);
+FE_API const char *fe_last_error(void);
+
+/* Library version as major*10000 + minor*100 + patch. */
+FE_API int fe_version(void);
+
+/* ---------------------------------------------------------------------
+ * Tuning (parameter-based tuning by exhaustive search over variants,
+ * Sec. 4.3).
+ * ------------------------------------------------------------------- */
+
+/* Time every valid variant for this problem on the caller's device buffers
+ * (they are overwritten with valid results), keep the fastest in the
+ * in-process tuning table and return it in *best (and its mean time in ms).
+ * Synchronises `stream`. */
+FE_API int fe_autotune(const fe_problem *problem, fe_elem_type elem_type, int64_t n_elem,
+                       const double *coords, const void *coeffs, const fe_quad_rule *quad_rule,
+                       void *out_K, void *out_F, int reps, fe_variant *best, double *best_ms,
+                       hipStream_t stream);
+/* Query / set the tuning table entry used by fe_integrate for a problem
+ * shape. fe_tuning_get returns FE_ERR_INVALID_ARG when no entry exists. */
+FE_API int fe_tuning_get(const fe_problem *problem, fe_elem_type elem_type, int n_q,
+                         fe_variant *out);
+FE_API int fe_tuning_set(const fe_problem *problem, fe_elem_type elem_type, int n_q,
+                         const fe_variant *v);
+/* Persist / restore the tuning table as text (one entry per line). */
+FE_API int fe_tuning_save(const char *path);
+FE_API int fe_tuning_load(const char *path);
+FE_API int fe_tuning_clear(void);
+
+/* ---------------------------------------------------------------------
+ * Measurement helper: copy n_bytes (a multiple of 16) from src to dst with
+ * a plain streaming kernel, used to calibrate HBM counters and the achieved
+ * copy ceiling beside the integration kernels.
+ * ------------------------------------------------------------------- */
+FE_API int fe_stream_copy(void *dst, const void *src, int64_t n_bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FE_H */

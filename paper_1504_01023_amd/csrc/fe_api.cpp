@@ -1,0 +1,491 @@
+// fe_api.cpp -- host side of the libfe C ABI: argument validation, reference
+// tables built from the caller's quadrature rule, kernel selection and
+// launch. Every per-element step runs in the HIP kernels; the host only
+// evaluates the reference element's shape functions at the rule's points
+// (an input of the integration procedure, Sec. 2.3) and picks a compiled
+// kernel.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "fe.h"
+#include "fe_api_internal.h"
+#include "fe_internal.h"
+
+namespace fe {
+
+static std::vector<KernelEntry> &registry()
+{
+    static std::vector<KernelEntry> r;
+    return r;
+}
+
+void register_kernel(const KernelEntry &e) { registry().push_back(e); }
+
+static bool same_key(const KernelKey &a, const KernelKey &b)
+{
+    return a.elem == b.elem && a.kind == b.kind && a.prec == b.prec && a.terms == b.terms &&
+           a.mode == b.mode && a.packed == b.packed && a.vec == b.vec && a.nt == b.nt &&
+           a.ref == b.ref && a.nq == b.nq;
+}
+
+const KernelEntry *find_kernel(const KernelKey &k)
+{
+    for (const KernelEntry &e : registry())
+        if (same_key(e.key, k))
+            return &e;
+    return nullptr;
+}
+
+int kernel_count() { return (int)registry().size(); }
+const KernelEntry *kernel_at(int i)
+{
+    return (i >= 0 && i < kernel_count()) ? &registry()[i] : nullptr;
+}
+
+static thread_local std::string g_last_error;
+
+int fail(int status, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return status;
+}
+
+// ------------------------------------------------------------ reference data
+// The library's own evaluation of the reference shape functions (the same
+// reference elements as documented in fe.h).
+static void ref_shape(int elem, const double *xi, double *phi, double (*dphi)[3])
+{
+    if (elem == FE_TET4) {
+        phi[0] = 1.0 - xi[0] - xi[1] - xi[2];
+        phi[1] = xi[0];
+        phi[2] = xi[1];
+        phi[3] = xi[2];
+        for (int k = 0; k < 3; ++k) {
+            dphi[0][k] = -1.0;
+            for (int r = 1; r < 4; ++r)
+                dphi[r][k] = (r - 1 == k) ? 1.0 : 0.0;
+        }
+    } else {
+        const double t[3] = {1.0 - xi[0] - xi[1], xi[0], xi[1]};
+        const double tx[3] = {-1.0, 1.0, 0.0}, ty[3] = {-1.0, 0.0, 1.0};
+        const double b = 0.5 * (1.0 - xi[2]), u = 0.5 * (1.0 + xi[2]);
+        for (int v = 0; v < 3; ++v) {
+            phi[v] = t[v] * b;
+            phi[v + 3] = t[v] * u;
+            dphi[v][0] = tx[v] * b;
+            dphi[v][1] = ty[v] * b;
+            dphi[v][2] = -0.5 * t[v];
+            dphi[v + 3][0] = tx[v] * u;
+            dphi[v + 3][1] = ty[v] * u;
+            dphi[v + 3][2] = 0.5 * t[v];
+        }
+    }
+}
+
+void fill_reference(int elem, const fe_quad_rule &rule, KArgs &a)
+{
+    const int ns = elem == FE_TET4 ? 4 : 6;
+    std::memset(a.w, 0, sizeof(a.w));
+    std::memset(a.phi, 0, sizeof(a.phi));
+    std::memset(a.dphi, 0, sizeof(a.dphi));
+    std::memset(a.m, 0, sizeof(a.m));
+    std::memset(a.M, 0, sizeof(a.M));
+    a.Wsum = 0.0;
+    a.n_q = rule.n_q;
+    for (int q = 0; q < rule.n_q; ++q) {
+        double phi[6], dphi[6][3];
+        ref_shape(elem, rule.xi + 3 * q, phi, dphi);
+        a.w[q] = rule.w[q];
+        a.Wsum += rule.w[q];
+        for (int r = 0; r < ns; ++r) {
+            a.phi[q][r] = phi[r];
+            for (int k = 0; k < 3; ++k)
+                a.dphi[q][r][k] = dphi[r][k];
+            a.m[r] += rule.w[q] * phi[r];
+            for (int s = 0; s < ns; ++s)
+                a.M[r][s] += rule.w[q] * phi[r] * phi[s];
+        }
+    }
+}
+
+// ------------------------------------------------------------- validation
+static int n_shape(int elem) { return elem == FE_TET4 ? 4 : 6; }
+static int n_comp(int kind) { return kind == FE_ELASTICITY ? 3 : 1; }
+static int n_slots(int kind) { return kind == FE_ELASTICITY ? 5 : 20; }
+
+static int check_problem(const fe_problem *p, int elem)
+{
+    if (!p)
+        return fail(FE_ERR_INVALID_ARG, "problem is NULL");
+    if (elem != FE_TET4 && elem != FE_PRISM6)
+        return fail(FE_ERR_INVALID_ARG, "bad element type %d", elem);
+    if (p->kind != FE_SCALAR_CDR && p->kind != FE_ELASTICITY)
+        return fail(FE_ERR_INVALID_ARG, "bad problem kind %d", p->kind);
+    if (p->precision != FE_FP64 && p->precision != FE_FP32_BULK)
+        return fail(FE_ERR_INVALID_ARG, "bad precision %d", p->precision);
+    if (p->coef_mode < FE_COEF_UNIFORM || p->coef_mode > FE_COEF_PER_QP)
+        return fail(FE_ERR_INVALID_ARG, "bad coefficient mode %d", p->coef_mode);
+    if (p->k_format != FE_K_FULL && p->k_format != FE_K_SYM_PACKED)
+        return fail(FE_ERR_INVALID_ARG, "bad K format %d", p->k_format);
+    if (p->reserved != 0)
+        return fail(FE_ERR_INVALID_ARG, "reserved field must be 0");
+    if (p->coef_mode != FE_COEF_UNIFORM && (p->coef_mask >> n_slots(p->kind)) != 0)
+        return fail(FE_ERR_INVALID_ARG, "coef_mask has bits beyond slot %d", n_slots(p->kind) - 1);
+    return FE_OK;
+}
+
+static uint32_t effective_mask(const fe_problem *p)
+{
+    return p->coef_mode == FE_COEF_UNIFORM ? 0u : p->coef_mask;
+}
+
+// Term groups a scalar problem needs: any slot read from memory or nonzero.
+static int needed_terms(const fe_problem *p)
+{
+    const uint32_t mask = effective_mask(p);
+    int t = 0;
+    const int groups[6] = {T_DIFF, T_CONVA, T_CONVB, T_MASS, T_DGRAD, T_D0};
+    for (int g : groups) {
+        const uint32_t sl = slots_of_terms(g);
+        bool need = (mask & sl) != 0;
+        for (int k = 0; k < 20; ++k)
+            if ((sl >> k & 1u) && p->uniform[k] != 0.0)
+                need = true;
+        if (need)
+            t |= g;
+    }
+    return t;
+}
+
+static int check_symmetry(const fe_problem *p)
+{
+    if (p->k_format != FE_K_SYM_PACKED || p->kind == FE_ELASTICITY)
+        return FE_OK;
+    const uint32_t mask = effective_mask(p);
+    const uint32_t conv = slots_of_terms(T_CONVA) | slots_of_terms(T_CONVB);
+    if (mask & conv)
+        return fail(FE_ERR_NOT_SYMMETRIC,
+                    "packed K requested with convection coefficients read from memory");
+    for (int i = 1; i <= 3; ++i) {
+        if (p->uniform[4 * i] != p->uniform[i])
+            return fail(FE_ERR_NOT_SYMMETRIC, "packed K requested with c^{%d;0} != c^{0;%d}", i, i);
+        for (int j = i + 1; j <= 3; ++j)
+            if (!(mask >> (4 * i + j) & 1u) && !(mask >> (4 * j + i) & 1u) &&
+                p->uniform[4 * i + j] != p->uniform[4 * j + i])
+                return fail(FE_ERR_NOT_SYMMETRIC, "packed K requested with non-symmetric c^{i;j}");
+    }
+    return FE_OK;
+}
+
+static int check_rule(const fe_quad_rule *r)
+{
+    if (!r)
+        return fail(FE_ERR_INVALID_ARG, "quad_rule is NULL");
+    if (r->n_q < 1 || r->n_q > FE_MAX_QP)
+        return fail(FE_ERR_UNSUPPORTED, "rule has %d points; 1..%d supported", r->n_q, FE_MAX_QP);
+    if (!r->xi || !r->w)
+        return fail(FE_ERR_INVALID_ARG, "rule points or weights are NULL");
+    for (int q = 0; q < r->n_q; ++q) {
+        if (!std::isfinite(r->w[q]))
+            return fail(FE_ERR_INVALID_ARG, "rule weight %d is not finite", q);
+        for (int k = 0; k < 3; ++k)
+            if (!std::isfinite(r->xi[3 * q + k]))
+                return fail(FE_ERR_INVALID_ARG, "rule point %d is not finite", q);
+    }
+    return FE_OK;
+}
+
+static bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+// ---------------------------------------------------------------- planning
+int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coords,
+         const void *coeffs, int64_t ld_in, const fe_quad_rule *rule, void *out_K, void *out_F,
+         int64_t ld_out, const fe_variant *variant, Plan &pl)
+{
+    int st = check_problem(problem, elem);
+    if (st)
+        return st;
+    if (n_elem < 0)
+        return fail(FE_ERR_INVALID_ARG, "n_elem is negative");
+    if ((st = check_rule(rule)))
+        return st;
+    if ((st = check_symmetry(problem)))
+        return st;
+    const uint32_t mask = effective_mask(problem);
+    if (n_elem > 0) {
+        if (!coords || !out_K || !out_F)
+            return fail(FE_ERR_INVALID_ARG, "NULL coordinates or output pointer");
+        if (mask && !coeffs)
+            return fail(FE_ERR_INVALID_ARG, "coeffs is NULL but coef_mask reads %u slots",
+                        (unsigned)__builtin_popcount(mask));
+        if (ld_in < n_elem || ld_out < n_elem)
+            return fail(FE_ERR_INVALID_ARG, "leading dimension smaller than n_elem");
+    }
+    const size_t tsz = problem->precision == FE_FP64 ? 8 : 4;
+    if (!aligned(coords, 8) || !aligned(out_K, tsz) || !aligned(out_F, tsz) ||
+        (mask && !aligned(coeffs, tsz)))
+        return fail(FE_ERR_UNSUPPORTED, "pointers must be aligned to their element size");
+
+    KernelKey k{};
+    k.elem = elem;
+    k.kind = problem->kind;
+    k.prec = problem->precision;
+    if (problem->kind == FE_ELASTICITY) {
+        k.terms = TS_ELAST;
+    } else {
+        const int need = needed_terms(problem);
+        k.terms = ((need & ~TS_POISSON) == 0) ? TS_POISSON : TS_FULL;
+    }
+    const bool per_qp = problem->coef_mode == FE_COEF_PER_QP;
+    if (mask == 0)
+        k.mode = M_UNIFORM;
+    else if (mask == slots_of_terms(k.terms))
+        k.mode = per_qp ? M_QP : M_ELEM;
+    else
+        k.mode = per_qp ? M_QP_MIXED : M_ELEM_MIXED;
+    k.packed = (problem->k_format == FE_K_SYM_PACKED) ? 1 : 0;
+
+    // variant: forced, tuned, or default
+    fe_variant v{};
+    bool forced = variant != nullptr;
+    if (forced) {
+        v = *variant;
+    } else if (tuning_lookup(k, rule->n_q, v) != FE_OK) {
+        v = fe_variant{};
+    }
+    const int wg = v.wg_size ? v.wg_size : 256;
+    if (wg != 64 && wg != 128 && wg != 256)
+        return fail(FE_ERR_UNSUPPORTED, "workgroup size %d not supported (64, 128, 256)", wg);
+    int vec = v.elems_per_thread ? v.elems_per_thread : (elem == FE_TET4 ? 2 : 1);
+    const int nt = (v.nontemporal == 2) ? 0 : 1;
+    const int ref = (v.ref_in_lds == 1) ? REF_LDS : REF_KARG;
+
+    // vector width needs aligned rows
+    auto vec_ok = [&](int V) {
+        if (V == 1)
+            return true;
+        if (ld_in % V || ld_out % V)
+            return false;
+        const size_t ca = std::min<size_t>(16, 8 * V), ta = std::min<size_t>(16, tsz * V);
+        return aligned(coords, ca) && aligned(out_K, ta) && aligned(out_F, ta) &&
+               (!mask || aligned(coeffs, ta));
+    };
+    if (!vec_ok(vec)) {
+        if (forced && v.elems_per_thread > 1)
+            return fail(FE_ERR_UNSUPPORTED, "elements per thread %d needs rows aligned to it", vec);
+        vec = 1;
+    }
+    k.vec = vec;
+    k.nt = nt;
+    k.ref = ref;
+    k.nq = rule->n_q;
+    const KernelEntry *e = find_kernel(k);
+    if (!e) {
+        k.nq = 0;
+        e = find_kernel(k);
+    }
+    if (!e && !forced) {
+        // fall back to the always-built base variant
+        k.vec = 1;
+        k.nt = 1;
+        k.ref = REF_KARG;
+        e = find_kernel(k);
+    }
+    if (!e)
+        return fail(FE_ERR_UNSUPPORTED,
+                    "no compiled kernel for elem=%d kind=%d prec=%d terms=%d mode=%d packed=%d "
+                    "vec=%d nt=%d ref=%d nq=%d",
+                    k.elem, k.kind, k.prec, k.terms, k.mode, k.packed, k.vec, k.nt, k.ref, k.nq);
+
+    KArgs &a = pl.args;
+    std::memset(&a, 0, sizeof(a));
+    a.coords = coords;
+    a.coeffs = coeffs;
+    a.out_K = out_K;
+    a.out_F = out_F;
+    a.n_elem = n_elem;
+    a.ld_in = ld_in;
+    a.ld_out = ld_out;
+    a.k_packed = k.packed;
+    int col = 0;
+    for (int s = 0; s < 20; ++s) {
+        a.col[s] = (s < n_slots(problem->kind) && (mask >> s & 1u)) ? col++ : -1;
+        a.uniform[s] = problem->uniform[s];
+    }
+    fill_reference(elem, *rule, a);
+    pl.entry = e;
+    pl.block = (unsigned)wg;
+    const int64_t groups = (n_elem + k.vec - 1) / k.vec;
+    int64_t grid = (groups + wg - 1) / wg;
+    if (v.blocks > 0 && v.blocks < grid)
+        grid = v.blocks;
+    if (grid > 0x7fffffff)
+        grid = 0x7fffffff;
+    pl.grid = (unsigned)(grid > 0 ? grid : 1);
+    pl.key = k;
+    pl.variant = fe_variant{wg, k.vec, ref == REF_LDS ? 1 : 2, nt ? 1 : 2, v.blocks};
+    return FE_OK;
+}
+
+int launch(const Plan &pl, hipStream_t stream)
+{
+    if (pl.args.n_elem == 0)
+        return FE_OK;
+    pl.entry->launch(pl.args, pl.grid, pl.block, stream);
+    const hipError_t err = hipGetLastError();
+    if (err != hipSuccess)
+        return fail(FE_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(err));
+    return FE_OK;
+}
+
+}  // namespace fe
+
+using namespace fe;
+
+// ------------------------------------------------------------------ C ABI
+extern "C" {
+
+int fe_integrate_ex(const fe_problem *problem, fe_elem_type elem_type, int64_t n_elem,
+                    const double *coords, const void *coeffs, int64_t ld_in,
+                    const fe_quad_rule *quad_rule, void *out_K, void *out_F, int64_t ld_out,
+                    const fe_variant *variant, hipStream_t stream)
+{
+    Plan pl;
+    int st = plan(problem, elem_type, n_elem, coords, coeffs, ld_in, quad_rule, out_K, out_F,
+                  ld_out, variant, pl);
+    if (st)
+        return st;
+    return launch(pl, stream);
+}
+
+int fe_integrate(const fe_problem *problem, fe_elem_type elem_type, int64_t n_elem,
+                 const double *coords, const void *coeffs, const fe_quad_rule *quad_rule,
+                 void *out_K, void *out_F, hipStream_t stream)
+{
+    return fe_integrate_ex(problem, elem_type, n_elem, coords, coeffs, n_elem, quad_rule, out_K,
+                           out_F, n_elem, nullptr, stream);
+}
+
+int64_t fe_k_entries(const fe_problem *problem, fe_elem_type elem_type)
+{
+    if (check_problem(problem, elem_type))
+        return -1;
+    const int64_t N = n_shape(elem_type) * n_comp(problem->kind);
+    return problem->k_format == FE_K_SYM_PACKED ? N * (N + 1) / 2 : N * N;
+}
+
+int64_t fe_f_entries(const fe_problem *problem, fe_elem_type elem_type)
+{
+    if (check_problem(problem, elem_type))
+        return -1;
+    return n_shape(elem_type) * n_comp(problem->kind);
+}
+
+int64_t fe_coeff_entries(const fe_problem *problem, fe_elem_type elem_type, int n_q)
+{
+    if (check_problem(problem, elem_type) || n_q < 1 || n_q > FE_MAX_QP)
+        return -1;
+    const int64_t c = __builtin_popcount(effective_mask(problem));
+    return problem->coef_mode == FE_COEF_PER_QP ? c * n_q : c;
+}
+
+int64_t fe_bytes_per_element(const fe_problem *problem, fe_elem_type elem_type, int n_q)
+{
+    const int64_t nk = fe_k_entries(problem, elem_type);
+    const int64_t nf = fe_f_entries(problem, elem_type);
+    const int64_t nc = fe_coeff_entries(problem, elem_type, n_q);
+    if (nk < 0 || nf < 0 || nc < 0)
+        return -1;
+    const int64_t t = problem->precision == FE_FP64 ? 8 : 4;
+    return 8 * 3 * n_shape(elem_type) + t * (nc + nk + nf);
+}
+
+int64_t fe_k_index(const fe_problem *problem, fe_elem_type elem_type, int row, int col)
+{
+    if (check_problem(problem, elem_type))
+        return -1;
+    const int N = n_shape(elem_type) * n_comp(problem->kind);
+    if (row < 0 || col < 0 || row >= N || col >= N)
+        return -1;
+    if (problem->k_format == FE_K_SYM_PACKED)
+        return col >= row ? (int64_t)row * N - (int64_t)row * (row - 1) / 2 + (col - row) : -1;
+    return (int64_t)row * N + col;
+}
+
+// Built-in rules, written out here independently of any other component.
+static double g_tet1_xi[3], g_tet1_w[1], g_tet4_xi[12], g_tet4_w[4], g_pri6_xi[18], g_pri6_w[6];
+static std::once_flag g_rules_once;
+
+static void init_rules()
+{
+    g_tet1_xi[0] = g_tet1_xi[1] = g_tet1_xi[2] = 0.25;
+    g_tet1_w[0] = 1.0 / 6.0;
+    const double r5 = std::sqrt(5.0);
+    const double hi = (5.0 + 3.0 * r5) / 20.0, lo = (5.0 - r5) / 20.0;
+    for (int q = 0; q < 4; ++q) {
+        for (int k = 0; k < 3; ++k)
+            g_tet4_xi[3 * q + k] = (q == k + 1) ? hi : lo;
+        g_tet4_w[q] = 1.0 / 24.0;
+    }
+    const double tri[3][2] = {{2.0 / 3.0, 1.0 / 6.0}, {1.0 / 6.0, 2.0 / 3.0}, {1.0 / 6.0, 1.0 / 6.0}};
+    const double z = 1.0 / std::sqrt(3.0);
+    for (int t = 0; t < 3; ++t)
+        for (int l = 0; l < 2; ++l) {
+            const int q = 2 * t + l;
+            g_pri6_xi[3 * q] = tri[t][0];
+            g_pri6_xi[3 * q + 1] = tri[t][1];
+            g_pri6_xi[3 * q + 2] = l ? z : -z;
+            g_pri6_w[q] = 1.0 / 6.0;
+        }
+}
+
+int fe_quad_rule_builtin(fe_elem_type elem_type, int n_q, fe_quad_rule *out)
+{
+    if (!out)
+        return fail(FE_ERR_INVALID_ARG, "out is NULL");
+    std::call_once(g_rules_once, init_rules);
+    if (elem_type == FE_TET4 && n_q == 1) {
+        *out = fe_quad_rule{1, g_tet1_xi, g_tet1_w};
+        return FE_OK;
+    }
+    if (elem_type == FE_TET4 && n_q == 4) {
+        *out = fe_quad_rule{4, g_tet4_xi, g_tet4_w};
+        return FE_OK;
+    }
+    if (elem_type == FE_PRISM6 && n_q == 6) {
+        *out = fe_quad_rule{6, g_pri6_xi, g_pri6_w};
+        return FE_OK;
+    }
+    return fail(FE_ERR_UNSUPPORTED, "no built-in rule for element %d with %d points", elem_type, n_q);
+}
+
+const char *fe_status_string(int status)
+{
+    switch (status) {
+    case FE_OK: return "ok";
+    case FE_ERR_INVALID_ARG: return "invalid argument";
+    case FE_ERR_UNSUPPORTED: return "unsupported";
+    case FE_ERR_NOT_SYMMETRIC: return "packed K requested for a non-symmetric problem";
+    case FE_ERR_HIP: return "HIP runtime error";
+    case FE_ERR_CAPACITY: return "capacity exceeded";
+    default: return "unknown status";
+    }
+}
+
+const char *fe_last_error(void) { return g_last_error.c_str(); }
+
+int fe_version(void) { return 1 * 10000 + 0 * 100 + 0; }
+
+}  // extern "C"

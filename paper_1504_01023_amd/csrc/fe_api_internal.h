@@ -1,0 +1,30 @@
+// fe_api_internal.h -- host-side helpers shared by the C-ABI translation
+// units (dispatcher, tuner, batcher). Not part of the public ABI.
+#pragma once
+
+#include "fe.h"
+#include "fe_internal.h"
+
+namespace fe {
+
+// A validated, fully resolved launch.
+struct Plan {
+    KArgs args;
+    const KernelEntry *entry = nullptr;
+    unsigned grid = 0, block = 0;
+    KernelKey key{};
+    fe_variant variant{};
+};
+
+int fail(int status, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+
+int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coords,
+         const void *coeffs, int64_t ld_in, const fe_quad_rule *rule, void *out_K, void *out_F,
+         int64_t ld_out, const fe_variant *variant, Plan &pl);
+int launch(const Plan &pl, hipStream_t stream);
+void fill_reference(int elem, const fe_quad_rule &rule, KArgs &a);
+
+// Tuning table: variant per (kernel family, point count).
+int tuning_lookup(const KernelKey &family, int n_q, fe_variant &out);
+
+}  // namespace fe

@@ -1,0 +1,40 @@
+// fe_copy.hip -- a plain streaming copy used to calibrate HBM byte counters
+// and to measure the achieved copy ceiling next to the integration kernels.
+#include <hip/hip_runtime.h>
+
+#include "fe.h"
+#include "fe_api_internal.h"
+
+namespace {
+
+typedef double d2_t __attribute__((ext_vector_type(2)));
+
+__global__ __launch_bounds__(256) void stream_copy_kernel(d2_t *__restrict__ dst,
+                                                          const d2_t *__restrict__ src, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
+}  // namespace
+
+extern "C" int fe_stream_copy(void *dst, const void *src, int64_t n_bytes, hipStream_t stream)
+{
+    if (n_bytes < 0 || (n_bytes % 16) != 0)
+        return fe::fail(FE_ERR_INVALID_ARG, "n_bytes must be a non-negative multiple of 16");
+    if (n_bytes == 0)
+        return FE_OK;
+    if (!dst || !src || ((uintptr_t)dst % 16) || ((uintptr_t)src % 16))
+        return fe::fail(FE_ERR_INVALID_ARG, "pointers must be non-NULL and 16-byte aligned");
+    const int64_t n = n_bytes / 16;
+    int64_t grid = (n + 255) / 256;
+    if (grid > 65536)
+        grid = 65536;
+    hipLaunchKernelGGL(stream_copy_kernel, dim3((unsigned)grid), dim3(256), 0, stream,
+                       static_cast<d2_t *>(dst), static_cast<const d2_t *>(src), n);
+    const hipError_t err = hipGetLastError();
+    if (err != hipSuccess)
+        return fe::fail(FE_ERR_HIP, "copy launch failed: %s", hipGetErrorString(err));
+    return FE_OK;
+}

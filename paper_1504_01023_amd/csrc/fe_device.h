@@ -1,0 +1,1048 @@
+// fe_device.h -- gfx950 device code for element-by-element numerical
+// integration (Sec. 2.3 of arXiv:1504.01023, parallelised one element per
+// thread as in Sec. 3.2).
+//
+// Design (MI355X / CDNA4):
+//  * Element streaming over structure-of-arrays data: every input and output
+//    array is indexed [row * ld + e], so a wavefront of 64 lanes touches 64
+//    consecutive elements of one row = whole 64-byte segments; with
+//    VEC = 2 or 4 contiguous elements per lane the loads and stores become
+//    16-byte vector accesses (global_load_dwordx4). This is the "coalesced"
+//    organisation of Sec. 4.2, with the data permutation moved into the
+//    layout instead of an LDS transpose.
+//  * Reference data (weights, shape-function values and reference
+//    derivatives at the points, tetrahedron moments) are either read as
+//    wave-uniform kernel arguments (scalar loads into SGPRs) or staged once
+//    per workgroup in LDS (Sec. 4.3 "shared memory usage"; the choice is a
+//    tuning parameter).
+//  * Jacobian terms (J, det J, adj J / det J) are always FP64, from FP64
+//    coordinates. In the FP32 bulk tier the global derivatives and vol are
+//    rounded to FP32 after they are formed and everything after that
+//    (coefficients, accumulation, outputs) is FP32.
+//  * The loop order is QSS (Algorithms 2 and 3): points outermost, then the
+//    two shape-function loops, with the derivative-index loops innermost and
+//    specialised per problem (Sec. 3.3). For tetrahedra the geometric terms
+//    are hoisted out of the point loop (Algorithm 3), and the sums over
+//    points of (weight x coefficient x reference shape values) are formed
+//    before the contraction with the constant gradients.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fe_internal.h"
+
+namespace fe {
+
+typedef double d2_t __attribute__((ext_vector_type(2)));
+typedef float f2_t __attribute__((ext_vector_type(2)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------------ memory
+template <bool NT, typename T>
+__device__ __forceinline__ T ld1(const T *p)
+{
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+
+template <bool NT, typename T>
+__device__ __forceinline__ void st1(T *p, T v)
+{
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
+// Load V consecutive values starting at p. Alignment of p to
+// min(16, V * sizeof(T)) bytes is guaranteed by the host dispatcher.
+template <int V, bool NT>
+__device__ __forceinline__ void loadv(const double *p, double (&v)[V])
+{
+    if constexpr (V == 1) {
+        v[0] = ld1<NT>(p);
+    } else {
+#pragma unroll
+        for (int i = 0; i < V; i += 2) {
+            const d2_t x = ld1<NT>(reinterpret_cast<const d2_t *>(p + i));
+            v[i] = x.x;
+            v[i + 1] = x.y;
+        }
+    }
+}
+
+template <int V, bool NT>
+__device__ __forceinline__ void loadv(const float *p, float (&v)[V])
+{
+    if constexpr (V == 1) {
+        v[0] = ld1<NT>(p);
+    } else if constexpr (V == 2) {
+        const f2_t x = ld1<NT>(reinterpret_cast<const f2_t *>(p));
+        v[0] = x.x;
+        v[1] = x.y;
+    } else {
+        const f4_t x = ld1<NT>(reinterpret_cast<const f4_t *>(p));
+        v[0] = x.x;
+        v[1] = x.y;
+        v[2] = x.z;
+        v[3] = x.w;
+    }
+}
+
+template <int V, bool NT>
+__device__ __forceinline__ void storev(double *p, const double (&v)[V])
+{
+    if constexpr (V == 1) {
+        st1<NT>(p, v[0]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < V; i += 2) {
+            d2_t x;
+            x.x = v[i];
+            x.y = v[i + 1];
+            st1<NT>(reinterpret_cast<d2_t *>(p + i), x);
+        }
+    }
+}
+
+template <int V, bool NT>
+__device__ __forceinline__ void storev(float *p, const float (&v)[V])
+{
+    if constexpr (V == 1) {
+        st1<NT>(p, v[0]);
+    } else if constexpr (V == 2) {
+        f2_t x;
+        x.x = v[0];
+        x.y = v[1];
+        st1<NT>(reinterpret_cast<f2_t *>(p), x);
+    } else {
+        f4_t x;
+        x.x = v[0];
+        x.y = v[1];
+        x.z = v[2];
+        x.w = v[3];
+        st1<NT>(reinterpret_cast<f4_t *>(p), x);
+    }
+}
+
+// ------------------------------------------------------------ small helpers
+__host__ __device__ constexpr int popc_below(uint32_t m, int k)
+{
+    int c = 0;
+    for (int i = 0; i < k; ++i)
+        c += (m >> i) & 1u;
+    return c;
+}
+
+// Packed upper-triangle index of (r, s), r <= s, in an N x N matrix.
+__host__ __device__ constexpr int pidx(int N, int r, int s) { return r * N - r * (r - 1) / 2 + (s - r); }
+
+// Value of coefficient slot k at point q for V consecutive elements.
+template <typename T, int MODE, uint32_t DENSE_SLOTS, int V, bool NT>
+__device__ __forceinline__ void coef(const KArgs &a, int k, int q, int64_t e0, T (&out)[V])
+{
+    if constexpr (MODE == M_UNIFORM) {
+        const T u = (T)a.uniform[k];
+#pragma unroll
+        for (int i = 0; i < V; ++i)
+            out[i] = u;
+    } else if constexpr (MODE == M_ELEM || MODE == M_QP) {
+        const int j = popc_below(DENSE_SLOTS, k);
+        const int64_t row = (MODE == M_QP) ? (int64_t)j * a.n_q + q : (int64_t)j;
+        loadv<V, NT>(static_cast<const T *>(a.coeffs) + row * a.ld_in + e0, out);
+    } else {
+        const int j = a.col[k];
+        if (j < 0) {
+            const T u = (T)a.uniform[k];
+#pragma unroll
+            for (int i = 0; i < V; ++i)
+                out[i] = u;
+        } else {
+            const int64_t row = (MODE == M_QP_MIXED) ? (int64_t)j * a.n_q + q : (int64_t)j;
+            loadv<V, NT>(static_cast<const T *>(a.coeffs) + row * a.ld_in + e0, out);
+        }
+    }
+}
+
+// Reference tables: kernel arguments or an LDS copy.
+struct RefLds {
+    double w[FE_MAX_QP];
+    double phi[FE_MAX_QP][6];
+    double dphi[FE_MAX_QP][6][3];
+};
+
+template <int REF>
+struct Ref {
+    const KArgs &a;
+    const RefLds *s;
+    __device__ __forceinline__ double w(int q) const { return REF == REF_LDS ? s->w[q] : a.w[q]; }
+    __device__ __forceinline__ double phi(int q, int r) const
+    {
+        return REF == REF_LDS ? s->phi[q][r] : a.phi[q][r];
+    }
+    __device__ __forceinline__ double dphi(int q, int r, int k) const
+    {
+        return REF == REF_LDS ? s->dphi[q][r][k] : a.dphi[q][r][k];
+    }
+};
+
+// ------------------------------------------------- tetrahedron geometry
+// Affine tetrahedron: the columns of J are X1-X0, X2-X0, X3-X0; the rows of
+// J^{-1} are the cross products (b x c, c x a, a x b) / det, which are the
+// global gradients of shape functions 1..3; gradient 0 is minus their sum.
+template <typename T>
+__device__ __forceinline__ void tet_geometry(const double (&X)[12], T (&g)[4][3], T &det_t)
+{
+    double a[3], b[3], c[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        a[d] = X[3 + d] - X[d];
+        b[d] = X[6 + d] - X[d];
+        c[d] = X[9 + d] - X[d];
+    }
+    double n[4][3];
+    n[1][0] = b[1] * c[2] - b[2] * c[1];
+    n[1][1] = b[2] * c[0] - b[0] * c[2];
+    n[1][2] = b[0] * c[1] - b[1] * c[0];
+    n[2][0] = c[1] * a[2] - c[2] * a[1];
+    n[2][1] = c[2] * a[0] - c[0] * a[2];
+    n[2][2] = c[0] * a[1] - c[1] * a[0];
+    n[3][0] = a[1] * b[2] - a[2] * b[1];
+    n[3][1] = a[2] * b[0] - a[0] * b[2];
+    n[3][2] = a[0] * b[1] - a[1] * b[0];
+    const double det = a[0] * n[1][0] + a[1] * n[1][1] + a[2] * n[1][2];
+    const double inv = 1.0 / det;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double g1 = n[1][d] * inv, g2 = n[2][d] * inv, g3 = n[3][d] * inv;
+        g[1][d] = (T)g1;
+        g[2][d] = (T)g2;
+        g[3][d] = (T)g3;
+        g[0][d] = (T)(-(g1 + g2 + g3));
+    }
+    det_t = (T)det;
+}
+
+// Vertex coordinates relative to vertex 0 (edge vectors). The reference
+// derivatives sum to zero, so J = sum_r (X_r - X_0) dphi_r/dxi exactly, and
+// the edge vectors avoid the cancellation of absolute coordinates in the
+// thin direction of sliver elements (the FP64 result stays within a few ulp
+// of the exact one there).
+template <int NS>
+__device__ __forceinline__ void to_edge_vectors(double (&X)[NS * 3])
+{
+#pragma unroll
+    for (int r = NS - 1; r >= 1; --r)
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            X[3 * r + i] -= X[i];
+}
+
+// Element given by tables (prism): Jacobian terms at one point from the
+// edge vectors E (E_r = X_r - X_0, r >= 1): J[i][k] = sum_r E_r,i dphi_r/dxi_k;
+// g_r = J^{-T} grad_ref phi_r.
+template <int NS, typename T, class R>
+__device__ __forceinline__ void point_geometry(const double (&E)[NS * 3], const R &ref, int q,
+                                               T (&g)[NS][3], T &vol_t)
+{
+    double J[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            double s = 0.0;
+#pragma unroll
+            for (int r = 1; r < NS; ++r)
+                s += E[3 * r + i] * ref.dphi(q, r, k);
+            J[i][k] = s;
+        }
+    const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+    const double inv = 1.0 / det;
+    double Ji[3][3];  // Ji[k][i] = (J^{-1})_{k i}
+    Ji[0][0] = c00 * inv;
+    Ji[1][0] = c01 * inv;
+    Ji[2][0] = c02 * inv;
+    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * inv;
+    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * inv;
+    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * inv;
+    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * inv;
+    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * inv;
+    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * inv;
+#pragma unroll
+    for (int r = 0; r < NS; ++r) {
+        const double d0 = ref.dphi(q, r, 0), d1 = ref.dphi(q, r, 1), d2 = ref.dphi(q, r, 2);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            g[r][i] = (T)(d0 * Ji[0][i] + d1 * Ji[1][i] + d2 * Ji[2][i]);
+    }
+    vol_t = (T)(det * ref.w(q));
+}
+
+// Lame parameters from Young's modulus and Poisson's ratio.
+template <typename T>
+__device__ __forceinline__ void lame(T E, T nu, T &lam, T &mu)
+{
+    lam = E * nu / ((T(1) + nu) * (T(1) - T(2) * nu));
+    mu = E / (T(2) * (T(1) + nu));
+}
+
+// ===================================================== tetrahedron, scalar
+template <typename T, int TERMS, int MODE, int PACKED>
+struct TetScalar {
+    static constexpr uint32_t SL = slots_of_terms(TERMS);
+    static constexpr bool DIFF = TERMS & T_DIFF, CA = TERMS & T_CONVA, CB = TERMS & T_CONVB,
+                          MASS = TERMS & T_MASS, DG = TERMS & T_DGRAD, D0 = TERMS & T_D0;
+    static constexpr bool PER_QP = (MODE == M_QP || MODE == M_QP_MIXED);
+
+    template <int V, bool NT, int REF>
+    __device__ __forceinline__ static void run(const KArgs &a, const Ref<REF> &ref, int64_t e0)
+    {
+        double X[V][12];
+#pragma unroll
+        for (int s = 0; s < 12; ++s) {
+            double t[V];
+            loadv<V, NT>(a.coords + s * a.ld_in + e0, t);
+#pragma unroll
+            for (int i = 0; i < V; ++i)
+                X[i][s] = t[i];
+        }
+        if constexpr (!PER_QP)
+            run_const<V, NT>(a, X, e0);
+        else
+            run_qp<V, NT, REF>(a, ref, X, e0);
+    }
+
+    template <int V, bool NT>
+    __device__ __forceinline__ static void store_K(const KArgs &a, int r, int s, int64_t e0,
+                                                   const T (&val)[V])
+    {
+        const int k = PACKED ? pidx(4, r, s) : 4 * r + s;
+        storev<V, NT>(static_cast<T *>(a.out_K) + k * a.ld_out + e0, val);
+    }
+
+    // Coefficients constant over the element: with the (constant) gradients
+    // g, the weighted moments W, m_r, M_rs of the reference shape functions
+    // carry the whole point sum:
+    //   K_rs = det [W g_r . C g_s + (c^{.;0} . g_r) m_s + m_r (c^{0;.} . g_s)
+    //               + c^{0;0} M_rs],   F_r = det [W d . g_r + d^0 m_r].
+    template <int V, bool NT>
+    __device__ __forceinline__ static void run_const(const KArgs &a, const double (&X)[V][12],
+                                                     int64_t e0)
+    {
+        T C[3][3][V], ca[3][V], cb[3][V], c00[V], d[3][V], d0[V];
+        if constexpr (DIFF) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+                    coef<T, MODE, SL, V, NT>(a, 4 * (i + 1) + 1 + j, 0, e0, C[i][j]);
+        }
+        if constexpr (CA) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                coef<T, MODE, SL, V, NT>(a, 4 * (i + 1), 0, e0, ca[i]);
+        }
+        if constexpr (CB) {
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                coef<T, MODE, SL, V, NT>(a, 1 + j, 0, e0, cb[j]);
+        }
+        if constexpr (MASS)
+            coef<T, MODE, SL, V, NT>(a, 0, 0, e0, c00);
+        if constexpr (DG) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                coef<T, MODE, SL, V, NT>(a, 17 + i, 0, e0, d[i]);
+        }
+        if constexpr (D0)
+            coef<T, MODE, SL, V, NT>(a, 16, 0, e0, d0);
+
+        const T W = (T)a.Wsum;
+        T Kv[4][4][V], Fv[4][V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            T g[4][3], det;
+            tet_geometry<T>(X[v], g, det);
+            const T sw = det * W;
+            T al[4], be[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                al[r] = T(0);
+                be[r] = T(0);
+                if constexpr (CA)
+                    al[r] = det * (ca[0][v] * g[r][0] + ca[1][v] * g[r][1] + ca[2][v] * g[r][2]);
+                if constexpr (CB)
+                    be[r] = det * (cb[0][v] * g[r][0] + cb[1][v] * g[r][1] + cb[2][v] * g[r][2]);
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                T t[3] = {T(0), T(0), T(0)};
+                if constexpr (DIFF) {
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+                        t[i] = sw * (C[i][0][v] * g[s][0] + C[i][1][v] * g[s][1] + C[i][2][v] * g[s][2]);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if (PACKED && s < r)
+                        continue;
+                    T x = T(0);
+                    if constexpr (DIFF)
+                        x = g[r][0] * t[0] + g[r][1] * t[1] + g[r][2] * t[2];
+                    if constexpr (CA)
+                        x += al[r] * (T)a.m[s];
+                    if constexpr (CB)
+                        x += (T)a.m[r] * be[s];
+                    if constexpr (MASS)
+                        x += det * c00[v] * (T)a.M[r][s];
+                    // stored below, element by element within the group
+                    Kv[r][s][v] = x;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                T x = T(0);
+                if constexpr (DG)
+                    x = sw * (d[0][v] * g[r][0] + d[1][v] * g[r][1] + d[2][v] * g[r][2]);
+                if constexpr (D0)
+                    x += det * d0[v] * (T)a.m[r];
+                Fv[r][v] = x;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int s = (PACKED ? r : 0); s < 4; ++s)
+                store_K<V, NT>(a, r, s, e0, Kv[r][s]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            storev<V, NT>(static_cast<T *>(a.out_F) + r * a.ld_out + e0, Fv[r]);
+    }
+
+    // Coefficients per point (Algorithm 3 with "calculate possibly
+    // coefficients" inside the point loop): the point sums of weight x
+    // coefficient x reference values are formed first, then contracted with
+    // the constant gradients:
+    //   Cb = sum_q w C_q, Pb_s = sum_q w phi_s c^{.;0}_q, Qb_r = sum_q w phi_r c^{0;.}_q,
+    //   Mb_rs = sum_q w c^{0;0}_q phi_r phi_s, Db = sum_q w d_q, fb_r = sum_q w d^0_q phi_r,
+    //   K_rs = det (g_r . Cb g_s + g_r . Pb_s + Qb_r . g_s + Mb_rs), F_r = det (Db . g_r + fb_r).
+    template <int V, bool NT, int REF>
+    __device__ __forceinline__ static void run_qp(const KArgs &a, const Ref<REF> &ref,
+                                                  const double (&X)[V][12], int64_t e0)
+    {
+        T Cb[V][3][3], Pb[V][4][3], Qb[V][4][3], Mb[V][4][4], Db[V][3], fb[V][4];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                Db[v][i] = T(0);
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+                    Cb[v][i][j] = T(0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                fb[v][r] = T(0);
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+                    Pb[v][r][i] = Qb[v][r][i] = T(0);
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    Mb[v][r][s] = T(0);
+            }
+        }
+        for (int q = 0; q < a.n_q; ++q) {
+            const T w = (T)ref.w(q);
+            T wp[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                wp[r] = w * (T)ref.phi(q, r);
+            T c[V];
+            if constexpr (DIFF) {
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        coef<T, MODE, SL, V, NT>(a, 4 * (i + 1) + 1 + j, q, e0, c);
+#pragma unroll
+                        for (int v = 0; v < V; ++v)
+                            Cb[v][i][j] += w * c[v];
+                    }
+            }
+            if constexpr (CA) {
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    coef<T, MODE, SL, V, NT>(a, 4 * (i + 1), q, e0, c);
+#pragma unroll
+                    for (int v = 0; v < V; ++v)
+#pragma unroll
+                        for (int s = 0; s < 4; ++s)
+                            Pb[v][s][i] += wp[s] * c[v];
+                }
+            }
+            if constexpr (CB) {
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    coef<T, MODE, SL, V, NT>(a, 1 + j, q, e0, c);
+#pragma unroll
+                    for (int v = 0; v < V; ++v)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            Qb[v][r][j] += wp[r] * c[v];
+                }
+            }
+            if constexpr (MASS) {
+                coef<T, MODE, SL, V, NT>(a, 0, q, e0, c);
+#pragma unroll
+                for (int v = 0; v < V; ++v)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int s = 0; s < 4; ++s)
+                            Mb[v][r][s] += wp[r] * (T)ref.phi(q, s) * c[v];
+            }
+            if constexpr (DG) {
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    coef<T, MODE, SL, V, NT>(a, 17 + i, q, e0, c);
+#pragma unroll
+                    for (int v = 0; v < V; ++v)
+                        Db[v][i] += w * c[v];
+                }
+            }
+            if constexpr (D0) {
+                coef<T, MODE, SL, V, NT>(a, 16, q, e0, c);
+#pragma unroll
+                for (int v = 0; v < V; ++v)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        fb[v][r] += wp[r] * c[v];
+            }
+        }
+        T Kv[4][4][V], Fv[4][V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            T g[4][3], det;
+            tet_geometry<T>(X[v], g, det);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                T t[3];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    T x = T(0);
+                    if constexpr (DIFF)
+                        x = Cb[v][i][0] * g[s][0] + Cb[v][i][1] * g[s][1] + Cb[v][i][2] * g[s][2];
+                    if constexpr (CA)
+                        x += Pb[v][s][i];
+                    t[i] = x;
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if (PACKED && s < r)
+                        continue;
+                    T x = T(0);
+                    if constexpr (DIFF || CA)
+                        x = g[r][0] * t[0] + g[r][1] * t[1] + g[r][2] * t[2];
+                    if constexpr (CB)
+                        x += Qb[v][r][0] * g[s][0] + Qb[v][r][1] * g[s][1] + Qb[v][r][2] * g[s][2];
+                    if constexpr (MASS)
+                        x += Mb[v][r][s];
+                    Kv[r][s][v] = det * x;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                T x = T(0);
+                if constexpr (DG)
+                    x = Db[v][0] * g[r][0] + Db[v][1] * g[r][1] + Db[v][2] * g[r][2];
+                if constexpr (D0)
+                    x += fb[v][r];
+                Fv[r][v] = det * x;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int s = (PACKED ? r : 0); s < 4; ++s)
+                store_K<V, NT>(a, r, s, e0, Kv[r][s]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            storev<V, NT>(static_cast<T *>(a.out_F) + r * a.ld_out + e0, Fv[r]);
+    }
+};
+
+// ================================================= tetrahedron, elasticity
+// K_(r a),(s b) = det [lam_b g_ra g_sb + mu_b g_rb g_sa + mu_b delta_ab g_r . g_s]
+// with lam_b = sum_q w_q lambda_q, mu_b likewise (gradients are constant);
+// F_(r a) = det sum_q w_q f_a,q phi_r(xi_q).
+template <typename T, int MODE, int PACKED>
+struct TetElastic {
+    static constexpr uint32_t SL = 31u;
+    static constexpr bool PER_QP = (MODE == M_QP || MODE == M_QP_MIXED);
+
+    template <int V, bool NT, int REF>
+    __device__ __forceinline__ static void run(const KArgs &a, const Ref<REF> &ref, int64_t e0)
+    {
+        double X[V][12];
+#pragma unroll
+        for (int s = 0; s < 12; ++s) {
+            double t[V];
+            loadv<V, NT>(a.coords + s * a.ld_in + e0, t);
+#pragma unroll
+            for (int i = 0; i < V; ++i)
+                X[i][s] = t[i];
+        }
+        T lb[V], mb[V], fb[V][4][3];
+        if constexpr (!PER_QP) {
+            T E[V], nu[V], f[3][V];
+            coef<T, MODE, SL, V, NT>(a, 0, 0, e0, E);
+            coef<T, MODE, SL, V, NT>(a, 1, 0, e0, nu);
+#pragma unroll
+            for (int al = 0; al < 3; ++al)
+                coef<T, MODE, SL, V, NT>(a, 2 + al, 0, e0, f[al]);
+            const T W = (T)a.Wsum;
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                T lam, mu;
+                lame<T>(E[v], nu[v], lam, mu);
+                lb[v] = W * lam;
+                mb[v] = W * mu;
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int al = 0; al < 3; ++al)
+                        fb[v][r][al] = (T)a.m[r] * f[al][v];
+            }
+        } else {
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                lb[v] = mb[v] = T(0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int al = 0; al < 3; ++al)
+                        fb[v][r][al] = T(0);
+            }
+            for (int q = 0; q < a.n_q; ++q) {
+                const T w = (T)ref.w(q);
+                T E[V], nu[V], f[3][V];
+                coef<T, MODE, SL, V, NT>(a, 0, q, e0, E);
+                coef<T, MODE, SL, V, NT>(a, 1, q, e0, nu);
+#pragma unroll
+                for (int al = 0; al < 3; ++al)
+                    coef<T, MODE, SL, V, NT>(a, 2 + al, q, e0, f[al]);
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    T lam, mu;
+                    lame<T>(E[v], nu[v], lam, mu);
+                    lb[v] += w * lam;
+                    mb[v] += w * mu;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const T wp = w * (T)ref.phi(q, r);
+#pragma unroll
+                        for (int al = 0; al < 3; ++al)
+                            fb[v][r][al] += wp * f[al][v];
+                    }
+                }
+            }
+        }
+        T g[V][4][3], det[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            tet_geometry<T>(X[v], g[v], det[v]);
+            lb[v] *= det[v];
+            mb[v] *= det[v];
+        }
+        T *outK = static_cast<T *>(a.out_K);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int s = (PACKED ? r : 0); s < 4; ++s) {
+                T dot[V];
+#pragma unroll
+                for (int v = 0; v < V; ++v)
+                    dot[v] = mb[v] * (g[v][r][0] * g[v][s][0] + g[v][r][1] * g[v][s][1] +
+                                      g[v][r][2] * g[v][s][2]);
+#pragma unroll
+                for (int al = 0; al < 3; ++al)
+#pragma unroll
+                    for (int be = 0; be < 3; ++be) {
+                        const int row = 3 * r + al, col = 3 * s + be;
+                        if (PACKED && col < row)
+                            continue;
+                        T val[V];
+#pragma unroll
+                        for (int v = 0; v < V; ++v) {
+                            T x = lb[v] * g[v][r][al] * g[v][s][be] + mb[v] * g[v][r][be] * g[v][s][al];
+                            if (al == be)
+                                x += dot[v];
+                            val[v] = x;
+                        }
+                        const int k = PACKED ? pidx(12, row, col) : 12 * row + col;
+                        storev<V, NT>(outK + k * a.ld_out + e0, val);
+                    }
+            }
+        T *outF = static_cast<T *>(a.out_F);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int al = 0; al < 3; ++al) {
+                T val[V];
+#pragma unroll
+                for (int v = 0; v < V; ++v)
+                    val[v] = det[v] * fb[v][r][al];
+                storev<V, NT>(outF + (3 * r + al) * a.ld_out + e0, val);
+            }
+    }
+};
+
+// ========================================================== prism, scalar
+// Algorithm 2 (QSS, geometry per point): for every point the Jacobian terms
+// and global derivatives are formed, then the S x S update. With
+// u_r = vol g_r, p_r = vol phi_r, t_s = C g_s + phi_s c^{.;0} and
+// sigma_s = c^{0;.} . g_s + c^{0;0} phi_s:  K_rs += u_r . t_s + p_r sigma_s,
+// F_r += u_r . d + p_r d^0.
+template <typename T, int TERMS, int MODE, int PACKED, int NQ>
+struct PrismScalar {
+    static constexpr uint32_t SL = slots_of_terms(TERMS);
+    static constexpr bool DIFF = TERMS & T_DIFF, CA = TERMS & T_CONVA, CB = TERMS & T_CONVB,
+                          MASS = TERMS & T_MASS, DG = TERMS & T_DGRAD, D0 = TERMS & T_D0;
+    static constexpr bool PER_QP = (MODE == M_QP || MODE == M_QP_MIXED);
+    static constexpr bool NEED_PHI = CA || CB || MASS || D0;
+
+    struct Coefs {
+        T C[3][3], ca[3], cb[3], c00, d[3], d0;
+    };
+
+    template <bool NT>
+    __device__ __forceinline__ static void load_coefs(const KArgs &a, int q, int64_t e, Coefs &c)
+    {
+        T x[1];
+        if constexpr (DIFF) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    coef<T, MODE, SL, 1, NT>(a, 4 * (i + 1) + 1 + j, q, e, x);
+                    c.C[i][j] = x[0];
+                }
+        }
+        if constexpr (CA) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                coef<T, MODE, SL, 1, NT>(a, 4 * (i + 1), q, e, x);
+                c.ca[i] = x[0];
+            }
+        }
+        if constexpr (CB) {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                coef<T, MODE, SL, 1, NT>(a, 1 + j, q, e, x);
+                c.cb[j] = x[0];
+            }
+        }
+        if constexpr (MASS) {
+            coef<T, MODE, SL, 1, NT>(a, 0, q, e, x);
+            c.c00 = x[0];
+        }
+        if constexpr (DG) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                coef<T, MODE, SL, 1, NT>(a, 17 + i, q, e, x);
+                c.d[i] = x[0];
+            }
+        }
+        if constexpr (D0) {
+            coef<T, MODE, SL, 1, NT>(a, 16, q, e, x);
+            c.d0 = x[0];
+        }
+    }
+
+    template <int V, bool NT, int REF>
+    __device__ __forceinline__ static void run(const KArgs &a, const Ref<REF> &ref, int64_t e)
+    {
+        static_assert(V == 1, "prisms are processed one element per lane");
+        double X[18];
+#pragma unroll
+        for (int s = 0; s < 18; ++s)
+            X[s] = ld1<NT>(a.coords + s * a.ld_in + e);
+        to_edge_vectors<6>(X);
+        constexpr int NK = PACKED ? 21 : 36;
+        T K[NK], F[6];
+#pragma unroll
+        for (int k = 0; k < NK; ++k)
+            K[k] = T(0);
+#pragma unroll
+        for (int r = 0; r < 6; ++r)
+            F[r] = T(0);
+        Coefs c;
+        if constexpr (!PER_QP)
+            load_coefs<NT>(a, 0, e, c);
+        const int nq = NQ > 0 ? NQ : a.n_q;
+#pragma unroll(NQ > 0 ? NQ : 1)
+        for (int q = 0; q < nq; ++q) {
+            if constexpr (PER_QP)
+                load_coefs<NT>(a, q, e, c);
+            T g[6][3], vol;
+            point_geometry<6, T>(X, ref, q, g, vol);
+            T phi[6];
+            if constexpr (NEED_PHI) {
+#pragma unroll
+                for (int r = 0; r < 6; ++r)
+                    phi[r] = (T)ref.phi(q, r);
+            }
+            T t[6][3], sg[6];
+#pragma unroll
+            for (int s = 0; s < 6; ++s) {
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    T x = T(0);
+                    if constexpr (DIFF)
+                        x = c.C[i][0] * g[s][0] + c.C[i][1] * g[s][1] + c.C[i][2] * g[s][2];
+                    if constexpr (CA)
+                        x += phi[s] * c.ca[i];
+                    t[s][i] = x;
+                }
+                T y = T(0);
+                if constexpr (CB)
+                    y = c.cb[0] * g[s][0] + c.cb[1] * g[s][1] + c.cb[2] * g[s][2];
+                if constexpr (MASS)
+                    y += c.c00 * phi[s];
+                sg[s] = y;
+            }
+#pragma unroll
+            for (int r = 0; r < 6; ++r) {
+                const T u0 = vol * g[r][0], u1 = vol * g[r][1], u2 = vol * g[r][2];
+                T p = T(0);
+                if constexpr (NEED_PHI)
+                    p = vol * phi[r];
+#pragma unroll
+                for (int s = (PACKED ? r : 0); s < 6; ++s) {
+                    const int k = PACKED ? pidx(6, r, s) : 6 * r + s;
+                    T x = K[k];
+                    if constexpr (DIFF || CA)
+                        x += u0 * t[s][0] + u1 * t[s][1] + u2 * t[s][2];
+                    if constexpr (CB || MASS)
+                        x += p * sg[s];
+                    K[k] = x;
+                }
+                if constexpr (DG)
+                    F[r] += u0 * c.d[0] + u1 * c.d[1] + u2 * c.d[2];
+                if constexpr (D0)
+                    F[r] += p * c.d0;
+            }
+        }
+        T *outK = static_cast<T *>(a.out_K);
+#pragma unroll
+        for (int k = 0; k < NK; ++k)
+            st1<NT>(outK + k * a.ld_out + e, K[k]);
+        T *outF = static_cast<T *>(a.out_F);
+#pragma unroll
+        for (int r = 0; r < 6; ++r)
+            st1<NT>(outF + r * a.ld_out + e, F[r]);
+    }
+};
+
+// ====================================================== prism, elasticity
+// Coefficients constant over the element: H_rs = sum_q vol_q g_r g_s^T
+// (r <= s), then K_(r a),(s b) = lam H_rs[a][b] + mu H_rs[b][a]
+// + mu delta_ab tr H_rs, and F_(r a) = f_a sum_q vol_q phi_r(xi_q).
+// Coefficients per point: the same expression accumulated point by point
+// with lambda_q, mu_q (and f_q), directly into the packed K.
+template <typename T, int MODE, int PACKED, int NQ>
+struct PrismElastic {
+    static constexpr uint32_t SL = 31u;
+    static constexpr bool PER_QP = (MODE == M_QP || MODE == M_QP_MIXED);
+    static constexpr int NP = 171;  // packed entries of the 18 x 18 matrix
+
+    template <int V, bool NT, int REF>
+    __device__ __forceinline__ static void run(const KArgs &a, const Ref<REF> &ref, int64_t e)
+    {
+        static_assert(V == 1, "prisms are processed one element per lane");
+        double X[18];
+#pragma unroll
+        for (int s = 0; s < 18; ++s)
+            X[s] = ld1<NT>(a.coords + s * a.ld_in + e);
+        to_edge_vectors<6>(X);
+        T Kp[NP], F[18];
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+            Kp[k] = T(0);
+#pragma unroll
+        for (int k = 0; k < 18; ++k)
+            F[k] = T(0);
+        const int nq = NQ > 0 ? NQ : a.n_q;
+        if constexpr (!PER_QP) {
+            // Kp holds H_rs (r <= s) in the positions of the packed K block
+            // (r, s): entry (3r+a, 3s+b); for r == s only b >= a.
+            T sphi[6];
+#pragma unroll
+            for (int r = 0; r < 6; ++r)
+                sphi[r] = T(0);
+#pragma unroll(NQ > 0 ? NQ : 1)
+            for (int q = 0; q < nq; ++q) {
+                T g[6][3], vol;
+                point_geometry<6, T>(X, ref, q, g, vol);
+#pragma unroll
+                for (int r = 0; r < 6; ++r) {
+                    const T u[3] = {vol * g[r][0], vol * g[r][1], vol * g[r][2]};
+                    sphi[r] += vol * (T)ref.phi(q, r);
+#pragma unroll
+                    for (int s = r; s < 6; ++s)
+#pragma unroll
+                        for (int al = 0; al < 3; ++al)
+#pragma unroll
+                            for (int be = (s == r ? al : 0); be < 3; ++be)
+                                Kp[pidx(18, 3 * r + al, 3 * s + be)] += u[al] * g[s][be];
+                }
+            }
+            T E[1], nu[1], f[3][1];
+            coef<T, MODE, SL, 1, NT>(a, 0, 0, e, E);
+            coef<T, MODE, SL, 1, NT>(a, 1, 0, e, nu);
+#pragma unroll
+            for (int al = 0; al < 3; ++al)
+                coef<T, MODE, SL, 1, NT>(a, 2 + al, 0, e, f[al]);
+            T lam, mu;
+            lame<T>(E[0], nu[0], lam, mu);
+            // Transform H -> K block by block, in place.
+#pragma unroll
+            for (int r = 0; r < 6; ++r)
+#pragma unroll
+                for (int s = r; s < 6; ++s) {
+                    T H[3][3];
+#pragma unroll
+                    for (int al = 0; al < 3; ++al)
+#pragma unroll
+                        for (int be = 0; be < 3; ++be) {
+                            if (s == r && be < al)
+                                H[al][be] = Kp[pidx(18, 3 * r + be, 3 * s + al)];
+                            else
+                                H[al][be] = Kp[pidx(18, 3 * r + al, 3 * s + be)];
+                        }
+                    const T tr = mu * (H[0][0] + H[1][1] + H[2][2]);
+#pragma unroll
+                    for (int al = 0; al < 3; ++al)
+#pragma unroll
+                        for (int be = (s == r ? al : 0); be < 3; ++be) {
+                            T x = lam * H[al][be] + mu * H[be][al];
+                            if (al == be)
+                                x += tr;
+                            Kp[pidx(18, 3 * r + al, 3 * s + be)] = x;
+                        }
+                }
+#pragma unroll
+            for (int r = 0; r < 6; ++r)
+#pragma unroll
+                for (int al = 0; al < 3; ++al)
+                    F[3 * r + al] = f[al][0] * sphi[r];
+        } else {
+#pragma unroll(NQ > 0 ? NQ : 1)
+            for (int q = 0; q < nq; ++q) {
+                T E[1], nu[1], f[3][1];
+                coef<T, MODE, SL, 1, NT>(a, 0, q, e, E);
+                coef<T, MODE, SL, 1, NT>(a, 1, q, e, nu);
+#pragma unroll
+                for (int al = 0; al < 3; ++al)
+                    coef<T, MODE, SL, 1, NT>(a, 2 + al, q, e, f[al]);
+                T lam, mu;
+                lame<T>(E[0], nu[0], lam, mu);
+                T g[6][3], vol;
+                point_geometry<6, T>(X, ref, q, g, vol);
+                const T vl = vol * lam, vm = vol * mu;
+#pragma unroll
+                for (int r = 0; r < 6; ++r) {
+                    const T p = vol * (T)ref.phi(q, r);
+#pragma unroll
+                    for (int al = 0; al < 3; ++al)
+                        F[3 * r + al] += p * f[al][0];
+#pragma unroll
+                    for (int s = r; s < 6; ++s) {
+                        const T dot = vm * (g[r][0] * g[s][0] + g[r][1] * g[s][1] + g[r][2] * g[s][2]);
+#pragma unroll
+                        for (int al = 0; al < 3; ++al)
+#pragma unroll
+                            for (int be = (s == r ? al : 0); be < 3; ++be) {
+                                T x = vl * g[r][al] * g[s][be] + vm * g[r][be] * g[s][al];
+                                if (al == be)
+                                    x += dot;
+                                Kp[pidx(18, 3 * r + al, 3 * s + be)] += x;
+                            }
+                    }
+                }
+            }
+        }
+        T *outK = static_cast<T *>(a.out_K);
+        if constexpr (PACKED) {
+#pragma unroll
+            for (int k = 0; k < NP; ++k)
+                st1<NT>(outK + k * a.ld_out + e, Kp[k]);
+        } else {
+#pragma unroll
+            for (int row = 0; row < 18; ++row)
+#pragma unroll
+                for (int col = 0; col < 18; ++col) {
+                    const int k = col >= row ? pidx(18, row, col) : pidx(18, col, row);
+                    st1<NT>(outK + (18 * row + col) * a.ld_out + e, Kp[k]);
+                }
+        }
+        T *outF = static_cast<T *>(a.out_F);
+#pragma unroll
+        for (int k = 0; k < 18; ++k)
+            st1<NT>(outF + k * a.ld_out + e, F[k]);
+    }
+};
+
+// ================================================================ kernel
+// Grid: element groups of V contiguous elements, one group per lane, with a
+// grid-stride loop so a launch may use fewer workgroups than groups. The
+// last, partial group is processed element by element.
+template <class P, int V, bool NT, int REF>
+__global__ __launch_bounds__(256) void fe_kernel(KArgs a)
+{
+    __shared__ RefLds lds_ref[REF == REF_LDS ? 1 : 0 + 1];
+    if constexpr (REF == REF_LDS) {
+        const int n_w = a.n_q, n_phi = a.n_q * 6, n_dphi = a.n_q * 18;
+        for (int i = threadIdx.x; i < n_w; i += blockDim.x)
+            lds_ref[0].w[i] = a.w[i];
+        for (int i = threadIdx.x; i < n_phi; i += blockDim.x)
+            (&lds_ref[0].phi[0][0])[i] = (&a.phi[0][0])[i];
+        for (int i = threadIdx.x; i < n_dphi; i += blockDim.x)
+            (&lds_ref[0].dphi[0][0][0])[i] = (&a.dphi[0][0][0])[i];
+        __syncthreads();
+    }
+    const Ref<REF> ref{a, &lds_ref[0]};
+    const int64_t n_groups = (a.n_elem + V - 1) / V;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_groups; g += stride) {
+        const int64_t e0 = g * V;
+        if (V == 1 || e0 + V <= a.n_elem) {
+            P::template run<V, NT, REF>(a, ref, e0);
+        } else {
+            for (int64_t e = e0; e < a.n_elem; ++e)
+                P::template run<1, NT, REF>(a, ref, e);
+        }
+    }
+}
+
+template <class P, int V, bool NT, int REF>
+void launch_fe_kernel(const KArgs &a, unsigned grid, unsigned block, hipStream_t stream)
+{
+    hipLaunchKernelGGL((fe_kernel<P, V, NT, REF>), dim3(grid), dim3(block), 0, stream, a);
+}
+
+template <class P, int V, bool NT, int REF>
+struct Registrar {
+    explicit Registrar(KernelKey k)
+    {
+        register_kernel(KernelEntry{k, &launch_fe_kernel<P, V, NT, REF>,
+                                    reinterpret_cast<const void *>(&fe_kernel<P, V, NT, REF>)});
+    }
+};
+
+}  // namespace fe

@@ -1,0 +1,106 @@
+// fe_internal.h -- structures shared by the host dispatcher (fe_api.cpp) and
+// the kernel translation units. Not part of the public ABI.
+#pragma once
+
+#include <cstdint>
+
+#include "fe.h"
+
+namespace fe {
+
+// Term groups of the scalar weak form (Sec. 2.1, eq. "weak_form"); a kernel
+// is compiled for a set of groups and the code for absent groups is removed.
+enum TermBits : int {
+    T_DIFF = 1,   // c^{i;j}, slots 5-7, 9-11, 13-15
+    T_CONVA = 2,  // c^{i;0}, slots 4, 8, 12 (derivative of the test function)
+    T_CONVB = 4,  // c^{0;j}, slots 1, 2, 3 (derivative of the trial function)
+    T_MASS = 8,   // c^{0;0}, slot 0
+    T_DGRAD = 16, // d^i, slots 17-19
+    T_D0 = 32,    // d^0, slot 16
+};
+constexpr int TS_POISSON = T_DIFF | T_D0;
+constexpr int TS_FULL = 63;
+constexpr int TS_ELAST = 64;  // marker for the elasticity kernels
+
+// Where coefficient values come from.
+enum ModeKind : int {
+    M_UNIFORM = 0,     // kernel arguments only
+    M_ELEM = 1,        // per element, every slot of the term set in memory (dense)
+    M_QP = 2,          // per point, dense
+    M_ELEM_MIXED = 3,  // per element, slot by slot from memory or arguments
+    M_QP_MIXED = 4,    // per point, slot by slot
+};
+
+enum RefKind : int { REF_KARG = 0, REF_LDS = 1 };
+
+constexpr uint32_t slots_of_terms(int terms)
+{
+    uint32_t m = 0;
+    if (terms & T_DIFF) m |= (1u << 5) | (1u << 6) | (1u << 7) | (1u << 9) | (1u << 10) |
+                             (1u << 11) | (1u << 13) | (1u << 14) | (1u << 15);
+    if (terms & T_CONVA) m |= (1u << 4) | (1u << 8) | (1u << 12);
+    if (terms & T_CONVB) m |= (1u << 1) | (1u << 2) | (1u << 3);
+    if (terms & T_MASS) m |= 1u;
+    if (terms & T_DGRAD) m |= (1u << 17) | (1u << 18) | (1u << 19);
+    if (terms & T_D0) m |= (1u << 16);
+    if (terms & TS_ELAST) m = 31u;
+    return m;
+}
+
+// Kernel arguments, passed by value (they live in the kernel-argument
+// segment and are read with wave-uniform scalar loads). Reference data are
+// evaluated on the host from the caller's rule: shape-function values and
+// reference derivatives at every point, weights, and for tetrahedra the
+// weighted moments W = sum_q w_q, m_r = sum_q w_q phi_r(xi_q),
+// M_rs = sum_q w_q phi_r(xi_q) phi_s(xi_q).
+struct KArgs {
+    const double *coords;
+    const void *coeffs;
+    void *out_K;
+    void *out_F;
+    int64_t n_elem;
+    int64_t ld_in;
+    int64_t ld_out;
+    int32_t n_q;
+    int32_t k_packed;
+    int32_t col[20];     // compact column of each slot in coeffs, -1 = uniform
+    double uniform[20];
+    double w[FE_MAX_QP];
+    double phi[FE_MAX_QP][6];
+    double dphi[FE_MAX_QP][6][3];
+    double Wsum;
+    double m[6];
+    double M[6][6];
+};
+static_assert(sizeof(KArgs) < 4096, "kernel arguments must stay below 4 KiB");
+
+// Identifies one compiled kernel.
+struct KernelKey {
+    int elem;      // fe_elem_type
+    int kind;      // fe_problem_kind
+    int prec;      // fe_precision
+    int terms;     // term set (scalar) or TS_ELAST
+    int mode;      // ModeKind
+    int packed;    // 1 = packed K store
+    int vec;       // elements per thread
+    int nt;        // non-temporal memory operations
+    int ref;       // RefKind
+    int nq;        // compiled point count, 0 = runtime loop
+};
+
+typedef void (*LaunchFn)(const KArgs &, unsigned grid, unsigned block, hipStream_t);
+
+struct KernelEntry {
+    KernelKey key;
+    LaunchFn launch;
+    const void *func;
+};
+
+// Registration of compiled kernels (each kernel translation unit registers
+// its instantiations at load time).
+void register_kernel(const KernelEntry &e);
+const KernelEntry *find_kernel(const KernelKey &k);
+int kernel_count();
+const KernelEntry *kernel_at(int i);
+
+}  // namespace fe

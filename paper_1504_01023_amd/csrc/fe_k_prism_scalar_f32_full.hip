@@ -1,0 +1,26 @@
+// Prism, scalar problem: kernel instantiations (float, TS_FULL).
+#include "fe_register.h"
+
+namespace {
+using namespace fe;
+typedef float T;
+constexpr int TS = TS_FULL;
+
+int register_all()
+{
+    // every coefficient mode and K format with a runtime point loop
+#define BASE(MODE) \
+    reg_prism_scalar<T, TS, MODE, 0, 0, 1, REF_KARG>(); reg_prism_scalar<T, TS, MODE, 1, 0, 1, REF_KARG>();
+    BASE(M_UNIFORM) BASE(M_ELEM) BASE(M_QP) BASE(M_ELEM_MIXED) BASE(M_QP_MIXED)
+#undef BASE
+    // tuning variants of the runtime point loop: cache policy and LDS
+    // staging of the reference tables
+#define TUNE(MODE, PK) \
+    reg_prism_scalar<T, TS, MODE, PK, 0, 0, REF_KARG>(); reg_prism_scalar<T, TS, MODE, PK, 0, 1, REF_LDS>(); \
+    reg_prism_scalar<T, TS, MODE, PK, 0, 0, REF_LDS>();
+    TUNE(M_QP, 0) TUNE(M_ELEM, 0) TUNE(M_UNIFORM, 1) TUNE(M_UNIFORM, 0)
+#undef TUNE
+    return 0;
+}
+const int registered = register_all();
+}  // namespace

@@ -1,0 +1,231 @@
+// fe_tune.cpp -- parameter-based tuning by exhaustive search (the approach
+// of Sec. 4.3: compile-time variants of one kernel, all run, the fastest
+// kept), extended with the GPU launch shape. The table maps a kernel family
+// (element, problem, precision, term set, coefficient mode, K format, point
+// count) to the variant fe_integrate uses.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <set>
+#include <tuple>
+#include <vector>
+
+#include "fe.h"
+#include "fe_api_internal.h"
+
+namespace fe {
+
+typedef std::tuple<int, int, int, int, int, int, int> FamilyKey;
+
+static std::mutex g_tune_mu;
+static std::map<FamilyKey, fe_variant> &table()
+{
+    static std::map<FamilyKey, fe_variant> t;
+    return t;
+}
+
+static FamilyKey family_of(const KernelKey &k, int n_q)
+{
+    return FamilyKey(k.elem, k.kind, k.prec, k.terms, k.mode, k.packed, n_q);
+}
+
+int tuning_lookup(const KernelKey &family, int n_q, fe_variant &out)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = table().find(family_of(family, n_q));
+    if (it == table().end())
+        return FE_ERR_INVALID_ARG;
+    out = it->second;
+    return FE_OK;
+}
+
+static int family_from_problem(const fe_problem *problem, fe_elem_type elem, int n_q, KernelKey &k)
+{
+    // Resolve the family by planning a zero-size launch with a dummy rule.
+    double xi[3 * FE_MAX_QP] = {0}, w[FE_MAX_QP] = {0};
+    if (n_q < 1 || n_q > FE_MAX_QP)
+        return fail(FE_ERR_UNSUPPORTED, "n_q %d out of range", n_q);
+    fe_quad_rule r{n_q, xi, w};
+    Plan pl;
+    const fe_variant base{256, 1, 2, 1, 0};
+    int st = plan(problem, elem, 0, nullptr, nullptr, 0, &r, nullptr, nullptr, 0, &base, pl);
+    if (st)
+        return st;
+    k = pl.key;
+    return FE_OK;
+}
+
+}  // namespace fe
+
+using namespace fe;
+
+extern "C" {
+
+int fe_tuning_get(const fe_problem *problem, fe_elem_type elem_type, int n_q, fe_variant *out)
+{
+    if (!out)
+        return fail(FE_ERR_INVALID_ARG, "out is NULL");
+    KernelKey k;
+    int st = family_from_problem(problem, elem_type, n_q, k);
+    if (st)
+        return st;
+    if (tuning_lookup(k, n_q, *out) != FE_OK)
+        return fail(FE_ERR_INVALID_ARG, "no tuning entry for this problem");
+    return FE_OK;
+}
+
+int fe_tuning_set(const fe_problem *problem, fe_elem_type elem_type, int n_q, const fe_variant *v)
+{
+    if (!v)
+        return fail(FE_ERR_INVALID_ARG, "variant is NULL");
+    KernelKey k;
+    int st = family_from_problem(problem, elem_type, n_q, k);
+    if (st)
+        return st;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    table()[family_of(k, n_q)] = *v;
+    return FE_OK;
+}
+
+int fe_tuning_clear(void)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    table().clear();
+    return FE_OK;
+}
+
+int fe_tuning_save(const char *path)
+{
+    if (!path)
+        return fail(FE_ERR_INVALID_ARG, "path is NULL");
+    FILE *f = std::fopen(path, "w");
+    if (!f)
+        return fail(FE_ERR_INVALID_ARG, "cannot open %s for writing", path);
+    std::fprintf(f, "# libfe tuning table v1: elem kind prec terms mode packed n_q | wg vec ref nt blocks\n");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto &kv : table()) {
+        const FamilyKey &k = kv.first;
+        const fe_variant &v = kv.second;
+        std::fprintf(f, "%d %d %d %d %d %d %d | %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k),
+                     std::get<2>(k), std::get<3>(k), std::get<4>(k), std::get<5>(k), std::get<6>(k),
+                     v.wg_size, v.elems_per_thread, v.ref_in_lds, v.nontemporal, v.blocks);
+    }
+    std::fclose(f);
+    return FE_OK;
+}
+
+int fe_tuning_load(const char *path)
+{
+    if (!path)
+        return fail(FE_ERR_INVALID_ARG, "path is NULL");
+    FILE *f = std::fopen(path, "r");
+    if (!f)
+        return fail(FE_ERR_INVALID_ARG, "cannot open %s", path);
+    char line[512];
+    int n = 0;
+    std::map<FamilyKey, fe_variant> loaded;
+    while (std::fgets(line, sizeof(line), f)) {
+        if (line[0] == '#' || line[0] == '\n')
+            continue;
+        int a[7];
+        fe_variant v{};
+        if (std::sscanf(line, "%d %d %d %d %d %d %d | %d %d %d %d %d", &a[0], &a[1], &a[2], &a[3],
+                        &a[4], &a[5], &a[6], &v.wg_size, &v.elems_per_thread, &v.ref_in_lds,
+                        &v.nontemporal, &v.blocks) != 12) {
+            std::fclose(f);
+            return fail(FE_ERR_INVALID_ARG, "malformed tuning line: %s", line);
+        }
+        loaded[FamilyKey(a[0], a[1], a[2], a[3], a[4], a[5], a[6])] = v;
+        ++n;
+    }
+    std::fclose(f);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto &kv : loaded)
+        table()[kv.first] = kv.second;
+    return FE_OK;
+}
+
+int fe_autotune(const fe_problem *problem, fe_elem_type elem_type, int64_t n_elem,
+                const double *coords, const void *coeffs, const fe_quad_rule *quad_rule,
+                void *out_K, void *out_F, int reps, fe_variant *best, double *best_ms,
+                hipStream_t stream)
+{
+    if (reps < 1)
+        reps = 1;
+    // Validate the call once with the default variant.
+    Plan base;
+    int st = plan(problem, elem_type, n_elem, coords, coeffs, n_elem, quad_rule, out_K, out_F,
+                  n_elem, nullptr, base);
+    if (st)
+        return st;
+    if (n_elem == 0)
+        return fail(FE_ERR_INVALID_ARG, "cannot tune on an empty batch");
+    // Candidate variants: every compiled (vec, nt, ref) of this family, times
+    // workgroup sizes and grid shapes.
+    std::set<std::tuple<int, int, int>> shapes;
+    for (int i = 0; i < kernel_count(); ++i) {
+        const KernelKey &k = kernel_at(i)->key;
+        if (k.elem == base.key.elem && k.kind == base.key.kind && k.prec == base.key.prec &&
+            k.terms == base.key.terms && k.mode == base.key.mode && k.packed == base.key.packed &&
+            (k.nq == quad_rule->n_q || k.nq == 0))
+            shapes.insert(std::make_tuple(k.vec, k.nt, k.ref));
+    }
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(FE_ERR_HIP, "hipEventCreate failed");
+    double best_t = 1e300;
+    fe_variant best_v{};
+    const int wgs[3] = {64, 128, 256};
+    const int grids[3] = {0, 2048, 8192};
+    for (const auto &sh : shapes) {
+        for (int wg : wgs) {
+            for (int gb : grids) {
+                fe_variant v{wg, std::get<0>(sh), std::get<2>(sh) == REF_LDS ? 1 : 2,
+                             std::get<1>(sh) ? 1 : 2, gb};
+                Plan pl;
+                if (plan(problem, elem_type, n_elem, coords, coeffs, n_elem, quad_rule, out_K,
+                         out_F, n_elem, &v, pl) != FE_OK)
+                    continue;
+                if (gb > 0 && (int64_t)gb >= (int64_t)pl.grid && gb != 0)
+                    continue;  // same as the one-group-per-thread grid
+                if (launch(pl, stream) != FE_OK)
+                    continue;
+                hipEventRecord(e0, stream);
+                for (int r = 0; r < reps; ++r)
+                    launch(pl, stream);
+                hipEventRecord(e1, stream);
+                if (hipEventSynchronize(e1) != hipSuccess) {
+                    hipEventDestroy(e0);
+                    hipEventDestroy(e1);
+                    return fail(FE_ERR_HIP, "synchronisation failed while tuning");
+                }
+                float ms = 0.f;
+                hipEventElapsedTime(&ms, e0, e1);
+                const double t = ms / reps;
+                if (t < best_t) {
+                    best_t = t;
+                    best_v = pl.variant;
+                }
+            }
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (best_t >= 1e300)
+        return fail(FE_ERR_UNSUPPORTED, "no variant could be launched");
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        table()[family_of(base.key, quad_rule->n_q)] = best_v;
+    }
+    if (best)
+        *best = best_v;
+    if (best_ms)
+        *best_ms = best_t;
+    return FE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,319 @@
+"""Thin Python binding of libfe.so (the C ABI declared in include/fe.h).
+
+Argument marshalling only: every step of the integration runs in the HIP
+kernels of libfe. Device memory and streams come from PyTorch (ROCm build):
+tensors are passed by ``data_ptr()`` and work is enqueued on
+``torch.cuda.current_stream()`` unless a stream is given. There is no CPU
+fallback: if libfe.so is missing or the device is not a GPU, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfe.so")
+
+TET4, PRISM6 = 0, 1
+SCALAR_CDR, ELASTICITY = 0, 1
+FP64, FP32_BULK = 0, 1
+COEF_UNIFORM, COEF_PER_ELEMENT, COEF_PER_QP = 0, 1, 2
+K_FULL, K_SYM_PACKED = 0, 1
+MAX_QP = 8
+
+ELEM = {"tet4": TET4, "prism6": PRISM6}
+KIND = {"scalar": SCALAR_CDR, "elasticity": ELASTICITY}
+MODE = {"uniform": COEF_UNIFORM, "element": COEF_PER_ELEMENT, "qp": COEF_PER_QP}
+KFMT = {"full": K_FULL, "packed": K_SYM_PACKED}
+PREC = {"fp64": FP64, "fp32": FP32_BULK}
+
+STATUS = {0: "FE_OK", 1: "FE_ERR_INVALID_ARG", 2: "FE_ERR_UNSUPPORTED", 3: "FE_ERR_NOT_SYMMETRIC",
+          4: "FE_ERR_HIP", 5: "FE_ERR_CAPACITY"}
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("coef_mode", ctypes.c_int32), ("coef_mask", ctypes.c_uint32),
+                ("k_format", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("uniform", ctypes.c_double * 20)]
+
+
+class QuadRule(ctypes.Structure):
+    _fields_ = [("n_q", ctypes.c_int32), ("xi", ctypes.POINTER(ctypes.c_double)),
+                ("w", ctypes.POINTER(ctypes.c_double))]
+
+
+class Variant(ctypes.Structure):
+    _fields_ = [("wg_size", ctypes.c_int32), ("elems_per_thread", ctypes.c_int32),
+                ("ref_in_lds", ctypes.c_int32), ("nontemporal", ctypes.c_int32),
+                ("blocks", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (self.wg_size, self.elems_per_thread, self.ref_in_lds, self.nontemporal, self.blocks)
+
+
+class FeError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libfe.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing; build it with "
+                               "`python -m paper_1504_01023_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, R, V = ctypes.POINTER(Problem), ctypes.POINTER(QuadRule), ctypes.POINTER(Variant)
+        vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+        L.fe_integrate.argtypes = [P, i32, i64, vp, vp, R, vp, vp, vp]
+        L.fe_integrate_ex.argtypes = [P, i32, i64, vp, vp, i64, R, vp, vp, i64, V, vp]
+        for f in ("fe_k_entries", "fe_f_entries"):
+            getattr(L, f).argtypes = [P, i32]
+            getattr(L, f).restype = i64
+        for f in ("fe_coeff_entries", "fe_bytes_per_element"):
+            getattr(L, f).argtypes = [P, i32, i32]
+            getattr(L, f).restype = i64
+        L.fe_k_index.argtypes = [P, i32, i32, i32]
+        L.fe_k_index.restype = i64
+        L.fe_quad_rule_builtin.argtypes = [i32, i32, R]
+        L.fe_status_string.argtypes = [i32]
+        L.fe_status_string.restype = ctypes.c_char_p
+        L.fe_last_error.restype = ctypes.c_char_p
+        L.fe_autotune.argtypes = [P, i32, i64, vp, vp, R, vp, vp, i32, V,
+                                  ctypes.POINTER(ctypes.c_double), vp]
+        L.fe_tuning_get.argtypes = [P, i32, i32, V]
+        L.fe_tuning_set.argtypes = [P, i32, i32, V]
+        L.fe_tuning_save.argtypes = [ctypes.c_char_p]
+        L.fe_tuning_load.argtypes = [ctypes.c_char_p]
+        L.fe_stream_copy.argtypes = [vp, vp, i64, vp]
+        _lib = L
+    return _lib
+
+
+def _check(status: int) -> None:
+    if status != 0:
+        raise FeError(status, lib().fe_last_error().decode())
+
+
+# ------------------------------------------------------------------ descriptors
+def problem(kind="scalar", precision="fp64", coef_mode="uniform", mask=0, uniform=None,
+            k_format="full") -> Problem:
+    p = Problem()
+    p.kind = KIND.get(kind, kind)
+    p.precision = PREC.get(precision, precision)
+    p.coef_mode = MODE.get(coef_mode, coef_mode)
+    p.coef_mask = int(mask)
+    p.k_format = KFMT.get(k_format, k_format)
+    p.reserved = 0
+    if uniform is not None:
+        u = np.asarray(uniform, dtype=np.float64).ravel()
+        for i, x in enumerate(u[:20]):
+            p.uniform[i] = float(x)
+    return p
+
+
+def problem_for(wl, precision="fp64") -> Problem:
+    """Descriptor for a generated workload (paper_1504_01023_amd.inputs)."""
+    return problem(wl.kind, precision, wl.coef_mode, wl.mask, wl.uniform, wl.k_format)
+
+
+class Rule:
+    """A quadrature rule held in host memory for the duration of the calls."""
+
+    def __init__(self, xi, w):
+        self.xi = np.ascontiguousarray(np.asarray(xi, dtype=np.float64).reshape(-1, 3))
+        self.w = np.ascontiguousarray(np.asarray(w, dtype=np.float64).reshape(-1))
+        self.c = QuadRule(len(self.w), self.xi.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                          self.w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+
+    @property
+    def n_q(self) -> int:
+        return len(self.w)
+
+
+def builtin_rule(elem, n_q: int) -> Rule:
+    r = QuadRule()
+    _check(lib().fe_quad_rule_builtin(ELEM.get(elem, elem), n_q, ctypes.byref(r)))
+    xi = np.ctypeslib.as_array(r.xi, shape=(n_q * 3,)).copy()
+    w = np.ctypeslib.as_array(r.w, shape=(n_q,)).copy()
+    return Rule(xi, w)
+
+
+def k_entries(p: Problem, elem) -> int:
+    return int(lib().fe_k_entries(ctypes.byref(p), ELEM.get(elem, elem)))
+
+
+def f_entries(p: Problem, elem) -> int:
+    return int(lib().fe_f_entries(ctypes.byref(p), ELEM.get(elem, elem)))
+
+
+def coeff_entries(p: Problem, elem, n_q: int) -> int:
+    return int(lib().fe_coeff_entries(ctypes.byref(p), ELEM.get(elem, elem), n_q))
+
+
+def bytes_per_element(p: Problem, elem, n_q: int) -> int:
+    return int(lib().fe_bytes_per_element(ctypes.byref(p), ELEM.get(elem, elem), n_q))
+
+
+def k_index(p: Problem, elem, row: int, col: int) -> int:
+    return int(lib().fe_k_index(ctypes.byref(p), ELEM.get(elem, elem), row, col))
+
+
+def variant(wg_size=0, elems_per_thread=0, ref_in_lds=0, nontemporal=0, blocks=0) -> Variant:
+    return Variant(wg_size, elems_per_thread, ref_in_lds, nontemporal, blocks)
+
+
+# ------------------------------------------------------------------- execution
+def _dtype(p: Problem):
+    import torch
+    return torch.float64 if p.precision == FP64 else torch.float32
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check_tensor(t, name, dtype, rows, ld):
+    if t is None:
+        return
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous() or t.dim() != 2 or t.shape[1] != ld or t.shape[0] < rows:
+        raise ValueError(f"{name} must be a contiguous ({rows}, {ld}) tensor, got "
+                         f"{tuple(t.shape)}")
+
+
+def integrate(p: Problem, elem, coords, coeffs, rule: Rule, out_K=None, out_F=None,
+              n_elem: int | None = None, variant: Variant | None = None, stream=None):
+    """Enqueue the integration of n_elem elements (default: all columns of
+    coords) and return (out_K, out_F) device tensors of shape
+    (k_entries, ld_out) and (f_entries, ld_out)."""
+    import torch
+    e = ELEM.get(elem, elem)
+    ld_in = coords.shape[1]
+    n = ld_in if n_elem is None else int(n_elem)
+    dt = _dtype(p)
+    nk, nf = k_entries(p, e), f_entries(p, e)
+    if out_K is None:
+        out_K = torch.empty((nk, n), dtype=dt, device=coords.device)
+    if out_F is None:
+        out_F = torch.empty((nf, out_K.shape[1]), dtype=dt, device=coords.device)
+    ld_out = out_K.shape[1]
+    _check_tensor(coords, "coords", torch.float64, 3 * (4 if e == TET4 else 6), ld_in)
+    nc = coeff_entries(p, e, rule.n_q)
+    if nc > 0:
+        if coeffs is None:
+            raise ValueError("this problem reads coefficients from memory; coeffs is None")
+        _check_tensor(coeffs, "coeffs", dt, nc, ld_in)
+    _check_tensor(out_K, "out_K", dt, nk, ld_out)
+    _check_tensor(out_F, "out_F", dt, nf, ld_out)
+    cptr = ctypes.c_void_p(coeffs.data_ptr()) if (coeffs is not None and nc > 0) else None
+    vptr = ctypes.byref(variant) if variant is not None else None
+    _check(lib().fe_integrate_ex(ctypes.byref(p), e, n, ctypes.c_void_p(coords.data_ptr()), cptr,
+                                 ld_in, ctypes.byref(rule.c), ctypes.c_void_p(out_K.data_ptr()),
+                                 ctypes.c_void_p(out_F.data_ptr()), ld_out, vptr,
+                                 _stream_handle(stream)))
+    return out_K, out_F
+
+
+def autotune(p: Problem, elem, coords, coeffs, rule: Rule, out_K, out_F, reps: int = 5,
+             stream=None):
+    """Exhaustive search over the compiled variants (synchronises the stream).
+    Returns (variant tuple, mean ms)."""
+    e = ELEM.get(elem, elem)
+    best = Variant()
+    ms = ctypes.c_double(0.0)
+    cptr = ctypes.c_void_p(coeffs.data_ptr()) if coeffs is not None else None
+    _check(lib().fe_autotune(ctypes.byref(p), e, coords.shape[1], ctypes.c_void_p(coords.data_ptr()),
+                             cptr, ctypes.byref(rule.c), ctypes.c_void_p(out_K.data_ptr()),
+                             ctypes.c_void_p(out_F.data_ptr()), reps, ctypes.byref(best),
+                             ctypes.byref(ms), _stream_handle(stream)))
+    return best.as_tuple(), ms.value
+
+
+def tuning_get(p: Problem, elem, n_q: int):
+    v = Variant()
+    st = lib().fe_tuning_get(ctypes.byref(p), ELEM.get(elem, elem), n_q, ctypes.byref(v))
+    return v.as_tuple() if st == 0 else None
+
+
+def tuning_set(p: Problem, elem, n_q: int, v: Variant) -> None:
+    _check(lib().fe_tuning_set(ctypes.byref(p), ELEM.get(elem, elem), n_q, ctypes.byref(v)))
+
+
+def tuning_save(path: str) -> None:
+    _check(lib().fe_tuning_save(path.encode()))
+
+
+def tuning_load(path: str) -> None:
+    _check(lib().fe_tuning_load(path.encode()))
+
+
+def tuning_clear() -> None:
+    lib().fe_tuning_clear()
+
+
+def stream_copy(dst, src, stream=None) -> None:
+    """Plain streaming copy of src into dst (same byte size, multiple of 16)."""
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nb:
+        raise ValueError("dst and src sizes differ")
+    _check(lib().fe_stream_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()),
+                                nb, _stream_handle(stream)))
+
+
+@dataclass
+class DeviceWorkload:
+    """A generated workload resident in device memory."""
+    wl: object
+    precision: str
+    problem: Problem
+    rule: Rule
+    coords: object
+    coeffs: object
+
+    @property
+    def n_elem(self) -> int:
+        return self.wl.n_elem
+
+
+def to_device(wl, precision="fp64", device="cuda", rule: Rule | None = None) -> DeviceWorkload:
+    """Upload a generated workload (coordinates FP64; coefficients in the
+    precision of the tier)."""
+    import torch
+    p = problem_for(wl, precision)
+    r = rule if rule is not None else builtin_rule(wl.elem, wl.n_q)
+    coords = torch.from_numpy(wl.mesh.coords).to(device)
+    coeffs = None
+    if wl.coeffs is not None and wl.coef_mode != "uniform":
+        dt = torch.float64 if precision == "fp64" else torch.float32
+        coeffs = torch.from_numpy(np.ascontiguousarray(wl.coeffs)).to(device=device, dtype=dt)
+    return DeviceWorkload(wl, precision, p, r, coords, coeffs)
+
+
+def unpack_full(K: np.ndarray, N: int, packed: bool) -> np.ndarray:
+    """(k_entries, n) SoA output -> (n, N, N) full matrices (host arrays)."""
+    n = K.shape[1]
+    out = np.empty((n, N, N), dtype=K.dtype)
+    if not packed:
+        return np.ascontiguousarray(K[: N * N].T.reshape(n, N, N))
+    k = 0
+    for r in range(N):
+        for s in range(r, N):
+            out[:, r, s] = K[k]
+            out[:, s, r] = K[k]
+            k += 1
+    return out

@@ -1,0 +1,95 @@
+"""Helpers for the GPU-vs-oracle parity tests: run a generated workload
+through the C ABI and through the oracle, and compare per element."""
+from __future__ import annotations
+
+import functools
+import os
+
+import numpy as np
+
+import oracle
+from paper_1504_01023_amd import fe, inputs
+
+# Relative Frobenius error bounds per element: FP64 path against the FP64
+# oracle, and the FP32 bulk tier against the FP64 oracle run on the FP32
+# coefficients promoted exactly (so only the arithmetic differs).
+TOL = {"fp64": 1e-12, "fp32": 2e-5}
+ORACLE_THREADS = max(1, min(16, os.cpu_count() or 1))
+
+
+def n_dof(wl) -> int:
+    return oracle.n_dof(wl.elem, wl.kind)
+
+
+def oracle_coeffs(wl, precision):
+    if wl.coeffs is None:
+        return None
+    if precision == "fp32":
+        return wl.coeffs.astype(np.float32).astype(np.float64)
+    return wl.coeffs
+
+
+def oracle_run(wl, precision="fp64", elements=None, rule=None):
+    coords, coeffs = wl.mesh.coords, oracle_coeffs(wl, precision)
+    if elements is not None:
+        coords = np.ascontiguousarray(coords[:, elements])
+        coeffs = None if coeffs is None else np.ascontiguousarray(coeffs[:, elements])
+    r = rule if rule is not None else oracle.quad_rule(wl.elem, wl.n_q)
+    return oracle.integrate(wl.elem, wl.kind, coords, r, wl.coef_mode, wl.mask, wl.uniform,
+                            coeffs, ORACLE_THREADS)
+
+
+def gpu_raw(wl, precision="fp64", variant=None, rule=None, device="cuda"):
+    import torch
+    dw = fe.to_device(wl, precision, device=device, rule=rule)
+    K, F = fe.integrate(dw.problem, wl.elem, dw.coords, dw.coeffs, dw.rule, variant=variant)
+    torch.cuda.synchronize()
+    return K.cpu().numpy(), F.cpu().numpy()
+
+
+def to_full(Kraw, Fraw, wl):
+    N = n_dof(wl)
+    K = fe.unpack_full(Kraw.astype(np.float64), N, wl.k_format == "packed")
+    return K, np.ascontiguousarray(Fraw.astype(np.float64).T)
+
+
+def rel_errors(Kg, Fg, Ko, Fo):
+    """Per-element relative Frobenius errors of K and F (an all-zero
+    reference F is compared in absolute terms against the scale of K)."""
+    dk = np.sqrt(((Kg - Ko) ** 2).sum(axis=(1, 2)))
+    nk = np.sqrt((Ko ** 2).sum(axis=(1, 2)))
+    df = np.sqrt(((Fg - Fo) ** 2).sum(axis=1))
+    nf = np.sqrt((Fo ** 2).sum(axis=1))
+    ek = dk / np.where(nk > 0, nk, 1.0)
+    ef = df / np.where(nf > 0, nf, np.where(nk > 0, nk, 1.0))
+    return ek, ef
+
+
+def assert_parity(wl, precision, Kraw, Fraw, elements=None, tol=None):
+    tol = TOL[precision] if tol is None else tol
+    Kg, Fg = to_full(Kraw, Fraw, wl)
+    if elements is not None:
+        Kg, Fg = Kg[elements], Fg[elements]
+    Ko, Fo = oracle_run(wl, precision, elements)
+    assert np.all(np.isfinite(Kg)) and np.all(np.isfinite(Fg))
+    ek, ef = rel_errors(Kg, Fg, Ko, Fo)
+    assert ek.max() <= tol, f"K rel err {ek.max():.3e} at element {int(ek.argmax())}"
+    assert ef.max() <= tol, f"F rel err {ef.max():.3e} at element {int(ef.argmax())}"
+    return float(ek.max()), float(ef.max())
+
+
+# Small workloads spanning several workgroups and a ragged tail.
+SMALL = {
+    "tet_poisson": lambda: inputs.tet_poisson(8, seed=1),
+    "tet_poisson_qp": lambda: inputs.tet_poisson_qp_rhs(7, seed=11),
+    "tet_cdr": lambda: inputs.tet_cdr(7, seed=2),
+    "prism_cdr_qp": lambda: inputs.prism_cdr_qp(9, 8, seed=3),
+    "prism_cdr": lambda: inputs.prism_cdr_element(9, 7, seed=13),
+    "tet_elasticity": lambda: inputs.tet_elasticity(7, seed=4),
+    "prism_elasticity": lambda: inputs.prism_elasticity(6, 6, seed=14),
+}
+
+
+@functools.lru_cache(maxsize=None)
+def small(name):
+    return SMALL[name]()

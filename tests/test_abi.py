@@ -1,0 +1,200 @@
+"""CPU-only checks of the C ABI: the library loads and exports every symbol
+include/fe.h declares, argument validation returns the documented status
+codes before anything is enqueued, and the host-side helpers (sizes,
+accounting, packed index map, built-in rules) are right. No GPU compute."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1504_01023_amd import fe
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "fe.h")).read()
+    return sorted(set(re.findall(r"FE_API\s+[\w\s\*]+?\b(fe_\w+)\s*\(", src)))
+
+
+def test_header_declares_entry_points():
+    syms = declared_symbols()
+    for must in ("fe_integrate", "fe_integrate_ex", "fe_k_entries", "fe_f_entries",
+                 "fe_coeff_entries", "fe_quad_rule_builtin", "fe_status_string", "fe_last_error",
+                 "fe_autotune", "fe_tuning_save", "fe_tuning_load", "fe_stream_copy"):
+        assert must in syms
+
+
+def test_library_exports_every_declared_symbol():
+    L = fe.lib()
+    missing = [s for s in declared_symbols() if not hasattr(L, s)]
+    assert not missing, missing
+
+
+def test_library_exports_nothing_undeclared():
+    # only the documented C ABI is visible (everything else is hidden)
+    out = os.popen(f"nm -D --defined-only {fe.LIB_PATH}").read()
+    exported = {ln.split()[-1] for ln in out.splitlines() if " T " in ln}
+    fe_syms = {s for s in exported if s.startswith("fe_")}
+    assert fe_syms == set(declared_symbols())
+
+
+def test_status_strings():
+    L = fe.lib()
+    for st in range(6):
+        assert L.fe_status_string(st)
+    assert L.fe_status_string(99) == b"unknown status"
+
+
+@pytest.mark.parametrize("elem,n_q", [("tet4", 1), ("tet4", 4), ("prism6", 6)])
+def test_builtin_rules_match_oracle_rules(elem, n_q):
+    r = fe.builtin_rule(elem, n_q)
+    xi, w = oracle.quad_rule(elem, n_q)
+    np.testing.assert_allclose(r.xi, xi, rtol=0, atol=1e-16)
+    np.testing.assert_allclose(r.w, w, rtol=0, atol=1e-17)
+
+
+def test_builtin_rule_unknown():
+    with pytest.raises(fe.FeError) as ei:
+        fe.builtin_rule("tet4", 5)
+    assert ei.value.status == 2
+
+
+def test_accounting_matches_paper_word_counts():
+    # Sec. 4.4, table "accesses_and_operations": global accesses per element
+    # 36 / 66 / 52 / 80 double words for tet Poisson, prism Poisson, tet
+    # conv-diff, prism conv-diff (4 / 6 Gauss points, full K, Poisson with one
+    # right-hand-side value per point, conv-diff with 20 element constants).
+    poisson = fe.problem("scalar", "fp64", "qp", 1 << 16, np.r_[np.zeros(5), 1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, np.zeros(4)], "full")
+    cdr = fe.problem("scalar", "fp64", "element", (1 << 20) - 1, None, "full")
+    assert fe.bytes_per_element(poisson, "tet4", 4) == 8 * 36
+    assert fe.bytes_per_element(poisson, "prism6", 6) == 8 * 66
+    assert fe.bytes_per_element(cdr, "tet4", 4) == 8 * 52
+    assert fe.bytes_per_element(cdr, "prism6", 6) == 8 * 80
+    # the headline workload: uniform Poisson, packed K: 96 + 80 + 32 bytes
+    p1 = fe.problem("scalar", "fp64", "uniform", 0, None, "packed")
+    assert fe.bytes_per_element(p1, "tet4", 1) == 208
+    # FP32 tier: coordinates stay FP64
+    c32 = fe.problem("scalar", "fp32", "element", (1 << 20) - 1, None, "full")
+    assert fe.bytes_per_element(c32, "tet4", 4) == 96 + 4 * (20 + 16 + 4)
+    el = fe.problem("elasticity", "fp64", "element", 31, None, "packed")
+    assert fe.bytes_per_element(el, "tet4", 1) == 96 + 8 * (5 + 78 + 12)
+    assert fe.bytes_per_element(el, "prism6", 6) == 144 + 8 * (5 + 171 + 18)
+
+
+def test_entry_counts_and_packed_index():
+    for kind, nc in (("scalar", 1), ("elasticity", 3)):
+        for elem, ns in (("tet4", 4), ("prism6", 6)):
+            N = ns * nc
+            pf = fe.problem(kind, "fp64", "uniform", 0, None, "full")
+            pp = fe.problem(kind, "fp64", "uniform", 0, None, "packed")
+            assert fe.k_entries(pf, elem) == N * N
+            assert fe.k_entries(pp, elem) == N * (N + 1) // 2
+            assert fe.f_entries(pf, elem) == N
+            seen = []
+            for r in range(N):
+                for s in range(N):
+                    assert fe.k_index(pf, elem, r, s) == r * N + s
+                    k = fe.k_index(pp, elem, r, s)
+                    if s < r:
+                        assert k == -1
+                    else:
+                        seen.append(k)
+            assert seen == list(range(N * (N + 1) // 2))
+            assert fe.k_index(pf, elem, N, 0) == -1
+
+
+def test_coeff_entries():
+    p = fe.problem("scalar", "fp64", "qp", (1 << 20) - 1, None, "full")
+    assert fe.coeff_entries(p, "prism6", 6) == 120
+    p = fe.problem("scalar", "fp64", "element", 0b101, None, "full")
+    assert fe.coeff_entries(p, "tet4", 4) == 2
+    p = fe.problem("scalar", "fp64", "uniform", 0b101, None, "full")
+    assert fe.coeff_entries(p, "tet4", 4) == 0
+
+
+def _call(p, elem=0, n=10, coords=0x1000, coeffs=None, ld_in=None, rule=None, K=0x2000, F=0x3000,
+          ld_out=None, variant=None):
+    L = fe.lib()
+    rule = rule if rule is not None else fe.builtin_rule("tet4", 1)
+    ld_in = n if ld_in is None else ld_in
+    ld_out = n if ld_out is None else ld_out
+    v = ctypes.byref(variant) if variant is not None else None
+    return L.fe_integrate_ex(ctypes.byref(p) if p is not None else None, elem, n, coords, coeffs,
+                             ld_in, ctypes.byref(rule.c), K, F, ld_out, v, None)
+
+
+# Every case below fails validation, so nothing is launched and the fake
+# addresses are never dereferenced.
+def test_validation_status_codes():
+    ok = fe.problem("scalar", "fp64", "uniform", 0, np.r_[np.zeros(5), 1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 1, 0, 0, 0], "packed")
+    assert _call(None) == 1
+    assert _call(ok, elem=7) == 1
+    assert _call(ok, n=-1) == 1
+    assert _call(ok, coords=None) == 1
+    assert _call(ok, K=None) == 1
+    assert _call(ok, ld_in=5) == 1
+    assert _call(ok, ld_out=9) == 1
+    bad = fe.problem("scalar", "fp64", "uniform", 0, None, "packed")
+    bad.kind = 5
+    assert _call(bad) == 1
+    bad = fe.problem("scalar", "fp64", "uniform", 0, None, "packed")
+    bad.precision = 9
+    assert _call(bad) == 1
+    bad = fe.problem("scalar", "fp64", "uniform", 0, None, "packed")
+    bad.reserved = 1
+    assert _call(bad) == 1
+    # per-element data without a coefficient pointer
+    pe = fe.problem("scalar", "fp64", "element", 1 << 16, None, "full")
+    assert _call(pe, coeffs=None) == 1
+    # mask bits beyond the elasticity slots
+    el = fe.problem("elasticity", "fp64", "element", 1 << 7, None, "packed")
+    assert _call(el, coeffs=0x4000) == 1
+    # unsupported point counts
+    assert _call(ok, rule=fe.Rule(np.zeros((9, 3)), np.ones(9))) == 2
+    # weights must be finite
+    assert _call(ok, rule=fe.Rule(np.zeros((1, 3)), [np.nan])) == 1
+    # misaligned pointer
+    assert _call(ok, coords=0x1004) == 2
+    # packed K with convection read from memory, or non-symmetric uniform data
+    conv = fe.problem("scalar", "fp64", "element", 1 << 4, None, "packed")
+    assert _call(conv, coeffs=0x4000) == 3
+    u = np.zeros(20)
+    u[4] = 1.0
+    assert _call(fe.problem("scalar", "fp64", "uniform", 0, u, "packed")) == 3
+    u = np.zeros(20)
+    u[6] = 1.0
+    assert _call(fe.problem("scalar", "fp64", "uniform", 0, u, "packed")) == 3
+    # symmetric convection pair is fine for packed: validation passes (n = 0)
+    u = np.zeros(20)
+    u[4] = u[1] = 0.5
+    assert _call(fe.problem("scalar", "fp64", "uniform", 0, u, "packed"), n=0) == 0
+    # forced variants that do not exist
+    assert _call(ok, variant=fe.variant(wg_size=96)) == 2
+    # two elements per lane need even leading dimensions
+    assert _call(ok, n=9, variant=fe.variant(elems_per_thread=2)) == 2
+    assert fe.lib().fe_last_error()
+
+
+def test_empty_batch_enqueues_nothing():
+    # n_elem == 0 is FE_OK without any pointer or device
+    p = fe.problem("scalar", "fp64", "uniform", 0, None, "full")
+    assert _call(p, n=0, coords=None, K=None, F=None) == 0
+
+
+def test_tuning_table_roundtrip(tmp_path):
+    fe.tuning_clear()
+    p = fe.problem("scalar", "fp64", "uniform", 0, None, "packed")
+    assert fe.tuning_get(p, "tet4", 1) is None
+    fe.tuning_set(p, "tet4", 1, fe.variant(128, 2, 2, 1, 0))
+    assert fe.tuning_get(p, "tet4", 1) == (128, 2, 2, 1, 0)
+    path = str(tmp_path / "tune.txt")
+    fe.tuning_save(path)
+    fe.tuning_clear()
+    assert fe.tuning_get(p, "tet4", 1) is None
+    fe.tuning_load(path)
+    assert fe.tuning_get(p, "tet4", 1) == (128, 2, 2, 1, 0)
+    fe.tuning_clear()

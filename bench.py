@@ -7,10 +7,12 @@ d^0 = 1) on the jittered unit cube with N = 119 cells per side split into
 and 4-vector F, FP64. One "step" is one fe_integrate call over the whole
 mesh with inputs already resident in HBM.
 
-Prints one JSON line (rank 0). Timing: W untimed warm-up steps (the first
-runs the exhaustive variant search of fe_autotune unless --no-tune), then K
+Prints one JSON line (rank 0). Timing: W untimed warm-up steps, then K
 timed steps between device synchronisations; the kernel's own duration is
 taken with HIP events recorded on the launch stream around every step.
+The launch variant comes from the committed MI355X tuning table
+(paper_1504_01023_amd/tuning_mi355x.txt); --tune re-runs the exhaustive
+search of fe_autotune during warm-up instead.
 
 Extra workloads (--workload): tet_cdr (N=119, 4-point rule, per-element
 coefficients, full K), prism_cdr_qp (141x141x100 prisms with per-point
@@ -20,6 +22,7 @@ coefficients), tet_elasticity (N=94, packed 12x12), prism_elasticity;
 from __future__ import annotations
 
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -107,16 +110,266 @@ def cpu_baseline(wl, min_s: float = 10.0, max_s: float = 30.0):
                       f"chunks of {chunk}), {el:.1f} s wall"}
 
 
+# ---------------------------------------------------------------- serving
+SERVED_KINDS = [("tet4", "scalar"), ("tet4", "elasticity"), ("prism6", "scalar"),
+                ("prism6", "elasticity")]
+
+
+def served_requests(n_req, seed=5):
+    """The mixed request stream: per request, in this order from one seeded
+    stream: unit-rate exponential inter-arrival gap (scaled by 1/lambda
+    later), n = exp(U[ln 1e3, ln 2e6]), element type 50/50, problem 70/30
+    scalar CDR / elasticity, tier 50/50, mesh seed."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_req):
+        gap = rng.exponential(1.0)
+        n = int(round(np.exp(rng.uniform(np.log(1e3), np.log(2e6)))))
+        elem = "tet4" if rng.random() < 0.5 else "prism6"
+        prob = "scalar" if rng.random() < 0.7 else "elasticity"
+        tier = "fp64" if rng.random() < 0.5 else "fp32"
+        mseed = int(rng.integers(0, 2 ** 31))
+        kind = SERVED_KINDS.index((elem, prob)) + (0 if tier == "fp64" else 4)
+        out.append({"gap": gap, "n": n, "kind": kind, "elem": elem, "prob": prob, "tier": tier,
+                    "seed": mseed})
+    return out
+
+
+def served_pools(torch):
+    """One 2.06M-element pinned host mesh (+ coefficients in both tiers) per
+    element type and problem; a request integrates the first n elements of
+    its pool, which stands in for a mesh of n elements."""
+    from paper_1504_01023_amd import inputs
+    pools = {}
+    for elem, prob in SERVED_KINDS:
+        if elem == "tet4":
+            wl = inputs.tet_cdr(70, seed=51) if prob == "scalar" else inputs.tet_elasticity(70, seed=52)
+        else:
+            wl = (inputs.prism_cdr_element(101, 101, seed=53) if prob == "scalar"
+                  else inputs.prism_elasticity(101, 101, seed=54))
+        hc = torch.from_numpy(wl.mesh.coords).pin_memory()
+        h64 = torch.from_numpy(wl.coeffs).pin_memory()
+        h32 = torch.from_numpy(wl.coeffs.astype(np.float32)).pin_memory()
+        pools[(elem, prob)] = {"wl": wl, "coords": hc, "fp64": h64, "fp32": h32}
+    return pools
+
+
+def run_served(a, torch, fe, serve) -> dict:
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    pools = served_pools(torch)
+    log(f"[served] pools generated in {time.time() - t0:.1f}s")
+    kinds = []
+    for tier in ("fp64", "fp32"):
+        for elem, prob in SERVED_KINDS:
+            wl = pools[(elem, prob)]["wl"]
+            kinds.append((fe.problem_for(wl, tier), elem, fe.builtin_rule(elem, wl.n_q)))
+    n_warm, n_meas = a.served_warmup, a.served_requests
+    reqs = served_requests(n_warm + n_meas)
+    meas = reqs[n_warm:]
+    tot_elems = sum(r["n"] for r in meas)
+
+    def host_ptrs(r):
+        pool = pools[(r["elem"], r["prob"])]
+        return pool["coords"].data_ptr(), pool[r["tier"]].data_ptr(), pool["wl"].n_elem
+
+    # --- sequential plain service (capacity): H2D of the request's inputs,
+    # then fe_integrate, one request at a time
+    stream = torch.cuda.current_stream()
+    dev_pool = {}
+    for key, pool in pools.items():
+        dev_pool[key] = {"coords": pool["coords"].to(dev), "fp64": pool["fp64"].to(dev),
+                         "fp32": pool["fp32"].to(dev)}
+    torch.cuda.synchronize()
+
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipMemcpy2DAsync.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                     ctypes.c_size_t, ctypes.c_size_t, ctypes.c_size_t,
+                                     ctypes.c_int, ctypes.c_void_p]
+
+    def h2d_rows(dst, src, n):
+        """Copy the first n columns of a pinned (rows, ld) host array into a
+        device (rows, ld') array, as the server does (one pitched copy)."""
+        es = src.element_size()
+        st = hip.hipMemcpy2DAsync(ctypes.c_void_p(dst.data_ptr()), dst.shape[1] * es,
+                                  ctypes.c_void_p(src.data_ptr()), src.shape[1] * es, n * es,
+                                  src.shape[0], 1, ctypes.c_void_p(stream.cuda_stream))
+        if st != 0:
+            raise RuntimeError(f"hipMemcpy2DAsync failed: {st}")
+
+    def plain_one(r, resident):
+        pool = pools[(r["elem"], r["prob"])]
+        k = kinds[r["kind"]]
+        n = r["n"]
+        if resident:
+            dp = dev_pool[(r["elem"], r["prob"])]
+            c, cf = dp["coords"], dp[r["tier"]]
+            Kt, Ft = fe.integrate(k[0], k[1], c, cf, k[2], n_elem=n)
+        else:
+            ld = (n + 3) // 4 * 4
+            src_c, src_k = pool["coords"], pool[r["tier"]]
+            c = torch.empty((src_c.shape[0], ld), dtype=src_c.dtype, device=dev)
+            cf = torch.empty((src_k.shape[0], ld), dtype=src_k.dtype, device=dev)
+            h2d_rows(c, src_c, n)
+            h2d_rows(cf, src_k, n)
+            Kt, Ft = fe.integrate(k[0], k[1], c, cf, k[2], n_elem=n)
+        return Kt, Ft
+
+    for r in reqs[:n_warm]:
+        plain_one(r, False)
+    torch.cuda.synchronize()
+    seq = {}
+    for resident in (False, True):
+        ts = []
+        for r in meas:
+            w0 = time.perf_counter()
+            plain_one(r, resident)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - w0)
+        seq["resident" if resident else "h2d"] = {
+            "mean_service_s": float(np.mean(ts)), "elements_per_s": tot_elems / float(np.sum(ts)),
+            "p50_s": float(np.percentile(ts, 50)), "p99_s": float(np.percentile(ts, 99))}
+    log(f"[served] sequential plain: {seq}")
+
+    def serve_run(srv, rate, resident, sample_ids=()):
+        """Submit the measured requests with the given arrival rate (None =
+        all at once), consume completions, return latencies and outputs'
+        checksums for sample_ids."""
+        import threading
+        srv.reset_stats()
+        gaps = [r["gap"] for r in meas]
+        arrivals = np.cumsum(gaps) / rate if rate else np.zeros(len(meas))
+        ids = {}
+        sums = {}
+        t_start = serve.now()
+        done = []
+
+        def submitter():
+            for i, r in enumerate(meas):
+                target = t_start + arrivals[i]
+                while True:
+                    dt = target - serve.now()
+                    if dt <= 0:
+                        break
+                    time.sleep(min(dt, 0.002))
+                if resident:
+                    dp = dev_pool[(r["elem"], r["prob"])]
+                    rid = srv.submit(r["kind"], r["n"], dp["coords"].data_ptr(),
+                                     dp[r["tier"]].data_ptr(), on_device=True,
+                                     ld_in=dp["coords"].shape[1], tag=i)
+                else:
+                    cp, kp, ld = host_ptrs(r)
+                    rid = srv.submit(r["kind"], r["n"], cp, kp, ld_in=ld, tag=i)
+                ids[rid] = i
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        while len(done) < len(meas):
+            for c in srv.poll(256, 0.01):
+                if c.status != 0:
+                    raise RuntimeError(f"served request failed with status {c.status}")
+                i = c.tag
+                if i in sample_ids:
+                    r = meas[i]
+                    k = kinds[r["kind"]]
+                    dt_ = torch.float64 if r["tier"] == "fp64" else torch.float32
+                    for name, ptr, rows in (("K", c.out_K, fe.k_entries(k[0], k[1])),
+                                            ("F", c.out_F, fe.f_entries(k[0], k[1]))):
+                        buf = torch.empty((rows, c.ld_out), dtype=dt_, device=dev)
+                        fe.lib().fe_stream_copy(ctypes.c_void_p(buf.data_ptr()), ctypes.c_void_p(ptr),
+                                                buf.numel() * buf.element_size(),
+                                                ctypes.c_void_p(stream.cuda_stream))
+                        sums[(i, name)] = buf[:, :r["n"]].contiguous().cpu().numpy().tobytes()
+                srv.release(c.id)
+                done.append(c)
+        th.join()
+        t_end = max(c.t_done for c in done)
+        lat = np.array([c.t_done - c.t_submit for c in done])
+        st = srv.stats()
+        return {"requests": len(done), "elements": tot_elems,
+                "elements_per_s": tot_elems / (t_end - t_start),
+                "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+                "mean_s": float(lat.mean()),
+                "mean_queue_s": st["mean_queue_s"], "mean_h2d_s": st["mean_h2d_s"],
+                "mean_device_s": st["mean_device_s"], "ticks": st["ticks"],
+                "peak_bytes": st["bytes_peak"]}, sums
+
+    budget = 64 << 30
+    out = {"n_requests": n_meas, "warmup_requests": n_warm, "total_elements": tot_elems,
+           "hbm_budget_bytes": budget, "max_slots": a.served_slots, "sequential_plain": seq}
+    rng = np.random.default_rng(55)
+    sample_ids = set(int(x) for x in rng.choice(n_meas, size=min(20, n_meas), replace=False))
+    with serve.Server(kinds, max_slots=a.served_slots, hbm_budget_bytes=budget, max_chunks=512,
+                      chunk_elems=16384, blocks_per_kind=0) as srv:
+        # warm-up
+        for r in reqs[:n_warm]:
+            cp, kp, ld = host_ptrs(r)
+            srv.submit(r["kind"], r["n"], cp, kp, ld_in=ld)
+        got = 0
+        while got < n_warm:
+            for c in srv.poll(64, 0.05):
+                srv.release(c.id)
+                got += 1
+        sat, sums_mix = serve_run(srv, None, False, sample_ids)
+        out["saturation"] = sat
+        out["served_speedup"] = sat["elements_per_s"] / seq["h2d"]["elements_per_s"]
+        log(f"[served] saturation: {sat}")
+        sat_r, _ = serve_run(srv, None, True)
+        out["saturation_resident"] = sat_r
+        out["served_speedup_resident"] = sat_r["elements_per_s"] / seq["resident"]["elements_per_s"]
+        cap = 1.0 / seq["h2d"]["mean_service_s"]
+        cap_r = 1.0 / seq["resident"]["mean_service_s"]
+        out["load"] = {}
+        for rho in a.served_rho:
+            res, _ = serve_run(srv, rho * cap, False)
+            res_r, _ = serve_run(srv, rho * cap_r, True)
+            out["load"][f"rho_{rho}"] = {"rate_per_s": rho * cap, "h2d": res,
+                                         "rate_resident_per_s": rho * cap_r, "resident": res_r}
+            log(f"[served] rho {rho}: p50 {res['p50_s']*1e3:.2f} ms p99 {res['p99_s']*1e3:.2f} ms; "
+                f"resident p50 {res_r['p50_s']*1e3:.2f} ms p99 {res_r['p99_s']*1e3:.2f} ms")
+        # the sampled requests again, one at a time through the server
+        same = 0
+        for i in sorted(sample_ids):
+            r = meas[i]
+            cp, kp, ld = host_ptrs(r)
+            rid = srv.submit(r["kind"], r["n"], cp, kp, ld_in=ld, tag=i)
+            c = []
+            while not c:
+                c = srv.poll(4, 0.05)
+            c = c[0]
+            k = kinds[r["kind"]]
+            dt_ = torch.float64 if r["tier"] == "fp64" else torch.float32
+            ok = True
+            for name, ptr, rows in (("K", c.out_K, fe.k_entries(k[0], k[1])),
+                                    ("F", c.out_F, fe.f_entries(k[0], k[1]))):
+                buf = torch.empty((rows, c.ld_out), dtype=dt_, device=dev)
+                fe.lib().fe_stream_copy(ctypes.c_void_p(buf.data_ptr()), ctypes.c_void_p(ptr),
+                                        buf.numel() * buf.element_size(), ctypes.c_void_p(stream.cuda_stream))
+                ok = ok and buf[:, :r["n"]].contiguous().cpu().numpy().tobytes() == sums_mix[(i, name)]
+            same += int(ok)
+            srv.release(c.id)
+        out["alone_vs_mix_bitwise_equal"] = f"{same}/{len(sample_ids)}"
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="tet_poisson", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="tet_poisson", choices=sorted(WORKLOADS) + ["served"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
-    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--tune", action="store_true",
+                    help="run the exhaustive variant search (fe_autotune) during warm-up")
+    ap.add_argument("--tuning-file", default=os.path.join(ROOT, "paper_1504_01023_amd", "tuning_mi355x.txt"),
+                    help="tuning table to load (the committed MI355X table by default)")
+    ap.add_argument("--save-tuning", default=None, help="write the tuning table here after the run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--parity-sample", type=int, default=20000)
+    ap.add_argument("--served-requests", type=int, default=1000)
+    ap.add_argument("--served-warmup", type=int, default=50)
+    ap.add_argument("--served-slots", type=int, default=64)
+    ap.add_argument("--served-rho", type=float, nargs="*", default=[0.5, 0.7, 0.9])
     a = ap.parse_args()
 
     if a.gpus != 1:
@@ -136,6 +389,23 @@ def main() -> int:
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
+    if a.workload == "served":
+        from paper_1504_01023_amd import serve
+        if a.tuning_file and os.path.exists(a.tuning_file):
+            fe.tuning_load(a.tuning_file)
+        res = run_served(a, torch, fe, serve)
+        sat = res["saturation"]
+        line = {"metric": "served elements/s (continuous batching, mixed stream, H2D included)",
+                "value": sat["elements_per_s"], "unit": "elements/s", "n_gpus": 1,
+                "steps": res["n_requests"], "warmup": res["warmup_requests"],
+                "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+                "vs_baseline": None, "dtype": "f64/f32 mix", "data": "synthetic",
+                "config": {"workload": "served", "mix": "50/50 tet/prism, 70/30 CDR/elasticity, "
+                           "50/50 FP64/FP32, n log-uniform in [1e3, 2e6], Poisson arrivals, seed 5"},
+                "served": res}
+        print(json.dumps(line), flush=True)
+        return 0
+
     t0 = time.time()
     wl = WORKLOADS[a.workload][0]()
     log(f"[bench] generated {a.workload}: {wl.n_elem} elements in {time.time() - t0:.1f}s")
@@ -148,10 +418,13 @@ def main() -> int:
     bpe = fe.bytes_per_element(p, wl.elem, rule.n_q)
     stream = torch.cuda.current_stream()
 
-    tuned = None
-    if not a.no_tune:
+    if a.tuning_file and os.path.exists(a.tuning_file):
+        fe.tuning_load(a.tuning_file)
+    if a.tune or fe.tuning_get(p, wl.elem, rule.n_q) is None:
         tuned, tms = fe.autotune(p, wl.elem, dw.coords, dw.coeffs, rule, K, F, reps=5)
         log(f"[bench] autotuned variant (wg, vec, ref, nt, blocks) = {tuned}: {tms:.4f} ms")
+    if a.save_tuning:
+        fe.tuning_save(a.save_tuning)
     variant_used = fe.tuning_get(p, wl.elem, rule.n_q)
 
     for _ in range(a.warmup):

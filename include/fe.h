@@ -213,6 +213,133 @@ FE_API int fe_tuning_load(const char *path);
 FE_API int fe_tuning_clear(void);
 
 /* ---------------------------------------------------------------------
+ * Persistent batched launches. Elements of the same type, problem and rule
+ * form one "kind" (the same-type element sets of Sec. 3.2 that one
+ * integration procedure processes in sequence, Algorithm 1). Requests of any
+ * size are cut into chunks of chunk_elems elements; fe_batch_launch replays a
+ * HIP graph captured at creation (copy of the chunk table to the device, then
+ * one persistent kernel per kind whose workgroups walk that kind's chunks),
+ * so many uneven requests cost one graph launch. Every element is computed by
+ * the same code path as in fe_integrate with the same kernel variant, so the
+ * results are bitwise identical to a plain launch of that variant.
+ * A fe_batch object is not thread-safe; calls on it must be serialised.
+ * ------------------------------------------------------------------- */
+#define FE_MAX_BATCH_KINDS 16
+
+typedef struct fe_batch_kind {
+    fe_problem problem;   /* coefficient values of uniform slots are fixed per kind */
+    int32_t elem_type;    /* fe_elem_type */
+    int32_t n_q;          /* rule, host memory, copied at creation */
+    const double *xi;
+    const double *w;
+} fe_batch_kind;
+
+typedef struct fe_batch fe_batch;
+
+/* Create a batcher for n_kinds kinds (1..FE_MAX_BATCH_KINDS) with a table of
+ * max_chunks chunks of chunk_elems elements (a multiple of 4) and
+ * blocks_per_kind workgroups per persistent kernel (0 = 1024). Allocates the
+ * device and pinned host tables and captures the graphs on the current
+ * device. Kernel variants come from the tuning table as at creation. */
+FE_API int fe_batch_create(const fe_batch_kind *kinds, int n_kinds, int max_chunks,
+                           int64_t chunk_elems, int blocks_per_kind, fe_batch **out);
+/* Append a request (device pointers, layouts as for fe_integrate_ex) to the
+ * pending table. FE_ERR_CAPACITY when its chunks do not fit (launch first);
+ * FE_ERR_UNSUPPORTED when its leading dimensions or alignment do not suit
+ * the kind's elements-per-lane. Nothing is enqueued until fe_batch_launch. */
+FE_API int fe_batch_add(fe_batch *b, int kind, int64_t n_elem, const double *coords,
+                        const void *coeffs, int64_t ld_in, void *out_K, void *out_F,
+                        int64_t ld_out);
+/* Number of pending chunks, or -1 for a NULL batch. */
+FE_API int fe_batch_pending(const fe_batch *b);
+/* Enqueue the pending chunks on `stream` (one graph launch) and clear the
+ * pending table. Blocks only if the table buffer it needs is still in use by
+ * the launch before the previous one. */
+FE_API int fe_batch_launch(fe_batch *b, hipStream_t stream);
+/* Wait for outstanding launches and free everything. */
+FE_API int fe_batch_destroy(fe_batch *b);
+
+/* ---------------------------------------------------------------------
+ * Continuous-batching server. Requests (one mesh of one kind each) are
+ * submitted at any time; a scheduler thread admits them in arrival order
+ * while a slot is free and their device bytes (inputs + outputs) fit in the
+ * HBM budget, copies host inputs to the device on a copy stream, and fuses
+ * the ready requests' chunks into persistent batched launches (fe_batch), so
+ * work that arrives while other requests run joins the next launch. Outputs
+ * stay resident on the device for the consumer (Sec. 3.1: element matrices
+ * are kept in memory available to the following solution steps) until
+ * fe_server_release. Host inputs must stay valid until the request
+ * completes; for asynchronous copies they should be pinned.
+ * ------------------------------------------------------------------- */
+#define FE_SERVER_GPU 0
+#define FE_SERVER_FAKE 1  /* timing model on the host, no device: for tests */
+
+typedef struct fe_server fe_server;
+
+typedef struct fe_server_config {
+    const fe_batch_kind *kinds;  /* copied at creation */
+    int32_t n_kinds;
+    int32_t max_slots;           /* requests admitted and not yet complete */
+    int64_t hbm_budget_bytes;    /* device arena for inputs and outputs */
+    int32_t max_chunks;          /* chunks per launch (tick) */
+    int32_t blocks_per_kind;     /* persistent workgroups per kind (0 = 1024) */
+    int64_t chunk_elems;         /* elements per chunk, multiple of 4 */
+    int32_t backend;             /* FE_SERVER_GPU or FE_SERVER_FAKE */
+    int32_t reserved;
+    double fake_ns_per_elem;     /* FAKE: device time per element */
+    double fake_h2d_bytes_per_s; /* FAKE: copy rate */
+    double fake_tick_overhead_s; /* FAKE: fixed cost per launch */
+} fe_server_config;
+
+typedef struct fe_request {
+    int32_t kind;
+    int32_t inputs_on_device;  /* 0: host inputs, copied to the device by the
+                                  server; 1: device inputs used in place */
+    int64_t n_elem;
+    const double *coords;      /* layouts as for fe_integrate_ex */
+    const void *coeffs;
+    int64_t ld_in;             /* leading dimension of coords/coeffs, >= n_elem */
+    uint64_t tag;              /* caller's value, returned in the completion */
+} fe_request;
+
+typedef struct fe_completion {
+    uint64_t id;
+    uint64_t tag;
+    int32_t status;            /* FE_OK, or why the request failed */
+    int32_t kind;
+    int64_t n_elem;
+    void *out_K;               /* device, [k * ld_out + e]; valid until release */
+    void *out_F;
+    int64_t ld_out;
+    double t_submit, t_admit, t_ready, t_done;  /* fe_server_now() clock, s */
+} fe_completion;
+
+typedef struct fe_server_stats {
+    int64_t submitted, admitted, completed, failed, in_queue, in_flight;
+    int64_t bytes_in_use, bytes_peak, elements_done, ticks;
+    double p50_s, p99_s, mean_s;                    /* submit -> done */
+    double mean_queue_s, mean_h2d_s, mean_device_s; /* breakdown */
+} fe_server_stats;
+
+/* Create a server (on the current device for FE_SERVER_GPU: allocates the
+ * arena, streams and the batched graphs once). */
+FE_API int fe_server_create(const fe_server_config *cfg, fe_server **out);
+/* Queue a request; *id receives its identifier. A request larger than the
+ * whole budget completes with FE_ERR_CAPACITY without affecting others. */
+FE_API int fe_server_submit(fe_server *s, const fe_request *req, uint64_t *id);
+/* Move up to max completions to out, waiting up to timeout_s seconds for the
+ * first; returns the number moved, or a negative status. */
+FE_API int fe_server_poll(fe_server *s, fe_completion *out, int max, double timeout_s);
+/* The consumer is done with a completed request's outputs: free its memory. */
+FE_API int fe_server_release(fe_server *s, uint64_t id);
+FE_API int fe_server_stats_get(fe_server *s, fe_server_stats *out);
+FE_API int fe_server_reset_stats(fe_server *s);
+/* Stop the scheduler, wait for the device and free everything. */
+FE_API int fe_server_destroy(fe_server *s);
+/* The server's clock (steady, seconds). */
+FE_API double fe_server_now(void);
+
+/* ---------------------------------------------------------------------
  * Measurement helper: copy n_bytes (a multiple of 16) from src to dst with
  * a plain streaming kernel, used to calibrate HBM counters and the achieved
  * copy ceiling beside the integration kernels.

@@ -127,6 +127,19 @@ __device__ __forceinline__ void storev(float *p, const float (&v)[V])
     }
 }
 
+// Where one batch of elements lives: the kernels read coordinates and
+// coefficients and write K and F through this view, so a plain launch
+// (one batch) and a persistent launch over a table of chunks of many
+// requests share the per-element code.
+struct Streams {
+    const double *coords;
+    const void *coeffs;
+    void *out_K;
+    void *out_F;
+    int64_t ld_in;
+    int64_t ld_out;
+};
+
 // ------------------------------------------------------------ small helpers
 __host__ __device__ constexpr int popc_below(uint32_t m, int k)
 {
@@ -141,7 +154,8 @@ __host__ __device__ constexpr int pidx(int N, int r, int s) { return r * N - r *
 
 // Value of coefficient slot k at point q for V consecutive elements.
 template <typename T, int MODE, uint32_t DENSE_SLOTS, int V, bool NT>
-__device__ __forceinline__ void coef(const KArgs &a, int k, int q, int64_t e0, T (&out)[V])
+__device__ __forceinline__ void coef(const KArgs &a, const Streams &st, int k, int q,
+                                     int64_t e0, T (&out)[V])
 {
     if constexpr (MODE == M_UNIFORM) {
         const T u = (T)a.uniform[k];
@@ -151,7 +165,7 @@ __device__ __forceinline__ void coef(const KArgs &a, int k, int q, int64_t e0, T
     } else if constexpr (MODE == M_ELEM || MODE == M_QP) {
         const int j = popc_below(DENSE_SLOTS, k);
         const int64_t row = (MODE == M_QP) ? (int64_t)j * a.n_q + q : (int64_t)j;
-        loadv<V, NT>(static_cast<const T *>(a.coeffs) + row * a.ld_in + e0, out);
+        loadv<V, NT>(static_cast<const T *>(st.coeffs) + row * st.ld_in + e0, out);
     } else {
         const int j = a.col[k];
         if (j < 0) {
@@ -161,7 +175,7 @@ __device__ __forceinline__ void coef(const KArgs &a, int k, int q, int64_t e0, T
                 out[i] = u;
         } else {
             const int64_t row = (MODE == M_QP_MIXED) ? (int64_t)j * a.n_q + q : (int64_t)j;
-            loadv<V, NT>(static_cast<const T *>(a.coeffs) + row * a.ld_in + e0, out);
+            loadv<V, NT>(static_cast<const T *>(st.coeffs) + row * st.ld_in + e0, out);
         }
     }
 }
@@ -300,29 +314,30 @@ struct TetScalar {
     static constexpr bool PER_QP = (MODE == M_QP || MODE == M_QP_MIXED);
 
     template <int V, bool NT, int REF>
-    __device__ __forceinline__ static void run(const KArgs &a, const Ref<REF> &ref, int64_t e0)
+    __device__ __forceinline__ static void run(const KArgs &a, const Streams &st, const Ref<REF> &ref,
+                                               int64_t e0)
     {
         double X[V][12];
 #pragma unroll
         for (int s = 0; s < 12; ++s) {
             double t[V];
-            loadv<V, NT>(a.coords + s * a.ld_in + e0, t);
+            loadv<V, NT>(st.coords + s * st.ld_in + e0, t);
 #pragma unroll
             for (int i = 0; i < V; ++i)
                 X[i][s] = t[i];
         }
         if constexpr (!PER_QP)
-            run_const<V, NT>(a, X, e0);
+            run_const<V, NT>(a, st, X, e0);
         else
-            run_qp<V, NT, REF>(a, ref, X, e0);
+            run_qp<V, NT, REF>(a, st, ref, X, e0);
     }
 
     template <int V, bool NT>
-    __device__ __forceinline__ static void store_K(const KArgs &a, int r, int s, int64_t e0,
+    __device__ __forceinline__ static void store_K(const Streams &st, int r, int s, int64_t e0,
                                                    const T (&val)[V])
     {
         const int k = PACKED ? pidx(4, r, s) : 4 * r + s;
-        storev<V, NT>(static_cast<T *>(a.out_K) + k * a.ld_out + e0, val);
+        storev<V, NT>(static_cast<T *>(st.out_K) + k * st.ld_out + e0, val);
     }
 
     // Coefficients constant over the element: with the (constant) gradients
@@ -331,7 +346,8 @@ struct TetScalar {
     //   K_rs = det [W g_r . C g_s + (c^{.;0} . g_r) m_s + m_r (c^{0;.} . g_s)
     //               + c^{0;0} M_rs],   F_r = det [W d . g_r + d^0 m_r].
     template <int V, bool NT>
-    __device__ __forceinline__ static void run_const(const KArgs &a, const double (&X)[V][12],
+    __device__ __forceinline__ static void run_const(const KArgs &a, const Streams &st,
+                                                     const double (&X)[V][12],
                                                      int64_t e0)
     {
         T C[3][3][V], ca[3][V], cb[3][V], c00[V], d[3][V], d0[V];
@@ -340,27 +356,27 @@ struct TetScalar {
             for (int i = 0; i < 3; ++i)
 #pragma unroll
                 for (int j = 0; j < 3; ++j)
-                    coef<T, MODE, SL, V, NT>(a, 4 * (i + 1) + 1 + j, 0, e0, C[i][j]);
+                    coef<T, MODE, SL, V, NT>(a, st, 4 * (i + 1) + 1 + j, 0, e0, C[i][j]);
         }
         if constexpr (CA) {
 #pragma unroll
             for (int i = 0; i < 3; ++i)
-                coef<T, MODE, SL, V, NT>(a, 4 * (i + 1), 0, e0, ca[i]);
+                coef<T, MODE, SL, V, NT>(a, st, 4 * (i + 1), 0, e0, ca[i]);
         }
         if constexpr (CB) {
 #pragma unroll
             for (int j = 0; j < 3; ++j)
-                coef<T, MODE, SL, V, NT>(a, 1 + j, 0, e0, cb[j]);
+                coef<T, MODE, SL, V, NT>(a, st, 1 + j, 0, e0, cb[j]);
         }
         if constexpr (MASS)
-            coef<T, MODE, SL, V, NT>(a, 0, 0, e0, c00);
+            coef<T, MODE, SL, V, NT>(a, st, 0, 0, e0, c00);
         if constexpr (DG) {
 #pragma unroll
             for (int i = 0; i < 3; ++i)
-                coef<T, MODE, SL, V, NT>(a, 17 + i, 0, e0, d[i]);
+                coef<T, MODE, SL, V, NT>(a, st, 17 + i, 0, e0, d[i]);
         }
         if constexpr (D0)
-            coef<T, MODE, SL, V, NT>(a, 16, 0, e0, d0);
+            coef<T, MODE, SL, V, NT>(a, st, 16, 0, e0, d0);
 
         const T W = (T)a.Wsum;
         T Kv[4][4][V], Fv[4][V];
@@ -418,10 +434,10 @@ struct TetScalar {
         for (int r = 0; r < 4; ++r)
 #pragma unroll
             for (int s = (PACKED ? r : 0); s < 4; ++s)
-                store_K<V, NT>(a, r, s, e0, Kv[r][s]);
+                store_K<V, NT>(st, r, s, e0, Kv[r][s]);
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            storev<V, NT>(static_cast<T *>(a.out_F) + r * a.ld_out + e0, Fv[r]);
+            storev<V, NT>(static_cast<T *>(st.out_F) + r * st.ld_out + e0, Fv[r]);
     }
 
     // Coefficients per point (Algorithm 3 with "calculate possibly
@@ -432,7 +448,7 @@ struct TetScalar {
     //   Mb_rs = sum_q w c^{0;0}_q phi_r phi_s, Db = sum_q w d_q, fb_r = sum_q w d^0_q phi_r,
     //   K_rs = det (g_r . Cb g_s + g_r . Pb_s + Qb_r . g_s + Mb_rs), F_r = det (Db . g_r + fb_r).
     template <int V, bool NT, int REF>
-    __device__ __forceinline__ static void run_qp(const KArgs &a, const Ref<REF> &ref,
+    __device__ __forceinline__ static void run_qp(const KArgs &a, const Streams &st, const Ref<REF> &ref,
                                                   const double (&X)[V][12], int64_t e0)
     {
         T Cb[V][3][3], Pb[V][4][3], Qb[V][4][3], Mb[V][4][4], Db[V][3], fb[V][4];
@@ -468,7 +484,7 @@ struct TetScalar {
                 for (int i = 0; i < 3; ++i)
 #pragma unroll
                     for (int j = 0; j < 3; ++j) {
-                        coef<T, MODE, SL, V, NT>(a, 4 * (i + 1) + 1 + j, q, e0, c);
+                        coef<T, MODE, SL, V, NT>(a, st, 4 * (i + 1) + 1 + j, q, e0, c);
 #pragma unroll
                         for (int v = 0; v < V; ++v)
                             Cb[v][i][j] += w * c[v];
@@ -477,7 +493,7 @@ struct TetScalar {
             if constexpr (CA) {
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
-                    coef<T, MODE, SL, V, NT>(a, 4 * (i + 1), q, e0, c);
+                    coef<T, MODE, SL, V, NT>(a, st, 4 * (i + 1), q, e0, c);
 #pragma unroll
                     for (int v = 0; v < V; ++v)
 #pragma unroll
@@ -488,7 +504,7 @@ struct TetScalar {
             if constexpr (CB) {
 #pragma unroll
                 for (int j = 0; j < 3; ++j) {
-                    coef<T, MODE, SL, V, NT>(a, 1 + j, q, e0, c);
+                    coef<T, MODE, SL, V, NT>(a, st, 1 + j, q, e0, c);
 #pragma unroll
                     for (int v = 0; v < V; ++v)
 #pragma unroll
@@ -497,7 +513,7 @@ struct TetScalar {
                 }
             }
             if constexpr (MASS) {
-                coef<T, MODE, SL, V, NT>(a, 0, q, e0, c);
+                coef<T, MODE, SL, V, NT>(a, st, 0, q, e0, c);
 #pragma unroll
                 for (int v = 0; v < V; ++v)
 #pragma unroll
@@ -509,14 +525,14 @@ struct TetScalar {
             if constexpr (DG) {
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
-                    coef<T, MODE, SL, V, NT>(a, 17 + i, q, e0, c);
+                    coef<T, MODE, SL, V, NT>(a, st, 17 + i, q, e0, c);
 #pragma unroll
                     for (int v = 0; v < V; ++v)
                         Db[v][i] += w * c[v];
                 }
             }
             if constexpr (D0) {
-                coef<T, MODE, SL, V, NT>(a, 16, q, e0, c);
+                coef<T, MODE, SL, V, NT>(a, st, 16, q, e0, c);
 #pragma unroll
                 for (int v = 0; v < V; ++v)
 #pragma unroll
@@ -569,10 +585,10 @@ struct TetScalar {
         for (int r = 0; r < 4; ++r)
 #pragma unroll
             for (int s = (PACKED ? r : 0); s < 4; ++s)
-                store_K<V, NT>(a, r, s, e0, Kv[r][s]);
+                store_K<V, NT>(st, r, s, e0, Kv[r][s]);
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            storev<V, NT>(static_cast<T *>(a.out_F) + r * a.ld_out + e0, Fv[r]);
+            storev<V, NT>(static_cast<T *>(st.out_F) + r * st.ld_out + e0, Fv[r]);
     }
 };
 
@@ -586,13 +602,14 @@ struct TetElastic {
     static constexpr bool PER_QP = (MODE == M_QP || MODE == M_QP_MIXED);
 
     template <int V, bool NT, int REF>
-    __device__ __forceinline__ static void run(const KArgs &a, const Ref<REF> &ref, int64_t e0)
+    __device__ __forceinline__ static void run(const KArgs &a, const Streams &st, const Ref<REF> &ref,
+                                               int64_t e0)
     {
         double X[V][12];
 #pragma unroll
         for (int s = 0; s < 12; ++s) {
             double t[V];
-            loadv<V, NT>(a.coords + s * a.ld_in + e0, t);
+            loadv<V, NT>(st.coords + s * st.ld_in + e0, t);
 #pragma unroll
             for (int i = 0; i < V; ++i)
                 X[i][s] = t[i];
@@ -600,11 +617,11 @@ struct TetElastic {
         T lb[V], mb[V], fb[V][4][3];
         if constexpr (!PER_QP) {
             T E[V], nu[V], f[3][V];
-            coef<T, MODE, SL, V, NT>(a, 0, 0, e0, E);
-            coef<T, MODE, SL, V, NT>(a, 1, 0, e0, nu);
+            coef<T, MODE, SL, V, NT>(a, st, 0, 0, e0, E);
+            coef<T, MODE, SL, V, NT>(a, st, 1, 0, e0, nu);
 #pragma unroll
             for (int al = 0; al < 3; ++al)
-                coef<T, MODE, SL, V, NT>(a, 2 + al, 0, e0, f[al]);
+                coef<T, MODE, SL, V, NT>(a, st, 2 + al, 0, e0, f[al]);
             const T W = (T)a.Wsum;
 #pragma unroll
             for (int v = 0; v < V; ++v) {
@@ -631,11 +648,11 @@ struct TetElastic {
             for (int q = 0; q < a.n_q; ++q) {
                 const T w = (T)ref.w(q);
                 T E[V], nu[V], f[3][V];
-                coef<T, MODE, SL, V, NT>(a, 0, q, e0, E);
-                coef<T, MODE, SL, V, NT>(a, 1, q, e0, nu);
+                coef<T, MODE, SL, V, NT>(a, st, 0, q, e0, E);
+                coef<T, MODE, SL, V, NT>(a, st, 1, q, e0, nu);
 #pragma unroll
                 for (int al = 0; al < 3; ++al)
-                    coef<T, MODE, SL, V, NT>(a, 2 + al, q, e0, f[al]);
+                    coef<T, MODE, SL, V, NT>(a, st, 2 + al, q, e0, f[al]);
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
                     T lam, mu;
@@ -659,7 +676,7 @@ struct TetElastic {
             lb[v] *= det[v];
             mb[v] *= det[v];
         }
-        T *outK = static_cast<T *>(a.out_K);
+        T *outK = static_cast<T *>(st.out_K);
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
@@ -685,10 +702,10 @@ struct TetElastic {
                             val[v] = x;
                         }
                         const int k = PACKED ? pidx(12, row, col) : 12 * row + col;
-                        storev<V, NT>(outK + k * a.ld_out + e0, val);
+                        storev<V, NT>(outK + k * st.ld_out + e0, val);
                     }
             }
-        T *outF = static_cast<T *>(a.out_F);
+        T *outF = static_cast<T *>(st.out_F);
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
@@ -697,7 +714,7 @@ struct TetElastic {
 #pragma unroll
                 for (int v = 0; v < V; ++v)
                     val[v] = det[v] * fb[v][r][al];
-                storev<V, NT>(outF + (3 * r + al) * a.ld_out + e0, val);
+                storev<V, NT>(outF + (3 * r + al) * st.ld_out + e0, val);
             }
     }
 };
@@ -721,7 +738,8 @@ struct PrismScalar {
     };
 
     template <bool NT>
-    __device__ __forceinline__ static void load_coefs(const KArgs &a, int q, int64_t e, Coefs &c)
+    __device__ __forceinline__ static void load_coefs(const KArgs &a, const Streams &st, int q,
+                                                      int64_t e, Coefs &c)
     {
         T x[1];
         if constexpr (DIFF) {
@@ -729,49 +747,50 @@ struct PrismScalar {
             for (int i = 0; i < 3; ++i)
 #pragma unroll
                 for (int j = 0; j < 3; ++j) {
-                    coef<T, MODE, SL, 1, NT>(a, 4 * (i + 1) + 1 + j, q, e, x);
+                    coef<T, MODE, SL, 1, NT>(a, st, 4 * (i + 1) + 1 + j, q, e, x);
                     c.C[i][j] = x[0];
                 }
         }
         if constexpr (CA) {
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                coef<T, MODE, SL, 1, NT>(a, 4 * (i + 1), q, e, x);
+                coef<T, MODE, SL, 1, NT>(a, st, 4 * (i + 1), q, e, x);
                 c.ca[i] = x[0];
             }
         }
         if constexpr (CB) {
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
-                coef<T, MODE, SL, 1, NT>(a, 1 + j, q, e, x);
+                coef<T, MODE, SL, 1, NT>(a, st, 1 + j, q, e, x);
                 c.cb[j] = x[0];
             }
         }
         if constexpr (MASS) {
-            coef<T, MODE, SL, 1, NT>(a, 0, q, e, x);
+            coef<T, MODE, SL, 1, NT>(a, st, 0, q, e, x);
             c.c00 = x[0];
         }
         if constexpr (DG) {
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                coef<T, MODE, SL, 1, NT>(a, 17 + i, q, e, x);
+                coef<T, MODE, SL, 1, NT>(a, st, 17 + i, q, e, x);
                 c.d[i] = x[0];
             }
         }
         if constexpr (D0) {
-            coef<T, MODE, SL, 1, NT>(a, 16, q, e, x);
+            coef<T, MODE, SL, 1, NT>(a, st, 16, q, e, x);
             c.d0 = x[0];
         }
     }
 
     template <int V, bool NT, int REF>
-    __device__ __forceinline__ static void run(const KArgs &a, const Ref<REF> &ref, int64_t e)
+    __device__ __forceinline__ static void run(const KArgs &a, const Streams &st, const Ref<REF> &ref,
+                                               int64_t e)
     {
         static_assert(V == 1, "prisms are processed one element per lane");
         double X[18];
 #pragma unroll
         for (int s = 0; s < 18; ++s)
-            X[s] = ld1<NT>(a.coords + s * a.ld_in + e);
+            X[s] = ld1<NT>(st.coords + s * st.ld_in + e);
         to_edge_vectors<6>(X);
         constexpr int NK = PACKED ? 21 : 36;
         T K[NK], F[6];
@@ -783,12 +802,12 @@ struct PrismScalar {
             F[r] = T(0);
         Coefs c;
         if constexpr (!PER_QP)
-            load_coefs<NT>(a, 0, e, c);
+            load_coefs<NT>(a, st, 0, e, c);
         const int nq = NQ > 0 ? NQ : a.n_q;
 #pragma unroll(NQ > 0 ? NQ : 1)
         for (int q = 0; q < nq; ++q) {
             if constexpr (PER_QP)
-                load_coefs<NT>(a, q, e, c);
+                load_coefs<NT>(a, st, q, e, c);
             T g[6][3], vol;
             point_geometry<6, T>(X, ref, q, g, vol);
             T phi[6];
@@ -838,14 +857,14 @@ struct PrismScalar {
                     F[r] += p * c.d0;
             }
         }
-        T *outK = static_cast<T *>(a.out_K);
+        T *outK = static_cast<T *>(st.out_K);
 #pragma unroll
         for (int k = 0; k < NK; ++k)
-            st1<NT>(outK + k * a.ld_out + e, K[k]);
-        T *outF = static_cast<T *>(a.out_F);
+            st1<NT>(outK + k * st.ld_out + e, K[k]);
+        T *outF = static_cast<T *>(st.out_F);
 #pragma unroll
         for (int r = 0; r < 6; ++r)
-            st1<NT>(outF + r * a.ld_out + e, F[r]);
+            st1<NT>(outF + r * st.ld_out + e, F[r]);
     }
 };
 
@@ -862,13 +881,14 @@ struct PrismElastic {
     static constexpr int NP = 171;  // packed entries of the 18 x 18 matrix
 
     template <int V, bool NT, int REF>
-    __device__ __forceinline__ static void run(const KArgs &a, const Ref<REF> &ref, int64_t e)
+    __device__ __forceinline__ static void run(const KArgs &a, const Streams &st, const Ref<REF> &ref,
+                                               int64_t e)
     {
         static_assert(V == 1, "prisms are processed one element per lane");
         double X[18];
 #pragma unroll
         for (int s = 0; s < 18; ++s)
-            X[s] = ld1<NT>(a.coords + s * a.ld_in + e);
+            X[s] = ld1<NT>(st.coords + s * st.ld_in + e);
         to_edge_vectors<6>(X);
         T Kp[NP], F[18];
 #pragma unroll
@@ -903,11 +923,11 @@ struct PrismElastic {
                 }
             }
             T E[1], nu[1], f[3][1];
-            coef<T, MODE, SL, 1, NT>(a, 0, 0, e, E);
-            coef<T, MODE, SL, 1, NT>(a, 1, 0, e, nu);
+            coef<T, MODE, SL, 1, NT>(a, st, 0, 0, e, E);
+            coef<T, MODE, SL, 1, NT>(a, st, 1, 0, e, nu);
 #pragma unroll
             for (int al = 0; al < 3; ++al)
-                coef<T, MODE, SL, 1, NT>(a, 2 + al, 0, e, f[al]);
+                coef<T, MODE, SL, 1, NT>(a, st, 2 + al, 0, e, f[al]);
             T lam, mu;
             lame<T>(E[0], nu[0], lam, mu);
             // Transform H -> K block by block, in place.
@@ -945,11 +965,11 @@ struct PrismElastic {
 #pragma unroll(NQ > 0 ? NQ : 1)
             for (int q = 0; q < nq; ++q) {
                 T E[1], nu[1], f[3][1];
-                coef<T, MODE, SL, 1, NT>(a, 0, q, e, E);
-                coef<T, MODE, SL, 1, NT>(a, 1, q, e, nu);
+                coef<T, MODE, SL, 1, NT>(a, st, 0, q, e, E);
+                coef<T, MODE, SL, 1, NT>(a, st, 1, q, e, nu);
 #pragma unroll
                 for (int al = 0; al < 3; ++al)
-                    coef<T, MODE, SL, 1, NT>(a, 2 + al, q, e, f[al]);
+                    coef<T, MODE, SL, 1, NT>(a, st, 2 + al, q, e, f[al]);
                 T lam, mu;
                 lame<T>(E[0], nu[0], lam, mu);
                 T g[6][3], vol;
@@ -977,24 +997,24 @@ struct PrismElastic {
                 }
             }
         }
-        T *outK = static_cast<T *>(a.out_K);
+        T *outK = static_cast<T *>(st.out_K);
         if constexpr (PACKED) {
 #pragma unroll
             for (int k = 0; k < NP; ++k)
-                st1<NT>(outK + k * a.ld_out + e, Kp[k]);
+                st1<NT>(outK + k * st.ld_out + e, Kp[k]);
         } else {
 #pragma unroll
             for (int row = 0; row < 18; ++row)
 #pragma unroll
                 for (int col = 0; col < 18; ++col) {
                     const int k = col >= row ? pidx(18, row, col) : pidx(18, col, row);
-                    st1<NT>(outK + (18 * row + col) * a.ld_out + e, Kp[k]);
+                    st1<NT>(outK + (18 * row + col) * st.ld_out + e, Kp[k]);
                 }
         }
-        T *outF = static_cast<T *>(a.out_F);
+        T *outF = static_cast<T *>(st.out_F);
 #pragma unroll
         for (int k = 0; k < 18; ++k)
-            st1<NT>(outF + k * a.ld_out + e, F[k]);
+            st1<NT>(outF + k * st.ld_out + e, F[k]);
     }
 };
 
@@ -1005,7 +1025,7 @@ struct PrismElastic {
 template <class P, int V, bool NT, int REF>
 __global__ __launch_bounds__(256) void fe_kernel(KArgs a)
 {
-    __shared__ RefLds lds_ref[REF == REF_LDS ? 1 : 0 + 1];
+    __shared__ RefLds lds_ref[1];
     if constexpr (REF == REF_LDS) {
         const int n_w = a.n_q, n_phi = a.n_q * 6, n_dphi = a.n_q * 18;
         for (int i = threadIdx.x; i < n_w; i += blockDim.x)
@@ -1017,17 +1037,64 @@ __global__ __launch_bounds__(256) void fe_kernel(KArgs a)
         __syncthreads();
     }
     const Ref<REF> ref{a, &lds_ref[0]};
+    const Streams st{a.coords, a.coeffs, a.out_K, a.out_F, a.ld_in, a.ld_out};
     const int64_t n_groups = (a.n_elem + V - 1) / V;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_groups; g += stride) {
         const int64_t e0 = g * V;
         if (V == 1 || e0 + V <= a.n_elem) {
-            P::template run<V, NT, REF>(a, ref, e0);
+            P::template run<V, NT, REF>(a, st, ref, e0);
         } else {
             for (int64_t e = e0; e < a.n_elem; ++e)
-                P::template run<1, NT, REF>(a, ref, e);
+                P::template run<1, NT, REF>(a, st, ref, e);
         }
     }
+}
+
+// Persistent batched form: the blocks of one launch walk the chunks of one
+// kind in the device table (chunk c by block c mod gridDim), so requests of
+// different sizes share one launch. Chunk starts are multiples of V, so every
+// element is processed by the same code path as in a plain launch.
+template <class P, int V, bool NT, int REF>
+__global__ __launch_bounds__(256) void fe_batch_kernel(KArgs a, const BatchHeader *__restrict__ hdr,
+                                                       const Chunk *__restrict__ chunks, int kind)
+{
+    __shared__ RefLds lds_ref[1];
+    if constexpr (REF == REF_LDS) {
+        const int n_w = a.n_q, n_phi = a.n_q * 6, n_dphi = a.n_q * 18;
+        for (int i = threadIdx.x; i < n_w; i += blockDim.x)
+            lds_ref[0].w[i] = a.w[i];
+        for (int i = threadIdx.x; i < n_phi; i += blockDim.x)
+            (&lds_ref[0].phi[0][0])[i] = (&a.phi[0][0])[i];
+        for (int i = threadIdx.x; i < n_dphi; i += blockDim.x)
+            (&lds_ref[0].dphi[0][0][0])[i] = (&a.dphi[0][0][0])[i];
+        __syncthreads();
+    }
+    const Ref<REF> ref{a, &lds_ref[0]};
+    const int begin = hdr->begin[kind], end = hdr->end[kind];
+    for (int c = begin + (int)blockIdx.x; c < end; c += (int)gridDim.x) {
+        const Chunk ch = chunks[c];
+        const Streams st{ch.coords, ch.coeffs, ch.out_K, ch.out_F, ch.ld_in, ch.ld_out};
+        const int64_t last = ch.e0 + ch.n;
+        const int64_t n_groups = (ch.n + V - 1) / V;
+        for (int64_t g = threadIdx.x; g < n_groups; g += blockDim.x) {
+            const int64_t e0 = ch.e0 + g * V;
+            if (V == 1 || e0 + V <= last) {
+                P::template run<V, NT, REF>(a, st, ref, e0);
+            } else {
+                for (int64_t e = e0; e < last; ++e)
+                    P::template run<1, NT, REF>(a, st, ref, e);
+            }
+        }
+    }
+}
+
+template <class P, int V, bool NT, int REF>
+void launch_fe_batch_kernel(const KArgs &a, const BatchHeader *hdr, const Chunk *chunks, int kind,
+                            unsigned grid, unsigned block, hipStream_t stream)
+{
+    hipLaunchKernelGGL((fe_batch_kernel<P, V, NT, REF>), dim3(grid), dim3(block), 0, stream, a, hdr,
+                       chunks, kind);
 }
 
 template <class P, int V, bool NT, int REF>
@@ -1035,14 +1102,5 @@ void launch_fe_kernel(const KArgs &a, unsigned grid, unsigned block, hipStream_t
 {
     hipLaunchKernelGGL((fe_kernel<P, V, NT, REF>), dim3(grid), dim3(block), 0, stream, a);
 }
-
-template <class P, int V, bool NT, int REF>
-struct Registrar {
-    explicit Registrar(KernelKey k)
-    {
-        register_kernel(KernelEntry{k, &launch_fe_kernel<P, V, NT, REF>,
-                                    reinterpret_cast<const void *>(&fe_kernel<P, V, NT, REF>)});
-    }
-};
 
 }  // namespace fe

@@ -90,10 +90,32 @@ struct KernelKey {
 
 typedef void (*LaunchFn)(const KArgs &, unsigned grid, unsigned block, hipStream_t);
 
+// Persistent batched launches: a table of chunks (element ranges of many
+// requests), grouped by kind; kind k owns chunks [begin[k], end[k]).
+constexpr int MAX_BATCH_KINDS = 16;
+struct Chunk {
+    const double *coords;
+    const void *coeffs;
+    void *out_K;
+    void *out_F;
+    int64_t ld_in;
+    int64_t ld_out;
+    int64_t e0;  // first element of the chunk (offset into the arrays above)
+    int64_t n;   // elements in the chunk
+};
+static_assert(sizeof(Chunk) == 64, "chunk records are one 64-byte line");
+struct BatchHeader {
+    int32_t begin[MAX_BATCH_KINDS];
+    int32_t end[MAX_BATCH_KINDS];
+};
+typedef void (*BatchLaunchFn)(const KArgs &, const BatchHeader *, const Chunk *, int kind,
+                              unsigned grid, unsigned block, hipStream_t);
+
 struct KernelEntry {
     KernelKey key;
     LaunchFn launch;
     const void *func;
+    BatchLaunchFn batch;  // persistent batched form, or nullptr
 };
 
 // Registration of compiled kernels (each kernel translation unit registers

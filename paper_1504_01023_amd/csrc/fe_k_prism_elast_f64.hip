@@ -8,7 +8,7 @@ typedef double T;
 int register_all()
 {
 #define BASE(MODE) \
-    reg_prism_elastic<T, MODE, 0, 0, 1, REF_KARG>(); reg_prism_elastic<T, MODE, 1, 0, 1, REF_KARG>();
+    reg_prism_elastic<T, MODE, 0, 0, 1, REF_KARG, 1>(); reg_prism_elastic<T, MODE, 1, 0, 1, REF_KARG, 1>();
     BASE(M_UNIFORM) BASE(M_ELEM) BASE(M_QP) BASE(M_ELEM_MIXED) BASE(M_QP_MIXED)
 #undef BASE
 #define TUNE(MODE, PK) \

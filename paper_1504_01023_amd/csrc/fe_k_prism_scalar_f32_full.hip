@@ -10,7 +10,7 @@ int register_all()
 {
     // every coefficient mode and K format with a runtime point loop
 #define BASE(MODE) \
-    reg_prism_scalar<T, TS, MODE, 0, 0, 1, REF_KARG>(); reg_prism_scalar<T, TS, MODE, 1, 0, 1, REF_KARG>();
+    reg_prism_scalar<T, TS, MODE, 0, 0, 1, REF_KARG, 1>(); reg_prism_scalar<T, TS, MODE, 1, 0, 1, REF_KARG, 1>();
     BASE(M_UNIFORM) BASE(M_ELEM) BASE(M_QP) BASE(M_ELEM_MIXED) BASE(M_QP_MIXED)
 #undef BASE
     // tuning variants of the runtime point loop: cache policy and LDS

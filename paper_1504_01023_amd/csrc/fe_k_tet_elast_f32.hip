@@ -7,11 +7,11 @@ typedef float T;
 
 int register_all()
 {
-#define BASE(MODE) reg_tet_elastic<T, MODE, 0, 1, 1>(); reg_tet_elastic<T, MODE, 1, 1, 1>();
+#define BASE(MODE) reg_tet_elastic<T, MODE, 0, 1, 1, 1>(); reg_tet_elastic<T, MODE, 1, 1, 1, 1>();
     BASE(M_UNIFORM) BASE(M_ELEM) BASE(M_QP) BASE(M_ELEM_MIXED) BASE(M_QP_MIXED)
 #undef BASE
 #define TUNE(MODE, PK) \
-    reg_tet_elastic<T, MODE, PK, 2, 1>(); reg_tet_elastic<T, MODE, PK, 4, 1>(); \
+    reg_tet_elastic<T, MODE, PK, 2, 1, 1>(); reg_tet_elastic<T, MODE, PK, 4, 1>(); \
     reg_tet_elastic<T, MODE, PK, 1, 0>(); reg_tet_elastic<T, MODE, PK, 2, 0>();
     TUNE(M_ELEM, 1) TUNE(M_ELEM, 0) TUNE(M_UNIFORM, 1)
 #undef TUNE

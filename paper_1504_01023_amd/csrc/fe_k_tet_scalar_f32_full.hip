@@ -9,13 +9,13 @@ constexpr int TS = TS_FULL;
 int register_all()
 {
     // every coefficient mode and K format, base variant (1 element per
-    // lane, non-temporal)
-#define BASE(MODE) reg_tet_scalar<T, TS, MODE, 0, 1, 1>(); reg_tet_scalar<T, TS, MODE, 1, 1, 1>();
+    // lane, non-temporal), plain and batched forms
+#define BASE(MODE) reg_tet_scalar<T, TS, MODE, 0, 1, 1, 1>(); reg_tet_scalar<T, TS, MODE, 1, 1, 1, 1>();
     BASE(M_UNIFORM) BASE(M_ELEM) BASE(M_QP) BASE(M_ELEM_MIXED) BASE(M_QP_MIXED)
 #undef BASE
     // tuning variants: elements per lane and cache policy
 #define TUNE(MODE, PK) \
-    reg_tet_scalar<T, TS, MODE, PK, 2, 1>(); reg_tet_scalar<T, TS, MODE, PK, 4, 1>(); \
+    reg_tet_scalar<T, TS, MODE, PK, 2, 1, 1>(); reg_tet_scalar<T, TS, MODE, PK, 4, 1>(); \
     reg_tet_scalar<T, TS, MODE, PK, 1, 0>(); reg_tet_scalar<T, TS, MODE, PK, 2, 0>(); \
     reg_tet_scalar<T, TS, MODE, PK, 4, 0>();
     TUNE(M_UNIFORM, 1) TUNE(M_UNIFORM, 0) TUNE(M_ELEM, 0) TUNE(M_ELEM, 1) TUNE(M_QP, 0)

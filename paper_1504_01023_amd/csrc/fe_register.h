@@ -7,42 +7,47 @@
 
 namespace fe {
 
-template <class P, int V, int NT, int REF>
+// Registers the plain kernel; kinds that serve batched (persistent) launches
+// also register the batched form (B = 1).
+template <class P, int V, int NT, int REF, int B = 0>
 inline void reg(int elem, int kind, int prec, int terms, int mode, int packed, int nq)
 {
     KernelKey k{elem, kind, prec, terms, mode, packed, V, NT, REF, nq};
+    BatchLaunchFn bl = nullptr;
+    if constexpr (B != 0)
+        bl = &launch_fe_batch_kernel<P, V, NT != 0, REF>;
     register_kernel(KernelEntry{k, &launch_fe_kernel<P, V, NT != 0, REF>,
-                                reinterpret_cast<const void *>(&fe_kernel<P, V, NT != 0, REF>)});
+                                reinterpret_cast<const void *>(&fe_kernel<P, V, NT != 0, REF>), bl});
 }
 
 template <typename T>
 constexpr int prec_of() { return std::is_same<T, float>::value ? FE_FP32_BULK : FE_FP64; }
 
-template <typename T, int TERMS, int MODE, int PK, int V, int NT>
+template <typename T, int TERMS, int MODE, int PK, int V, int NT, int B = 0>
 inline void reg_tet_scalar()
 {
-    reg<TetScalar<T, TERMS, MODE, PK>, V, NT, REF_KARG>(FE_TET4, FE_SCALAR_CDR, prec_of<T>(), TERMS,
+    reg<TetScalar<T, TERMS, MODE, PK>, V, NT, REF_KARG, B>(FE_TET4, FE_SCALAR_CDR, prec_of<T>(), TERMS,
                                                         MODE, PK, 0);
 }
 
-template <typename T, int MODE, int PK, int V, int NT>
+template <typename T, int MODE, int PK, int V, int NT, int B = 0>
 inline void reg_tet_elastic()
 {
-    reg<TetElastic<T, MODE, PK>, V, NT, REF_KARG>(FE_TET4, FE_ELASTICITY, prec_of<T>(), TS_ELAST,
+    reg<TetElastic<T, MODE, PK>, V, NT, REF_KARG, B>(FE_TET4, FE_ELASTICITY, prec_of<T>(), TS_ELAST,
                                                   MODE, PK, 0);
 }
 
-template <typename T, int TERMS, int MODE, int PK, int NQ, int NT, int REF>
+template <typename T, int TERMS, int MODE, int PK, int NQ, int NT, int REF, int B = 0>
 inline void reg_prism_scalar()
 {
-    reg<PrismScalar<T, TERMS, MODE, PK, NQ>, 1, NT, REF>(FE_PRISM6, FE_SCALAR_CDR, prec_of<T>(),
+    reg<PrismScalar<T, TERMS, MODE, PK, NQ>, 1, NT, REF, B>(FE_PRISM6, FE_SCALAR_CDR, prec_of<T>(),
                                                          TERMS, MODE, PK, NQ);
 }
 
-template <typename T, int MODE, int PK, int NQ, int NT, int REF>
+template <typename T, int MODE, int PK, int NQ, int NT, int REF, int B = 0>
 inline void reg_prism_elastic()
 {
-    reg<PrismElastic<T, MODE, PK, NQ>, 1, NT, REF>(FE_PRISM6, FE_ELASTICITY, prec_of<T>(), TS_ELAST,
+    reg<PrismElastic<T, MODE, PK, NQ>, 1, NT, REF, B>(FE_PRISM6, FE_ELASTICITY, prec_of<T>(), TS_ELAST,
                                                    MODE, PK, NQ);
 }
 

@@ -317,3 +317,68 @@ def unpack_full(K: np.ndarray, N: int, packed: bool) -> np.ndarray:
             out[:, s, r] = K[k]
             k += 1
     return out
+
+
+# ------------------------------------------------------------ batched launches
+class BatchKind(ctypes.Structure):
+    _fields_ = [("problem", Problem), ("elem_type", ctypes.c_int32), ("n_q", ctypes.c_int32),
+                ("xi", ctypes.POINTER(ctypes.c_double)), ("w", ctypes.POINTER(ctypes.c_double))]
+
+
+def _batch_sigs(L):
+    if getattr(L, "_batch_sigs", False):
+        return
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    L.fe_batch_create.argtypes = [ctypes.POINTER(BatchKind), i32, i32, i64, i32,
+                                  ctypes.POINTER(vp)]
+    L.fe_batch_add.argtypes = [vp, i32, i64, vp, vp, i64, vp, vp, i64]
+    L.fe_batch_pending.argtypes = [vp]
+    L.fe_batch_launch.argtypes = [vp, vp]
+    L.fe_batch_destroy.argtypes = [vp]
+    L._batch_sigs = True
+
+
+class Batch:
+    """Persistent batched launches over a fixed set of kinds
+    (fe_batch_create / fe_batch_add / fe_batch_launch)."""
+
+    def __init__(self, kinds, max_chunks=1024, chunk_elems=16384, blocks_per_kind=0):
+        """kinds: list of (Problem, elem, Rule)."""
+        L = lib()
+        _batch_sigs(L)
+        self._rules = [k[2] for k in kinds]
+        arr = (BatchKind * len(kinds))()
+        for i, (p, elem, rule) in enumerate(kinds):
+            arr[i].problem = p
+            arr[i].elem_type = ELEM.get(elem, elem)
+            arr[i].n_q = rule.n_q
+            arr[i].xi = rule.c.xi
+            arr[i].w = rule.c.w
+        self.kinds = list(kinds)
+        self._h = ctypes.c_void_p()
+        _check(L.fe_batch_create(arr, len(kinds), max_chunks, chunk_elems, blocks_per_kind,
+                                 ctypes.byref(self._h)))
+
+    def add(self, kind: int, coords, coeffs, out_K, out_F, n_elem=None) -> None:
+        n = coords.shape[1] if n_elem is None else int(n_elem)
+        _check(lib().fe_batch_add(self._h, kind, n, ctypes.c_void_p(coords.data_ptr()),
+                                  ctypes.c_void_p(coeffs.data_ptr()) if coeffs is not None else None,
+                                  coords.shape[1], ctypes.c_void_p(out_K.data_ptr()),
+                                  ctypes.c_void_p(out_F.data_ptr()), out_K.shape[1]))
+
+    def pending(self) -> int:
+        return int(lib().fe_batch_pending(self._h))
+
+    def launch(self, stream=None) -> None:
+        _check(lib().fe_batch_launch(self._h, _stream_handle(stream)))
+
+    def close(self) -> None:
+        if self._h:
+            lib().fe_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

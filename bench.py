@@ -58,16 +58,33 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-def source_hash() -> str:
-    """Hash of the kernel sources; a stored counter reading is only reused
-    while this matches."""
+KERNEL_UNITS = {
+    ("tet_poisson", "fp64"): "fe_k_tet_scalar_f64_poisson.hip",
+    ("tet_poisson", "fp32"): "fe_k_tet_scalar_f32_poisson.hip",
+    ("tet_poisson_qp", "fp64"): "fe_k_tet_scalar_f64_poisson.hip",
+    ("tet_poisson_qp", "fp32"): "fe_k_tet_scalar_f32_poisson.hip",
+    ("tet_cdr", "fp64"): "fe_k_tet_scalar_f64_full.hip",
+    ("tet_cdr", "fp32"): "fe_k_tet_scalar_f32_full.hip",
+    ("prism_cdr_qp", "fp64"): "fe_k_prism_scalar_f64_full.hip",
+    ("prism_cdr_qp", "fp32"): "fe_k_prism_scalar_f32_full.hip",
+    ("tet_elasticity", "fp64"): "fe_k_tet_elast_f64.hip",
+    ("tet_elasticity", "fp32"): "fe_k_tet_elast_f32.hip",
+    ("prism_elasticity", "fp64"): "fe_k_prism_elast_f64.hip",
+    ("prism_elasticity", "fp32"): "fe_k_prism_elast_f32.hip",
+}
+
+
+def source_hash(workload: str, precision: str) -> str:
+    """Hash of the sources that define the measured kernel (device code,
+    shared headers, the family's instantiation unit); a stored counter
+    reading is only reused while this matches."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1504_01023_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".h", ".hip", ".cpp")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode())
-                h.update(f.read())
+    for name in ("fe_device.h", "fe_internal.h", "fe_register.h",
+                 KERNEL_UNITS[(workload, precision)]):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
@@ -483,7 +500,7 @@ def main() -> int:
     tol = 1e-12 if a.precision == "fp64" else 2e-5
 
     achieved = bpe * wl.n_elem / avg_kern_s / 1e9
-    shash = source_hash()
+    shash = source_hash(a.workload, a.precision)
     traffic = stored_traffic(a.workload, a.precision, shash)
     cpu = None
     if not a.no_cpu:

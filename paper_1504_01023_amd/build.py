@@ -29,6 +29,10 @@ ARCH = "gfx950"
 CFLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-x", "hip",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # contract a*b+c into FMA only within one expression, so every launch
+    # variant of a kernel (elements per lane, batched or plain) performs the
+    # same rounding sequence per element and gives bitwise identical results
+    "-ffp-contract=on",
     "-fvisibility=hidden", "-Wall", "-Wno-unused-variable", "-Wno-unused-function",
     "-Wno-pass-failed", "-I", INCLUDE, "-I", CSRC,
 ]

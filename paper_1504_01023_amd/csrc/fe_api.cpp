@@ -32,7 +32,7 @@ static bool same_key(const KernelKey &a, const KernelKey &b)
 {
     return a.elem == b.elem && a.kind == b.kind && a.prec == b.prec && a.terms == b.terms &&
            a.mode == b.mode && a.packed == b.packed && a.vec == b.vec && a.nt == b.nt &&
-           a.ref == b.ref && a.nq == b.nq;
+           a.ref == b.ref && a.nq == b.nq && a.split == b.split;
 }
 
 const KernelEntry *find_kernel(const KernelKey &k)
@@ -271,6 +271,7 @@ int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coor
     int vec = v.elems_per_thread ? v.elems_per_thread : (elem == FE_TET4 ? 2 : 1);
     const int nt = (v.nontemporal == 2) ? 0 : 1;
     const int ref = (v.ref_in_lds == 1) ? REF_LDS : REF_KARG;
+    const int split = (v.row_split == 2 || v.row_split == 3) ? v.row_split : 1;
 
     // vector width needs aligned rows
     auto vec_ok = [&](int V) {
@@ -290,6 +291,7 @@ int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coor
     k.vec = vec;
     k.nt = nt;
     k.ref = ref;
+    k.split = split;
     k.nq = rule->n_q;
     const KernelEntry *e = find_kernel(k);
     if (!e) {
@@ -301,13 +303,16 @@ int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coor
         k.vec = 1;
         k.nt = 1;
         k.ref = REF_KARG;
+        k.split = 1;
+        k.nq = 0;
         e = find_kernel(k);
     }
     if (!e)
         return fail(FE_ERR_UNSUPPORTED,
                     "no compiled kernel for elem=%d kind=%d prec=%d terms=%d mode=%d packed=%d "
-                    "vec=%d nt=%d ref=%d nq=%d",
-                    k.elem, k.kind, k.prec, k.terms, k.mode, k.packed, k.vec, k.nt, k.ref, k.nq);
+                    "vec=%d nt=%d ref=%d nq=%d split=%d",
+                    k.elem, k.kind, k.prec, k.terms, k.mode, k.packed, k.vec, k.nt, k.ref, k.nq,
+                    k.split);
 
     KArgs &a = pl.args;
     std::memset(&a, 0, sizeof(a));
@@ -335,7 +340,7 @@ int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coor
         grid = 0x7fffffff;
     pl.grid = (unsigned)(grid > 0 ? grid : 1);
     pl.key = k;
-    pl.variant = fe_variant{wg, k.vec, ref == REF_LDS ? 1 : 2, nt ? 1 : 2, v.blocks};
+    pl.variant = fe_variant{wg, k.vec, ref == REF_LDS ? 1 : 2, nt ? 1 : 2, v.blocks, k.split};
     return FE_OK;
 }
 

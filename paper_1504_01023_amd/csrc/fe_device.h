@@ -874,11 +874,117 @@ struct PrismScalar {
 // + mu delta_ab tr H_rs, and F_(r a) = f_a sum_q vol_q phi_r(xi_q).
 // Coefficients per point: the same expression accumulated point by point
 // with lambda_q, mu_q (and f_q), directly into the packed K.
-template <typename T, int MODE, int PACKED, int NQ>
+//
+// SPLIT = 2 or 3 processes the rows of K in passes over the points (shape
+// functions {0,1},{2..5} or {0},{1,2},{3..5} as test functions), recomputing
+// the Jacobian terms in every pass: the SQS idea of Algorithm 4 used only to
+// bound the live FP64 accumulators (93 or 75 instead of 171) so that more
+// waves fit on a SIMD.
+template <typename T, int MODE, int PACKED, int NQ, int SPLIT = 1>
 struct PrismElastic {
     static constexpr uint32_t SL = 31u;
     static constexpr bool PER_QP = (MODE == M_QP || MODE == M_QP_MIXED);
     static constexpr int NP = 171;  // packed entries of the 18 x 18 matrix
+
+    template <int V, bool NT>
+    __device__ __forceinline__ static void store_block(const Streams &st, int64_t e, int k0,
+                                                       int k1, const T *Kp)
+    {
+        T *outK = static_cast<T *>(st.out_K);
+        if constexpr (PACKED) {
+#pragma unroll
+            for (int k = k0; k < k1; ++k)
+                st1<NT>(outK + k * st.ld_out + e, Kp[k - k0]);
+        } else {
+#pragma unroll
+            for (int row = 0; row < 18; ++row)
+#pragma unroll
+                for (int col = row; col < 18; ++col) {
+                    const int k = pidx(18, row, col);
+                    if (k < k0 || k >= k1)
+                        continue;
+                    st1<NT>(outK + (18 * row + col) * st.ld_out + e, Kp[k - k0]);
+                    if (col != row)
+                        st1<NT>(outK + (18 * col + row) * st.ld_out + e, Kp[k - k0]);
+                }
+        }
+    }
+
+    // Shape functions R0..R1-1 as test functions (rows 3*R0 .. 3*R1-1 of K):
+    // accumulate H over the points, transform to K, store.
+    template <int R0, int R1, bool WITH_F, bool NT, int REF>
+    __device__ __forceinline__ static void const_pass(const KArgs &a, const Streams &st,
+                                                      const Ref<REF> &ref, const double (&X)[18],
+                                                      int64_t e, T lam, T mu, const T (&f)[3])
+    {
+        constexpr int K0 = pidx(18, 3 * R0, 3 * R0);
+        constexpr int K1 = R1 == 6 ? NP : pidx(18, 3 * R1, 3 * R1);
+        T Kp[K1 - K0];
+#pragma unroll
+        for (int k = 0; k < K1 - K0; ++k)
+            Kp[k] = T(0);
+        T sphi[6];
+#pragma unroll
+        for (int r = 0; r < 6; ++r)
+            sphi[r] = T(0);
+        const int nq = NQ > 0 ? NQ : a.n_q;
+#pragma unroll(NQ > 0 ? NQ : 1)
+        for (int q = 0; q < nq; ++q) {
+            T g[6][3], vol;
+            point_geometry<6, T>(X, ref, q, g, vol);
+            if constexpr (WITH_F) {
+#pragma unroll
+                for (int r = 0; r < 6; ++r)
+                    sphi[r] += vol * (T)ref.phi(q, r);
+            }
+#pragma unroll
+            for (int r = R0; r < R1; ++r) {
+                const T u[3] = {vol * g[r][0], vol * g[r][1], vol * g[r][2]};
+#pragma unroll
+                for (int s = r; s < 6; ++s)
+#pragma unroll
+                    for (int al = 0; al < 3; ++al)
+#pragma unroll
+                        for (int be = (s == r ? al : 0); be < 3; ++be)
+                            Kp[pidx(18, 3 * r + al, 3 * s + be) - K0] += u[al] * g[s][be];
+            }
+        }
+        // H -> K block by block, in place
+#pragma unroll
+        for (int r = R0; r < R1; ++r)
+#pragma unroll
+            for (int s = r; s < 6; ++s) {
+                T H[3][3];
+#pragma unroll
+                for (int al = 0; al < 3; ++al)
+#pragma unroll
+                    for (int be = 0; be < 3; ++be) {
+                        if (s == r && be < al)
+                            H[al][be] = Kp[pidx(18, 3 * r + be, 3 * s + al) - K0];
+                        else
+                            H[al][be] = Kp[pidx(18, 3 * r + al, 3 * s + be) - K0];
+                    }
+                const T tr = mu * (H[0][0] + H[1][1] + H[2][2]);
+#pragma unroll
+                for (int al = 0; al < 3; ++al)
+#pragma unroll
+                    for (int be = (s == r ? al : 0); be < 3; ++be) {
+                        T x = lam * H[al][be] + mu * H[be][al];
+                        if (al == be)
+                            x += tr;
+                        Kp[pidx(18, 3 * r + al, 3 * s + be) - K0] = x;
+                    }
+            }
+        store_block<1, NT>(st, e, K0, K1, Kp);
+        if constexpr (WITH_F) {
+            T *outF = static_cast<T *>(st.out_F);
+#pragma unroll
+            for (int r = 0; r < 6; ++r)
+#pragma unroll
+                for (int al = 0; al < 3; ++al)
+                    st1<NT>(outF + (3 * r + al) * st.ld_out + e, f[al] * sphi[r]);
+        }
+    }
 
     template <int V, bool NT, int REF>
     __device__ __forceinline__ static void run(const KArgs &a, const Streams &st, const Ref<REF> &ref,
@@ -890,38 +996,7 @@ struct PrismElastic {
         for (int s = 0; s < 18; ++s)
             X[s] = ld1<NT>(st.coords + s * st.ld_in + e);
         to_edge_vectors<6>(X);
-        T Kp[NP], F[18];
-#pragma unroll
-        for (int k = 0; k < NP; ++k)
-            Kp[k] = T(0);
-#pragma unroll
-        for (int k = 0; k < 18; ++k)
-            F[k] = T(0);
-        const int nq = NQ > 0 ? NQ : a.n_q;
         if constexpr (!PER_QP) {
-            // Kp holds H_rs (r <= s) in the positions of the packed K block
-            // (r, s): entry (3r+a, 3s+b); for r == s only b >= a.
-            T sphi[6];
-#pragma unroll
-            for (int r = 0; r < 6; ++r)
-                sphi[r] = T(0);
-#pragma unroll(NQ > 0 ? NQ : 1)
-            for (int q = 0; q < nq; ++q) {
-                T g[6][3], vol;
-                point_geometry<6, T>(X, ref, q, g, vol);
-#pragma unroll
-                for (int r = 0; r < 6; ++r) {
-                    const T u[3] = {vol * g[r][0], vol * g[r][1], vol * g[r][2]};
-                    sphi[r] += vol * (T)ref.phi(q, r);
-#pragma unroll
-                    for (int s = r; s < 6; ++s)
-#pragma unroll
-                        for (int al = 0; al < 3; ++al)
-#pragma unroll
-                            for (int be = (s == r ? al : 0); be < 3; ++be)
-                                Kp[pidx(18, 3 * r + al, 3 * s + be)] += u[al] * g[s][be];
-                }
-            }
             T E[1], nu[1], f[3][1];
             coef<T, MODE, SL, 1, NT>(a, st, 0, 0, e, E);
             coef<T, MODE, SL, 1, NT>(a, st, 1, 0, e, nu);
@@ -930,38 +1005,27 @@ struct PrismElastic {
                 coef<T, MODE, SL, 1, NT>(a, st, 2 + al, 0, e, f[al]);
             T lam, mu;
             lame<T>(E[0], nu[0], lam, mu);
-            // Transform H -> K block by block, in place.
-#pragma unroll
-            for (int r = 0; r < 6; ++r)
-#pragma unroll
-                for (int s = r; s < 6; ++s) {
-                    T H[3][3];
-#pragma unroll
-                    for (int al = 0; al < 3; ++al)
-#pragma unroll
-                        for (int be = 0; be < 3; ++be) {
-                            if (s == r && be < al)
-                                H[al][be] = Kp[pidx(18, 3 * r + be, 3 * s + al)];
-                            else
-                                H[al][be] = Kp[pidx(18, 3 * r + al, 3 * s + be)];
-                        }
-                    const T tr = mu * (H[0][0] + H[1][1] + H[2][2]);
-#pragma unroll
-                    for (int al = 0; al < 3; ++al)
-#pragma unroll
-                        for (int be = (s == r ? al : 0); be < 3; ++be) {
-                            T x = lam * H[al][be] + mu * H[be][al];
-                            if (al == be)
-                                x += tr;
-                            Kp[pidx(18, 3 * r + al, 3 * s + be)] = x;
-                        }
-                }
-#pragma unroll
-            for (int r = 0; r < 6; ++r)
-#pragma unroll
-                for (int al = 0; al < 3; ++al)
-                    F[3 * r + al] = f[al][0] * sphi[r];
+            const T fv[3] = {f[0][0], f[1][0], f[2][0]};
+            if constexpr (SPLIT == 3) {
+                const_pass<0, 1, true, NT, REF>(a, st, ref, X, e, lam, mu, fv);
+                const_pass<1, 3, false, NT, REF>(a, st, ref, X, e, lam, mu, fv);
+                const_pass<3, 6, false, NT, REF>(a, st, ref, X, e, lam, mu, fv);
+            } else if constexpr (SPLIT == 2) {
+                const_pass<0, 2, true, NT, REF>(a, st, ref, X, e, lam, mu, fv);
+                const_pass<2, 6, false, NT, REF>(a, st, ref, X, e, lam, mu, fv);
+            } else {
+                const_pass<0, 6, true, NT, REF>(a, st, ref, X, e, lam, mu, fv);
+            }
+            return;
         } else {
+            T Kp[NP], F[18];
+#pragma unroll
+            for (int k = 0; k < NP; ++k)
+                Kp[k] = T(0);
+#pragma unroll
+            for (int k = 0; k < 18; ++k)
+                F[k] = T(0);
+            const int nq = NQ > 0 ? NQ : a.n_q;
 #pragma unroll(NQ > 0 ? NQ : 1)
             for (int q = 0; q < nq; ++q) {
                 T E[1], nu[1], f[3][1];
@@ -996,25 +1060,12 @@ struct PrismElastic {
                     }
                 }
             }
+            store_block<1, NT>(st, e, 0, NP, Kp);
+            T *outF = static_cast<T *>(st.out_F);
+#pragma unroll
+            for (int k = 0; k < 18; ++k)
+                st1<NT>(outF + k * st.ld_out + e, F[k]);
         }
-        T *outK = static_cast<T *>(st.out_K);
-        if constexpr (PACKED) {
-#pragma unroll
-            for (int k = 0; k < NP; ++k)
-                st1<NT>(outK + k * st.ld_out + e, Kp[k]);
-        } else {
-#pragma unroll
-            for (int row = 0; row < 18; ++row)
-#pragma unroll
-                for (int col = 0; col < 18; ++col) {
-                    const int k = col >= row ? pidx(18, row, col) : pidx(18, col, row);
-                    st1<NT>(outK + (18 * row + col) * st.ld_out + e, Kp[k]);
-                }
-        }
-        T *outF = static_cast<T *>(st.out_F);
-#pragma unroll
-        for (int k = 0; k < 18; ++k)
-            st1<NT>(outF + k * st.ld_out + e, F[k]);
     }
 };
 

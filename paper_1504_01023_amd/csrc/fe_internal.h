@@ -86,6 +86,7 @@ struct KernelKey {
     int nt;        // non-temporal memory operations
     int ref;       // RefKind
     int nq;        // compiled point count, 0 = runtime loop
+    int split;     // passes over the points (row split of K), 1 or 2
 };
 
 typedef void (*LaunchFn)(const KArgs &, unsigned grid, unsigned block, hipStream_t);

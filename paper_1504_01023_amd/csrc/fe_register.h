@@ -10,9 +10,9 @@ namespace fe {
 // Registers the plain kernel; kinds that serve batched (persistent) launches
 // also register the batched form (B = 1).
 template <class P, int V, int NT, int REF, int B = 0>
-inline void reg(int elem, int kind, int prec, int terms, int mode, int packed, int nq)
+inline void reg(int elem, int kind, int prec, int terms, int mode, int packed, int nq, int split = 1)
 {
-    KernelKey k{elem, kind, prec, terms, mode, packed, V, NT, REF, nq};
+    KernelKey k{elem, kind, prec, terms, mode, packed, V, NT, REF, nq, split};
     BatchLaunchFn bl = nullptr;
     if constexpr (B != 0)
         bl = &launch_fe_batch_kernel<P, V, NT != 0, REF>;
@@ -44,11 +44,11 @@ inline void reg_prism_scalar()
                                                          TERMS, MODE, PK, NQ);
 }
 
-template <typename T, int MODE, int PK, int NQ, int NT, int REF, int B = 0>
+template <typename T, int MODE, int PK, int NQ, int NT, int REF, int B = 0, int SPLIT = 1>
 inline void reg_prism_elastic()
 {
-    reg<PrismElastic<T, MODE, PK, NQ>, 1, NT, REF, B>(FE_PRISM6, FE_ELASTICITY, prec_of<T>(), TS_ELAST,
-                                                   MODE, PK, NQ);
+    reg<PrismElastic<T, MODE, PK, NQ, SPLIT>, 1, NT, REF, B>(FE_PRISM6, FE_ELASTICITY, prec_of<T>(),
+                                                             TS_ELAST, MODE, PK, NQ, SPLIT);
 }
 
 }  // namespace fe

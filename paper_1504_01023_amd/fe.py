@@ -49,10 +49,11 @@ class QuadRule(ctypes.Structure):
 class Variant(ctypes.Structure):
     _fields_ = [("wg_size", ctypes.c_int32), ("elems_per_thread", ctypes.c_int32),
                 ("ref_in_lds", ctypes.c_int32), ("nontemporal", ctypes.c_int32),
-                ("blocks", ctypes.c_int32)]
+                ("blocks", ctypes.c_int32), ("row_split", ctypes.c_int32)]
 
     def as_tuple(self):
-        return (self.wg_size, self.elems_per_thread, self.ref_in_lds, self.nontemporal, self.blocks)
+        return (self.wg_size, self.elems_per_thread, self.ref_in_lds, self.nontemporal, self.blocks,
+                self.row_split)
 
 
 class FeError(RuntimeError):
@@ -168,8 +169,9 @@ def k_index(p: Problem, elem, row: int, col: int) -> int:
     return int(lib().fe_k_index(ctypes.byref(p), ELEM.get(elem, elem), row, col))
 
 
-def variant(wg_size=0, elems_per_thread=0, ref_in_lds=0, nontemporal=0, blocks=0) -> Variant:
-    return Variant(wg_size, elems_per_thread, ref_in_lds, nontemporal, blocks)
+def variant(wg_size=0, elems_per_thread=0, ref_in_lds=0, nontemporal=0, blocks=0,
+            row_split=0) -> Variant:
+    return Variant(wg_size, elems_per_thread, ref_in_lds, nontemporal, blocks, row_split)
 
 
 # ------------------------------------------------------------------- execution

@@ -30,8 +30,9 @@ def test_small_parity(name, precision):
 
 
 VARIANTS = [
-    dict(wg_size=wg, elems_per_thread=v, nontemporal=nt, ref_in_lds=ref, blocks=b)
+    dict(wg_size=wg, elems_per_thread=v, nontemporal=nt, ref_in_lds=ref, blocks=b, row_split=sp)
     for wg in (64, 128, 256) for v in (1, 2, 4) for nt in (1, 2) for ref in (1, 2) for b in (0, 7)
+    for sp in (1, 2, 3)
 ]
 
 
@@ -197,3 +198,39 @@ def test_stream_copy():
     fe.stream_copy(y, x)
     torch.cuda.synchronize()
     assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("name", ["tet_poisson", "tet_cdr", "tet_elasticity", "prism_cdr_qp",
+                                  "prism_elasticity"])
+def test_variants_are_bitwise_identical(name):
+    """Every compiled variant of a family (elements per lane, cache policy,
+    reference-table placement, workgroup and grid shape, row split) performs
+    the same per-element rounding sequence, so all outputs agree bit for bit
+    (on an odd element count, which also exercises the partial last group)."""
+    wl = P.small(name)
+    n = wl.n_elem - (1 - wl.n_elem % 2)
+    dw = fe.to_device(wl, "fp64")
+    ld = (wl.n_elem + 3) // 4 * 4
+    c = torch.zeros((dw.coords.shape[0], ld), dtype=torch.float64, device="cuda")
+    c[:, :wl.n_elem] = dw.coords
+    k = None
+    if dw.coeffs is not None:
+        k = torch.zeros((dw.coeffs.shape[0], ld), dtype=dw.coeffs.dtype, device="cuda")
+        k[:, :wl.n_elem] = dw.coeffs
+    nk, nf = fe.k_entries(dw.problem, wl.elem), fe.f_entries(dw.problem, wl.elem)
+    ref = None
+    for kw in VARIANTS:
+        K = torch.full((nk, ld), 7.0, dtype=torch.float64, device="cuda")
+        F = torch.full((nf, ld), 7.0, dtype=torch.float64, device="cuda")
+        try:
+            fe.integrate(dw.problem, wl.elem, c, k, dw.rule, out_K=K, out_F=F, n_elem=n,
+                         variant=fe.variant(**kw))
+        except fe.FeError as e:
+            assert e.status == 2
+            continue
+        torch.cuda.synchronize()
+        assert torch.all(K[:, n:] == 7.0) and torch.all(F[:, n:] == 7.0)
+        if ref is None:
+            ref = (K, F)
+        else:
+            assert torch.equal(K, ref[0]) and torch.equal(F, ref[1]), kw

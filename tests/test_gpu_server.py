@@ -116,7 +116,9 @@ def test_served_mix_matches_oracle_and_is_identical_alone():
         ci[:, :n] = dw.coords
         ki = torch.zeros((dw.coeffs.shape[0], ld), dtype=dw.coeffs.dtype, device="cuda")
         ki[:, :n] = dw.coeffs
-        K2, F2 = fe.integrate(dw.problem, wl.elem, ci, ki, dw.rule, n_elem=n)
+        K2 = torch.empty_like(K)
+        F2 = torch.empty_like(F)
+        fe.integrate(dw.problem, wl.elem, ci, ki, dw.rule, out_K=K2, out_F=F2, n_elem=n)
         torch.cuda.synchronize()
         assert torch.equal(K2[:, :n], K[:, :n]) and torch.equal(F2[:, :n], F[:, :n])
     for _, (kind, wl, prec, K, F, ld) in alone.items():

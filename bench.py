@@ -3,7 +3,7 @@
 
 Default workload (the headline one): scalar Poisson (c^{i;j} = identity,
 d^0 = 1) on the jittered unit cube with N = 119 cells per side split into
-6 Kuhn tetrahedra (10,111,074 elements, seed 1), 1-point rule, packed 4x4 K
+6 Kuhn tetrahedra (10,110,954 elements, seed 1), 1-point rule, packed 4x4 K
 and 4-vector F, FP64. One "step" is one fe_integrate call over the whole
 mesh with inputs already resident in HBM.
 
@@ -40,7 +40,7 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E peak, vendor figure
 WORKLOADS = {
     # name: (builder, description)
     "tet_poisson": (lambda: __import__("paper_1504_01023_amd.inputs", fromlist=["x"]).tet_poisson(119, 1),
-                    "Poisson on jittered unit cube N=119 x 6 Kuhn tets (10,111,074), tet 1-point rule, packed K"),
+                    "Poisson on jittered unit cube N=119 x 6 Kuhn tets (10,110,954), tet 1-point rule, packed K"),
     "tet_poisson_qp": (lambda: __import__("paper_1504_01023_amd.inputs", fromlist=["x"]).tet_poisson_qp_rhs(119, 1),
                        "Poisson with d^0 per point of the tet 4-point rule, full K (36 words/element), N=119"),
     "tet_cdr": (lambda: __import__("paper_1504_01023_amd.inputs", fromlist=["x"]).tet_cdr(119, 2),
@@ -374,7 +374,8 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="tet_poisson", choices=sorted(WORKLOADS) + ["served"])
+    ap.add_argument("--workload", default="tet_poisson",
+                    choices=sorted(WORKLOADS) + [w + "_indexed" for w in sorted(WORKLOADS)] + ["served"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--tune", action="store_true",
                     help="run the exhaustive variant search (fe_autotune) during warm-up")
@@ -423,8 +424,10 @@ def main() -> int:
         print(json.dumps(line), flush=True)
         return 0
 
+    indexed = a.workload.endswith("_indexed")
+    base = a.workload[: -len("_indexed")] if indexed else a.workload
     t0 = time.time()
-    wl = WORKLOADS[a.workload][0]()
+    wl = WORKLOADS[base][0]()
     log(f"[bench] generated {a.workload}: {wl.n_elem} elements in {time.time() - t0:.1f}s")
     dw = fe.to_device(wl, a.precision, device=dev)
     p, rule = dw.problem, dw.rule
@@ -434,6 +437,19 @@ def main() -> int:
     F = torch.empty((nf, wl.n_elem), dtype=dt, device=dev)
     bpe = fe.bytes_per_element(p, wl.elem, rule.n_q)
     stream = torch.cuda.current_stream()
+    nv = 4 if wl.elem == "tet4" else 6
+    if indexed:
+        # per element: connectivity (4 B per vertex) instead of 24 B per vertex
+        # of coordinates, plus every node's 24 B read once
+        nodes = torch.from_numpy(wl.mesh.nodes).to(dev).contiguous()
+        conn = torch.from_numpy(np.ascontiguousarray(wl.mesh.conn.T.astype(np.int32))).to(dev)
+        bpe = bpe - 24 * nv + 4 * nv + 24.0 * wl.mesh.nodes.shape[0] / wl.n_elem
+
+    def step():
+        if indexed:
+            fe.integrate_indexed(p, wl.elem, nodes, conn, dw.coeffs, rule, out_K=K, out_F=F)
+        else:
+            fe.integrate(p, wl.elem, dw.coords, dw.coeffs, rule, out_K=K, out_F=F)
 
     if a.tuning_file and os.path.exists(a.tuning_file):
         fe.tuning_load(a.tuning_file)
@@ -445,7 +461,7 @@ def main() -> int:
     variant_used = fe.tuning_get(p, wl.elem, rule.n_q)
 
     for _ in range(a.warmup):
-        fe.integrate(p, wl.elem, dw.coords, dw.coeffs, rule, out_K=K, out_F=F)
+        step()
     torch.cuda.synchronize()
 
     # copy ceiling on the same byte volume (context for the roofline)
@@ -470,7 +486,7 @@ def main() -> int:
     w0 = time.perf_counter()
     for i in range(a.steps):
         starts[i].record(stream)
-        fe.integrate(p, wl.elem, dw.coords, dw.coeffs, rule, out_K=K, out_F=F)
+        step()
         ends[i].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
@@ -500,7 +516,7 @@ def main() -> int:
     tol = 1e-12 if a.precision == "fp64" else 2e-5
 
     achieved = bpe * wl.n_elem / avg_kern_s / 1e9
-    shash = source_hash(a.workload, a.precision)
+    shash = source_hash(base, a.precision)
     traffic = stored_traffic(a.workload, a.precision, shash)
     cpu = None
     if not a.no_cpu:
@@ -520,7 +536,9 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f64" if a.precision == "fp64" else "f32 (FP64 Jacobian)",
         "data": "synthetic",
-        "config": {"workload": a.workload, "description": WORKLOADS[a.workload][1],
+        "config": {"workload": a.workload,
+                   "description": WORKLOADS[base][1] + (" (indexed geometry: node array + int32 "
+                                                        "connectivity)" if indexed else ""),
                    "n_elem": wl.n_elem, "precision": a.precision, "n_q": rule.n_q,
                    "k_format": wl.k_format, "bytes_per_element": bpe,
                    "variant_wg_vec_ref_nt_blocks": variant_used, "parallelism": "single GPU"},

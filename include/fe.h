@@ -160,6 +160,20 @@ FE_API int fe_integrate_ex(const fe_problem *problem, fe_elem_type elem_type, in
                            const fe_quad_rule *quad_rule, void *out_K, void *out_F, int64_t ld_out,
                            const fe_variant *variant, hipStream_t stream);
 
+/* Indexed geometry: the geometry degrees of freedom of Sec. 2.3 given as a
+ * global node array nodes[3 * id + d] (FP64, n_nodes nodes) and int32
+ * connectivity conn[v * ld_conn + e] (local vertex v of element e), instead
+ * of coordinates duplicated per element. Coefficients (leading dimension
+ * ld_in; pass n_elem when none are read) and outputs are laid out as for
+ * fe_integrate_ex. Node ids outside [0, n_nodes) are clamped to the range
+ * (those elements' results are then meaningless, but nothing faults). */
+FE_API int fe_integrate_indexed(const fe_problem *problem, fe_elem_type elem_type,
+                                int64_t n_elem, const double *nodes, int64_t n_nodes,
+                                const int32_t *conn, int64_t ld_conn, const void *coeffs,
+                                int64_t ld_in, const fe_quad_rule *quad_rule, void *out_K,
+                                void *out_F, int64_t ld_out, const fe_variant *variant,
+                                hipStream_t stream);
+
 /* ---------------------------------------------------------------------
  * Sizes and accounting (Sec. 4.1, table "memory_requirements"; Sec. 4.4,
  * table "accesses_and_operations"). Each returns -1 on invalid input.

@@ -212,7 +212,8 @@ static bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 // ---------------------------------------------------------------- planning
 int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coords,
          const void *coeffs, int64_t ld_in, const fe_quad_rule *rule, void *out_K, void *out_F,
-         int64_t ld_out, const fe_variant *variant, Plan &pl)
+         int64_t ld_out, const fe_variant *variant, Plan &pl, int form, const int32_t *conn,
+         int64_t ld_conn)
 {
     int st = check_problem(problem, elem);
     if (st)
@@ -224,9 +225,13 @@ int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coor
     if ((st = check_symmetry(problem)))
         return st;
     const uint32_t mask = effective_mask(problem);
+    if (form == 1)
+        coords = nullptr;  // indexed geometry: no per-element coordinates
     if (n_elem > 0) {
-        if (!coords || !out_K || !out_F)
-            return fail(FE_ERR_INVALID_ARG, "NULL coordinates or output pointer");
+        if ((form == 0 && !coords) || (form == 1 && !conn) || !out_K || !out_F)
+            return fail(FE_ERR_INVALID_ARG, "NULL coordinates, connectivity or output pointer");
+        if (form == 1 && ld_conn < n_elem)
+            return fail(FE_ERR_INVALID_ARG, "connectivity leading dimension smaller than n_elem");
         if (mask && !coeffs)
             return fail(FE_ERR_INVALID_ARG, "coeffs is NULL but coef_mask reads %u slots",
                         (unsigned)__builtin_popcount(mask));
@@ -235,7 +240,7 @@ int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coor
     }
     const size_t tsz = problem->precision == FE_FP64 ? 8 : 4;
     if (!aligned(coords, 8) || !aligned(out_K, tsz) || !aligned(out_F, tsz) ||
-        (mask && !aligned(coeffs, tsz)))
+        (mask && !aligned(coeffs, tsz)) || !aligned(conn, 4))
         return fail(FE_ERR_UNSUPPORTED, "pointers must be aligned to their element size");
 
     KernelKey k{};
@@ -280,6 +285,9 @@ int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coor
         if (ld_in % V || ld_out % V)
             return false;
         const size_t ca = std::min<size_t>(16, 8 * V), ta = std::min<size_t>(16, tsz * V);
+        const size_t ia = std::min<size_t>(16, 4 * V);
+        if (form == 1 && (ld_conn % V || !aligned(conn, ia)))
+            return false;
         return aligned(coords, ca) && aligned(out_K, ta) && aligned(out_F, ta) &&
                (!mask || aligned(coeffs, ta));
     };
@@ -293,12 +301,13 @@ int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coor
     k.ref = ref;
     k.split = split;
     k.nq = rule->n_q;
+    auto usable = [&](const KernelEntry *x) { return x && (form == 0 || x->idx != nullptr); };
     const KernelEntry *e = find_kernel(k);
-    if (!e) {
+    if (!usable(e)) {
         k.nq = 0;
         e = find_kernel(k);
     }
-    if (!e && !forced) {
+    if (!usable(e) && !forced) {
         // fall back to the always-built base variant
         k.vec = 1;
         k.nt = 1;
@@ -307,6 +316,8 @@ int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coor
         k.nq = 0;
         e = find_kernel(k);
     }
+    if (!usable(e))
+        e = nullptr;
     if (!e)
         return fail(FE_ERR_UNSUPPORTED,
                     "no compiled kernel for elem=%d kind=%d prec=%d terms=%d mode=%d packed=%d "
@@ -355,6 +366,17 @@ int launch(const Plan &pl, hipStream_t stream)
     return FE_OK;
 }
 
+int launch_indexed(const Plan &pl, const IdxArgs &gi, hipStream_t stream)
+{
+    if (pl.args.n_elem == 0)
+        return FE_OK;
+    pl.entry->idx(pl.args, gi, pl.grid, pl.block, stream);
+    const hipError_t err = hipGetLastError();
+    if (err != hipSuccess)
+        return fail(FE_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(err));
+    return FE_OK;
+}
+
 }  // namespace fe
 
 using namespace fe;
@@ -373,6 +395,25 @@ int fe_integrate_ex(const fe_problem *problem, fe_elem_type elem_type, int64_t n
     if (st)
         return st;
     return launch(pl, stream);
+}
+
+int fe_integrate_indexed(const fe_problem *problem, fe_elem_type elem_type, int64_t n_elem,
+                         const double *nodes, int64_t n_nodes, const int32_t *conn,
+                         int64_t ld_conn, const void *coeffs, int64_t ld_in,
+                         const fe_quad_rule *quad_rule, void *out_K, void *out_F, int64_t ld_out,
+                         const fe_variant *variant, hipStream_t stream)
+{
+    if (n_elem > 0 && (!nodes || n_nodes < 1 || n_nodes > 0x7fffffffLL))
+        return fail(FE_ERR_INVALID_ARG, "need a node array with 1 .. 2^31-1 nodes");
+    if (nodes && ((uintptr_t)nodes % 8))
+        return fail(FE_ERR_UNSUPPORTED, "nodes must be 8-byte aligned");
+    Plan pl;
+    int st = plan(problem, elem_type, n_elem, nullptr, coeffs, ld_in, quad_rule, out_K, out_F,
+                  ld_out, variant, pl, 1, conn, ld_conn);
+    if (st)
+        return st;
+    IdxArgs gi{nodes, conn, ld_conn, (uint32_t)n_nodes};
+    return launch_indexed(pl, gi, stream);
 }
 
 int fe_integrate(const fe_problem *problem, fe_elem_type elem_type, int64_t n_elem,

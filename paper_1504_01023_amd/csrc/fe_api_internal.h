@@ -18,9 +18,13 @@ struct Plan {
 
 int fail(int status, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 
+// form: 0 = plain launch (coordinates per element), 1 = indexed geometry
+// (coordinates gathered through connectivity; `coords` is ignored and the
+// element-group alignment applies to the connectivity array instead).
 int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coords,
          const void *coeffs, int64_t ld_in, const fe_quad_rule *rule, void *out_K, void *out_F,
-         int64_t ld_out, const fe_variant *variant, Plan &pl);
+         int64_t ld_out, const fe_variant *variant, Plan &pl, int form = 0,
+         const int32_t *conn = nullptr, int64_t ld_conn = 0);
 int launch(const Plan &pl, hipStream_t stream);
 void fill_reference(int elem, const fe_quad_rule &rule, KArgs &a);
 

@@ -125,6 +125,22 @@ int fe_batch_create(const fe_batch_kind *kinds, int n_kinds, int max_chunks, int
             return st;
         }
         if (!K.plan.entry->batch) {
+            // The tuned variant has no batched form: keep its workgroup and
+            // width with streaming memory operations, else the base variant.
+            const fe_variant tuned = K.plan.variant;
+            const fe_variant alts[2] = {
+                {tuned.wg_size, tuned.elems_per_thread, tuned.ref_in_lds, 1, 0, tuned.row_split},
+                {256, 1, 2, 1, 0, 1}};
+            for (const fe_variant &v : alts) {
+                Plan alt;
+                if (plan(&bk.problem, bk.elem_type, 0, nullptr, nullptr, 0, &rule, nullptr, nullptr,
+                         0, &v, alt) == FE_OK && alt.entry->batch) {
+                    K.plan = alt;
+                    break;
+                }
+            }
+        }
+        if (!K.plan.entry->batch) {
             destroy_batch(b);
             return fail(FE_ERR_UNSUPPORTED, "kind %d has no batched kernel (elem=%d kind=%d mode=%d)",
                         k, K.plan.key.elem, K.plan.key.kind, K.plan.key.mode);

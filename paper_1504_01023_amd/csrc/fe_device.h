@@ -91,6 +91,27 @@ __device__ __forceinline__ void loadv(const float *p, float (&v)[V])
     }
 }
 
+typedef int int2_t __attribute__((ext_vector_type(2)));
+typedef int int4_t __attribute__((ext_vector_type(4)));
+
+template <int V, bool NT>
+__device__ __forceinline__ void loadv(const int32_t *p, int32_t (&v)[V])
+{
+    if constexpr (V == 1) {
+        v[0] = ld1<NT>(p);
+    } else if constexpr (V == 2) {
+        const int2_t x = ld1<NT>(reinterpret_cast<const int2_t *>(p));
+        v[0] = x.x;
+        v[1] = x.y;
+    } else {
+        const int4_t x = ld1<NT>(reinterpret_cast<const int4_t *>(p));
+        v[0] = x.x;
+        v[1] = x.y;
+        v[2] = x.z;
+        v[3] = x.w;
+    }
+}
+
 template <int V, bool NT>
 __device__ __forceinline__ void storev(double *p, const double (&v)[V])
 {
@@ -138,6 +159,51 @@ struct Streams {
     void *out_F;
     int64_t ld_in;
     int64_t ld_out;
+
+    // Vertex coordinates of V consecutive elements: X[i][3 v + d].
+    template <int NV, int V, bool NT>
+    __device__ __forceinline__ void load_coords(int64_t e0, double (&X)[V][3 * NV]) const
+    {
+#pragma unroll
+        for (int s = 0; s < 3 * NV; ++s) {
+            double t[V];
+            loadv<V, NT>(coords + s * ld_in + e0, t);
+#pragma unroll
+            for (int i = 0; i < V; ++i)
+                X[i][s] = t[i];
+        }
+    }
+};
+
+// Indexed geometry: vertex coordinates gathered from a global node array
+// nodes[3 * id + d] through connectivity conn[v * ld_conn + e] (int32).
+// Neighbouring elements share nodes, so after the first touch the gathers
+// are served by L2 / MALL and HBM sees each node about once.
+struct StreamsIdx : Streams {
+    const double *nodes;
+    const int32_t *conn;
+    int64_t ld_conn;
+    uint32_t n_nodes;
+
+    template <int NV, int V, bool NT>
+    __device__ __forceinline__ void load_coords(int64_t e0, double (&X)[V][3 * NV]) const
+    {
+        int32_t id[NV][V];
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            loadv<V, NT>(conn + v * ld_conn + e0, id[v]);
+#pragma unroll
+        for (int i = 0; i < V; ++i)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                // out-of-range ids are clamped: never a fault, whatever the input
+                const uint32_t u = (uint32_t)id[v][i];
+                const double *p = nodes + 3 * (int64_t)(u < n_nodes ? u : n_nodes - 1);
+                X[i][3 * v + 0] = p[0];
+                X[i][3 * v + 1] = p[1];
+                X[i][3 * v + 2] = p[2];
+            }
+    }
 };
 
 // ------------------------------------------------------------ small helpers
@@ -313,19 +379,12 @@ struct TetScalar {
                           MASS = TERMS & T_MASS, DG = TERMS & T_DGRAD, D0 = TERMS & T_D0;
     static constexpr bool PER_QP = (MODE == M_QP || MODE == M_QP_MIXED);
 
-    template <int V, bool NT, int REF>
-    __device__ __forceinline__ static void run(const KArgs &a, const Streams &st, const Ref<REF> &ref,
+    template <int V, bool NT, int REF, class S>
+    __device__ __forceinline__ static void run(const KArgs &a, const S &st, const Ref<REF> &ref,
                                                int64_t e0)
     {
         double X[V][12];
-#pragma unroll
-        for (int s = 0; s < 12; ++s) {
-            double t[V];
-            loadv<V, NT>(st.coords + s * st.ld_in + e0, t);
-#pragma unroll
-            for (int i = 0; i < V; ++i)
-                X[i][s] = t[i];
-        }
+        st.template load_coords<4, V, NT>(e0, X);
         if constexpr (!PER_QP)
             run_const<V, NT>(a, st, X, e0);
         else
@@ -601,19 +660,12 @@ struct TetElastic {
     static constexpr uint32_t SL = 31u;
     static constexpr bool PER_QP = (MODE == M_QP || MODE == M_QP_MIXED);
 
-    template <int V, bool NT, int REF>
-    __device__ __forceinline__ static void run(const KArgs &a, const Streams &st, const Ref<REF> &ref,
+    template <int V, bool NT, int REF, class S>
+    __device__ __forceinline__ static void run(const KArgs &a, const S &st, const Ref<REF> &ref,
                                                int64_t e0)
     {
         double X[V][12];
-#pragma unroll
-        for (int s = 0; s < 12; ++s) {
-            double t[V];
-            loadv<V, NT>(st.coords + s * st.ld_in + e0, t);
-#pragma unroll
-            for (int i = 0; i < V; ++i)
-                X[i][s] = t[i];
-        }
+        st.template load_coords<4, V, NT>(e0, X);
         T lb[V], mb[V], fb[V][4][3];
         if constexpr (!PER_QP) {
             T E[V], nu[V], f[3][V];
@@ -782,15 +834,17 @@ struct PrismScalar {
         }
     }
 
-    template <int V, bool NT, int REF>
-    __device__ __forceinline__ static void run(const KArgs &a, const Streams &st, const Ref<REF> &ref,
+    template <int V, bool NT, int REF, class S>
+    __device__ __forceinline__ static void run(const KArgs &a, const S &st, const Ref<REF> &ref,
                                                int64_t e)
     {
         static_assert(V == 1, "prisms are processed one element per lane");
+        double Xg[1][18];
+        st.template load_coords<6, 1, NT>(e, Xg);
         double X[18];
 #pragma unroll
         for (int s = 0; s < 18; ++s)
-            X[s] = ld1<NT>(st.coords + s * st.ld_in + e);
+            X[s] = Xg[0][s];
         to_edge_vectors<6>(X);
         constexpr int NK = PACKED ? 21 : 36;
         T K[NK], F[6];
@@ -986,15 +1040,17 @@ struct PrismElastic {
         }
     }
 
-    template <int V, bool NT, int REF>
-    __device__ __forceinline__ static void run(const KArgs &a, const Streams &st, const Ref<REF> &ref,
+    template <int V, bool NT, int REF, class S>
+    __device__ __forceinline__ static void run(const KArgs &a, const S &st, const Ref<REF> &ref,
                                                int64_t e)
     {
         static_assert(V == 1, "prisms are processed one element per lane");
+        double Xg[1][18];
+        st.template load_coords<6, 1, NT>(e, Xg);
         double X[18];
 #pragma unroll
         for (int s = 0; s < 18; ++s)
-            X[s] = ld1<NT>(st.coords + s * st.ld_in + e);
+            X[s] = Xg[0][s];
         to_edge_vectors<6>(X);
         if constexpr (!PER_QP) {
             T E[1], nu[1], f[3][1];
@@ -1146,6 +1202,53 @@ void launch_fe_batch_kernel(const KArgs &a, const BatchHeader *hdr, const Chunk 
 {
     hipLaunchKernelGGL((fe_batch_kernel<P, V, NT, REF>), dim3(grid), dim3(block), 0, stream, a, hdr,
                        chunks, kind);
+}
+
+// Indexed-geometry form of fe_kernel.
+template <class P, int V, bool NT, int REF>
+__global__ __launch_bounds__(256) void fe_kernel_idx(KArgs a, IdxArgs gi)
+{
+    __shared__ RefLds lds_ref[1];
+    if constexpr (REF == REF_LDS) {
+        const int n_w = a.n_q, n_phi = a.n_q * 6, n_dphi = a.n_q * 18;
+        for (int i = threadIdx.x; i < n_w; i += blockDim.x)
+            lds_ref[0].w[i] = a.w[i];
+        for (int i = threadIdx.x; i < n_phi; i += blockDim.x)
+            (&lds_ref[0].phi[0][0])[i] = (&a.phi[0][0])[i];
+        for (int i = threadIdx.x; i < n_dphi; i += blockDim.x)
+            (&lds_ref[0].dphi[0][0][0])[i] = (&a.dphi[0][0][0])[i];
+        __syncthreads();
+    }
+    const Ref<REF> ref{a, &lds_ref[0]};
+    StreamsIdx st;
+    st.coords = nullptr;
+    st.coeffs = a.coeffs;
+    st.out_K = a.out_K;
+    st.out_F = a.out_F;
+    st.ld_in = a.ld_in;
+    st.ld_out = a.ld_out;
+    st.nodes = gi.nodes;
+    st.conn = gi.conn;
+    st.ld_conn = gi.ld_conn;
+    st.n_nodes = gi.n_nodes;
+    const int64_t n_groups = (a.n_elem + V - 1) / V;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_groups; g += stride) {
+        const int64_t e0 = g * V;
+        if (V == 1 || e0 + V <= a.n_elem) {
+            P::template run<V, NT, REF>(a, st, ref, e0);
+        } else {
+            for (int64_t e = e0; e < a.n_elem; ++e)
+                P::template run<1, NT, REF>(a, st, ref, e);
+        }
+    }
+}
+
+template <class P, int V, bool NT, int REF>
+void launch_fe_kernel_idx(const KArgs &a, const IdxArgs &gi, unsigned grid, unsigned block,
+                          hipStream_t stream)
+{
+    hipLaunchKernelGGL((fe_kernel_idx<P, V, NT, REF>), dim3(grid), dim3(block), 0, stream, a, gi);
 }
 
 template <class P, int V, bool NT, int REF>

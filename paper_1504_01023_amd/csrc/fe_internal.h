@@ -112,11 +112,23 @@ struct BatchHeader {
 typedef void (*BatchLaunchFn)(const KArgs &, const BatchHeader *, const Chunk *, int kind,
                               unsigned grid, unsigned block, hipStream_t);
 
+// Indexed geometry: coordinates gathered from a node array through
+// connectivity instead of being duplicated per element.
+struct IdxArgs {
+    const double *nodes;   // [3 * id + d]
+    const int32_t *conn;   // [v * ld_conn + e]
+    int64_t ld_conn;
+    uint32_t n_nodes;      // ids are clamped to [0, n_nodes)
+};
+typedef void (*IdxLaunchFn)(const KArgs &, const IdxArgs &, unsigned grid, unsigned block,
+                            hipStream_t);
+
 struct KernelEntry {
     KernelKey key;
     LaunchFn launch;
     const void *func;
     BatchLaunchFn batch;  // persistent batched form, or nullptr
+    IdxLaunchFn idx;      // indexed-geometry form, or nullptr
 };
 
 // Registration of compiled kernels (each kernel translation unit registers

@@ -16,7 +16,7 @@ int register_all()
     // tuning variants: elements per lane and cache policy
 #define TUNE(MODE, PK) \
     reg_tet_scalar<T, TS, MODE, PK, 2, 1, 1>(); reg_tet_scalar<T, TS, MODE, PK, 4, 1>(); \
-    reg_tet_scalar<T, TS, MODE, PK, 1, 0>(); reg_tet_scalar<T, TS, MODE, PK, 2, 0>(); \
+    reg_tet_scalar<T, TS, MODE, PK, 1, 0>(); reg_tet_scalar<T, TS, MODE, PK, 2, 0, 1>(); \
     reg_tet_scalar<T, TS, MODE, PK, 4, 0>();
     TUNE(M_UNIFORM, 1) TUNE(M_UNIFORM, 0) TUNE(M_ELEM, 0) TUNE(M_ELEM, 1) TUNE(M_QP, 0)
 #undef TUNE

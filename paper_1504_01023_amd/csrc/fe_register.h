@@ -7,17 +7,21 @@
 
 namespace fe {
 
-// Registers the plain kernel; kinds that serve batched (persistent) launches
-// also register the batched form (B = 1).
+// Registers the plain kernel; B = 1 also registers the batched (persistent)
+// form and the indexed-geometry form.
 template <class P, int V, int NT, int REF, int B = 0>
 inline void reg(int elem, int kind, int prec, int terms, int mode, int packed, int nq, int split = 1)
 {
     KernelKey k{elem, kind, prec, terms, mode, packed, V, NT, REF, nq, split};
     BatchLaunchFn bl = nullptr;
-    if constexpr (B != 0)
+    IdxLaunchFn il = nullptr;
+    if constexpr (B != 0) {
         bl = &launch_fe_batch_kernel<P, V, NT != 0, REF>;
+        il = &launch_fe_kernel_idx<P, V, NT != 0, REF>;
+    }
     register_kernel(KernelEntry{k, &launch_fe_kernel<P, V, NT != 0, REF>,
-                                reinterpret_cast<const void *>(&fe_kernel<P, V, NT != 0, REF>), bl});
+                                reinterpret_cast<const void *>(&fe_kernel<P, V, NT != 0, REF>), bl,
+                                il});
 }
 
 template <typename T>

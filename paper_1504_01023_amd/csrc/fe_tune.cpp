@@ -167,8 +167,9 @@ int fe_autotune(const fe_problem *problem, fe_elem_type elem_type, int64_t n_ele
         return st;
     if (n_elem == 0)
         return fail(FE_ERR_INVALID_ARG, "cannot tune on an empty batch");
-    // Candidate variants: every compiled (vec, nt, ref) of this family, times
-    // workgroup sizes and grid shapes.
+    // Candidate variants: every compiled (vec, nt, ref, split) of this family,
+    // times workgroup sizes and grid shapes (one group per lane, or a
+    // persistent grid of 512..8192 workgroups).
     std::set<std::tuple<int, int, int, int>> shapes;
     for (int i = 0; i < kernel_count(); ++i) {
         const KernelKey &k = kernel_at(i)->key;
@@ -183,7 +184,7 @@ int fe_autotune(const fe_problem *problem, fe_elem_type elem_type, int64_t n_ele
     double best_t = 1e300;
     fe_variant best_v{};
     const int wgs[3] = {64, 128, 256};
-    const int grids[3] = {0, 2048, 8192};
+    const int grids[6] = {0, 512, 1024, 2048, 4096, 8192};
     for (const auto &sh : shapes) {
         for (int wg : wgs) {
             for (int gb : grids) {

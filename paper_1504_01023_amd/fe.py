@@ -96,6 +96,8 @@ def lib():
         L.fe_tuning_save.argtypes = [ctypes.c_char_p]
         L.fe_tuning_load.argtypes = [ctypes.c_char_p]
         L.fe_stream_copy.argtypes = [vp, vp, i64, vp]
+        L.fe_integrate_indexed.argtypes = [P, i32, i64, vp, i64, vp, i64, vp, i64, R, vp, vp, i64,
+                                           V, vp]
         _lib = L
     return _lib
 
@@ -228,6 +230,43 @@ def integrate(p: Problem, elem, coords, coeffs, rule: Rule, out_K=None, out_F=No
                                  ld_in, ctypes.byref(rule.c), ctypes.c_void_p(out_K.data_ptr()),
                                  ctypes.c_void_p(out_F.data_ptr()), ld_out, vptr,
                                  _stream_handle(stream)))
+    return out_K, out_F
+
+
+def integrate_indexed(p: Problem, elem, nodes, conn, coeffs, rule: Rule, out_K=None, out_F=None,
+                      n_elem: int | None = None, variant: Variant | None = None, stream=None):
+    """Indexed geometry: nodes (n_nodes, 3) FP64 and conn (n_vert, ld) int32
+    device tensors. Returns (out_K, out_F)."""
+    import torch
+    e = ELEM.get(elem, elem)
+    nv = 4 if e == TET4 else 6
+    ld_conn = conn.shape[1]
+    n = ld_conn if n_elem is None else int(n_elem)
+    dt = _dtype(p)
+    nk, nf = k_entries(p, e), f_entries(p, e)
+    if out_K is None:
+        out_K = torch.empty((nk, n), dtype=dt, device=conn.device)
+    if out_F is None:
+        out_F = torch.empty((nf, out_K.shape[1]), dtype=dt, device=conn.device)
+    if not (nodes.is_cuda and nodes.dtype == torch.float64 and nodes.is_contiguous()
+            and nodes.dim() == 2 and nodes.shape[1] == 3):
+        raise ValueError("nodes must be a contiguous (n_nodes, 3) float64 GPU tensor")
+    _check_tensor(conn, "conn", torch.int32, nv, ld_conn)
+    nc = coeff_entries(p, e, rule.n_q)
+    ld_in = coeffs.shape[1] if (coeffs is not None and nc > 0) else n
+    if nc > 0:
+        _check_tensor(coeffs, "coeffs", dt, nc, ld_in)
+    ld_out = out_K.shape[1]
+    _check_tensor(out_K, "out_K", dt, nk, ld_out)
+    _check_tensor(out_F, "out_F", dt, nf, ld_out)
+    cptr = ctypes.c_void_p(coeffs.data_ptr()) if (coeffs is not None and nc > 0) else None
+    vptr = ctypes.byref(variant) if variant is not None else None
+    _check(lib().fe_integrate_indexed(ctypes.byref(p), e, n, ctypes.c_void_p(nodes.data_ptr()),
+                                      nodes.shape[0], ctypes.c_void_p(conn.data_ptr()), ld_conn,
+                                      cptr, ld_in, ctypes.byref(rule.c),
+                                      ctypes.c_void_p(out_K.data_ptr()),
+                                      ctypes.c_void_p(out_F.data_ptr()), ld_out, vptr,
+                                      _stream_handle(stream)))
     return out_K, out_F
 
 

@@ -352,7 +352,7 @@ class Workload:
 def tet_poisson(N: int, seed: int = 1) -> Workload:
     """Scalar Poisson on the jittered tet cube: c^{i;j} = I, d^0 = 1 uniform,
     1-point rule, packed K (the headline workload; N = 8 gives 3,072
-    elements, N = 119 gives 10,111,074)."""
+    elements, N = 119 gives 10,110,954)."""
     mesh = tet_cube(N, seed)
     return Workload("tet_poisson", "tet4", "scalar", 1, "uniform", 0,
                     identity_diffusion_uniform(1.0), "packed", mesh, None)

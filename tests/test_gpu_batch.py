@@ -104,3 +104,24 @@ def test_batch_rejects_unbatched_kind():
     b.close()
     with pytest.raises(fe.FeError):
         fe.Batch(k, max_chunks=16, chunk_elems=63)
+
+
+def test_batch_falls_back_when_tuned_variant_has_no_batched_form():
+    wl = P.small("tet_cdr")
+    p = fe.problem_for(wl, "fp64")
+    rule = fe.builtin_rule("tet4", 4)
+    fe.tuning_clear()
+    # one element per lane with caching stores: compiled without a batched form
+    fe.tuning_set(p, "tet4", 4, fe.variant(256, 1, 2, 2, 0, 1))
+    try:
+        b = fe.Batch([(p, "tet4", rule)], max_chunks=16, chunk_elems=256)
+        dw = fe.to_device(wl, "fp64")
+        K = torch.empty((16, wl.n_elem), dtype=torch.float64, device="cuda")
+        F = torch.empty((4, wl.n_elem), dtype=torch.float64, device="cuda")
+        b.add(0, dw.coords, dw.coeffs, K, F)
+        b.launch()
+        torch.cuda.synchronize()
+        P.assert_parity(wl, "fp64", K.cpu().numpy(), F.cpu().numpy())
+        b.close()
+    finally:
+        fe.tuning_clear()

@@ -234,3 +234,41 @@ def test_variants_are_bitwise_identical(name):
             ref = (K, F)
         else:
             assert torch.equal(K, ref[0]) and torch.equal(F, ref[1]), kw
+
+
+@pytest.mark.parametrize("name", ["tet_poisson", "tet_cdr", "tet_elasticity", "prism_cdr_qp",
+                                  "prism_elasticity"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_indexed_geometry(name, precision):
+    """Coordinates gathered from the node array through the connectivity give
+    bit for bit the results of per-element coordinates (same arithmetic on
+    the same values), and so match the oracle."""
+    wl = P.small(name)
+    dw = fe.to_device(wl, precision)
+    nodes = torch.from_numpy(wl.mesh.nodes).cuda().contiguous()
+    conn = torch.from_numpy(np.ascontiguousarray(wl.mesh.conn.T.astype(np.int32))).cuda()
+    for v in (None, fe.variant(elems_per_thread=1), fe.variant(elems_per_thread=2, nontemporal=2)):
+        try:
+            K0, F0 = fe.integrate(dw.problem, wl.elem, dw.coords, dw.coeffs, dw.rule, variant=v)
+            K1, F1 = fe.integrate_indexed(dw.problem, wl.elem, nodes, conn, dw.coeffs, dw.rule,
+                                          variant=v)
+        except fe.FeError as e:
+            assert e.status == 2
+            continue
+        torch.cuda.synchronize()
+        assert torch.equal(K0, K1) and torch.equal(F0, F1)
+    P.assert_parity(wl, precision, K1.cpu().numpy(), F1.cpu().numpy())
+
+
+def test_indexed_geometry_clamps_bad_ids():
+    wl = P.small("tet_poisson")
+    dw = fe.to_device(wl, "fp64")
+    nodes = torch.from_numpy(wl.mesh.nodes).cuda().contiguous()
+    c = wl.mesh.conn.T.astype(np.int32).copy()
+    c[0, 5] = -3
+    c[2, 7] = 10 ** 9
+    conn = torch.from_numpy(c).cuda()
+    K, F = fe.integrate_indexed(dw.problem, wl.elem, nodes, conn, None, dw.rule)
+    torch.cuda.synchronize()
+    good = np.setdiff1d(np.arange(wl.n_elem), [5, 7])
+    P.assert_parity(wl, "fp64", K.cpu().numpy(), F.cpu().numpy(), elements=good)

@@ -47,6 +47,10 @@ WORKLOADS = {
                 "convection-diffusion-reaction, 20 coefficients per element, tet 4-point rule, full K, N=119"),
     "prism_cdr_qp": (lambda: __import__("paper_1504_01023_amd.inputs", fromlist=["x"]).prism_cdr_qp(141, 100, 3),
                      "prisms 141x141x100 (3,976,200, 1% slivers), 20 smooth coefficients per point, 6-point rule, full K"),
+    "prism_poisson_qp": (lambda: __import__("paper_1504_01023_amd.inputs", fromlist=["x"]).prism_poisson_qp_rhs(141, 100, 3),
+                         "prisms 141x141x100 (3,976,200), Laplacian with d^0 per point of the 6-point rule, full K (66 words/element)"),
+    "prism_cdr": (lambda: __import__("paper_1504_01023_amd.inputs", fromlist=["x"]).prism_cdr_element(141, 100, 3),
+                  "prisms 141x141x100 (3,976,200), 20 coefficients per element, 6-point rule, full K (80 words/element)"),
     "tet_elasticity": (lambda: __import__("paper_1504_01023_amd.inputs", fromlist=["x"]).tet_elasticity(94, 4),
                        "isotropic elasticity on tets N=94 (4,983,504), per-element E, nu, f, 1-point rule, packed 12x12"),
     "prism_elasticity": (lambda: __import__("paper_1504_01023_amd.inputs", fromlist=["x"]).prism_elasticity(100, 100, 4),
@@ -70,6 +74,10 @@ KERNEL_UNITS = {
     ("tet_elasticity", "fp64"): "fe_k_tet_elast_f64.hip",
     ("tet_elasticity", "fp32"): "fe_k_tet_elast_f32.hip",
     ("prism_elasticity", "fp64"): "fe_k_prism_elast_f64.hip",
+    ("prism_poisson_qp", "fp64"): "fe_k_prism_scalar_f64_poisson.hip",
+    ("prism_poisson_qp", "fp32"): "fe_k_prism_scalar_f32_poisson.hip",
+    ("prism_cdr", "fp64"): "fe_k_prism_scalar_f64_full.hip",
+    ("prism_cdr", "fp32"): "fe_k_prism_scalar_f32_full.hip",
     ("prism_elasticity", "fp32"): "fe_k_prism_elast_f32.hip",
 }
 
@@ -369,13 +377,122 @@ def run_served(a, torch, fe, serve) -> dict:
     return out
 
 
+# ------------------------------------------- the paper's order experiment
+# The four cases of Sec. 4.1 / Table 7 (words per element and operation
+# counts of Table 4 for the QSS, SQS and SSQ orders) and the measured
+# Tesla K20m times of Table 7 (ns per element), quoted as context.
+PAPER_CASES = [
+    # (name, workload, words, {order: paper ops}, {order: K20m ns})
+    ("tet Poisson", "tet_poisson_qp", 36, {"QSS": 290, "SQS": 290, "SSQ": 290},
+     {"QSS": 2.02, "SQS": 2.02, "SSQ": 2.02}),
+    ("prism Poisson", "prism_poisson_qp", 66, {"QSS": 2700, "SQS": 10416, "SSQ": 54876},
+     {"QSS": 12.80, "SQS": 38.39, "SSQ": 94.99}),
+    ("tet conv-diff", "tet_cdr", 52, {"QSS": 986, "SQS": 986, "SSQ": 1623},
+     {"QSS": 4.46, "SQS": 6.05, "SSQ": 6.13}),
+    ("prism conv-diff", "prism_cdr", 80, {"QSS": 4806, "SQS": 12492, "SSQ": 65232},
+     {"QSS": 15.58, "SQS": 64.81, "SSQ": 194.93}),
+]
+ORDER_CODE = {"QSS": 1, "SQS": 2, "SSQ": 3}
+
+
+def run_paper(a, torch, fe) -> dict:
+    import oracle
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    # the model's two "benchmark" rates, measured here: a streaming copy and
+    # an FP64 matrix product (the paper used STREAM and DGEMM)
+    src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        fe.stream_copy(dst, src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(20):
+        fe.stream_copy(dst, src)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbps = 2 * src.numel() * 8 * 20 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    m = 8192
+    A = torch.rand((m, m), dtype=torch.float64, device=dev)
+    B = torch.rand((m, m), dtype=torch.float64, device=dev)
+    for _ in range(2):
+        torch.matmul(A, B)
+    e0.record(stream)
+    for _ in range(5):
+        torch.matmul(A, B)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    dgemm_tf = 2 * m ** 3 * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e12
+    del A, B
+    log(f"[paper] copy {copy_gbps:.0f} GB/s, FP64 matmul {dgemm_tf:.1f} TFLOP/s")
+    rows = []
+    for name, wname, words, ops, k20 in PAPER_CASES:
+        wl = WORKLOADS[wname][0]()
+        dw = fe.to_device(wl, "fp64", device=dev)
+        p, rule = dw.problem, dw.rule
+        K = torch.empty((fe.k_entries(p, wl.elem), wl.n_elem), dtype=torch.float64, device=dev)
+        F = torch.empty((fe.f_entries(p, wl.elem), wl.n_elem), dtype=torch.float64, device=dev)
+        orders = ["QSS", "SQS", "SSQ"] if wl.elem == "prism6" else ["QSS"]
+        for order in orders:
+            best = None
+            for wg in (64, 128, 256):
+                for nt in (1, 2):
+                    v = fe.variant(wg_size=wg, nontemporal=nt, loop_order=ORDER_CODE[order],
+                                   elems_per_thread=2 if wl.elem == "tet4" else 1)
+                    try:
+                        fe.integrate(p, wl.elem, dw.coords, dw.coeffs, rule, K, F, variant=v)
+                    except fe.FeError:
+                        continue
+                    e0.record(stream)
+                    for _ in range(5):
+                        fe.integrate(p, wl.elem, dw.coords, dw.coeffs, rule, K, F, variant=v)
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                    ms = e0.elapsed_time(e1) / 5
+                    if best is None or ms < best[0]:
+                        best = (ms, (wg, nt))
+            ms, (wg, nt) = best
+            fe.integrate(p, wl.elem, dw.coords, dw.coeffs, rule, K, F,
+                         variant=fe.variant(wg_size=wg, nontemporal=nt, loop_order=ORDER_CODE[order],
+                                            elems_per_thread=2 if wl.elem == "tet4" else 1))
+            torch.cuda.synchronize()
+            sample = np.arange(0, wl.n_elem, max(1, wl.n_elem // 2000))
+            idx = torch.from_numpy(sample).to(dev)
+            Ks = K.index_select(1, idx).cpu().numpy()
+            Fs = F.index_select(1, idx).cpu().numpy()
+            Ko, Fo = oracle.integrate(wl.elem, wl.kind, wl.mesh.coords[:, sample],
+                                      oracle.quad_rule(wl.elem, wl.n_q), wl.coef_mode, wl.mask,
+                                      wl.uniform, None if wl.coeffs is None else wl.coeffs[:, sample],
+                                      threads=max(1, min(16, os.cpu_count() or 1)))
+            N = oracle.n_dof(wl.elem, wl.kind)
+            Kg = fe.unpack_full(Ks, N, False)
+            ek = float(np.sqrt(((Kg - Ko) ** 2).sum(axis=(1, 2)) / (Ko ** 2).sum(axis=(1, 2))).max())
+            ns = ms * 1e6 / wl.n_elem
+            bound_mem = 8 * words / copy_gbps
+            bound_op = ops[order] / (dgemm_tf * 1e3)
+            bound = max(bound_mem, bound_op)
+            rows.append({"case": name, "order": order, "n_elem": wl.n_elem, "ns_per_element": ns,
+                         "elements_per_s": wl.n_elem / (ms * 1e-3),
+                         "GBps": 8 * words * wl.n_elem / (ms * 1e-3) / 1e9,
+                         "model_bound_ns": bound, "pct_of_bound": 100 * bound / ns,
+                         "K20m_ns": k20[order], "speedup_vs_K20m": k20[order] / ns,
+                         "variant_wg_nt": [wg, nt], "parity_max_rel_err_K": ek})
+            log(f"[paper] {name:16s} {order}: {ns:.3f} ns/elem ({100 * bound / ns:.0f}% of bound "
+                f"{bound:.3f}), K20m {k20[order]} ns, parity {ek:.1e}")
+        del dw, K, F
+        torch.cuda.empty_cache()
+    return {"copy_GBps": copy_gbps, "fp64_matmul_TFLOPs": dgemm_tf, "rows": rows}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="tet_poisson",
-                    choices=sorted(WORKLOADS) + [w + "_indexed" for w in sorted(WORKLOADS)] + ["served"])
+                    choices=sorted(WORKLOADS) + [w + "_indexed" for w in sorted(WORKLOADS)]
+                    + ["served", "paper"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--tune", action="store_true",
                     help="run the exhaustive variant search (fe_autotune) during warm-up")
@@ -406,6 +523,16 @@ def main() -> int:
         return 1
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+
+    if a.workload == "paper":
+        res = run_paper(a, torch, fe)
+        line = {"metric": "ns per element by loop order (the paper's Table 7 experiment on MI355X)",
+                "value": None, "unit": "ns/element", "n_gpus": 1, "steps": 5, "warmup": 1,
+                "ms_per_step": None, "higher_is_better": False, "scaling": "weak",
+                "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+                "config": {"workload": "paper"}, "paper": res}
+        print(json.dumps(line), flush=True)
+        return 0
 
     if a.workload == "served":
         from paper_1504_01023_amd import serve
@@ -465,7 +592,7 @@ def main() -> int:
     torch.cuda.synchronize()
 
     # copy ceiling on the same byte volume (context for the roofline)
-    nbytes = (bpe * wl.n_elem) // 32 * 16
+    nbytes = int(bpe * wl.n_elem) // 32 * 16
     src = torch.empty(nbytes // 8, dtype=torch.float64, device=dev)
     dst = torch.empty_like(src)
     src.fill_(1.0)

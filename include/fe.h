@@ -137,6 +137,9 @@ typedef struct fe_variant {
     int32_t blocks;            /* grid size; 0 = one element group per thread */
     int32_t row_split;         /* passes over the points with the rows of K split
                                   between them (prism elasticity): 1, 2 or 3 */
+    int32_t loop_order;        /* order of the point and shape-function loops
+                                  (Sec. 3.3, Algorithms 2, 4, 6) for prism
+                                  scalar kernels: 1 QSS, 2 SQS, 3 SSQ */
 } fe_variant;
 
 /* ---------------------------------------------------------------------

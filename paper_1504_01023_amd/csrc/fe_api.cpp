@@ -32,7 +32,7 @@ static bool same_key(const KernelKey &a, const KernelKey &b)
 {
     return a.elem == b.elem && a.kind == b.kind && a.prec == b.prec && a.terms == b.terms &&
            a.mode == b.mode && a.packed == b.packed && a.vec == b.vec && a.nt == b.nt &&
-           a.ref == b.ref && a.nq == b.nq && a.split == b.split;
+           a.ref == b.ref && a.nq == b.nq && a.split == b.split && a.order == b.order;
 }
 
 const KernelEntry *find_kernel(const KernelKey &k)
@@ -277,6 +277,7 @@ int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coor
     const int nt = (v.nontemporal == 2) ? 0 : 1;
     const int ref = (v.ref_in_lds == 1) ? REF_LDS : REF_KARG;
     const int split = (v.row_split == 2 || v.row_split == 3) ? v.row_split : 1;
+    const int order = (v.loop_order == 2 || v.loop_order == 3) ? v.loop_order : 1;
 
     // vector width needs aligned rows
     auto vec_ok = [&](int V) {
@@ -300,6 +301,7 @@ int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coor
     k.nt = nt;
     k.ref = ref;
     k.split = split;
+    k.order = order;
     k.nq = rule->n_q;
     auto usable = [&](const KernelEntry *x) { return x && (form == 0 || x->idx != nullptr); };
     const KernelEntry *e = find_kernel(k);
@@ -313,6 +315,7 @@ int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coor
         k.nt = 1;
         k.ref = REF_KARG;
         k.split = 1;
+        k.order = 1;
         k.nq = 0;
         e = find_kernel(k);
     }
@@ -321,9 +324,9 @@ int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coor
     if (!e)
         return fail(FE_ERR_UNSUPPORTED,
                     "no compiled kernel for elem=%d kind=%d prec=%d terms=%d mode=%d packed=%d "
-                    "vec=%d nt=%d ref=%d nq=%d split=%d",
+                    "vec=%d nt=%d ref=%d nq=%d split=%d order=%d",
                     k.elem, k.kind, k.prec, k.terms, k.mode, k.packed, k.vec, k.nt, k.ref, k.nq,
-                    k.split);
+                    k.split, k.order);
 
     KArgs &a = pl.args;
     std::memset(&a, 0, sizeof(a));
@@ -351,7 +354,7 @@ int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coor
         grid = 0x7fffffff;
     pl.grid = (unsigned)(grid > 0 ? grid : 1);
     pl.key = k;
-    pl.variant = fe_variant{wg, k.vec, ref == REF_LDS ? 1 : 2, nt ? 1 : 2, v.blocks, k.split};
+    pl.variant = fe_variant{wg, k.vec, ref == REF_LDS ? 1 : 2, nt ? 1 : 2, v.blocks, k.split, k.order};
     return FE_OK;
 }
 

@@ -129,8 +129,8 @@ int fe_batch_create(const fe_batch_kind *kinds, int n_kinds, int max_chunks, int
             // width with streaming memory operations, else the base variant.
             const fe_variant tuned = K.plan.variant;
             const fe_variant alts[2] = {
-                {tuned.wg_size, tuned.elems_per_thread, tuned.ref_in_lds, 1, 0, tuned.row_split},
-                {256, 1, 2, 1, 0, 1}};
+                {tuned.wg_size, tuned.elems_per_thread, tuned.ref_in_lds, 1, 0, tuned.row_split, 1},
+                {256, 1, 2, 1, 0, 1, 1}};
             for (const fe_variant &v : alts) {
                 Plan alt;
                 if (plan(&bk.problem, bk.elem_type, 0, nullptr, nullptr, 0, &rule, nullptr, nullptr,

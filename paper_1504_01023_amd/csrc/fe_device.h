@@ -922,6 +922,177 @@ struct PrismScalar {
     }
 };
 
+// ====================================== prism, scalar, SQS and SSQ orders
+// The other loop orders of Sec. 3.3 for geo_generic elements: SQS
+// (Algorithm 4) loops over the rows of K outermost and recomputes the
+// Jacobian terms at every point for every row; SSQ (Algorithm 6) loops over
+// the entries of K outermost and recomputes them for every entry (with only
+// the two global derivatives that entry needs). They hold fewer values at a
+// time (one row; one entry) at the price of repeated geometry, and exist to
+// compare the orders on gfx950 as the paper's experiments compare them on its
+// processors; QSS (PrismScalar) remains the production kernel.
+enum LoopOrder { ORDER_QSS = 1, ORDER_SQS = 2, ORDER_SSQ = 3 };
+
+// Jacobian terms at one point: (J^{-1})[k][i] and det J, from edge vectors.
+template <class R>
+__device__ __forceinline__ void point_jinv(const double (&E)[18], const R &ref, int q,
+                                           double (&Ji)[3][3], double &det)
+{
+    double J[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            double s = 0.0;
+#pragma unroll
+            for (int r = 1; r < 6; ++r)
+                s += E[3 * r + i] * ref.dphi(q, r, k);
+            J[i][k] = s;
+        }
+    const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+    const double inv = 1.0 / det;
+    Ji[0][0] = c00 * inv;
+    Ji[1][0] = c01 * inv;
+    Ji[2][0] = c02 * inv;
+    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * inv;
+    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * inv;
+    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * inv;
+    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * inv;
+    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * inv;
+    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * inv;
+}
+
+// Global derivatives of shape function r (r may be a runtime index).
+template <typename T, class R>
+__device__ __forceinline__ void grad_of(const R &ref, int q, int r, const double (&Ji)[3][3],
+                                        T (&g)[3])
+{
+    const double d0 = ref.dphi(q, r, 0), d1 = ref.dphi(q, r, 1), d2 = ref.dphi(q, r, 2);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        g[i] = (T)(d0 * Ji[0][i] + d1 * Ji[1][i] + d2 * Ji[2][i]);
+}
+
+template <typename T, int TERMS, int MODE, int PACKED, int ORDER>
+struct PrismScalarOrder {
+    using Q = PrismScalar<T, TERMS, MODE, PACKED, 0>;
+    static constexpr bool DIFF = Q::DIFF, CA = Q::CA, CB = Q::CB, MASS = Q::MASS, DG = Q::DG,
+                          D0 = Q::D0, PER_QP = Q::PER_QP;
+
+    // vol [g_r . C g_s + (c^{.;0} . g_r) phi_s + phi_r (c^{0;.} . g_s) + c^{0;0} phi_r phi_s]
+    __device__ __forceinline__ static T entry(const typename Q::Coefs &c, const T (&gr)[3],
+                                              const T (&gs)[3], T pr, T ps)
+    {
+        T x = T(0);
+        if constexpr (DIFF) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                x += gr[i] * (c.C[i][0] * gs[0] + c.C[i][1] * gs[1] + c.C[i][2] * gs[2]);
+        }
+        if constexpr (CA)
+            x += (c.ca[0] * gr[0] + c.ca[1] * gr[1] + c.ca[2] * gr[2]) * ps;
+        if constexpr (CB)
+            x += pr * (c.cb[0] * gs[0] + c.cb[1] * gs[1] + c.cb[2] * gs[2]);
+        if constexpr (MASS)
+            x += c.c00 * pr * ps;
+        return x;
+    }
+
+    __device__ __forceinline__ static T load_entry(const typename Q::Coefs &c, const T (&gr)[3],
+                                                   T pr)
+    {
+        T x = T(0);
+        if constexpr (DG)
+            x = c.d[0] * gr[0] + c.d[1] * gr[1] + c.d[2] * gr[2];
+        if constexpr (D0)
+            x += c.d0 * pr;
+        return x;
+    }
+
+    template <int V, bool NT, int REF, class S>
+    __device__ __forceinline__ static void run(const KArgs &a, const S &st, const Ref<REF> &ref,
+                                               int64_t e)
+    {
+        static_assert(V == 1, "prisms are processed one element per lane");
+        double Xg[1][18];
+        st.template load_coords<6, 1, NT>(e, Xg);
+        double X[18];
+#pragma unroll
+        for (int s = 0; s < 18; ++s)
+            X[s] = Xg[0][s];
+        to_edge_vectors<6>(X);
+        typename Q::Coefs c;
+        if constexpr (!PER_QP)
+            Q::template load_coefs<NT>(a, st, 0, e, c);
+        T *outK = static_cast<T *>(st.out_K);
+        T *outF = static_cast<T *>(st.out_F);
+        const int nq = a.n_q;
+        if constexpr (ORDER == ORDER_SQS) {
+#pragma unroll 1
+            for (int r = 0; r < 6; ++r) {
+                T Kr[6], Fr = T(0);
+#pragma unroll
+                for (int s = 0; s < 6; ++s)
+                    Kr[s] = T(0);
+                for (int q = 0; q < nq; ++q) {
+                    if constexpr (PER_QP)
+                        Q::template load_coefs<NT>(a, st, q, e, c);
+                    double Ji[3][3], det;
+                    point_jinv(X, ref, q, Ji, det);
+                    const T vol = (T)(det * ref.w(q));
+                    T gr[3];
+                    grad_of<T>(ref, q, r, Ji, gr);
+                    const T pr = (T)ref.phi(q, r);
+#pragma unroll
+                    for (int s = 0; s < 6; ++s) {
+                        T gs[3];
+                        grad_of<T>(ref, q, s, Ji, gs);
+                        Kr[s] += vol * entry(c, gr, gs, pr, (T)ref.phi(q, s));
+                    }
+                    Fr += vol * load_entry(c, gr, pr);
+                }
+#pragma unroll
+                for (int s = 0; s < 6; ++s) {
+                    if (PACKED && s < r)
+                        continue;
+                    const int k = PACKED ? r * 6 - r * (r - 1) / 2 + (s - r) : 6 * r + s;
+                    st1<NT>(outK + k * st.ld_out + e, Kr[s]);
+                }
+                st1<NT>(outF + r * st.ld_out + e, Fr);
+            }
+        } else {
+#pragma unroll 1
+            for (int r = 0; r < 6; ++r) {
+#pragma unroll 1
+                for (int s = PACKED ? r : 0; s < 6; ++s) {
+                    T acc = T(0), fr = T(0);
+                    for (int q = 0; q < nq; ++q) {
+                        if constexpr (PER_QP)
+                            Q::template load_coefs<NT>(a, st, q, e, c);
+                        double Ji[3][3], det;
+                        point_jinv(X, ref, q, Ji, det);
+                        const T vol = (T)(det * ref.w(q));
+                        T gr[3], gs[3];
+                        grad_of<T>(ref, q, r, Ji, gr);
+                        grad_of<T>(ref, q, s, Ji, gs);
+                        const T pr = (T)ref.phi(q, r);
+                        acc += vol * entry(c, gr, gs, pr, (T)ref.phi(q, s));
+                        if (r == s)
+                            fr += vol * load_entry(c, gr, pr);
+                    }
+                    const int k = PACKED ? r * 6 - r * (r - 1) / 2 + (s - r) : 6 * r + s;
+                    st1<NT>(outK + k * st.ld_out + e, acc);
+                    if (r == s)
+                        st1<NT>(outF + r * st.ld_out + e, fr);
+                }
+            }
+        }
+    }
+};
+
 // ====================================================== prism, elasticity
 // Coefficients constant over the element: H_rs = sum_q vol_q g_r g_s^T
 // (r <= s), then K_(r a),(s b) = lam H_rs[a][b] + mu H_rs[b][a]

@@ -86,7 +86,8 @@ struct KernelKey {
     int nt;        // non-temporal memory operations
     int ref;       // RefKind
     int nq;        // compiled point count, 0 = runtime loop
-    int split;     // passes over the points (row split of K), 1 or 2
+    int split;     // passes over the points (row split of K), 1, 2 or 3
+    int order;     // loop order (1 QSS, 2 SQS, 3 SSQ)
 };
 
 typedef void (*LaunchFn)(const KArgs &, unsigned grid, unsigned block, hipStream_t);

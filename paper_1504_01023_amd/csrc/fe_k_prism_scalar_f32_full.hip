@@ -20,6 +20,13 @@ int register_all()
     reg_prism_scalar<T, TS, MODE, PK, 0, 0, REF_LDS>();
     TUNE(M_QP, 0) TUNE(M_ELEM, 0) TUNE(M_UNIFORM, 1) TUNE(M_UNIFORM, 0)
 #undef TUNE
+    // the SQS and SSQ loop orders, for the order comparison (the paper's
+    // "Poisson": per-point right-hand side; "conv-diff": element constants)
+#define ORDERS(MODE) \
+    reg_prism_scalar_order<T, TS, MODE, 0, ORDER_SQS, 1>(); reg_prism_scalar_order<T, TS, MODE, 0, ORDER_SSQ, 1>(); \
+    reg_prism_scalar_order<T, TS, MODE, 0, ORDER_SQS, 0>(); reg_prism_scalar_order<T, TS, MODE, 0, ORDER_SSQ, 0>();
+    ORDERS(M_QP_MIXED) ORDERS(M_ELEM) ORDERS(M_QP)
+#undef ORDERS
     return 0;
 }
 const int registered = register_all();

@@ -10,9 +10,10 @@ namespace fe {
 // Registers the plain kernel; B = 1 also registers the batched (persistent)
 // form and the indexed-geometry form.
 template <class P, int V, int NT, int REF, int B = 0>
-inline void reg(int elem, int kind, int prec, int terms, int mode, int packed, int nq, int split = 1)
+inline void reg(int elem, int kind, int prec, int terms, int mode, int packed, int nq, int split = 1,
+                int order = 1)
 {
-    KernelKey k{elem, kind, prec, terms, mode, packed, V, NT, REF, nq, split};
+    KernelKey k{elem, kind, prec, terms, mode, packed, V, NT, REF, nq, split, order};
     BatchLaunchFn bl = nullptr;
     IdxLaunchFn il = nullptr;
     if constexpr (B != 0) {
@@ -46,6 +47,14 @@ inline void reg_prism_scalar()
 {
     reg<PrismScalar<T, TERMS, MODE, PK, NQ>, 1, NT, REF, B>(FE_PRISM6, FE_SCALAR_CDR, prec_of<T>(),
                                                          TERMS, MODE, PK, NQ);
+}
+
+// Prism scalar kernels in the SQS / SSQ loop orders (one element per lane).
+template <typename T, int TERMS, int MODE, int PK, int ORDER, int NT>
+inline void reg_prism_scalar_order()
+{
+    reg<PrismScalarOrder<T, TERMS, MODE, PK, ORDER>, 1, NT, REF_KARG>(
+        FE_PRISM6, FE_SCALAR_CDR, prec_of<T>(), TERMS, MODE, PK, 0, 1, ORDER);
 }
 
 template <typename T, int MODE, int PK, int NQ, int NT, int REF, int B = 0, int SPLIT = 1>

@@ -49,11 +49,12 @@ class QuadRule(ctypes.Structure):
 class Variant(ctypes.Structure):
     _fields_ = [("wg_size", ctypes.c_int32), ("elems_per_thread", ctypes.c_int32),
                 ("ref_in_lds", ctypes.c_int32), ("nontemporal", ctypes.c_int32),
-                ("blocks", ctypes.c_int32), ("row_split", ctypes.c_int32)]
+                ("blocks", ctypes.c_int32), ("row_split", ctypes.c_int32),
+                ("loop_order", ctypes.c_int32)]
 
     def as_tuple(self):
         return (self.wg_size, self.elems_per_thread, self.ref_in_lds, self.nontemporal, self.blocks,
-                self.row_split)
+                self.row_split, self.loop_order)
 
 
 class FeError(RuntimeError):
@@ -172,8 +173,9 @@ def k_index(p: Problem, elem, row: int, col: int) -> int:
 
 
 def variant(wg_size=0, elems_per_thread=0, ref_in_lds=0, nontemporal=0, blocks=0,
-            row_split=0) -> Variant:
-    return Variant(wg_size, elems_per_thread, ref_in_lds, nontemporal, blocks, row_split)
+            row_split=0, loop_order=0) -> Variant:
+    return Variant(wg_size, elems_per_thread, ref_in_lds, nontemporal, blocks, row_split,
+                   loop_order)
 
 
 # ------------------------------------------------------------------- execution

@@ -415,3 +415,13 @@ def prism_elasticity(n: int, L: int, seed: int = 4, sliver: bool = True) -> Work
     coeffs = elasticity_per_element(mesh.n_elem, rng)
     return Workload("prism_elasticity", "prism6", "elasticity", 6, "element", ALL_ELAST_MASK,
                     np.zeros(N_ELAST_SLOTS), "packed", mesh, coeffs)
+
+
+def prism_poisson_qp_rhs(n: int, L: int, seed: int = 3, sliver: bool = True) -> Workload:
+    """The paper's prismatic "Poisson" shape: Laplacian, d^0 given per point
+    of the 6-point rule, full K (66 words per element)."""
+    rng = np.random.default_rng(seed)
+    mesh = prism_layers(n, L, rng, sliver=sliver)
+    coeffs = rhs_per_qp(mesh.n_elem, 6, rng)
+    return Workload("prism_poisson_qp", "prism6", "scalar", 6, "qp", 1 << 16,
+                    identity_diffusion_uniform(0.0), "full", mesh, coeffs)

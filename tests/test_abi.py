@@ -189,12 +189,12 @@ def test_tuning_table_roundtrip(tmp_path):
     fe.tuning_clear()
     p = fe.problem("scalar", "fp64", "uniform", 0, None, "packed")
     assert fe.tuning_get(p, "tet4", 1) is None
-    fe.tuning_set(p, "tet4", 1, fe.variant(128, 2, 2, 1, 0, 1))
-    assert fe.tuning_get(p, "tet4", 1) == (128, 2, 2, 1, 0, 1)
+    fe.tuning_set(p, "tet4", 1, fe.variant(128, 2, 2, 1, 0, 1, 1))
+    assert fe.tuning_get(p, "tet4", 1) == (128, 2, 2, 1, 0, 1, 1)
     path = str(tmp_path / "tune.txt")
     fe.tuning_save(path)
     fe.tuning_clear()
     assert fe.tuning_get(p, "tet4", 1) is None
     fe.tuning_load(path)
-    assert fe.tuning_get(p, "tet4", 1) == (128, 2, 2, 1, 0, 1)
+    assert fe.tuning_get(p, "tet4", 1) == (128, 2, 2, 1, 0, 1, 1)
     fe.tuning_clear()

@@ -112,7 +112,7 @@ def test_batch_falls_back_when_tuned_variant_has_no_batched_form():
     rule = fe.builtin_rule("tet4", 4)
     fe.tuning_clear()
     # one element per lane with caching stores: compiled without a batched form
-    fe.tuning_set(p, "tet4", 4, fe.variant(256, 1, 2, 2, 0, 1))
+    fe.tuning_set(p, "tet4", 4, fe.variant(256, 1, 2, 2, 0, 1, 1))
     try:
         b = fe.Batch([(p, "tet4", rule)], max_chunks=16, chunk_elems=256)
         dw = fe.to_device(wl, "fp64")

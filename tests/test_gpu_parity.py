@@ -34,6 +34,9 @@ VARIANTS = [
     for wg in (64, 128, 256) for v in (1, 2, 4) for nt in (1, 2) for ref in (1, 2) for b in (0, 7)
     for sp in (1, 2, 3)
 ]
+# the SQS / SSQ loop orders sum in a different order: parity, not bitwise
+ORDER_VARIANTS = [dict(wg_size=wg, nontemporal=nt, loop_order=o)
+                  for wg in (64, 256) for nt in (1, 2) for o in (2, 3)]
 
 
 @pytest.mark.parametrize("name", ["tet_poisson", "tet_cdr", "prism_cdr_qp", "tet_elasticity",
@@ -46,7 +49,7 @@ def test_every_compiled_variant(name):
     dw = fe.to_device(wl, "fp64")
     Ko, Fo = P.oracle_run(wl, "fp64")
     ran = 0
-    for kw in VARIANTS:
+    for kw in VARIANTS + ORDER_VARIANTS:
         v = fe.variant(**kw)
         try:
             K, F = fe.integrate(dw.problem, wl.elem, dw.coords, dw.coeffs, dw.rule, variant=v)

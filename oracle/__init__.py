@@ -22,11 +22,11 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 TET4, PRISM6 = 0, 1
 SCALAR, ELASTICITY = 0, 1
-UNIFORM, PER_ELEMENT, PER_QP = 0, 1, 2
+UNIFORM, PER_ELEMENT, PER_QP, FUNCTION = 0, 1, 2, 3
 
 _ELEM = {"tet4": TET4, "prism6": PRISM6}
 _KIND = {"scalar": SCALAR, "elasticity": ELASTICITY}
-_MODE = {"uniform": UNIFORM, "element": PER_ELEMENT, "qp": PER_QP}
+_MODE = {"uniform": UNIFORM, "element": PER_ELEMENT, "qp": PER_QP, "function": FUNCTION}
 
 
 def build(force: bool = True) -> str:
@@ -113,7 +113,11 @@ def integrate(elem: str, kind: str, coords, rule, coef_mode: str = "uniform", ma
         u[: len(uniform)] = np.asarray(uniform, dtype=np.float64)
     c = None
     ldc = n
-    if coef_mode != "uniform" and mask:
+    if coef_mode == "function":
+        c = np.ascontiguousarray(coeffs, dtype=np.float64).reshape(-1)
+        if c.size != 122:
+            raise ValueError("a coefficient function takes 122 parameters")
+    elif coef_mode != "uniform" and mask:
         c = np.ascontiguousarray(coeffs, dtype=np.float64)
         ldc = c.shape[1]
     K = np.empty((n, N, N))
@@ -160,6 +164,7 @@ def integrate_workload(wl, threads: int = 1, elements=None):
     if elements is not None:
         idx = np.asarray(elements)
         coords = coords[:, idx]
-        coeffs = None if coeffs is None else coeffs[:, idx]
+        if coeffs is not None and wl.coef_mode != "function":
+            coeffs = coeffs[:, idx]
     return integrate(wl.elem, wl.kind, coords, quad_rule(wl.elem, wl.n_q), wl.coef_mode, wl.mask,
                      wl.uniform, coeffs, threads)

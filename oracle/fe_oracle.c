@@ -39,7 +39,9 @@
  *  slots whose bit is set in `mask`, in increasing slot order j; per element
  *  coeffs[j*ldc + e], per point coeffs[(j*n_q + q)*ldc + e]. Slots whose bit
  *  is clear take the value uniform[slot]. Scalar slots: 4a+b -> c[a][b],
- *  16+a -> d[a]. Elasticity slots: E, nu, f_x, f_y, f_z.
+ *  16+a -> d[a]. Elasticity slots: E, nu, f_x, f_y, f_z. In the function
+ *  mode `coeffs` holds the 122 parameters of the coefficient function (see
+ *  fn_raw) and the slots in `mask` are computed from it at every point.
  *
  * Output: full matrices, element-major: K[e*N*N + row*N + col], F[e*N + row],
  * N = number of shape functions times components.
@@ -59,6 +61,8 @@
 #define OR_UNIFORM 0
 #define OR_PER_ELEMENT 1
 #define OR_PER_QP 2
+#define OR_FUNCTION 3
+#define OR_FN_PARAMS 122
 
 #define OR_OK 0
 #define OR_EINVAL 1
@@ -172,6 +176,56 @@ int oracle_shape(int elem, const double *xi, double *phi, double *dphi)
 }
 
 /* ------------------------------------------------------------------------
+ * Coefficient functions (the paper's option of computing the coefficients
+ * at the integration points from problem-dependent parameters, Sec. 2.3 and
+ * Sec. 3.3). Parameters, for slot k: p[6k..6k+5] = alpha, beta, omega_x,
+ * omega_y, omega_z, theta; the raw value at point x is
+ *   alpha + beta sin(2 pi (omega . x) + theta).
+ * If p[121] != 0, the diffusion block is then replaced by A A^T + p[120] I
+ * with A[i][j] the raw value of slot 4(i+1)+1+j (symmetric positive
+ * definite for p[120] > 0).
+ * ---------------------------------------------------------------------- */
+static void physical_point(int elem, const double xi[3], const double X[6][3], double x[3])
+{
+    double ph[6], dph[6][3];
+    if (elem == OR_TET4)
+        tet4_shape(xi, ph, dph);
+    else
+        prism6_shape(xi, ph, dph);
+    for (int i = 0; i < 3; ++i) {
+        x[i] = 0.0;
+        for (int r = 0; r < n_shape(elem); ++r)
+            x[i] += ph[r] * X[r][i];
+    }
+}
+
+static double fn_raw(const double *p, int k, const double x[3])
+{
+    const double *a = p + 6 * k;
+    const double two_pi = 6.283185307179586476925286766559;
+    return a[0] + a[1] * sin(two_pi * (a[2] * x[0] + a[3] * x[1] + a[4] * x[2]) + a[5]);
+}
+
+static void fn_spd_diffusion(const double *p, double *par)
+{
+    if (p[121] == 0.0)
+        return;
+    double A[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            A[i][j] = par[4 * (i + 1) + 1 + j];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double c = 0.0;
+            for (int m = 0; m < 3; ++m)
+                c += A[i][m] * A[j][m];
+            if (i == j)
+                c += p[120];
+            par[4 * (i + 1) + 1 + j] = c;
+        }
+}
+
+/* ------------------------------------------------------------------------
  * The element loop.
  * ---------------------------------------------------------------------- */
 typedef struct {
@@ -188,6 +242,7 @@ typedef struct {
     double *K, *F;
     int n_slots;
     int slot_col[20]; /* compact column of each slot, -1 = uniform */
+    const double *fn; /* coefficient-function parameters (OR_FUNCTION) */
 } job_t;
 
 typedef struct {
@@ -248,25 +303,34 @@ static void integrate_element(const job_t *jb, scratch_t *sc, int64_t e)
     double *Ke = jb->K + (size_t)e * N * N;
     double *Fe = jb->F + (size_t)e * N;
 
-    /* read problem dependent parameters specific to the element */
-    for (int q = 0; q < nq; ++q)
+    /* read geometry data for the element */
+    double X[6][3];
+    for (int v = 0; v < ns; ++v)
+        for (int d = 0; d < 3; ++d)
+            X[v][d] = jb->coords[(int64_t)(v * 3 + d) * jb->ld + e];
+
+    /* read problem dependent parameters specific to the element, or compute
+     * the coefficients from the parameters of the coefficient function */
+    for (int q = 0; q < nq; ++q) {
+        double x[3] = {0.0, 0.0, 0.0};
+        if (jb->coef_mode == OR_FUNCTION)
+            physical_point(jb->elem, &jb->xi[3 * q], X, x);
         for (int k = 0; k < jb->n_slots; ++k) {
             const int j = jb->slot_col[k];
             double v = jb->uniform[k];
             if (j >= 0) {
-                if (jb->coef_mode == OR_PER_QP)
+                if (jb->coef_mode == OR_FUNCTION)
+                    v = fn_raw(jb->fn, k, x);
+                else if (jb->coef_mode == OR_PER_QP)
                     v = jb->coeffs[((int64_t)j * nq + q) * jb->ldc + e];
                 else
                     v = jb->coeffs[(int64_t)j * jb->ldc + e];
             }
             sc->par[q * 20 + k] = v;
         }
-
-    /* read geometry data for the element */
-    double X[6][3];
-    for (int v = 0; v < ns; ++v)
-        for (int d = 0; d < 3; ++d)
-            X[v][d] = jb->coords[(int64_t)(v * 3 + d) * jb->ld + e];
+        if (jb->coef_mode == OR_FUNCTION)
+            fn_spd_diffusion(jb->fn, &sc->par[q * 20]);
+    }
 
     /* initialise A^e and b^e */
     for (int i = 0; i < N * N; ++i)
@@ -400,7 +464,7 @@ int oracle_integrate(int elem, int kind, int coef_mode, unsigned mask, const dou
                      double *F, int n_threads)
 {
     if ((elem != OR_TET4 && elem != OR_PRISM6) || (kind != OR_SCALAR && kind != OR_ELASTICITY) ||
-        coef_mode < OR_UNIFORM || coef_mode > OR_PER_QP || n_elem < 0 || n_q < 1 || !uniform ||
+        coef_mode < OR_UNIFORM || coef_mode > OR_FUNCTION || n_elem < 0 || n_q < 1 || !uniform ||
         !xi || !w)
         return OR_EINVAL;
     if (n_elem == 0)
@@ -417,8 +481,13 @@ int oracle_integrate(int elem, int kind, int coef_mode, unsigned mask, const dou
     int col = 0;
     for (int k = 0; k < jb.n_slots; ++k)
         jb.slot_col[k] = (jb.mask >> k & 1u) ? col++ : -1;
-    if (col > 0 && (!coeffs || ldc < n_elem))
+    if (coef_mode == OR_FUNCTION) {
+        if (kind != OR_SCALAR || (col > 0 && !coeffs))
+            return OR_EINVAL;
+        jb.fn = coeffs;
+    } else if (col > 0 && (!coeffs || ldc < n_elem)) {
         return OR_EINVAL;
+    }
     jb.uniform = uniform;
     jb.n_elem = n_elem;
     jb.coords = coords;

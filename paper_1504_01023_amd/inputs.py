@@ -425,3 +425,47 @@ def prism_poisson_qp_rhs(n: int, L: int, seed: int = 3, sliver: bool = True) -> 
     coeffs = rhs_per_qp(mesh.n_elem, 6, rng)
     return Workload("prism_poisson_qp", "prism6", "scalar", 6, "qp", 1 << 16,
                     identity_diffusion_uniform(0.0), "full", mesh, coeffs)
+
+
+# --------------------------------------------------------------------------
+# Coefficient functions: parameters instead of values.
+# --------------------------------------------------------------------------
+N_FN_PARAMS = 122
+
+
+def smooth_cdr_params(rng: np.random.Generator, spd_shift: float = 0.5) -> np.ndarray:
+    """Parameters of the smooth coefficient fields of smooth_cdr_per_qp, in the
+    same draw order, for the function mode: row k of the (122,) table holds
+    (alpha_k, beta_k, omega_k, theta_k) at [6k .. 6k+5]; slots 0 and 16 get
+    alpha = beta = 1/2 (the [0, 1] mapping); [120] is the shift of the SPD
+    diffusion transform and [121] = 1 enables it."""
+    alpha = rng.uniform(-1.0, 1.0, N_SCALAR_SLOTS)
+    beta = rng.uniform(0.0, 0.5, N_SCALAR_SLOTS)
+    omega = rng.integers(1, 4, (N_SCALAR_SLOTS, 3))
+    theta = rng.uniform(0.0, 2.0 * math.pi, N_SCALAR_SLOTS)
+    p = np.zeros(N_FN_PARAMS)
+    for k in range(N_SCALAR_SLOTS):
+        a, b = (0.5, 0.5) if k in (0, 16) else (alpha[k], beta[k])
+        p[6 * k: 6 * k + 6] = (a, b, omega[k, 0], omega[k, 1], omega[k, 2], theta[k])
+    p[120] = spd_shift
+    p[121] = 1.0
+    return p
+
+
+def prism_cdr_fn(n: int, L: int, seed: int = 3, sliver: bool = True) -> Workload:
+    """Prisms with all twenty coefficients computed at the points from the
+    smooth-field parameters (the per-point workload's fields, evaluated in the
+    kernel instead of read from memory)."""
+    rng = np.random.default_rng(seed)
+    mesh = prism_layers(n, L, rng, sliver=sliver)
+    return Workload("prism_cdr_fn", "prism6", "scalar", 6, "function", ALL_SCALAR_MASK,
+                    np.zeros(N_SCALAR_SLOTS), "full", mesh, smooth_cdr_params(rng))
+
+
+def tet_cdr_fn(N: int, seed: int = 2) -> Workload:
+    """Tets with the twenty coefficients as smooth functions of position,
+    4-point rule, full K."""
+    rng = np.random.default_rng(seed)
+    mesh = tet_cube(N, rng)
+    return Workload("tet_cdr_fn", "tet4", "scalar", 4, "function", ALL_SCALAR_MASK,
+                    np.zeros(N_SCALAR_SLOTS), "full", mesh, smooth_cdr_params(rng))

@@ -482,3 +482,66 @@ def test_sliver_prisms_match_extended_precision():
         ek = np.sqrt(((K[e] - Kx) ** 2).sum() / (Kx ** 2).sum())
         ef = np.sqrt(((F[e] - Fx) ** 2).sum() / (Fx ** 2).sum())
         assert ek < 1e-14 and ef < 1e-14, (e, float(ek), float(ef))
+
+
+# ---------------------------------------------------------------- coefficient functions
+def test_function_mode_matches_values_at_the_points():
+    # the function mode evaluates the same fields that smooth_cdr_per_qp
+    # samples at the 6-point rule's points: same parameters -> same matrices
+    seed = 17
+    rng = np.random.default_rng(seed)
+    mesh = inputs.prism_layers(3, 4, rng)
+    vals = inputs.smooth_cdr_per_qp(mesh.coords, inputs.prism_sample_weights(), rng)
+    rng2 = np.random.default_rng(seed)
+    inputs.prism_layers(3, 4, rng2)
+    params = inputs.smooth_cdr_params(rng2)
+    rule = oracle.quad_rule("prism6", 6)
+    Kv, Fv = oracle.integrate("prism6", "scalar", mesh.coords, rule, "qp", inputs.ALL_SCALAR_MASK,
+                              None, vals)
+    Kf, Ff = oracle.integrate("prism6", "scalar", mesh.coords, rule, "function",
+                              inputs.ALL_SCALAR_MASK, None, params)
+    np.testing.assert_allclose(Kf, Kv, rtol=0, atol=1e-12 * np.abs(Kv).max())
+    np.testing.assert_allclose(Ff, Fv, rtol=0, atol=1e-12 * np.abs(Fv).max())
+
+
+def test_function_mode_constant_fields_reduce_to_uniform():
+    # beta = 0 and no SPD transform: every slot is its alpha everywhere
+    rng = np.random.default_rng(19)
+    mesh = inputs.tet_cube(2, rng)
+    p = np.zeros(122)
+    alpha = inputs.cdr_per_element(1, rng)[:, 0]
+    for k in range(20):
+        p[6 * k] = alpha[k]
+        p[6 * k + 2: 6 * k + 5] = (1, 2, 3)
+        p[6 * k + 5] = 0.3
+    rule = oracle.quad_rule("tet4", 4)
+    Ku, Fu = oracle.integrate("tet4", "scalar", mesh.coords, rule, uniform=alpha)
+    Kf, Ff = oracle.integrate("tet4", "scalar", mesh.coords, rule, "function",
+                              inputs.ALL_SCALAR_MASK, None, p)
+    assert np.array_equal(Kf, Ku) and np.array_equal(Ff, Fu)
+    # slots outside the mask take their uniform values
+    Km, Fm = oracle.integrate("tet4", "scalar", mesh.coords, rule, "function", 1 << 16, alpha, p)
+    assert np.array_equal(Km, Ku) and np.array_equal(Fm, Fu)
+
+
+def test_function_mode_spd_transform():
+    # with the transform the diffusion block is A A^T + s I: a field with
+    # A = a constant lower-triangular matrix gives c^{i;j} = (A A^T + s I)_ij
+    rng = np.random.default_rng(23)
+    mesh = inputs.tet_cube(2, rng)
+    A = np.tril(rng.uniform(-1, 1, (3, 3)))
+    p = np.zeros(122)
+    for i in range(3):
+        for j in range(3):
+            p[6 * (4 * (i + 1) + 1 + j)] = A[i, j]
+    p[120], p[121] = 0.25, 1.0
+    u = np.zeros(20)
+    C = A @ A.T + 0.25 * np.eye(3)
+    for i in range(3):
+        for j in range(3):
+            u[4 * (i + 1) + 1 + j] = C[i, j]
+    rule = oracle.quad_rule("tet4", 4)
+    Ku, _ = oracle.integrate("tet4", "scalar", mesh.coords, rule, uniform=u)
+    Kf, _ = oracle.integrate("tet4", "scalar", mesh.coords, rule, "function",
+                             inputs.ALL_SCALAR_MASK, None, p)
+    np.testing.assert_allclose(Kf, Ku, rtol=0, atol=1e-15 * np.abs(Ku).max())

@@ -51,6 +51,10 @@ WORKLOADS = {
                          "prisms 141x141x100 (3,976,200), Laplacian with d^0 per point of the 6-point rule, full K (66 words/element)"),
     "prism_cdr": (lambda: __import__("paper_1504_01023_amd.inputs", fromlist=["x"]).prism_cdr_element(141, 100, 3),
                   "prisms 141x141x100 (3,976,200), 20 coefficients per element, 6-point rule, full K (80 words/element)"),
+    "prism_cdr_fn": (lambda: __import__("paper_1504_01023_amd.inputs", fromlist=["x"]).prism_cdr_fn(141, 100, 3),
+                     "prisms 141x141x100 (3,976,200), 20 smooth coefficient fields evaluated in the kernel at the 6 points, full K"),
+    "tet_cdr_fn": (lambda: __import__("paper_1504_01023_amd.inputs", fromlist=["x"]).tet_cdr_fn(119, 2),
+                   "tets N=119, 20 smooth coefficient fields evaluated in the kernel at the 4 points, full K"),
     "tet_elasticity": (lambda: __import__("paper_1504_01023_amd.inputs", fromlist=["x"]).tet_elasticity(94, 4),
                        "isotropic elasticity on tets N=94 (4,983,504), per-element E, nu, f, 1-point rule, packed 12x12"),
     "prism_elasticity": (lambda: __import__("paper_1504_01023_amd.inputs", fromlist=["x"]).prism_elasticity(100, 100, 4),
@@ -78,6 +82,10 @@ KERNEL_UNITS = {
     ("prism_poisson_qp", "fp32"): "fe_k_prism_scalar_f32_poisson.hip",
     ("prism_cdr", "fp64"): "fe_k_prism_scalar_f64_full.hip",
     ("prism_cdr", "fp32"): "fe_k_prism_scalar_f32_full.hip",
+    ("prism_cdr_fn", "fp64"): "fe_k_prism_scalar_f64_full.hip",
+    ("prism_cdr_fn", "fp32"): "fe_k_prism_scalar_f32_full.hip",
+    ("tet_cdr_fn", "fp64"): "fe_k_tet_scalar_f64_full.hip",
+    ("tet_cdr_fn", "fp32"): "fe_k_tet_scalar_f32_full.hip",
     ("prism_elasticity", "fp32"): "fe_k_prism_elast_f32.hip",
 }
 
@@ -324,8 +332,8 @@ def run_served(a, torch, fe, serve) -> dict:
            "hbm_budget_bytes": budget, "max_slots": a.served_slots, "sequential_plain": seq}
     rng = np.random.default_rng(55)
     sample_ids = set(int(x) for x in rng.choice(n_meas, size=min(20, n_meas), replace=False))
-    with serve.Server(kinds, max_slots=a.served_slots, hbm_budget_bytes=budget, max_chunks=512,
-                      chunk_elems=16384, blocks_per_kind=0) as srv:
+    with serve.Server(kinds, max_slots=a.served_slots, hbm_budget_bytes=budget, max_chunks=2048,
+                      chunk_elems=4096, blocks_per_kind=0) as srv:
         # warm-up
         for r in reqs[:n_warm]:
             cp, kp, ld = host_ptrs(r)
@@ -629,7 +637,9 @@ def main() -> int:
     Ks = K.index_select(1, idx).cpu().numpy().astype(np.float64)
     Fs = F.index_select(1, idx).cpu().numpy().astype(np.float64)
     coeffs = None
-    if wl.coeffs is not None:
+    if wl.coeffs is not None and wl.coef_mode == "function":
+        coeffs = wl.coeffs
+    elif wl.coeffs is not None:
         coeffs = wl.coeffs[:, sample]
         if a.precision == "fp32":
             coeffs = coeffs.astype(np.float32).astype(np.float64)

@@ -99,10 +99,21 @@ typedef enum fe_precision { FE_FP64 = 0, FE_FP32_BULK = 1 } fe_precision;
 
 /* Coefficients constant over the whole element (Sec. 3.3) or given at each
  * quadrature point (the paper's "Poisson" right-hand side, Sec. 4.1). */
+/* FE_COEF_FUNCTION (scalar problems): the slots in coef_mask are computed at
+ * every point from the parameters of a coefficient function (the "problem
+ * dependent parameters used for computing coefficients" of Sec. 2.3):
+ * `coeffs` points to FE_COEF_FN_PARAMS FP64 values in device memory, shared
+ * by all elements; slot k's value at the physical point x is
+ *   p[6k] + p[6k+1] sin(2 pi (p[6k+2] x + p[6k+3] y + p[6k+4] z) + p[6k+5]),
+ * and if p[121] != 0 the diffusion block is then replaced by
+ * A A^T + p[120] I, A being the computed block (a symmetric positive definite
+ * field for p[120] > 0). Evaluated in FP64 in both tiers. */
+#define FE_COEF_FN_PARAMS 122
 typedef enum fe_coef_mode {
     FE_COEF_UNIFORM = 0,
     FE_COEF_PER_ELEMENT = 1,
-    FE_COEF_PER_QP = 2
+    FE_COEF_PER_QP = 2,
+    FE_COEF_FUNCTION = 3
 } fe_coef_mode;
 
 typedef enum fe_k_format { FE_K_FULL = 0, FE_K_SYM_PACKED = 1 } fe_k_format;
@@ -187,7 +198,8 @@ FE_API int64_t fe_k_entries(const fe_problem *problem, fe_elem_type elem_type);
 /* Rows of out_F per element (N). */
 FE_API int64_t fe_f_entries(const fe_problem *problem, fe_elem_type elem_type);
 /* Rows of coeffs for this problem and rule size (popcount(mask) per element,
- * times n_q for per-point data; 0 for uniform). */
+ * times n_q for per-point data; 0 for uniform; FE_COEF_FN_PARAMS values in
+ * total, not per element, for the function mode). */
 FE_API int64_t fe_coeff_entries(const fe_problem *problem, fe_elem_type elem_type, int n_q);
 /* Algorithmic global-memory bytes per element: every input word read once
  * and every output word written once. */
@@ -349,7 +361,9 @@ FE_API int fe_server_submit(fe_server *s, const fe_request *req, uint64_t *id);
 /* Move up to max completions to out, waiting up to timeout_s seconds for the
  * first; returns the number moved, or a negative status. */
 FE_API int fe_server_poll(fe_server *s, fe_completion *out, int max, double timeout_s);
-/* The consumer is done with a completed request's outputs: free its memory. */
+/* The consumer is done with a completed request's outputs: free its memory.
+ * The scheduler returns the memory to the budget on its next pass (the
+ * statistics show it then); the outputs must not be used after this call. */
 FE_API int fe_server_release(fe_server *s, uint64_t id);
 FE_API int fe_server_stats_get(fe_server *s, fe_server_stats *out);
 FE_API int fe_server_reset_stats(fe_server *s);

@@ -135,8 +135,10 @@ static int check_problem(const fe_problem *p, int elem)
         return fail(FE_ERR_INVALID_ARG, "bad problem kind %d", p->kind);
     if (p->precision != FE_FP64 && p->precision != FE_FP32_BULK)
         return fail(FE_ERR_INVALID_ARG, "bad precision %d", p->precision);
-    if (p->coef_mode < FE_COEF_UNIFORM || p->coef_mode > FE_COEF_PER_QP)
+    if (p->coef_mode < FE_COEF_UNIFORM || p->coef_mode > FE_COEF_FUNCTION)
         return fail(FE_ERR_INVALID_ARG, "bad coefficient mode %d", p->coef_mode);
+    if (p->coef_mode == FE_COEF_FUNCTION && p->kind != FE_SCALAR_CDR)
+        return fail(FE_ERR_UNSUPPORTED, "coefficient functions are built for scalar problems");
     if (p->k_format != FE_K_FULL && p->k_format != FE_K_SYM_PACKED)
         return fail(FE_ERR_INVALID_ARG, "bad K format %d", p->k_format);
     if (p->reserved != 0)
@@ -239,8 +241,10 @@ int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coor
             return fail(FE_ERR_INVALID_ARG, "leading dimension smaller than n_elem");
     }
     const size_t tsz = problem->precision == FE_FP64 ? 8 : 4;
+    const bool fn = problem->coef_mode == FE_COEF_FUNCTION;
+    const size_t csz = fn ? 8 : tsz;  // function parameters are FP64
     if (!aligned(coords, 8) || !aligned(out_K, tsz) || !aligned(out_F, tsz) ||
-        (mask && !aligned(coeffs, tsz)) || !aligned(conn, 4))
+        (mask && !aligned(coeffs, csz)) || !aligned(conn, 4))
         return fail(FE_ERR_UNSUPPORTED, "pointers must be aligned to their element size");
 
     KernelKey k{};
@@ -256,6 +260,8 @@ int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coor
     const bool per_qp = problem->coef_mode == FE_COEF_PER_QP;
     if (mask == 0)
         k.mode = M_UNIFORM;
+    else if (fn)
+        k.mode = M_FUNC;
     else if (mask == slots_of_terms(k.terms))
         k.mode = per_qp ? M_QP : M_ELEM;
     else
@@ -290,7 +296,7 @@ int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coor
         if (form == 1 && (ld_conn % V || !aligned(conn, ia)))
             return false;
         return aligned(coords, ca) && aligned(out_K, ta) && aligned(out_F, ta) &&
-               (!mask || aligned(coeffs, ta));
+               (!mask || fn || aligned(coeffs, ta));
     };
     if (!vec_ok(vec)) {
         if (forced && v.elems_per_thread > 1)
@@ -447,6 +453,8 @@ int64_t fe_coeff_entries(const fe_problem *problem, fe_elem_type elem_type, int 
     if (check_problem(problem, elem_type) || n_q < 1 || n_q > FE_MAX_QP)
         return -1;
     const int64_t c = __builtin_popcount(effective_mask(problem));
+    if (problem->coef_mode == FE_COEF_FUNCTION)
+        return c ? FE_COEF_FN_PARAMS : 0;
     return problem->coef_mode == FE_COEF_PER_QP ? c * n_q : c;
 }
 
@@ -458,7 +466,9 @@ int64_t fe_bytes_per_element(const fe_problem *problem, fe_elem_type elem_type, 
     if (nk < 0 || nf < 0 || nc < 0)
         return -1;
     const int64_t t = problem->precision == FE_FP64 ? 8 : 4;
-    return 8 * 3 * n_shape(elem_type) + t * (nc + nk + nf);
+    // function parameters are read once per launch, not per element
+    const int64_t ncpe = problem->coef_mode == FE_COEF_FUNCTION ? 0 : nc;
+    return 8 * 3 * n_shape(elem_type) + t * (ncpe + nk + nf);
 }
 
 int64_t fe_k_index(const fe_problem *problem, fe_elem_type elem_type, int row, int col)

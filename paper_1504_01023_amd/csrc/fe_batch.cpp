@@ -7,8 +7,8 @@
 // different sizes are cut into fixed-size chunks and processed by one
 // persistent launch per kind. The chunk table lives in pinned host memory,
 // is copied to the device by the first node of a HIP graph captured once at
-// creation, and the graph (copy -> one persistent kernel per kind) is
-// replayed for every batch, so a batch costs one graph launch whatever the
+// creation, and the graph (copy -> one persistent kernel per kind, the kinds
+// on parallel branches) is replayed for every batch, so a batch costs one graph launch whatever the
 // number of requests in it. Two tables and two graph instances alternate so
 // the host can fill one while the other is in flight.
 #include <hip/hip_runtime.h>
@@ -55,6 +55,8 @@ struct fe_batch {
     Buffer buf[2];
     int next = 0;
     hipStream_t capture = nullptr;
+    hipStream_t branch[MAX_BATCH_KINDS] = {};
+    hipEvent_t forked = nullptr, joined[MAX_BATCH_KINDS] = {};
 };
 
 static void destroy_batch(fe_batch *b)
@@ -75,6 +77,14 @@ static void destroy_batch(fe_batch *b)
         if (B.host)
             (void)hipHostFree(B.host);
     }
+    for (int k = 0; k < MAX_BATCH_KINDS; ++k) {
+        if (b->branch[k])
+            (void)hipStreamDestroy(b->branch[k]);
+        if (b->joined[k])
+            (void)hipEventDestroy(b->joined[k]);
+    }
+    if (b->forked)
+        (void)hipEventDestroy(b->forked);
     if (b->capture)
         (void)hipStreamDestroy(b->capture);
     delete b;
@@ -149,8 +159,14 @@ int fe_batch_create(const fe_batch_kind *kinds, int n_kinds, int max_chunks, int
         K.tsize = bk.problem.precision == FE_FP64 ? 8 : 4;
         const unsigned per_kind = blocks_per_kind > 0 ? (unsigned)blocks_per_kind : 1024u;
         K.plan.grid = per_kind;
+        K.plan.args.n_elem = chunk_elems;  // the kernel's tile count per chunk
     }
     HIP_TRY(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
+    for (int k = 0; k < n_kinds; ++k) {
+        HIP_TRY(hipStreamCreateWithFlags(&b->branch[k], hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&b->joined[k], hipEventDisableTiming));
+    }
+    HIP_TRY(hipEventCreateWithFlags(&b->forked, hipEventDisableTiming));
     for (Buffer &B : b->buf) {
         HIP_TRY(hipHostMalloc(&B.host, b->table_bytes, hipHostMallocDefault));
         std::memset(B.host, 0, b->table_bytes);
@@ -162,10 +178,20 @@ int fe_batch_create(const fe_batch_kind *kinds, int n_kinds, int max_chunks, int
         const BatchHeader *hdr = static_cast<const BatchHeader *>(B.dev);
         const Chunk *chunks =
             reinterpret_cast<const Chunk *>(static_cast<const char *>(B.dev) + HEADER_BYTES);
+        // One branch per kind after the table copy, so kinds run side by side.
+        if (cerr == hipSuccess)
+            cerr = hipEventRecord(b->forked, b->capture);
         for (int k = 0; k < n_kinds && cerr == hipSuccess; ++k) {
             const Kind &K = b->kinds[k];
-            K.plan.entry->batch(K.plan.args, hdr, chunks, k, K.plan.grid, K.plan.block, b->capture);
+            cerr = hipStreamWaitEvent(b->branch[k], b->forked, 0);
+            if (cerr != hipSuccess)
+                break;
+            K.plan.entry->batch(K.plan.args, hdr, chunks, k, K.plan.grid, K.plan.block, b->branch[k]);
             cerr = hipGetLastError();
+            if (cerr == hipSuccess)
+                cerr = hipEventRecord(b->joined[k], b->branch[k]);
+            if (cerr == hipSuccess)
+                cerr = hipStreamWaitEvent(b->capture, b->joined[k], 0);
         }
         hipError_t eerr = hipStreamEndCapture(b->capture, &B.graph);
         if (cerr != hipSuccess || eerr != hipSuccess) {

@@ -246,6 +246,82 @@ __device__ __forceinline__ void coef(const KArgs &a, const Streams &st, int k, i
     }
 }
 
+// Coefficient functions: slot k's value at the physical point x is
+// alpha_k + beta_k sin(2 pi (omega_k . x) + theta_k), parameters p[6k..6k+5]
+// (read with wave-uniform scalar loads); with p[121] != 0 the diffusion block
+// becomes A A^T + p[120] I. Evaluated in FP64 with the device sin; only the
+// slots of the term set that the mask marks are computed.
+template <uint32_t SL, int V>
+__device__ __forceinline__ void fn_values(const KArgs &a, const double *p, const double (&x)[V][3],
+                                          double (&fv)[20][V])
+{
+    const double two_pi = 6.283185307179586476925286766559;
+#pragma unroll
+    for (int k = 0; k < 20; ++k) {
+        if (!((SL >> k) & 1u))
+            continue;
+        if (a.col[k] < 0) {
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+                fv[k][v] = a.uniform[k];
+            continue;
+        }
+        const double al = p[6 * k], be = p[6 * k + 1], wx = p[6 * k + 2], wy = p[6 * k + 3],
+                     wz = p[6 * k + 4], th = p[6 * k + 5];
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+            fv[k][v] = al + be * sin(two_pi * (wx * x[v][0] + wy * x[v][1] + wz * x[v][2]) + th);
+    }
+    if constexpr ((SL >> 5) & 1u) {
+        if (p[121] != 0.0) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                double A[3][3];
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j)
+                        A[i][j] = fv[4 * (i + 1) + 1 + j][v];
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        double c = A[i][0] * A[j][0] + A[i][1] * A[j][1] + A[i][2] * A[j][2];
+                        if (i == j)
+                            c += p[120];
+                        fv[4 * (i + 1) + 1 + j][v] = c;
+                    }
+            }
+        }
+    }
+}
+
+// Coefficient values at one point for V elements: read from memory or
+// uniform (coef), or computed from the coefficient function.
+template <typename T, int MODE, uint32_t SL, int V, bool NT>
+struct PointCoefs {
+    double fv[MODE == M_FUNC ? 20 : 1][V];
+
+    // x: physical coordinates of the point for each element (function mode)
+    __device__ __forceinline__ void prepare(const KArgs &a, const double (&x)[V][3])
+    {
+        if constexpr (MODE == M_FUNC)
+            fn_values<SL, V>(a, static_cast<const double *>(a.coeffs), x, fv);
+    }
+
+    __device__ __forceinline__ void get(const KArgs &a, const Streams &st, int k, int q,
+                                        int64_t e0, T (&out)[V]) const
+    {
+        if constexpr (MODE == M_FUNC) {
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+                out[v] = (T)fv[k][v];
+        } else {
+            coef<T, MODE, SL, V, NT>(a, st, k, q, e0, out);
+        }
+    }
+};
+
 // Reference tables: kernel arguments or an LDS copy.
 struct RefLds {
     double w[FE_MAX_QP];
@@ -377,7 +453,7 @@ struct TetScalar {
     static constexpr uint32_t SL = slots_of_terms(TERMS);
     static constexpr bool DIFF = TERMS & T_DIFF, CA = TERMS & T_CONVA, CB = TERMS & T_CONVB,
                           MASS = TERMS & T_MASS, DG = TERMS & T_DGRAD, D0 = TERMS & T_D0;
-    static constexpr bool PER_QP = (MODE == M_QP || MODE == M_QP_MIXED);
+    static constexpr bool PER_QP = (MODE == M_QP || MODE == M_QP_MIXED || MODE == M_FUNC);
 
     template <int V, bool NT, int REF, class S>
     __device__ __forceinline__ static void run(const KArgs &a, const S &st, const Ref<REF> &ref,
@@ -532,6 +608,19 @@ struct TetScalar {
             }
         }
         for (int q = 0; q < a.n_q; ++q) {
+            PointCoefs<T, MODE, SL, V, NT> pc;
+            if constexpr (MODE == M_FUNC) {
+                // physical point x(xi_q) = X_0 + sum_r phi_r(xi_q) (X_r - X_0)
+                double x[V][3];
+#pragma unroll
+                for (int v = 0; v < V; ++v)
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+                        x[v][i] = X[v][i] + ref.phi(q, 1) * (X[v][3 + i] - X[v][i]) +
+                                  ref.phi(q, 2) * (X[v][6 + i] - X[v][i]) +
+                                  ref.phi(q, 3) * (X[v][9 + i] - X[v][i]);
+                pc.prepare(a, x);
+            }
             const T w = (T)ref.w(q);
             T wp[4];
 #pragma unroll
@@ -543,7 +632,7 @@ struct TetScalar {
                 for (int i = 0; i < 3; ++i)
 #pragma unroll
                     for (int j = 0; j < 3; ++j) {
-                        coef<T, MODE, SL, V, NT>(a, st, 4 * (i + 1) + 1 + j, q, e0, c);
+                        pc.get(a, st, 4 * (i + 1) + 1 + j, q, e0, c);
 #pragma unroll
                         for (int v = 0; v < V; ++v)
                             Cb[v][i][j] += w * c[v];
@@ -552,7 +641,7 @@ struct TetScalar {
             if constexpr (CA) {
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
-                    coef<T, MODE, SL, V, NT>(a, st, 4 * (i + 1), q, e0, c);
+                    pc.get(a, st, 4 * (i + 1), q, e0, c);
 #pragma unroll
                     for (int v = 0; v < V; ++v)
 #pragma unroll
@@ -563,7 +652,7 @@ struct TetScalar {
             if constexpr (CB) {
 #pragma unroll
                 for (int j = 0; j < 3; ++j) {
-                    coef<T, MODE, SL, V, NT>(a, st, 1 + j, q, e0, c);
+                    pc.get(a, st, 1 + j, q, e0, c);
 #pragma unroll
                     for (int v = 0; v < V; ++v)
 #pragma unroll
@@ -572,7 +661,7 @@ struct TetScalar {
                 }
             }
             if constexpr (MASS) {
-                coef<T, MODE, SL, V, NT>(a, st, 0, q, e0, c);
+                pc.get(a, st, 0, q, e0, c);
 #pragma unroll
                 for (int v = 0; v < V; ++v)
 #pragma unroll
@@ -584,14 +673,14 @@ struct TetScalar {
             if constexpr (DG) {
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
-                    coef<T, MODE, SL, V, NT>(a, st, 17 + i, q, e0, c);
+                    pc.get(a, st, 17 + i, q, e0, c);
 #pragma unroll
                     for (int v = 0; v < V; ++v)
                         Db[v][i] += w * c[v];
                 }
             }
             if constexpr (D0) {
-                coef<T, MODE, SL, V, NT>(a, st, 16, q, e0, c);
+                pc.get(a, st, 16, q, e0, c);
 #pragma unroll
                 for (int v = 0; v < V; ++v)
 #pragma unroll
@@ -658,7 +747,7 @@ struct TetScalar {
 template <typename T, int MODE, int PACKED>
 struct TetElastic {
     static constexpr uint32_t SL = 31u;
-    static constexpr bool PER_QP = (MODE == M_QP || MODE == M_QP_MIXED);
+    static constexpr bool PER_QP = (MODE == M_QP || MODE == M_QP_MIXED || MODE == M_FUNC);
 
     template <int V, bool NT, int REF, class S>
     __device__ __forceinline__ static void run(const KArgs &a, const S &st, const Ref<REF> &ref,
@@ -782,54 +871,77 @@ struct PrismScalar {
     static constexpr uint32_t SL = slots_of_terms(TERMS);
     static constexpr bool DIFF = TERMS & T_DIFF, CA = TERMS & T_CONVA, CB = TERMS & T_CONVB,
                           MASS = TERMS & T_MASS, DG = TERMS & T_DGRAD, D0 = TERMS & T_D0;
-    static constexpr bool PER_QP = (MODE == M_QP || MODE == M_QP_MIXED);
+    static constexpr bool PER_QP = (MODE == M_QP || MODE == M_QP_MIXED || MODE == M_FUNC);
     static constexpr bool NEED_PHI = CA || CB || MASS || D0;
 
     struct Coefs {
         T C[3][3], ca[3], cb[3], c00, d[3], d0;
     };
 
-    template <bool NT>
-    __device__ __forceinline__ static void load_coefs(const KArgs &a, const Streams &st, int q,
-                                                      int64_t e, Coefs &c)
+    // Physical point x(xi_q) = X_0 + sum_r phi_r(xi_q) E_r from the edge
+    // vectors E (function mode only).
+    template <class R>
+    __device__ __forceinline__ static void point_x(const double (&X0)[3], const double (&E)[18],
+                                                   const R &ref, int q, double (&x)[1][3])
     {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            double s = X0[i];
+#pragma unroll
+            for (int r = 1; r < 6; ++r)
+                s += ref.phi(q, r) * E[3 * r + i];
+            x[0][i] = s;
+        }
+    }
+
+    template <bool NT, class R>
+    __device__ __forceinline__ static void load_coefs(const KArgs &a, const Streams &st, const R &ref,
+                                                      int q, int64_t e, const double (&X0)[3],
+                                                      const double (&E)[18], Coefs &c)
+    {
+        PointCoefs<T, MODE, SL, 1, NT> pc;
+        if constexpr (MODE == M_FUNC) {
+            double x[1][3];
+            point_x(X0, E, ref, q, x);
+            pc.prepare(a, x);
+        }
         T x[1];
         if constexpr (DIFF) {
 #pragma unroll
             for (int i = 0; i < 3; ++i)
 #pragma unroll
                 for (int j = 0; j < 3; ++j) {
-                    coef<T, MODE, SL, 1, NT>(a, st, 4 * (i + 1) + 1 + j, q, e, x);
+                    pc.get(a, st, 4 * (i + 1) + 1 + j, q, e, x);
                     c.C[i][j] = x[0];
                 }
         }
         if constexpr (CA) {
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                coef<T, MODE, SL, 1, NT>(a, st, 4 * (i + 1), q, e, x);
+                pc.get(a, st, 4 * (i + 1), q, e, x);
                 c.ca[i] = x[0];
             }
         }
         if constexpr (CB) {
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
-                coef<T, MODE, SL, 1, NT>(a, st, 1 + j, q, e, x);
+                pc.get(a, st, 1 + j, q, e, x);
                 c.cb[j] = x[0];
             }
         }
         if constexpr (MASS) {
-            coef<T, MODE, SL, 1, NT>(a, st, 0, q, e, x);
+            pc.get(a, st, 0, q, e, x);
             c.c00 = x[0];
         }
         if constexpr (DG) {
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                coef<T, MODE, SL, 1, NT>(a, st, 17 + i, q, e, x);
+                pc.get(a, st, 17 + i, q, e, x);
                 c.d[i] = x[0];
             }
         }
         if constexpr (D0) {
-            coef<T, MODE, SL, 1, NT>(a, st, 16, q, e, x);
+            pc.get(a, st, 16, q, e, x);
             c.d0 = x[0];
         }
     }
@@ -845,6 +957,7 @@ struct PrismScalar {
 #pragma unroll
         for (int s = 0; s < 18; ++s)
             X[s] = Xg[0][s];
+        const double X0[3] = {X[0], X[1], X[2]};
         to_edge_vectors<6>(X);
         constexpr int NK = PACKED ? 21 : 36;
         T K[NK], F[6];
@@ -856,12 +969,12 @@ struct PrismScalar {
             F[r] = T(0);
         Coefs c;
         if constexpr (!PER_QP)
-            load_coefs<NT>(a, st, 0, e, c);
+            load_coefs<NT>(a, st, ref, 0, e, X0, X, c);
         const int nq = NQ > 0 ? NQ : a.n_q;
 #pragma unroll(NQ > 0 ? NQ : 1)
         for (int q = 0; q < nq; ++q) {
             if constexpr (PER_QP)
-                load_coefs<NT>(a, st, q, e, c);
+                load_coefs<NT>(a, st, ref, q, e, X0, X, c);
             T g[6][3], vol;
             point_geometry<6, T>(X, ref, q, g, vol);
             T phi[6];
@@ -1023,10 +1136,11 @@ struct PrismScalarOrder {
 #pragma unroll
         for (int s = 0; s < 18; ++s)
             X[s] = Xg[0][s];
+        const double X0[3] = {X[0], X[1], X[2]};
         to_edge_vectors<6>(X);
         typename Q::Coefs c;
         if constexpr (!PER_QP)
-            Q::template load_coefs<NT>(a, st, 0, e, c);
+            Q::template load_coefs<NT>(a, st, ref, 0, e, X0, X, c);
         T *outK = static_cast<T *>(st.out_K);
         T *outF = static_cast<T *>(st.out_F);
         const int nq = a.n_q;
@@ -1039,7 +1153,7 @@ struct PrismScalarOrder {
                     Kr[s] = T(0);
                 for (int q = 0; q < nq; ++q) {
                     if constexpr (PER_QP)
-                        Q::template load_coefs<NT>(a, st, q, e, c);
+                        Q::template load_coefs<NT>(a, st, ref, q, e, X0, X, c);
                     double Ji[3][3], det;
                     point_jinv(X, ref, q, Ji, det);
                     const T vol = (T)(det * ref.w(q));
@@ -1071,7 +1185,7 @@ struct PrismScalarOrder {
                     T acc = T(0), fr = T(0);
                     for (int q = 0; q < nq; ++q) {
                         if constexpr (PER_QP)
-                            Q::template load_coefs<NT>(a, st, q, e, c);
+                            Q::template load_coefs<NT>(a, st, ref, q, e, X0, X, c);
                         double Ji[3][3], det;
                         point_jinv(X, ref, q, Ji, det);
                         const T vol = (T)(det * ref.w(q));
@@ -1108,7 +1222,7 @@ struct PrismScalarOrder {
 template <typename T, int MODE, int PACKED, int NQ, int SPLIT = 1>
 struct PrismElastic {
     static constexpr uint32_t SL = 31u;
-    static constexpr bool PER_QP = (MODE == M_QP || MODE == M_QP_MIXED);
+    static constexpr bool PER_QP = (MODE == M_QP || MODE == M_QP_MIXED || MODE == M_FUNC);
     static constexpr int NP = 171;  // packed entries of the 18 x 18 matrix
 
     template <int V, bool NT>
@@ -1349,20 +1463,26 @@ __global__ __launch_bounds__(256) void fe_batch_kernel(KArgs a, const BatchHeade
         __syncthreads();
     }
     const Ref<REF> ref{a, &lds_ref[0]};
+    // Work is handed out per tile (one element group per lane) across all
+    // chunks of this kind, so a batch of few chunks still fills the grid.
+    // a.n_elem holds the batch's chunk size, the element count of every
+    // chunk but a request's last.
     const int begin = hdr->begin[kind], end = hdr->end[kind];
-    for (int c = begin + (int)blockIdx.x; c < end; c += (int)gridDim.x) {
-        const Chunk ch = chunks[c];
-        const Streams st{ch.coords, ch.coeffs, ch.out_K, ch.out_F, ch.ld_in, ch.ld_out};
+    const int64_t tile = (int64_t)blockDim.x * V;
+    const int64_t tiles_per_chunk = (a.n_elem + tile - 1) / tile;
+    const int64_t n_tiles = (int64_t)(end - begin) * tiles_per_chunk;
+    for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+        const Chunk ch = chunks[begin + (int)(t / tiles_per_chunk)];
+        const int64_t e0 = ch.e0 + (t % tiles_per_chunk) * tile + (int64_t)threadIdx.x * V;
         const int64_t last = ch.e0 + ch.n;
-        const int64_t n_groups = (ch.n + V - 1) / V;
-        for (int64_t g = threadIdx.x; g < n_groups; g += blockDim.x) {
-            const int64_t e0 = ch.e0 + g * V;
-            if (V == 1 || e0 + V <= last) {
-                P::template run<V, NT, REF>(a, st, ref, e0);
-            } else {
-                for (int64_t e = e0; e < last; ++e)
-                    P::template run<1, NT, REF>(a, st, ref, e);
-            }
+        if (e0 >= last)
+            continue;
+        const Streams st{ch.coords, ch.coeffs, ch.out_K, ch.out_F, ch.ld_in, ch.ld_out};
+        if (V == 1 || e0 + V <= last) {
+            P::template run<V, NT, REF>(a, st, ref, e0);
+        } else {
+            for (int64_t e = e0; e < last; ++e)
+                P::template run<1, NT, REF>(a, st, ref, e);
         }
     }
 }

@@ -29,6 +29,7 @@ enum ModeKind : int {
     M_QP = 2,          // per point, dense
     M_ELEM_MIXED = 3,  // per element, slot by slot from memory or arguments
     M_QP_MIXED = 4,    // per point, slot by slot
+    M_FUNC = 5,        // per point, computed from coefficient-function parameters
 };
 
 enum RefKind : int { REF_KARG = 0, REF_LDS = 1 };

@@ -11,14 +11,14 @@ int register_all()
     // every coefficient mode and K format with a runtime point loop
 #define BASE(MODE) \
     reg_prism_scalar<T, TS, MODE, 0, 0, 1, REF_KARG, 1>(); reg_prism_scalar<T, TS, MODE, 1, 0, 1, REF_KARG, 1>();
-    BASE(M_UNIFORM) BASE(M_ELEM) BASE(M_QP) BASE(M_ELEM_MIXED) BASE(M_QP_MIXED)
+    BASE(M_UNIFORM) BASE(M_ELEM) BASE(M_QP) BASE(M_ELEM_MIXED) BASE(M_QP_MIXED) BASE(M_FUNC)
 #undef BASE
     // tuning variants of the runtime point loop: cache policy and LDS
     // staging of the reference tables
 #define TUNE(MODE, PK) \
     reg_prism_scalar<T, TS, MODE, PK, 0, 0, REF_KARG>(); reg_prism_scalar<T, TS, MODE, PK, 0, 1, REF_LDS>(); \
     reg_prism_scalar<T, TS, MODE, PK, 0, 0, REF_LDS>();
-    TUNE(M_QP, 0) TUNE(M_ELEM, 0) TUNE(M_UNIFORM, 1) TUNE(M_UNIFORM, 0)
+    TUNE(M_QP, 0) TUNE(M_ELEM, 0) TUNE(M_UNIFORM, 1) TUNE(M_UNIFORM, 0) TUNE(M_FUNC, 0)
 #undef TUNE
     // the SQS and SSQ loop orders, for the order comparison (the paper's
     // "Poisson": per-point right-hand side; "conv-diff": element constants)

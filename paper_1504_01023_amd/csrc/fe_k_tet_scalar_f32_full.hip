@@ -11,8 +11,10 @@ int register_all()
     // every coefficient mode and K format, base variant (1 element per
     // lane, non-temporal), plain and batched forms
 #define BASE(MODE) reg_tet_scalar<T, TS, MODE, 0, 1, 1, 1>(); reg_tet_scalar<T, TS, MODE, 1, 1, 1, 1>();
-    BASE(M_UNIFORM) BASE(M_ELEM) BASE(M_QP) BASE(M_ELEM_MIXED) BASE(M_QP_MIXED)
+    BASE(M_UNIFORM) BASE(M_ELEM) BASE(M_QP) BASE(M_ELEM_MIXED) BASE(M_QP_MIXED) BASE(M_FUNC)
 #undef BASE
+    reg_tet_scalar<T, TS, M_FUNC, 0, 2, 1>();
+    reg_tet_scalar<T, TS, M_FUNC, 0, 2, 0>();
     // tuning variants: elements per lane and cache policy
 #define TUNE(MODE, PK) \
     reg_tet_scalar<T, TS, MODE, PK, 2, 1, 1>(); reg_tet_scalar<T, TS, MODE, PK, 4, 1>(); \

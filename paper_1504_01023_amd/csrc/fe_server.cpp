@@ -37,6 +37,7 @@
 #include <new>
 #include <thread>
 #include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "fe.h"
@@ -128,6 +129,8 @@ struct Req {
     int status = FE_OK;
     int64_t next_elem = 0;       // first element not yet dispatched
     int64_t chunks_total = 0, chunks_done = 0;
+    int64_t chunks_inflight = 0; // dispatched in ticks that have not finished
+    bool released = false;       // the consumer released it while chunks ran
     hipEvent_t ev_in = nullptr;  // GPU: inputs copied
     double fake_ready = 0;       // FAKE: time the inputs are ready
     double t_submit = 0, t_admit = 0, t_ready = 0, t_done = 0;
@@ -158,22 +161,29 @@ struct fe_server {
     int device = 0;
     double fake_copy_free = 0, fake_dev_free = 0;
 
-    // request bookkeeping (guarded by mu)
-    std::mutex mu;
-    std::condition_variable cv_work, cv_done;
+    // Scheduler-owned state: only the scheduler thread touches these.
     std::deque<uint64_t> queue;
     std::unordered_map<uint64_t, std::unique_ptr<Req>> reqs;
     std::vector<uint64_t> active;  // admitted, not done, in admission order
-    std::deque<fe_completion> done_q;
     std::deque<Tick> ticks;
-    uint64_t next_id = 1;
     int slots_used = 0;
+    std::vector<fe_completion> finished;  // completions of this iteration
+
+    // Hand-over between callers and the scheduler (io_mu, held briefly).
+    std::mutex io_mu;
+    std::condition_variable cv_work, cv_done;
+    std::vector<std::unique_ptr<Req>> inbox;
+    std::vector<uint64_t> release_q;
+    std::deque<fe_completion> done_q;
+    std::unordered_set<uint64_t> completed;  // done, not yet released
+    uint64_t next_id = 1;
     bool stop = false;
     std::thread thread;
 
-    // statistics (guarded by mu)
+    // Statistics (stats_mu).
+    std::mutex stats_mu;
     int64_t n_submitted = 0, n_admitted = 0, n_completed = 0, n_failed = 0, n_ticks = 0;
-    int64_t elements_done = 0;
+    int64_t elements_done = 0, bytes_in_use = 0, bytes_peak = 0, n_queue = 0, n_active = 0;
     std::vector<double> lat, q_t, h2d_t, dev_t;
 };
 
@@ -231,20 +241,12 @@ void complete(fe_server *s, Req &r, int status, double t)
     c.t_admit = r.t_admit;
     c.t_ready = r.t_ready;
     c.t_done = r.t_done;
-    if (status == FE_OK) {
-        ++s->n_completed;
-        s->elements_done += r.n;
-        s->lat.push_back(r.t_done - r.t_submit);
-        s->q_t.push_back(r.t_admit - r.t_submit);
-        s->h2d_t.push_back(r.t_ready - r.t_admit);
-        s->dev_t.push_back(r.t_done - r.t_ready);
-    } else {
-        ++s->n_failed;
+    // A failed request's memory is reused only once no launched chunk of it
+    // can still write there.
+    if (status != FE_OK && r.chunks_inflight == 0)
         free_request_memory(s, r);
-    }
     s->active.erase(std::remove(s->active.begin(), s->active.end(), r.id), s->active.end());
-    s->done_q.push_back(c);
-    s->cv_done.notify_all();
+    s->finished.push_back(c);
 }
 
 // Device bytes a request needs and its layout.
@@ -304,7 +306,10 @@ bool admit_one(fe_server *s)
     r.state = ADMITTED;
     r.t_admit = t;
     ++s->slots_used;
-    ++s->n_admitted;
+    {
+        std::lock_guard<std::mutex> lk(s->stats_mu);
+        ++s->n_admitted;
+    }
     s->active.push_back(r.id);
     const KindInfo &ki = s->kinfo[r.kind];
     if (r.dev_inputs) {
@@ -423,7 +428,12 @@ void launch_tick(fe_server *s)
             return;
         }
     }
-    ++s->n_ticks;
+    for (auto &pr : tk.parts)
+        s->reqs[pr.first]->chunks_inflight += pr.second;
+    {
+        std::lock_guard<std::mutex> lk(s->stats_mu);
+        ++s->n_ticks;
+    }
     s->ticks.push_back(std::move(tk));
 }
 
@@ -434,13 +444,74 @@ bool tick_done(fe_server *s, Tick &tk, double t)
     return hipEventQuery(tk.ev) == hipSuccess;
 }
 
+// Hand completions to the callers and update the statistics.
+void publish(fe_server *s)
+{
+    {
+        std::lock_guard<std::mutex> lk(s->stats_mu);
+        for (const fe_completion &c : s->finished) {
+            if (c.status == FE_OK) {
+                ++s->n_completed;
+                s->elements_done += c.n_elem;
+                s->lat.push_back(c.t_done - c.t_submit);
+                s->q_t.push_back(c.t_admit - c.t_submit);
+                s->h2d_t.push_back(c.t_ready - c.t_admit);
+                s->dev_t.push_back(c.t_done - c.t_ready);
+            } else {
+                ++s->n_failed;
+            }
+        }
+        s->bytes_in_use = s->arena->used();
+        s->bytes_peak = s->arena->peak();
+        s->n_queue = (int64_t)s->queue.size();
+        s->n_active = (int64_t)s->active.size();
+    }
+    if (!s->finished.empty()) {
+        {
+            std::lock_guard<std::mutex> lk(s->io_mu);
+            for (const fe_completion &c : s->finished) {
+                s->done_q.push_back(c);
+                s->completed.insert(c.id);
+            }
+        }
+        s->cv_done.notify_all();
+        s->finished.clear();
+    }
+}
+
 void loop(fe_server *s)
 {
     if (!s->fake)
         (void)hipSetDevice(s->device);
-    std::unique_lock<std::mutex> lk(s->mu);
-    while (!s->stop) {
-        bool progress = false;
+    std::vector<std::unique_ptr<Req>> arrived;
+    std::vector<uint64_t> released;
+    for (;;) {
+        {
+            std::lock_guard<std::mutex> lk(s->io_mu);
+            if (s->stop)
+                break;
+            arrived.swap(s->inbox);
+            released.swap(s->release_q);
+        }
+        bool progress = !arrived.empty() || !released.empty();
+        for (auto &r : arrived) {
+            const uint64_t id = r->id;
+            s->queue.push_back(id);
+            s->reqs[id] = std::move(r);
+        }
+        arrived.clear();
+        for (uint64_t id : released) {
+            auto it = s->reqs.find(id);
+            if (it == s->reqs.end())
+                continue;
+            if (it->second->chunks_inflight > 0) {
+                it->second->released = true;  // freed when its last tick ends
+                continue;
+            }
+            free_request_memory(s, *it->second);
+            s->reqs.erase(it);
+        }
+        released.clear();
         while (admit_one(s))
             progress = true;
         double t = now_s();
@@ -462,9 +533,17 @@ void loop(fe_server *s)
             give_event(s, tk.ev);
             for (auto &pr : tk.parts) {
                 auto it = s->reqs.find(pr.first);
-                if (it == s->reqs.end() || it->second->state == DONE)
-                    continue;
                 Req &r = *it->second;
+                r.chunks_inflight -= pr.second;
+                if (r.state == DONE) {
+                    // failed while this tick ran: its memory is free to go now
+                    if (r.chunks_inflight == 0) {
+                        free_request_memory(s, r);
+                        if (r.released)
+                            s->reqs.erase(it);
+                    }
+                    continue;
+                }
                 r.chunks_done += pr.second;
                 if (r.chunks_done >= r.chunks_total && r.next_elem >= r.n)
                     complete(s, r, FE_OK, t);
@@ -476,11 +555,13 @@ void loop(fe_server *s)
             launch_tick(s);
             progress = progress || s->ticks.size() != before;
         }
+        publish(s);
         if (!progress) {
             // Poll quickly while work is in flight; sleep until woken otherwise.
             const bool busy = !s->ticks.empty() || !s->active.empty();
-            s->cv_work.wait_for(lk, busy ? std::chrono::microseconds(20)
-                                         : std::chrono::milliseconds(5));
+            std::unique_lock<std::mutex> lk(s->io_mu);
+            s->cv_work.wait_for(lk, busy ? std::chrono::microseconds(20) : std::chrono::milliseconds(5),
+                                [&] { return s->stop || !s->inbox.empty() || !s->release_q.empty(); });
         }
     }
 }
@@ -490,7 +571,7 @@ void destroy_server(fe_server *s)
     if (!s)
         return;
     {
-        std::lock_guard<std::mutex> lk(s->mu);
+        std::lock_guard<std::mutex> lk(s->io_mu);
         s->stop = true;
     }
     s->cv_work.notify_all();
@@ -654,13 +735,15 @@ int fe_server_submit(fe_server *s, const fe_request *req, uint64_t *id)
     }
     r->t_submit = now_s();
     {
-        std::lock_guard<std::mutex> lk(s->mu);
+        std::lock_guard<std::mutex> lk(s->stats_mu);
+        ++s->n_submitted;
+    }
+    {
+        std::lock_guard<std::mutex> lk(s->io_mu);
         r->id = s->next_id++;
         if (id)
             *id = r->id;
-        s->queue.push_back(r->id);
-        ++s->n_submitted;
-        s->reqs[r->id] = std::move(r);
+        s->inbox.push_back(std::move(r));
     }
     s->cv_work.notify_all();
     return FE_OK;
@@ -670,7 +753,7 @@ int fe_server_poll(fe_server *s, fe_completion *out, int max, double timeout_s)
 {
     if (!s || !out || max < 1)
         return -FE_ERR_INVALID_ARG;
-    std::unique_lock<std::mutex> lk(s->mu);
+    std::unique_lock<std::mutex> lk(s->io_mu);
     if (s->done_q.empty() && timeout_s > 0)
         s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s),
                             [&] { return !s->done_q.empty(); });
@@ -687,15 +770,16 @@ int fe_server_release(fe_server *s, uint64_t id)
     if (!s)
         return fail(FE_ERR_INVALID_ARG, "server is NULL");
     {
-        std::lock_guard<std::mutex> lk(s->mu);
-        auto it = s->reqs.find(id);
-        if (it == s->reqs.end())
+        std::lock_guard<std::mutex> lk(s->io_mu);
+        auto it = s->completed.find(id);
+        if (it == s->completed.end()) {
+            if (id >= 1 && id < s->next_id)
+                return fail(FE_ERR_INVALID_ARG, "request %llu has not completed or was released",
+                            (unsigned long long)id);
             return fail(FE_ERR_INVALID_ARG, "unknown request %llu", (unsigned long long)id);
-        if (it->second->state != DONE)
-            return fail(FE_ERR_INVALID_ARG, "request %llu has not completed",
-                        (unsigned long long)id);
-        free_request_memory(s, *it->second);
-        s->reqs.erase(it);
+        }
+        s->completed.erase(it);
+        s->release_q.push_back(id);
     }
     s->cv_work.notify_all();
     return FE_OK;
@@ -705,16 +789,16 @@ int fe_server_stats_get(fe_server *s, fe_server_stats *out)
 {
     if (!s || !out)
         return fail(FE_ERR_INVALID_ARG, "server or out is NULL");
-    std::lock_guard<std::mutex> lk(s->mu);
+    std::lock_guard<std::mutex> lk(s->stats_mu);
     std::memset(out, 0, sizeof(*out));
     out->submitted = s->n_submitted;
     out->admitted = s->n_admitted;
     out->completed = s->n_completed;
     out->failed = s->n_failed;
-    out->in_queue = (int64_t)s->queue.size();
-    out->in_flight = (int64_t)s->active.size();
-    out->bytes_in_use = s->arena->used();
-    out->bytes_peak = s->arena->peak();
+    out->in_queue = s->n_queue;
+    out->in_flight = s->n_active;
+    out->bytes_in_use = s->bytes_in_use;
+    out->bytes_peak = s->bytes_peak;
     out->elements_done = s->elements_done;
     out->ticks = s->n_ticks;
     out->p50_s = percentile(s->lat, 0.50);
@@ -730,7 +814,7 @@ int fe_server_reset_stats(fe_server *s)
 {
     if (!s)
         return fail(FE_ERR_INVALID_ARG, "server is NULL");
-    std::lock_guard<std::mutex> lk(s->mu);
+    std::lock_guard<std::mutex> lk(s->stats_mu);
     s->n_submitted = s->n_admitted = s->n_completed = s->n_failed = s->n_ticks = 0;
     s->elements_done = 0;
     s->lat.clear();

@@ -20,13 +20,15 @@ LIB_PATH = os.path.join(_PKG, "libfe.so")
 TET4, PRISM6 = 0, 1
 SCALAR_CDR, ELASTICITY = 0, 1
 FP64, FP32_BULK = 0, 1
-COEF_UNIFORM, COEF_PER_ELEMENT, COEF_PER_QP = 0, 1, 2
+COEF_UNIFORM, COEF_PER_ELEMENT, COEF_PER_QP, COEF_FUNCTION = 0, 1, 2, 3
+FN_PARAMS = 122
 K_FULL, K_SYM_PACKED = 0, 1
 MAX_QP = 8
 
 ELEM = {"tet4": TET4, "prism6": PRISM6}
 KIND = {"scalar": SCALAR_CDR, "elasticity": ELASTICITY}
-MODE = {"uniform": COEF_UNIFORM, "element": COEF_PER_ELEMENT, "qp": COEF_PER_QP}
+MODE = {"uniform": COEF_UNIFORM, "element": COEF_PER_ELEMENT, "qp": COEF_PER_QP,
+        "function": COEF_FUNCTION}
 KFMT = {"full": K_FULL, "packed": K_SYM_PACKED}
 PREC = {"fp64": FP64, "fp32": FP32_BULK}
 
@@ -202,6 +204,16 @@ def _check_tensor(t, name, dtype, rows, ld):
                          f"{tuple(t.shape)}")
 
 
+def _check_coeffs(p: Problem, coeffs, dt, nc, ld_in):
+    import torch
+    if p.coef_mode == COEF_FUNCTION:
+        if not (coeffs.is_cuda and coeffs.dtype == torch.float64 and coeffs.is_contiguous()
+                and coeffs.numel() == FN_PARAMS):
+            raise ValueError(f"function parameters must be {FN_PARAMS} contiguous float64 GPU values")
+        return
+    _check_tensor(coeffs, "coeffs", dt, nc, ld_in)
+
+
 def integrate(p: Problem, elem, coords, coeffs, rule: Rule, out_K=None, out_F=None,
               n_elem: int | None = None, variant: Variant | None = None, stream=None):
     """Enqueue the integration of n_elem elements (default: all columns of
@@ -223,7 +235,7 @@ def integrate(p: Problem, elem, coords, coeffs, rule: Rule, out_K=None, out_F=No
     if nc > 0:
         if coeffs is None:
             raise ValueError("this problem reads coefficients from memory; coeffs is None")
-        _check_tensor(coeffs, "coeffs", dt, nc, ld_in)
+        _check_coeffs(p, coeffs, dt, nc, ld_in)
     _check_tensor(out_K, "out_K", dt, nk, ld_out)
     _check_tensor(out_F, "out_F", dt, nf, ld_out)
     cptr = ctypes.c_void_p(coeffs.data_ptr()) if (coeffs is not None and nc > 0) else None
@@ -255,9 +267,9 @@ def integrate_indexed(p: Problem, elem, nodes, conn, coeffs, rule: Rule, out_K=N
         raise ValueError("nodes must be a contiguous (n_nodes, 3) float64 GPU tensor")
     _check_tensor(conn, "conn", torch.int32, nv, ld_conn)
     nc = coeff_entries(p, e, rule.n_q)
-    ld_in = coeffs.shape[1] if (coeffs is not None and nc > 0) else n
+    ld_in = coeffs.shape[1] if (coeffs is not None and nc > 0 and coeffs.dim() == 2) else n
     if nc > 0:
-        _check_tensor(coeffs, "coeffs", dt, nc, ld_in)
+        _check_coeffs(p, coeffs, dt, nc, ld_in)
     ld_out = out_K.shape[1]
     _check_tensor(out_K, "out_K", dt, nk, ld_out)
     _check_tensor(out_F, "out_F", dt, nf, ld_out)
@@ -341,7 +353,9 @@ def to_device(wl, precision="fp64", device="cuda", rule: Rule | None = None) -> 
     r = rule if rule is not None else builtin_rule(wl.elem, wl.n_q)
     coords = torch.from_numpy(wl.mesh.coords).to(device)
     coeffs = None
-    if wl.coeffs is not None and wl.coef_mode != "uniform":
+    if wl.coeffs is not None and wl.coef_mode == "function":
+        coeffs = torch.from_numpy(np.ascontiguousarray(wl.coeffs, dtype=np.float64)).to(device)
+    elif wl.coeffs is not None and wl.coef_mode != "uniform":
         dt = torch.float64 if precision == "fp64" else torch.float32
         coeffs = torch.from_numpy(np.ascontiguousarray(wl.coeffs)).to(device=device, dtype=dt)
     return DeviceWorkload(wl, precision, p, r, coords, coeffs)

@@ -68,8 +68,8 @@ def now() -> float:
 
 
 class Server:
-    def __init__(self, kinds, max_slots=64, hbm_budget_bytes=64 << 30, max_chunks=512,
-                 chunk_elems=16384, blocks_per_kind=0, backend=GPU, fake_ns_per_elem=0.1,
+    def __init__(self, kinds, max_slots=64, hbm_budget_bytes=64 << 30, max_chunks=2048,
+                 chunk_elems=4096, blocks_per_kind=0, backend=GPU, fake_ns_per_elem=0.1,
                  fake_h2d_bytes_per_s=50e9, fake_tick_overhead_s=20e-6):
         """kinds: list of (Problem, elem, Rule)."""
         L = fe.lib()

@@ -24,6 +24,8 @@ def n_dof(wl) -> int:
 def oracle_coeffs(wl, precision):
     if wl.coeffs is None:
         return None
+    if wl.coef_mode == "function":
+        return wl.coeffs  # FP64 parameters in both tiers
     if precision == "fp32":
         return wl.coeffs.astype(np.float32).astype(np.float64)
     return wl.coeffs
@@ -33,7 +35,8 @@ def oracle_run(wl, precision="fp64", elements=None, rule=None):
     coords, coeffs = wl.mesh.coords, oracle_coeffs(wl, precision)
     if elements is not None:
         coords = np.ascontiguousarray(coords[:, elements])
-        coeffs = None if coeffs is None else np.ascontiguousarray(coeffs[:, elements])
+        if coeffs is not None and wl.coef_mode != "function":
+            coeffs = np.ascontiguousarray(coeffs[:, elements])
     r = rule if rule is not None else oracle.quad_rule(wl.elem, wl.n_q)
     return oracle.integrate(wl.elem, wl.kind, coords, r, wl.coef_mode, wl.mask, wl.uniform,
                             coeffs, ORACLE_THREADS)
@@ -87,6 +90,8 @@ SMALL = {
     "prism_cdr": lambda: inputs.prism_cdr_element(9, 7, seed=13),
     "tet_elasticity": lambda: inputs.tet_elasticity(7, seed=4),
     "prism_elasticity": lambda: inputs.prism_elasticity(6, 6, seed=14),
+    "tet_cdr_fn": lambda: inputs.tet_cdr_fn(6, seed=15),
+    "prism_cdr_fn": lambda: inputs.prism_cdr_fn(8, 6, seed=16),
 }
 
 

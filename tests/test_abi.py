@@ -198,3 +198,13 @@ def test_tuning_table_roundtrip(tmp_path):
     fe.tuning_load(path)
     assert fe.tuning_get(p, "tet4", 1) == (128, 2, 2, 1, 0, 1, 1)
     fe.tuning_clear()
+
+
+def test_function_mode_sizes_and_validation():
+    p = fe.problem("scalar", "fp64", "function", (1 << 20) - 1, None, "full")
+    assert fe.coeff_entries(p, "prism6", 6) == 122
+    # parameters are not per-element traffic
+    assert fe.bytes_per_element(p, "prism6", 6) == 144 + 8 * (36 + 6)
+    el = fe.problem("elasticity", "fp64", "function", 31, None, "packed")
+    assert _call(el, coeffs=0x4000) == 2
+    assert _call(p, coeffs=None) == 1

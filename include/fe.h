@@ -362,8 +362,8 @@ FE_API int fe_server_submit(fe_server *s, const fe_request *req, uint64_t *id);
  * first; returns the number moved, or a negative status. */
 FE_API int fe_server_poll(fe_server *s, fe_completion *out, int max, double timeout_s);
 /* The consumer is done with a completed request's outputs: free its memory.
- * The scheduler returns the memory to the budget on its next pass (the
- * statistics show it then); the outputs must not be used after this call. */
+ * Returns once the scheduler has put the memory back into the budget (the
+ * statistics show it); the outputs must not be used after this call. */
 FE_API int fe_server_release(fe_server *s, uint64_t id);
 FE_API int fe_server_stats_get(fe_server *s, fe_server_stats *out);
 FE_API int fe_server_reset_stats(fe_server *s);

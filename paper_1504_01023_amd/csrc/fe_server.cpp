@@ -177,6 +177,7 @@ struct fe_server {
     std::deque<fe_completion> done_q;
     std::unordered_set<uint64_t> completed;  // done, not yet released
     uint64_t next_id = 1;
+    uint64_t release_posted = 0, release_done = 0;  // release calls queued / applied
     bool stop = false;
     std::thread thread;
 
@@ -486,13 +487,16 @@ void loop(fe_server *s)
     std::vector<std::unique_ptr<Req>> arrived;
     std::vector<uint64_t> released;
     for (;;) {
+        uint64_t release_seq = 0;
         {
             std::lock_guard<std::mutex> lk(s->io_mu);
             if (s->stop)
                 break;
             arrived.swap(s->inbox);
             released.swap(s->release_q);
+            release_seq = s->release_posted;
         }
+        const bool had_releases = !released.empty();
         bool progress = !arrived.empty() || !released.empty();
         for (auto &r : arrived) {
             const uint64_t id = r->id;
@@ -556,6 +560,13 @@ void loop(fe_server *s)
             progress = progress || s->ticks.size() != before;
         }
         publish(s);
+        if (had_releases) {
+            {
+                std::lock_guard<std::mutex> lk(s->io_mu);
+                s->release_done = release_seq;
+            }
+            s->cv_done.notify_all();
+        }
         if (!progress) {
             // Poll quickly while work is in flight; sleep until woken otherwise.
             const bool busy = !s->ticks.empty() || !s->active.empty();
@@ -575,6 +586,7 @@ void destroy_server(fe_server *s)
         s->stop = true;
     }
     s->cv_work.notify_all();
+    s->cv_done.notify_all();
     if (s->thread.joinable())
         s->thread.join();
     if (!s->fake) {
@@ -769,6 +781,7 @@ int fe_server_release(fe_server *s, uint64_t id)
 {
     if (!s)
         return fail(FE_ERR_INVALID_ARG, "server is NULL");
+    uint64_t seq = 0;
     {
         std::lock_guard<std::mutex> lk(s->io_mu);
         auto it = s->completed.find(id);
@@ -780,8 +793,12 @@ int fe_server_release(fe_server *s, uint64_t id)
         }
         s->completed.erase(it);
         s->release_q.push_back(id);
+        seq = ++s->release_posted;
     }
     s->cv_work.notify_all();
+    // Return once the scheduler has put the memory back into the budget.
+    std::unique_lock<std::mutex> lk(s->io_mu);
+    s->cv_done.wait(lk, [&] { return s->release_done >= seq || s->stop; });
     return FE_OK;
 }
 

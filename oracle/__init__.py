@@ -21,11 +21,11 @@ _SRC = os.path.join(_HERE, "fe_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 TET4, PRISM6 = 0, 1
-SCALAR, ELASTICITY = 0, 1
+SCALAR, ELASTICITY, VECTOR = 0, 1, 2
 UNIFORM, PER_ELEMENT, PER_QP, FUNCTION = 0, 1, 2, 3
 
 _ELEM = {"tet4": TET4, "prism6": PRISM6}
-_KIND = {"scalar": SCALAR, "elasticity": ELASTICITY}
+_KIND = {"scalar": SCALAR, "elasticity": ELASTICITY, "vector": VECTOR}
 _MODE = {"uniform": UNIFORM, "element": PER_ELEMENT, "qp": PER_QP, "function": FUNCTION}
 
 
@@ -92,7 +92,7 @@ def shape(elem: str, xi):
 
 
 def n_dof(elem: str, kind: str) -> int:
-    return (4 if elem == "tet4" else 6) * (3 if kind == "elasticity" else 1)
+    return (4 if elem == "tet4" else 6) * (1 if kind == "scalar" else 3)
 
 
 def integrate(elem: str, kind: str, coords, rule, coef_mode: str = "uniform", mask: int = 0,
@@ -101,13 +101,15 @@ def integrate(elem: str, kind: str, coords, rule, coef_mode: str = "uniform", ma
 
     ``coords`` is the SoA (n_vert*3, n) array; ``coeffs`` the compact
     coefficient array (float64, or float32 promoted exactly); ``rule`` a pair
-    (xi (n_q,3), w (n_q,))."""
+    (xi (n_q,3), w (n_q,)). For kind "vector" (156 slots) ``mask`` has one
+    bit per block (bits 0..15: the 3x3 blocks c^{a;b}, bits 16..19: the
+    3-vectors d^a) and absent blocks are zero."""
     coords = np.ascontiguousarray(coords, dtype=np.float64)
     n = coords.shape[1]
     N = n_dof(elem, kind)
     xi = np.ascontiguousarray(rule[0], dtype=np.float64).reshape(-1, 3)
     w = np.ascontiguousarray(rule[1], dtype=np.float64).reshape(-1)
-    n_slots = 20 if kind == "scalar" else 5
+    n_slots = {"scalar": 20, "elasticity": 5, "vector": 20}[kind]
     u = np.zeros(20)
     if uniform is not None:
         u[: len(uniform)] = np.asarray(uniform, dtype=np.float64)

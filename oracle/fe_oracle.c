@@ -32,7 +32,12 @@
  *    isotropic elasticity tensor is C_{i alpha j beta} = lambda d_{i alpha}
  *    d_{j beta} + mu (d_ij d_{alpha beta} + d_{i beta} d_{j alpha}) for the
  *    product w^alpha_{,i} u^beta_{,j}, lambda and mu from E and nu, and the
- *    body force enters as d^0_alpha.
+ *    body force enters as d^0_alpha;
+ *  - the general 3-component problem (every c^{a;b} and d^a of the weak form
+ *    a 3x3 matrix or 3-vector over the components, Sec. 2.1 and 3.3) keeps the
+ *    component of the test function first: c^{a;b}_{alpha beta} multiplies
+ *    the alpha component of the test function and the beta component of the
+ *    trial function.
  *
  * Input layouts (identical to what the GPU library consumes):
  *  coords[(v*3+d)*ld + e]; coefficient array in "compact" form: only the
@@ -42,6 +47,11 @@
  *  16+a -> d[a]. Elasticity slots: E, nu, f_x, f_y, f_z. In the function
  *  mode `coeffs` holds the 122 parameters of the coefficient function (see
  *  fn_raw) and the slots in `mask` are computed from it at every point.
+ *  General 3-component problem: 156 slots, (4a+b)*9 + 3 alpha + beta ->
+ *  c^{a;b}_{alpha beta} for the first 144 and 144 + 3a + alpha -> d^a_alpha;
+ *  `mask` has one bit per block (bit 4a+b: the nine c^{a;b}_{..}; bit 16+a:
+ *  the three d^a_.), a block whose bit is clear is zero, and the compact
+ *  array holds the slots of the present blocks in slot order.
  *
  * Output: full matrices, element-major: K[e*N*N + row*N + col], F[e*N + row],
  * N = number of shape functions times components.
@@ -58,6 +68,8 @@
 #define OR_PRISM6 1
 #define OR_SCALAR 0
 #define OR_ELASTICITY 1
+#define OR_VECTOR 2
+#define OR_MAX_SLOTS 156
 #define OR_UNIFORM 0
 #define OR_PER_ELEMENT 1
 #define OR_PER_QP 2
@@ -241,7 +253,7 @@ typedef struct {
     const double *xi, *w;
     double *K, *F;
     int n_slots;
-    int slot_col[20]; /* compact column of each slot, -1 = uniform */
+    int slot_col[OR_MAX_SLOTS]; /* compact column of each slot, -1 = uniform (or 0) */
     const double *fn; /* coefficient-function parameters (OR_FUNCTION) */
 } job_t;
 
@@ -249,7 +261,7 @@ typedef struct {
     /* per-thread scratch, sized by n_q */
     double *vol;   /* [n_q] */
     double *phi;   /* [4][6][n_q]: phi[(d*6 + r)*n_q + q] */
-    double *par;   /* [n_q][20] slot values */
+    double *par;   /* [n_q][OR_MAX_SLOTS] slot values */
     double *c;     /* scalar: [4][4][n_q]; elasticity: [4][4][3][3][n_q] */
     double *d;     /* scalar: [4][n_q];    elasticity: [4][3][n_q] */
 } scratch_t;
@@ -297,7 +309,7 @@ static double kd(int a, int b) { return a == b ? 1.0 : 0.0; }
 static void integrate_element(const job_t *jb, scratch_t *sc, int64_t e)
 {
     const int ns = n_shape(jb->elem);
-    const int nc = (jb->kind == OR_ELASTICITY) ? 3 : 1;
+    const int nc = (jb->kind == OR_SCALAR) ? 1 : 3;
     const int N = ns * nc;
     const int nq = jb->n_q;
     double *Ke = jb->K + (size_t)e * N * N;
@@ -317,7 +329,7 @@ static void integrate_element(const job_t *jb, scratch_t *sc, int64_t e)
             physical_point(jb->elem, &jb->xi[3 * q], X, x);
         for (int k = 0; k < jb->n_slots; ++k) {
             const int j = jb->slot_col[k];
-            double v = jb->uniform[k];
+            double v = (jb->kind == OR_VECTOR) ? 0.0 : jb->uniform[k];
             if (j >= 0) {
                 if (jb->coef_mode == OR_FUNCTION)
                     v = fn_raw(jb->fn, k, x);
@@ -326,10 +338,10 @@ static void integrate_element(const job_t *jb, scratch_t *sc, int64_t e)
                 else
                     v = jb->coeffs[(int64_t)j * jb->ldc + e];
             }
-            sc->par[q * 20 + k] = v;
+            sc->par[q * OR_MAX_SLOTS + k] = v;
         }
         if (jb->coef_mode == OR_FUNCTION)
-            fn_spd_diffusion(jb->fn, &sc->par[q * 20]);
+            fn_spd_diffusion(jb->fn, &sc->par[q * OR_MAX_SLOTS]);
     }
 
     /* initialise A^e and b^e */
@@ -360,13 +372,23 @@ static void integrate_element(const job_t *jb, scratch_t *sc, int64_t e)
 
     /* loop over points: coefficients c and d at the points */
     for (int q = 0; q < nq; ++q) {
-        const double *p = &sc->par[q * 20];
+        const double *p = &sc->par[q * OR_MAX_SLOTS];
         if (jb->kind == OR_SCALAR) {
             for (int a = 0; a < 4; ++a) {
                 for (int b = 0; b < 4; ++b)
                     sc->c[(a * 4 + b) * nq + q] = p[4 * a + b];
                 sc->d[a * nq + q] = p[16 + a];
             }
+        } else if (jb->kind == OR_VECTOR) {
+            for (int a = 0; a < 4; ++a)
+                for (int b = 0; b < 4; ++b)
+                    for (int al = 0; al < 3; ++al)
+                        for (int be = 0; be < 3; ++be)
+                            sc->c[(((a * 4 + b) * 3 + al) * 3 + be) * nq + q] =
+                                p[(4 * a + b) * 9 + 3 * al + be];
+            for (int a = 0; a < 4; ++a)
+                for (int al = 0; al < 3; ++al)
+                    sc->d[(a * 3 + al) * nq + q] = p[144 + 3 * a + al];
         } else {
             const double E = p[0], nu = p[1];
             const double lambda = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
@@ -438,7 +460,7 @@ static void *run_range(void *arg)
     scratch_t sc;
     sc.vol = (double *)malloc(sizeof(double) * nq);
     sc.phi = (double *)malloc(sizeof(double) * 4 * 6 * nq);
-    sc.par = (double *)malloc(sizeof(double) * 20 * nq);
+    sc.par = (double *)malloc(sizeof(double) * OR_MAX_SLOTS * nq);
     sc.c = (double *)malloc(sizeof(double) * 4 * 4 * 9 * nq);
     sc.d = (double *)malloc(sizeof(double) * 4 * 3 * nq);
     if (!sc.vol || !sc.phi || !sc.par || !sc.c || !sc.d) {
@@ -463,9 +485,12 @@ int oracle_integrate(int elem, int kind, int coef_mode, unsigned mask, const dou
                      int64_t ldc, int n_q, const double *xi, const double *w, double *K,
                      double *F, int n_threads)
 {
-    if ((elem != OR_TET4 && elem != OR_PRISM6) || (kind != OR_SCALAR && kind != OR_ELASTICITY) ||
+    if ((elem != OR_TET4 && elem != OR_PRISM6) ||
+        (kind != OR_SCALAR && kind != OR_ELASTICITY && kind != OR_VECTOR) ||
         coef_mode < OR_UNIFORM || coef_mode > OR_FUNCTION || n_elem < 0 || n_q < 1 || !uniform ||
         !xi || !w)
+        return OR_EINVAL;
+    if (kind == OR_VECTOR && coef_mode != OR_PER_ELEMENT && coef_mode != OR_PER_QP)
         return OR_EINVAL;
     if (n_elem == 0)
         return OR_OK;
@@ -476,11 +501,21 @@ int oracle_integrate(int elem, int kind, int coef_mode, unsigned mask, const dou
     jb.elem = elem;
     jb.kind = kind;
     jb.coef_mode = coef_mode;
-    jb.n_slots = (kind == OR_SCALAR) ? 20 : 5;
-    jb.mask = (coef_mode == OR_UNIFORM) ? 0u : (mask & ((1u << jb.n_slots) - 1u));
     int col = 0;
-    for (int k = 0; k < jb.n_slots; ++k)
-        jb.slot_col[k] = (jb.mask >> k & 1u) ? col++ : -1;
+    if (kind == OR_VECTOR) {
+        /* one mask bit per block of slots */
+        jb.n_slots = OR_MAX_SLOTS;
+        jb.mask = mask & 0xFFFFFu;
+        for (int k = 0; k < OR_MAX_SLOTS; ++k) {
+            const int block = (k < 144) ? k / 9 : 16 + (k - 144) / 3;
+            jb.slot_col[k] = (jb.mask >> block & 1u) ? col++ : -1;
+        }
+    } else {
+        jb.n_slots = (kind == OR_SCALAR) ? 20 : 5;
+        jb.mask = (coef_mode == OR_UNIFORM) ? 0u : (mask & ((1u << jb.n_slots) - 1u));
+        for (int k = 0; k < jb.n_slots; ++k)
+            jb.slot_col[k] = (jb.mask >> k & 1u) ? col++ : -1;
+    }
     if (coef_mode == OR_FUNCTION) {
         if (kind != OR_SCALAR || (col > 0 && !coeffs))
             return OR_EINVAL;

@@ -251,6 +251,64 @@ def elasticity_per_element(n_elem: int, rng: np.random.Generator) -> np.ndarray:
     return out
 
 
+N_VECTOR_SLOTS = 156
+ALL_VECTOR_MASK = (1 << 20) - 1   # one bit per block of the 3-component problem
+
+
+def vector_slot(a: int, b: int | None, alpha: int, beta: int | None = None) -> int:
+    """Slot of c^{a;b}_{alpha beta} (b, beta given) or d^a_alpha (b None)."""
+    if b is None:
+        return 144 + 3 * a + alpha
+    return (4 * a + b) * 9 + 3 * alpha + beta
+
+
+def vector_block_rows(mask: int) -> int:
+    """Rows of the compact coefficient array of a 3-component problem."""
+    return sum((9 if k < 16 else 3) for k in range(20) if mask >> k & 1)
+
+
+def vector_per_element(n_elem: int, rng: np.random.Generator) -> np.ndarray:
+    """All 156 coefficients of the general 3-component problem, constant per
+    element, (156, n_elem) in slot order.
+
+    Draw order: B ~ U[-1,1]^{9x9} giving the diffusion tensor over the index
+    pairs (i alpha), (j beta) as B B^T / 9 + I/2 (positive definite, so the
+    operator is strongly elliptic); then c^{i;0}, c^{0;i} ~ U[-1,1]^{3x3x3},
+    c^{0;0} ~ U[0,1]^{3x3}, d^i ~ U[-1,1]^{3x3}, d^0 ~ U[-1,1]^3."""
+    B = rng.uniform(-1.0, 1.0, (n_elem, 9, 9))
+    D = np.einsum("epk,eqk->epq", B, B) / 9.0 + 0.5 * np.eye(9)   # [(3i+alpha), (3j+beta)]
+    ci0 = rng.uniform(-1.0, 1.0, (n_elem, 3, 3, 3))   # [i, alpha, beta]
+    c0i = rng.uniform(-1.0, 1.0, (n_elem, 3, 3, 3))
+    c00 = rng.uniform(0.0, 1.0, (n_elem, 3, 3))
+    di = rng.uniform(-1.0, 1.0, (n_elem, 3, 3))       # [i, alpha]
+    d0 = rng.uniform(-1.0, 1.0, (n_elem, 3))
+    out = np.zeros((N_VECTOR_SLOTS, n_elem))
+    for al in range(3):
+        for be in range(3):
+            out[vector_slot(0, 0, al, be)] = c00[:, al, be]
+            for i in range(3):
+                out[vector_slot(i + 1, 0, al, be)] = ci0[:, i, al, be]
+                out[vector_slot(0, i + 1, al, be)] = c0i[:, i, al, be]
+                for j in range(3):
+                    out[vector_slot(i + 1, j + 1, al, be)] = D[:, 3 * i + al, 3 * j + be]
+        for i in range(3):
+            out[vector_slot(i + 1, None, al)] = di[:, i, al]
+        out[vector_slot(0, None, al)] = d0[:, al]
+    return out
+
+
+def vector_compact(full: np.ndarray, mask: int, n_q: int = 1) -> np.ndarray:
+    """Keep the rows of the blocks present in ``mask`` (slot order); for
+    per-point data ``full`` is (156 * n_q, n) with rows slot * n_q + q."""
+    rows = []
+    for k in range(20):
+        if mask >> k & 1:
+            base = k * 9 if k < 16 else 144 + 3 * (k - 16)
+            for c in range(9 if k < 16 else 3):
+                rows.extend((base + c) * n_q + q for q in range(n_q))
+    return np.ascontiguousarray(full[rows])
+
+
 def rhs_per_qp(n_elem: int, n_q: int, rng: np.random.Generator) -> np.ndarray:
     """A right-hand side d^0 ~ U[0,1] per quadrature point (the paper's
     "Poisson" input of one coefficient per point), compact (n_q, n_elem)."""
@@ -335,7 +393,7 @@ def smooth_cdr_per_qp(coords: np.ndarray, sample_w: np.ndarray, rng: np.random.G
 class Workload:
     name: str
     elem: str            # "tet4" | "prism6"
-    kind: str            # "scalar" | "elasticity"
+    kind: str            # "scalar" | "elasticity" | "vector"
     n_q: int
     coef_mode: str       # "uniform" | "element" | "qp"
     mask: int            # which slots are read from the coefficient array
@@ -430,6 +488,26 @@ def prism_poisson_qp_rhs(n: int, L: int, seed: int = 3, sliver: bool = True) -> 
 # --------------------------------------------------------------------------
 # Coefficient functions: parameters instead of values.
 # --------------------------------------------------------------------------
+def tet_vector(N: int, seed: int = 6) -> Workload:
+    """General 3-component convection-diffusion-reaction on tets: all 156
+    coefficients per element, 4-point rule, full 12x12 K."""
+    rng = np.random.default_rng(seed)
+    mesh = tet_cube(N, rng)
+    coeffs = vector_per_element(mesh.n_elem, rng)
+    return Workload("tet_vector", "tet4", "vector", 4, "element", ALL_VECTOR_MASK,
+                    np.zeros(N_SCALAR_SLOTS), "full", mesh, coeffs)
+
+
+def prism_vector(n: int, L: int, seed: int = 7, sliver: bool = True) -> Workload:
+    """General 3-component problem on prisms, 156 coefficients per element,
+    6-point rule, full 18x18 K."""
+    rng = np.random.default_rng(seed)
+    mesh = prism_layers(n, L, rng, sliver=sliver)
+    coeffs = vector_per_element(mesh.n_elem, rng)
+    return Workload("prism_vector", "prism6", "vector", 6, "element", ALL_VECTOR_MASK,
+                    np.zeros(N_SCALAR_SLOTS), "full", mesh, coeffs)
+
+
 N_FN_PARAMS = 122
 
 

@@ -61,6 +61,30 @@ def tet_closed_form_scalar(X, slots):
     return K, F
 
 
+def tet_closed_form_vector(X, slots):
+    """Exact integrals of the general 3-component weak form over one affine
+    tet. slots: the 156 values ((4a+b)*9 + 3 alpha + beta -> c^{a;b}_{alpha
+    beta}, 144 + 3a + alpha -> d^a_alpha). Unknowns node-major (3r + alpha);
+    every (alpha, beta) block is the scalar closed form with that block's
+    coefficients."""
+    slots = np.asarray(slots, dtype=np.float64)
+    K = np.zeros((12, 12))
+    F = np.zeros(12)
+    for al in range(3):
+        for be in range(3):
+            sl = np.zeros(20)
+            for ab in range(16):
+                sl[ab] = slots[ab * 9 + 3 * al + be]
+            Kb, _ = tet_closed_form_scalar(X, sl)
+            K[al::3, be::3] = Kb
+        sl = np.zeros(20)
+        for a in range(4):
+            sl[16 + a] = slots[144 + 3 * a + al]
+        _, Fb = tet_closed_form_scalar(X, sl)
+        F[al::3] = Fb
+    return K, F
+
+
 def lame(E, nu):
     return E * nu / ((1 + nu) * (1 - 2 * nu)), E / (2 * (1 + nu))
 

@@ -59,6 +59,10 @@ WORKLOADS = {
                        "isotropic elasticity on tets N=94 (4,983,504), per-element E, nu, f, 1-point rule, packed 12x12"),
     "prism_elasticity": (lambda: __import__("paper_1504_01023_amd.inputs", fromlist=["x"]).prism_elasticity(100, 100, 4),
                          "isotropic elasticity on prisms 100x100x100 (2,000,000), per-element E, nu, f, 6-point rule, packed 18x18"),
+    "tet_vector": (lambda: __import__("paper_1504_01023_amd.inputs", fromlist=["x"]).tet_vector(94, 6),
+                   "general 3-component CDR on tets N=94 (4,983,504), 156 coefficients per element, 4-point rule, full 12x12"),
+    "prism_vector": (lambda: __import__("paper_1504_01023_amd.inputs", fromlist=["x"]).prism_vector(100, 100, 7),
+                     "general 3-component CDR on prisms 100x100x100 (2,000,000), 156 coefficients per element, 6-point rule, full 18x18"),
 }
 
 
@@ -87,6 +91,10 @@ KERNEL_UNITS = {
     ("tet_cdr_fn", "fp64"): "fe_k_tet_scalar_f64_full.hip",
     ("tet_cdr_fn", "fp32"): "fe_k_tet_scalar_f32_full.hip",
     ("prism_elasticity", "fp32"): "fe_k_prism_elast_f32.hip",
+    ("tet_vector", "fp64"): "fe_k_tet_vector_f64.hip",
+    ("tet_vector", "fp32"): "fe_k_tet_vector_f32.hip",
+    ("prism_vector", "fp64"): "fe_k_prism_vector_f64.hip",
+    ("prism_vector", "fp32"): "fe_k_prism_vector_f32.hip",
 }
 
 

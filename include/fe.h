@@ -17,8 +17,10 @@
  * (Sec. 3.1).
  *
  * Elements: affine 4-node tetrahedra and 6-node linear prisms. Problems:
- * scalar convection-diffusion-reaction, and 3-component isotropic linear
- * elasticity (a vector problem, Sec. 3.3).
+ * scalar convection-diffusion-reaction, 3-component isotropic linear
+ * elasticity, and the general 3-component convection-diffusion-reaction
+ * problem in which every coefficient is a matrix over the components (the
+ * vector problems of Sec. 2.1 and Sec. 3.3).
  *
  * Conventions (readings where the paper is silent):
  *  - Reference tetrahedron (0,0,0),(1,0,0),(0,1,0),(0,0,1), shape functions
@@ -52,6 +54,14 @@
  * bit is set in coef_mask is read from `coeffs`; every other slot takes the
  * value problem->uniform[slot] (zero for absent terms). With
  * FE_COEF_UNIFORM no slot is read from memory.
+ * General 3-component problem (FE_VECTOR_CDR, 156 slots): c^{a;b}_{alpha
+ * beta} (alpha: component of the test function, beta: of the trial function)
+ * is slot (4a+b)*9 + 3 alpha + beta, d^a_alpha is slot 144 + 3a + alpha.
+ * coef_mask has one bit per block: bit 4a+b stands for the nine slots of
+ * c^{a;b}, bit 16+a for the three of d^a; the compact array holds the slots
+ * of the present blocks in slot order, and absent blocks are zero
+ * (problem->uniform is not used). Coefficients per element or per point;
+ * K is full.
  *
  * Ownership and streams: every device pointer is owned by the caller and must
  * stay valid until the work enqueued on `stream` has completed. Quadrature
@@ -90,7 +100,11 @@ typedef enum fe_status {
 } fe_status;
 
 typedef enum fe_elem_type { FE_TET4 = 0, FE_PRISM6 = 1 } fe_elem_type;
-typedef enum fe_problem_kind { FE_SCALAR_CDR = 0, FE_ELASTICITY = 1 } fe_problem_kind;
+typedef enum fe_problem_kind {
+    FE_SCALAR_CDR = 0,
+    FE_ELASTICITY = 1,
+    FE_VECTOR_CDR = 2  /* general 3-component convection-diffusion-reaction */
+} fe_problem_kind;
 
 /* FE_FP32_BULK: coordinates stay FP64 and the Jacobian terms (J, det J, its
  * inverse), the global derivatives and vol are computed in FP64, then rounded
@@ -199,7 +213,8 @@ FE_API int64_t fe_k_entries(const fe_problem *problem, fe_elem_type elem_type);
 FE_API int64_t fe_f_entries(const fe_problem *problem, fe_elem_type elem_type);
 /* Rows of coeffs for this problem and rule size (popcount(mask) per element,
  * times n_q for per-point data; 0 for uniform; FE_COEF_FN_PARAMS values in
- * total, not per element, for the function mode). */
+ * total, not per element, for the function mode; for FE_VECTOR_CDR nine rows
+ * per c block and three per d block in the mask). */
 FE_API int64_t fe_coeff_entries(const fe_problem *problem, fe_elem_type elem_type, int n_q);
 /* Algorithmic global-memory bytes per element: every input word read once
  * and every output word written once. */

@@ -122,8 +122,18 @@ void fill_reference(int elem, const fe_quad_rule &rule, KArgs &a)
 
 // ------------------------------------------------------------- validation
 static int n_shape(int elem) { return elem == FE_TET4 ? 4 : 6; }
-static int n_comp(int kind) { return kind == FE_ELASTICITY ? 3 : 1; }
+static int n_comp(int kind) { return kind == FE_SCALAR_CDR ? 1 : 3; }
+// mask bits: slots (scalar, elasticity) or blocks of slots (3-component CDR)
 static int n_slots(int kind) { return kind == FE_ELASTICITY ? 5 : 20; }
+// 3-component CDR: coefficient rows of the blocks present in the mask
+static int vector_rows(uint32_t mask)
+{
+    int n = 0;
+    for (int k = 0; k < 20; ++k)
+        if (mask >> k & 1u)
+            n += k < 16 ? 9 : 3;
+    return n;
+}
 
 static int check_problem(const fe_problem *p, int elem)
 {
@@ -131,7 +141,7 @@ static int check_problem(const fe_problem *p, int elem)
         return fail(FE_ERR_INVALID_ARG, "problem is NULL");
     if (elem != FE_TET4 && elem != FE_PRISM6)
         return fail(FE_ERR_INVALID_ARG, "bad element type %d", elem);
-    if (p->kind != FE_SCALAR_CDR && p->kind != FE_ELASTICITY)
+    if (p->kind != FE_SCALAR_CDR && p->kind != FE_ELASTICITY && p->kind != FE_VECTOR_CDR)
         return fail(FE_ERR_INVALID_ARG, "bad problem kind %d", p->kind);
     if (p->precision != FE_FP64 && p->precision != FE_FP32_BULK)
         return fail(FE_ERR_INVALID_ARG, "bad precision %d", p->precision);
@@ -143,6 +153,13 @@ static int check_problem(const fe_problem *p, int elem)
         return fail(FE_ERR_INVALID_ARG, "bad K format %d", p->k_format);
     if (p->reserved != 0)
         return fail(FE_ERR_INVALID_ARG, "reserved field must be 0");
+    if (p->kind == FE_VECTOR_CDR) {
+        if (p->coef_mode != FE_COEF_PER_ELEMENT && p->coef_mode != FE_COEF_PER_QP)
+            return fail(FE_ERR_UNSUPPORTED,
+                        "the 3-component problem takes coefficients per element or per point");
+        if (p->k_format != FE_K_FULL)
+            return fail(FE_ERR_UNSUPPORTED, "the 3-component problem stores K in full");
+    }
     if (p->coef_mode != FE_COEF_UNIFORM && (p->coef_mask >> n_slots(p->kind)) != 0)
         return fail(FE_ERR_INVALID_ARG, "coef_mask has bits beyond slot %d", n_slots(p->kind) - 1);
     return FE_OK;
@@ -173,7 +190,7 @@ static int needed_terms(const fe_problem *p)
 
 static int check_symmetry(const fe_problem *p)
 {
-    if (p->k_format != FE_K_SYM_PACKED || p->kind == FE_ELASTICITY)
+    if (p->k_format != FE_K_SYM_PACKED || p->kind != FE_SCALAR_CDR)
         return FE_OK;
     const uint32_t mask = effective_mask(p);
     const uint32_t conv = slots_of_terms(T_CONVA) | slots_of_terms(T_CONVB);
@@ -253,6 +270,8 @@ int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coor
     k.prec = problem->precision;
     if (problem->kind == FE_ELASTICITY) {
         k.terms = TS_ELAST;
+    } else if (problem->kind == FE_VECTOR_CDR) {
+        k.terms = TS_FULL;
     } else {
         const int need = needed_terms(problem);
         k.terms = ((need & ~TS_POISSON) == 0) ? TS_POISSON : TS_FULL;
@@ -262,8 +281,8 @@ int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coor
         k.mode = M_UNIFORM;
     else if (fn)
         k.mode = M_FUNC;
-    else if (mask == slots_of_terms(k.terms))
-        k.mode = per_qp ? M_QP : M_ELEM;
+    else if (mask == slots_of_terms(k.terms) || problem->kind == FE_VECTOR_CDR)
+        k.mode = per_qp ? M_QP : M_ELEM;  // 3-component blocks are addressed through col[]
     else
         k.mode = per_qp ? M_QP_MIXED : M_ELEM_MIXED;
     k.packed = (problem->k_format == FE_K_SYM_PACKED) ? 1 : 0;
@@ -346,8 +365,15 @@ int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coor
     a.k_packed = k.packed;
     int col = 0;
     for (int s = 0; s < 20; ++s) {
-        a.col[s] = (s < n_slots(problem->kind) && (mask >> s & 1u)) ? col++ : -1;
-        a.uniform[s] = problem->uniform[s];
+        if (problem->kind == FE_VECTOR_CDR) {
+            // first row of block s in the compact array
+            a.col[s] = (mask >> s & 1u) ? col : -1;
+            col += (mask >> s & 1u) ? (s < 16 ? 9 : 3) : 0;
+            a.uniform[s] = 0.0;
+        } else {
+            a.col[s] = (s < n_slots(problem->kind) && (mask >> s & 1u)) ? col++ : -1;
+            a.uniform[s] = problem->uniform[s];
+        }
     }
     fill_reference(elem, *rule, a);
     pl.entry = e;
@@ -452,7 +478,8 @@ int64_t fe_coeff_entries(const fe_problem *problem, fe_elem_type elem_type, int 
 {
     if (check_problem(problem, elem_type) || n_q < 1 || n_q > FE_MAX_QP)
         return -1;
-    const int64_t c = __builtin_popcount(effective_mask(problem));
+    const int64_t c = problem->kind == FE_VECTOR_CDR ? vector_rows(effective_mask(problem))
+                                                     : __builtin_popcount(effective_mask(problem));
     if (problem->coef_mode == FE_COEF_FUNCTION)
         return c ? FE_COEF_FN_PARAMS : 0;
     return problem->coef_mode == FE_COEF_PER_QP ? c * n_q : c;

@@ -246,6 +246,53 @@ __device__ __forceinline__ void coef(const KArgs &a, const Streams &st, int k, i
     }
 }
 
+// Addressing of one problem block. ScalarBlock is the scalar problem itself;
+// VecBlock is the (alpha = A, beta = B) block of the general 3-component
+// problem: its scalar slot k stands for c^{a;b}_{A B} (k = 4a+b) or d^a_A
+// (k = 16+a), read from row col[k] + component of the compact array (col[k]
+// < 0: the block is absent and zero), and its K entry (r, s) is the entry
+// (3r+A, 3s+B) of the full matrix. F belongs to the B = 0 blocks. A and B are
+// wave-uniform run-time values, so the nine blocks share one copy of the code.
+struct ScalarBlock {
+    __device__ __forceinline__ bool with_f() const { return true; }
+    template <typename T, int MODE, uint32_t SL, int V, bool NT>
+    __device__ __forceinline__ void coef(const KArgs &a, const Streams &st, int k, int q,
+                                         int64_t e0, T (&out)[V]) const
+    {
+        fe::coef<T, MODE, SL, V, NT>(a, st, k, q, e0, out);
+    }
+    __device__ __forceinline__ int k_index(int NS, int packed, int r, int s) const
+    {
+        return packed ? pidx(NS, r, s) : NS * r + s;
+    }
+    __device__ __forceinline__ int f_index(int r) const { return r; }
+};
+
+struct VecBlock {
+    int A, B;
+    __device__ __forceinline__ bool with_f() const { return B == 0; }
+    template <typename T, int MODE, uint32_t SL, int V, bool NT>
+    __device__ __forceinline__ void coef(const KArgs &a, const Streams &st, int k, int q,
+                                         int64_t e0, T (&out)[V]) const
+    {
+        const int j = a.col[k];
+        if (j < 0) {
+#pragma unroll
+            for (int i = 0; i < V; ++i)
+                out[i] = T(0);
+            return;
+        }
+        const int64_t row = j + (k < 16 ? 3 * A + B : A);
+        const int64_t r = (MODE == M_QP) ? row * a.n_q + q : row;
+        loadv<V, NT>(static_cast<const T *>(st.coeffs) + r * st.ld_in + e0, out);
+    }
+    __device__ __forceinline__ int k_index(int NS, int, int r, int s) const
+    {
+        return (3 * r + A) * (3 * NS) + 3 * s + B;
+    }
+    __device__ __forceinline__ int f_index(int r) const { return 3 * r + A; }
+};
+
 // Coefficient functions: slot k's value at the physical point x is
 // alpha_k + beta_k sin(2 pi (omega_k . x) + theta_k), parameters p[6k..6k+5]
 // (read with wave-uniform scalar loads); with p[121] != 0 the diffusion block
@@ -298,9 +345,12 @@ __device__ __forceinline__ void fn_values(const KArgs &a, const double *p, const
 
 // Coefficient values at one point for V elements: read from memory or
 // uniform (coef), or computed from the coefficient function.
-template <typename T, int MODE, uint32_t SL, int V, bool NT>
+template <typename T, int MODE, uint32_t SL, int V, bool NT, class BL = ScalarBlock>
 struct PointCoefs {
     double fv[MODE == M_FUNC ? 20 : 1][V];
+    BL bl;
+
+    __device__ __forceinline__ explicit PointCoefs(const BL &b = BL()) : bl(b) {}
 
     // x: physical coordinates of the point for each element (function mode)
     __device__ __forceinline__ void prepare(const KArgs &a, const double (&x)[V][3])
@@ -317,7 +367,7 @@ struct PointCoefs {
             for (int v = 0; v < V; ++v)
                 out[v] = (T)fv[k][v];
         } else {
-            coef<T, MODE, SL, V, NT>(a, st, k, q, e0, out);
+            bl.template coef<T, MODE, SL, V, NT>(a, st, k, q, e0, out);
         }
     }
 };
@@ -448,7 +498,7 @@ __device__ __forceinline__ void lame(T E, T nu, T &lam, T &mu)
 }
 
 // ===================================================== tetrahedron, scalar
-template <typename T, int TERMS, int MODE, int PACKED>
+template <typename T, int TERMS, int MODE, int PACKED, class BL = ScalarBlock>
 struct TetScalar {
     static constexpr uint32_t SL = slots_of_terms(TERMS);
     static constexpr bool DIFF = TERMS & T_DIFF, CA = TERMS & T_CONVA, CB = TERMS & T_CONVB,
@@ -469,9 +519,9 @@ struct TetScalar {
 
     template <int V, bool NT>
     __device__ __forceinline__ static void store_K(const Streams &st, int r, int s, int64_t e0,
-                                                   const T (&val)[V])
+                                                   const T (&val)[V], const BL &bl)
     {
-        const int k = PACKED ? pidx(4, r, s) : 4 * r + s;
+        const int k = bl.k_index(4, PACKED, r, s);
         storev<V, NT>(static_cast<T *>(st.out_K) + k * st.ld_out + e0, val);
     }
 
@@ -483,7 +533,7 @@ struct TetScalar {
     template <int V, bool NT>
     __device__ __forceinline__ static void run_const(const KArgs &a, const Streams &st,
                                                      const double (&X)[V][12],
-                                                     int64_t e0)
+                                                     int64_t e0, const BL &bl = BL())
     {
         T C[3][3][V], ca[3][V], cb[3][V], c00[V], d[3][V], d0[V];
         if constexpr (DIFF) {
@@ -491,27 +541,38 @@ struct TetScalar {
             for (int i = 0; i < 3; ++i)
 #pragma unroll
                 for (int j = 0; j < 3; ++j)
-                    coef<T, MODE, SL, V, NT>(a, st, 4 * (i + 1) + 1 + j, 0, e0, C[i][j]);
+                    bl.template coef<T, MODE, SL, V, NT>(a, st, 4 * (i + 1) + 1 + j, 0, e0, C[i][j]);
         }
         if constexpr (CA) {
 #pragma unroll
             for (int i = 0; i < 3; ++i)
-                coef<T, MODE, SL, V, NT>(a, st, 4 * (i + 1), 0, e0, ca[i]);
+                bl.template coef<T, MODE, SL, V, NT>(a, st, 4 * (i + 1), 0, e0, ca[i]);
         }
         if constexpr (CB) {
 #pragma unroll
             for (int j = 0; j < 3; ++j)
-                coef<T, MODE, SL, V, NT>(a, st, 1 + j, 0, e0, cb[j]);
+                bl.template coef<T, MODE, SL, V, NT>(a, st, 1 + j, 0, e0, cb[j]);
         }
         if constexpr (MASS)
-            coef<T, MODE, SL, V, NT>(a, st, 0, 0, e0, c00);
+            bl.template coef<T, MODE, SL, V, NT>(a, st, 0, 0, e0, c00);
+        const bool wf = bl.with_f();
         if constexpr (DG) {
 #pragma unroll
-            for (int i = 0; i < 3; ++i)
-                coef<T, MODE, SL, V, NT>(a, st, 17 + i, 0, e0, d[i]);
+            for (int i = 0; i < 3; ++i) {
+#pragma unroll
+                for (int v = 0; v < V; ++v)
+                    d[i][v] = T(0);
+                if (wf)
+                    bl.template coef<T, MODE, SL, V, NT>(a, st, 17 + i, 0, e0, d[i]);
+            }
         }
-        if constexpr (D0)
-            coef<T, MODE, SL, V, NT>(a, st, 16, 0, e0, d0);
+        if constexpr (D0) {
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+                d0[v] = T(0);
+            if (wf)
+                bl.template coef<T, MODE, SL, V, NT>(a, st, 16, 0, e0, d0);
+        }
 
         const T W = (T)a.Wsum;
         T Kv[4][4][V], Fv[4][V];
@@ -569,10 +630,12 @@ struct TetScalar {
         for (int r = 0; r < 4; ++r)
 #pragma unroll
             for (int s = (PACKED ? r : 0); s < 4; ++s)
-                store_K<V, NT>(st, r, s, e0, Kv[r][s]);
+                store_K<V, NT>(st, r, s, e0, Kv[r][s], bl);
+        if (bl.with_f()) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-            storev<V, NT>(static_cast<T *>(st.out_F) + r * st.ld_out + e0, Fv[r]);
+            for (int r = 0; r < 4; ++r)
+                storev<V, NT>(static_cast<T *>(st.out_F) + bl.f_index(r) * st.ld_out + e0, Fv[r]);
+        }
     }
 
     // Coefficients per point (Algorithm 3 with "calculate possibly
@@ -584,8 +647,10 @@ struct TetScalar {
     //   K_rs = det (g_r . Cb g_s + g_r . Pb_s + Qb_r . g_s + Mb_rs), F_r = det (Db . g_r + fb_r).
     template <int V, bool NT, int REF>
     __device__ __forceinline__ static void run_qp(const KArgs &a, const Streams &st, const Ref<REF> &ref,
-                                                  const double (&X)[V][12], int64_t e0)
+                                                  const double (&X)[V][12], int64_t e0,
+                                                  const BL &bl = BL())
     {
+        const bool wf = bl.with_f();
         T Cb[V][3][3], Pb[V][4][3], Qb[V][4][3], Mb[V][4][4], Db[V][3], fb[V][4];
 #pragma unroll
         for (int v = 0; v < V; ++v) {
@@ -608,7 +673,7 @@ struct TetScalar {
             }
         }
         for (int q = 0; q < a.n_q; ++q) {
-            PointCoefs<T, MODE, SL, V, NT> pc;
+            PointCoefs<T, MODE, SL, V, NT, BL> pc(bl);
             if constexpr (MODE == M_FUNC) {
                 // physical point x(xi_q) = X_0 + sum_r phi_r(xi_q) (X_r - X_0)
                 double x[V][3];
@@ -671,21 +736,25 @@ struct TetScalar {
                             Mb[v][r][s] += wp[r] * (T)ref.phi(q, s) * c[v];
             }
             if constexpr (DG) {
+                if (wf) {
 #pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    pc.get(a, st, 17 + i, q, e0, c);
+                    for (int i = 0; i < 3; ++i) {
+                        pc.get(a, st, 17 + i, q, e0, c);
 #pragma unroll
-                    for (int v = 0; v < V; ++v)
-                        Db[v][i] += w * c[v];
+                        for (int v = 0; v < V; ++v)
+                            Db[v][i] += w * c[v];
+                    }
                 }
             }
             if constexpr (D0) {
-                pc.get(a, st, 16, q, e0, c);
+                if (wf) {
+                    pc.get(a, st, 16, q, e0, c);
 #pragma unroll
-                for (int v = 0; v < V; ++v)
+                    for (int v = 0; v < V; ++v)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        fb[v][r] += wp[r] * c[v];
+                        for (int r = 0; r < 4; ++r)
+                            fb[v][r] += wp[r] * c[v];
+                }
             }
         }
         T Kv[4][4][V], Fv[4][V];
@@ -733,10 +802,40 @@ struct TetScalar {
         for (int r = 0; r < 4; ++r)
 #pragma unroll
             for (int s = (PACKED ? r : 0); s < 4; ++s)
-                store_K<V, NT>(st, r, s, e0, Kv[r][s]);
+                store_K<V, NT>(st, r, s, e0, Kv[r][s], bl);
+        if (bl.with_f()) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-            storev<V, NT>(static_cast<T *>(st.out_F) + r * st.ld_out + e0, Fv[r]);
+            for (int r = 0; r < 4; ++r)
+                storev<V, NT>(static_cast<T *>(st.out_F) + bl.f_index(r) * st.ld_out + e0, Fv[r]);
+        }
+    }
+};
+
+// ============================================ tetrahedron, 3-component CDR
+// The general 3-component problem block by block: the (alpha, beta) block of
+// K is the scalar form with the coefficients c^{a;b}_{alpha beta}, and F_alpha
+// the scalar load with d^a_alpha, so each of the nine blocks runs the scalar
+// contraction on the same vertex coordinates (the geometry is recomputed per
+// block; it is a few dozen operations against the block's memory traffic).
+template <typename T, int MODE>
+struct TetVector {
+    static constexpr bool PER_QP = (MODE == M_QP);
+    typedef TetScalar<T, TS_FULL, MODE, 0, VecBlock> P;
+
+    template <int V, bool NT, int REF, class S>
+    __device__ __forceinline__ static void run(const KArgs &a, const S &st, const Ref<REF> &ref,
+                                               int64_t e0)
+    {
+        double X[V][12];
+        st.template load_coords<4, V, NT>(e0, X);
+#pragma unroll 1
+        for (int b = 0; b < 9; ++b) {
+            const VecBlock bl{b / 3, b % 3};
+            if constexpr (PER_QP)
+                P::template run_qp<V, NT, REF>(a, st, ref, X, e0, bl);
+            else
+                P::template run_const<V, NT>(a, st, X, e0, bl);
+        }
     }
 };
 
@@ -866,7 +965,7 @@ struct TetElastic {
 // u_r = vol g_r, p_r = vol phi_r, t_s = C g_s + phi_s c^{.;0} and
 // sigma_s = c^{0;.} . g_s + c^{0;0} phi_s:  K_rs += u_r . t_s + p_r sigma_s,
 // F_r += u_r . d + p_r d^0.
-template <typename T, int TERMS, int MODE, int PACKED, int NQ>
+template <typename T, int TERMS, int MODE, int PACKED, int NQ, class BL = ScalarBlock>
 struct PrismScalar {
     static constexpr uint32_t SL = slots_of_terms(TERMS);
     static constexpr bool DIFF = TERMS & T_DIFF, CA = TERMS & T_CONVA, CB = TERMS & T_CONVB,
@@ -897,9 +996,10 @@ struct PrismScalar {
     template <bool NT, class R>
     __device__ __forceinline__ static void load_coefs(const KArgs &a, const Streams &st, const R &ref,
                                                       int q, int64_t e, const double (&X0)[3],
-                                                      const double (&E)[18], Coefs &c)
+                                                      const double (&E)[18], Coefs &c,
+                                                      const BL &bl = BL())
     {
-        PointCoefs<T, MODE, SL, 1, NT> pc;
+        PointCoefs<T, MODE, SL, 1, NT, BL> pc(bl);
         if constexpr (MODE == M_FUNC) {
             double x[1][3];
             point_x(X0, E, ref, q, x);
@@ -933,16 +1033,23 @@ struct PrismScalar {
             pc.get(a, st, 0, q, e, x);
             c.c00 = x[0];
         }
+        const bool wf = bl.with_f();
         if constexpr (DG) {
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                pc.get(a, st, 17 + i, q, e, x);
-                c.d[i] = x[0];
+                c.d[i] = T(0);
+                if (wf) {
+                    pc.get(a, st, 17 + i, q, e, x);
+                    c.d[i] = x[0];
+                }
             }
         }
         if constexpr (D0) {
-            pc.get(a, st, 16, q, e, x);
-            c.d0 = x[0];
+            c.d0 = T(0);
+            if (wf) {
+                pc.get(a, st, 16, q, e, x);
+                c.d0 = x[0];
+            }
         }
     }
 
@@ -959,6 +1066,16 @@ struct PrismScalar {
             X[s] = Xg[0][s];
         const double X0[3] = {X[0], X[1], X[2]};
         to_edge_vectors<6>(X);
+        body<NT>(a, st, ref, e, X0, X);
+    }
+
+    // Point loop and stores for one element, from vertex 0 and the edge
+    // vectors X_r - X_0.
+    template <bool NT, class R>
+    __device__ __forceinline__ static void body(const KArgs &a, const Streams &st, const R &ref,
+                                                int64_t e, const double (&X0)[3], const double (&X)[18],
+                                                const BL &bl = BL())
+    {
         constexpr int NK = PACKED ? 21 : 36;
         T K[NK], F[6];
 #pragma unroll
@@ -969,12 +1086,12 @@ struct PrismScalar {
             F[r] = T(0);
         Coefs c;
         if constexpr (!PER_QP)
-            load_coefs<NT>(a, st, ref, 0, e, X0, X, c);
+            load_coefs<NT>(a, st, ref, 0, e, X0, X, c, bl);
         const int nq = NQ > 0 ? NQ : a.n_q;
 #pragma unroll(NQ > 0 ? NQ : 1)
         for (int q = 0; q < nq; ++q) {
             if constexpr (PER_QP)
-                load_coefs<NT>(a, st, ref, q, e, X0, X, c);
+                load_coefs<NT>(a, st, ref, q, e, X0, X, c, bl);
             T g[6][3], vol;
             point_geometry<6, T>(X, ref, q, g, vol);
             T phi[6];
@@ -1026,12 +1143,44 @@ struct PrismScalar {
         }
         T *outK = static_cast<T *>(st.out_K);
 #pragma unroll
-        for (int k = 0; k < NK; ++k)
-            st1<NT>(outK + k * st.ld_out + e, K[k]);
-        T *outF = static_cast<T *>(st.out_F);
-#pragma unroll
         for (int r = 0; r < 6; ++r)
-            st1<NT>(outF + r * st.ld_out + e, F[r]);
+#pragma unroll
+            for (int s = (PACKED ? r : 0); s < 6; ++s)
+                st1<NT>(outK + bl.k_index(6, PACKED, r, s) * st.ld_out + e,
+                        K[PACKED ? pidx(6, r, s) : 6 * r + s]);
+        if (bl.with_f()) {
+            T *outF = static_cast<T *>(st.out_F);
+#pragma unroll
+            for (int r = 0; r < 6; ++r)
+                st1<NT>(outF + bl.f_index(r) * st.ld_out + e, F[r]);
+        }
+    }
+};
+
+// ================================================= prism, 3-component CDR
+// Block by block as for tetrahedra: the (alpha, beta) block runs the scalar
+// point loop with the block's coefficients, so a lane holds one 6x6 block of
+// accumulators at a time instead of the whole 18x18 matrix (the per-point
+// Jacobian terms are recomputed for each block).
+template <typename T, int MODE, int NQ>
+struct PrismVector {
+    template <int V, bool NT, int REF, class S>
+    __device__ __forceinline__ static void run(const KArgs &a, const S &st, const Ref<REF> &ref,
+                                               int64_t e)
+    {
+        static_assert(V == 1, "prisms are processed one element per lane");
+        double Xg[1][18];
+        st.template load_coords<6, 1, NT>(e, Xg);
+        double X[18];
+#pragma unroll
+        for (int s = 0; s < 18; ++s)
+            X[s] = Xg[0][s];
+        const double X0[3] = {X[0], X[1], X[2]};
+        to_edge_vectors<6>(X);
+#pragma unroll 1
+        for (int b = 0; b < 9; ++b)
+            PrismScalar<T, TS_FULL, MODE, 0, NQ, VecBlock>::template body<NT>(a, st, ref, e, X0, X,
+                                                                               VecBlock{b / 3, b % 3});
     }
 };
 

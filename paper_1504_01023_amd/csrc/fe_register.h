@@ -64,4 +64,18 @@ inline void reg_prism_elastic()
                                                              TS_ELAST, MODE, PK, NQ, SPLIT);
 }
 
+// General 3-component CDR (coefficients per element or per point, full K).
+template <typename T, int MODE, int V, int NT>
+inline void reg_tet_vector()
+{
+    reg<TetVector<T, MODE>, V, NT, REF_KARG>(FE_TET4, FE_VECTOR_CDR, prec_of<T>(), TS_FULL, MODE, 0, 0);
+}
+
+template <typename T, int MODE, int NQ, int NT, int REF>
+inline void reg_prism_vector()
+{
+    reg<PrismVector<T, MODE, NQ>, 1, NT, REF>(FE_PRISM6, FE_VECTOR_CDR, prec_of<T>(), TS_FULL, MODE, 0,
+                                               NQ);
+}
+
 }  // namespace fe

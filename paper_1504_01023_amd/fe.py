@@ -18,7 +18,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libfe.so")
 
 TET4, PRISM6 = 0, 1
-SCALAR_CDR, ELASTICITY = 0, 1
+SCALAR_CDR, ELASTICITY, VECTOR_CDR = 0, 1, 2
 FP64, FP32_BULK = 0, 1
 COEF_UNIFORM, COEF_PER_ELEMENT, COEF_PER_QP, COEF_FUNCTION = 0, 1, 2, 3
 FN_PARAMS = 122
@@ -26,7 +26,7 @@ K_FULL, K_SYM_PACKED = 0, 1
 MAX_QP = 8
 
 ELEM = {"tet4": TET4, "prism6": PRISM6}
-KIND = {"scalar": SCALAR_CDR, "elasticity": ELASTICITY}
+KIND = {"scalar": SCALAR_CDR, "elasticity": ELASTICITY, "vector": VECTOR_CDR}
 MODE = {"uniform": COEF_UNIFORM, "element": COEF_PER_ELEMENT, "qp": COEF_PER_QP,
         "function": COEF_FUNCTION}
 KFMT = {"full": K_FULL, "packed": K_SYM_PACKED}

@@ -276,7 +276,7 @@ def vector_per_element(n_elem: int, rng: np.random.Generator) -> np.ndarray:
     operator is strongly elliptic); then c^{i;0}, c^{0;i} ~ U[-1,1]^{3x3x3},
     c^{0;0} ~ U[0,1]^{3x3}, d^i ~ U[-1,1]^{3x3}, d^0 ~ U[-1,1]^3."""
     B = rng.uniform(-1.0, 1.0, (n_elem, 9, 9))
-    D = np.einsum("epk,eqk->epq", B, B) / 9.0 + 0.5 * np.eye(9)   # [(3i+alpha), (3j+beta)]
+    D = np.matmul(B, B.transpose(0, 2, 1)) / 9.0 + 0.5 * np.eye(9)   # [(3i+alpha), (3j+beta)]
     ci0 = rng.uniform(-1.0, 1.0, (n_elem, 3, 3, 3))   # [i, alpha, beta]
     c0i = rng.uniform(-1.0, 1.0, (n_elem, 3, 3, 3))
     c00 = rng.uniform(0.0, 1.0, (n_elem, 3, 3))

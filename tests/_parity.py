@@ -92,6 +92,8 @@ SMALL = {
     "prism_elasticity": lambda: inputs.prism_elasticity(6, 6, seed=14),
     "tet_cdr_fn": lambda: inputs.tet_cdr_fn(6, seed=15),
     "prism_cdr_fn": lambda: inputs.prism_cdr_fn(8, 6, seed=16),
+    "tet_vector": lambda: inputs.tet_vector(6, seed=17),
+    "prism_vector": lambda: inputs.prism_vector(7, 5, seed=18),
 }
 
 

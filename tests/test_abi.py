@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_1504_01023_amd import fe
+from paper_1504_01023_amd import fe, inputs
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -207,4 +207,24 @@ def test_function_mode_sizes_and_validation():
     assert fe.bytes_per_element(p, "prism6", 6) == 144 + 8 * (36 + 6)
     el = fe.problem("elasticity", "fp64", "function", 31, None, "packed")
     assert _call(el, coeffs=0x4000) == 2
+    assert _call(p, coeffs=None) == 1
+
+
+def test_vector_problem_sizes_and_validation():
+    full = inputs.ALL_VECTOR_MASK
+    p = fe.problem("vector", "fp64", "element", full, None, "full")
+    assert fe.k_entries(p, "tet4") == 144 and fe.f_entries(p, "tet4") == 12
+    assert fe.k_entries(p, "prism6") == 324 and fe.f_entries(p, "prism6") == 18
+    assert fe.coeff_entries(p, "tet4", 4) == 156
+    assert fe.bytes_per_element(p, "tet4", 4) == 96 + 8 * (156 + 144 + 12)
+    q = fe.problem("vector", "fp32", "qp", (1 << 5) | (1 << 16), None, "full")
+    assert fe.coeff_entries(q, "prism6", 6) == (9 + 3) * 6
+    assert fe.bytes_per_element(q, "prism6", 6) == 144 + 4 * (72 + 324 + 18)
+    assert fe.k_index(p, "tet4", 11, 0) == 132
+    # per element or per point only, full K only
+    for mode, fmt, mask in (("uniform", "full", 0), ("function", "full", full),
+                            ("element", "packed", full)):
+        bad = fe.problem("vector", "fp64", mode, mask, None, fmt)
+        assert fe.k_entries(bad, "tet4") == -1
+        assert _call(bad, coeffs=0x4000) == 2
     assert _call(p, coeffs=None) == 1

@@ -170,3 +170,31 @@ def integrate_workload(wl, threads: int = 1, elements=None):
             coeffs = coeffs[:, idx]
     return integrate(wl.elem, wl.kind, coords, quad_rule(wl.elem, wl.n_q), wl.coef_mode, wl.mask,
                      wl.uniform, coeffs, threads)
+
+
+def apply_assembled(elem: str, kind: str, nodes, conn, rule, coef_mode: str = "uniform",
+                    mask: int = 0, uniform=None, coeffs=None, x=None, threads: int = 1):
+    """The assembled operator applied to a nodal vector, and the assembled
+    load vector, from the element matrices (Sec. 3.2: the global system is
+    the sum of the element contributions at their nodes):
+
+        y = sum_e P_e^T K^e P_e x,    b = sum_e P_e^T F^e
+
+    ``nodes`` (n_nodes, 3), ``conn`` (n_elem, n_vert) node ids; ``x`` (n_nodes *
+    n_comp,) node-major (node * n_comp + component). K^e, F^e come from
+    ``integrate`` on the gathered coordinates; the scatter is numpy's add.at.
+    Returns (y, b), float64."""
+    nodes = np.asarray(nodes, dtype=np.float64)
+    conn = np.asarray(conn, dtype=np.int64)
+    n, nv = conn.shape
+    nc = 1 if kind == "scalar" else 3
+    coords = np.ascontiguousarray(nodes[conn].transpose(1, 2, 0).reshape(nv * 3, n))
+    K, F = integrate(elem, kind, coords, rule, coef_mode, mask, uniform, coeffs, threads)
+    dof = (conn[:, :, None] * nc + np.arange(nc)[None, None, :]).reshape(n, nv * nc)
+    x = np.asarray(x, dtype=np.float64)
+    ye = np.einsum("ers,es->er", K, x[dof])
+    y = np.zeros(nodes.shape[0] * nc)
+    b = np.zeros(nodes.shape[0] * nc)
+    np.add.at(y, dof.ravel(), ye.ravel())
+    np.add.at(b, dof.ravel(), F.ravel())
+    return y, b

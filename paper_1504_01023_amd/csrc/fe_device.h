@@ -266,6 +266,18 @@ struct ScalarBlock {
         return packed ? pidx(NS, r, s) : NS * r + s;
     }
     __device__ __forceinline__ int f_index(int r) const { return r; }
+    // Results: K entry (r, s) of an N x N matrix and F entry r, for V elements.
+    template <int V, bool NT, typename T>
+    __device__ __forceinline__ void put_k(const Streams &st, int N, int packed, int r, int s,
+                                          int64_t e0, const T (&val)[V]) const
+    {
+        storev<V, NT>(static_cast<T *>(st.out_K) + k_index(N, packed, r, s) * st.ld_out + e0, val);
+    }
+    template <int V, bool NT, typename T>
+    __device__ __forceinline__ void put_f(const Streams &st, int r, int64_t e0, const T (&val)[V]) const
+    {
+        storev<V, NT>(static_cast<T *>(st.out_F) + f_index(r) * st.ld_out + e0, val);
+    }
 };
 
 struct VecBlock {
@@ -291,6 +303,44 @@ struct VecBlock {
         return (3 * r + A) * (3 * NS) + 3 * s + B;
     }
     __device__ __forceinline__ int f_index(int r) const { return 3 * r + A; }
+    template <int V, bool NT, typename T>
+    __device__ __forceinline__ void put_k(const Streams &st, int N, int packed, int r, int s,
+                                          int64_t e0, const T (&val)[V]) const
+    {
+        storev<V, NT>(static_cast<T *>(st.out_K) + k_index(N, packed, r, s) * st.ld_out + e0, val);
+    }
+    template <int V, bool NT, typename T>
+    __device__ __forceinline__ void put_f(const Streams &st, int r, int64_t e0, const T (&val)[V]) const
+    {
+        storev<V, NT>(static_cast<T *>(st.out_F) + f_index(r) * st.ld_out + e0, val);
+    }
+};
+
+// Matrix-free consumer of one element's results (one element per lane): K
+// is applied to the element's nodal values x as its entries are produced,
+// y_r += K_rs x_s (and y_s += K_rs x_r for the mirrored entry of a packed
+// symmetric K), and F is added to b when b is requested. The element matrix
+// is never stored. x, y, b are the lane's local arrays.
+template <typename T>
+struct ApplyBlock : ScalarBlock {
+    const T *x;
+    T *y;
+    T *b;  // nullptr: no load vector
+    __device__ __forceinline__ bool with_f() const { return b != nullptr; }
+    template <int V, bool NT, typename U>
+    __device__ __forceinline__ void put_k(const Streams &, int, int packed, int r, int s, int64_t,
+                                          const U (&val)[V]) const
+    {
+        static_assert(V == 1, "matrix-free application is one element per lane");
+        y[r] += val[0] * x[s];
+        if (packed && r != s)
+            y[s] += val[0] * x[r];
+    }
+    template <int V, bool NT, typename U>
+    __device__ __forceinline__ void put_f(const Streams &, int r, int64_t, const U (&val)[V]) const
+    {
+        b[r] += val[0];
+    }
 };
 
 // Coefficient functions: slot k's value at the physical point x is
@@ -521,8 +571,7 @@ struct TetScalar {
     __device__ __forceinline__ static void store_K(const Streams &st, int r, int s, int64_t e0,
                                                    const T (&val)[V], const BL &bl)
     {
-        const int k = bl.k_index(4, PACKED, r, s);
-        storev<V, NT>(static_cast<T *>(st.out_K) + k * st.ld_out + e0, val);
+        bl.template put_k<V, NT>(st, 4, PACKED, r, s, e0, val);
     }
 
     // Coefficients constant over the element: with the (constant) gradients
@@ -634,7 +683,7 @@ struct TetScalar {
         if (bl.with_f()) {
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                storev<V, NT>(static_cast<T *>(st.out_F) + bl.f_index(r) * st.ld_out + e0, Fv[r]);
+                bl.template put_f<V, NT>(st, r, e0, Fv[r]);
         }
     }
 
@@ -806,7 +855,7 @@ struct TetScalar {
         if (bl.with_f()) {
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                storev<V, NT>(static_cast<T *>(st.out_F) + bl.f_index(r) * st.ld_out + e0, Fv[r]);
+                bl.template put_f<V, NT>(st, r, e0, Fv[r]);
         }
     }
 };
@@ -843,7 +892,7 @@ struct TetVector {
 // K_(r a),(s b) = det [lam_b g_ra g_sb + mu_b g_rb g_sa + mu_b delta_ab g_r . g_s]
 // with lam_b = sum_q w_q lambda_q, mu_b likewise (gradients are constant);
 // F_(r a) = det sum_q w_q f_a,q phi_r(xi_q).
-template <typename T, int MODE, int PACKED>
+template <typename T, int MODE, int PACKED, class BL = ScalarBlock>
 struct TetElastic {
     static constexpr uint32_t SL = 31u;
     static constexpr bool PER_QP = (MODE == M_QP || MODE == M_QP_MIXED || MODE == M_FUNC);
@@ -854,6 +903,14 @@ struct TetElastic {
     {
         double X[V][12];
         st.template load_coords<4, V, NT>(e0, X);
+        run_x<V, NT, REF>(a, st, ref, X, e0);
+    }
+
+    template <int V, bool NT, int REF>
+    __device__ __forceinline__ static void run_x(const KArgs &a, const Streams &st, const Ref<REF> &ref,
+                                                 const double (&X)[V][12], int64_t e0,
+                                                 const BL &bl = BL())
+    {
         T lb[V], mb[V], fb[V][4][3];
         if constexpr (!PER_QP) {
             T E[V], nu[V], f[3][V];
@@ -916,7 +973,6 @@ struct TetElastic {
             lb[v] *= det[v];
             mb[v] *= det[v];
         }
-        T *outK = static_cast<T *>(st.out_K);
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
@@ -941,21 +997,21 @@ struct TetElastic {
                                 x += dot[v];
                             val[v] = x;
                         }
-                        const int k = PACKED ? pidx(12, row, col) : 12 * row + col;
-                        storev<V, NT>(outK + k * st.ld_out + e0, val);
+                        bl.template put_k<V, NT>(st, 12, PACKED, row, col, e0, val);
                     }
             }
-        T *outF = static_cast<T *>(st.out_F);
+        if (bl.with_f()) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+            for (int r = 0; r < 4; ++r)
 #pragma unroll
-            for (int al = 0; al < 3; ++al) {
-                T val[V];
+                for (int al = 0; al < 3; ++al) {
+                    T val[V];
 #pragma unroll
-                for (int v = 0; v < V; ++v)
-                    val[v] = det[v] * fb[v][r][al];
-                storev<V, NT>(outF + (3 * r + al) * st.ld_out + e0, val);
-            }
+                    for (int v = 0; v < V; ++v)
+                        val[v] = det[v] * fb[v][r][al];
+                    bl.template put_f<V, NT>(st, 3 * r + al, e0, val);
+                }
+        }
     }
 };
 
@@ -1141,18 +1197,19 @@ struct PrismScalar {
                     F[r] += p * c.d0;
             }
         }
-        T *outK = static_cast<T *>(st.out_K);
 #pragma unroll
         for (int r = 0; r < 6; ++r)
 #pragma unroll
-            for (int s = (PACKED ? r : 0); s < 6; ++s)
-                st1<NT>(outK + bl.k_index(6, PACKED, r, s) * st.ld_out + e,
-                        K[PACKED ? pidx(6, r, s) : 6 * r + s]);
+            for (int s = (PACKED ? r : 0); s < 6; ++s) {
+                const T v[1] = {K[PACKED ? pidx(6, r, s) : 6 * r + s]};
+                bl.template put_k<1, NT>(st, 6, PACKED, r, s, e, v);
+            }
         if (bl.with_f()) {
-            T *outF = static_cast<T *>(st.out_F);
 #pragma unroll
-            for (int r = 0; r < 6; ++r)
-                st1<NT>(outF + bl.f_index(r) * st.ld_out + e, F[r]);
+            for (int r = 0; r < 6; ++r) {
+                const T v[1] = {F[r]};
+                bl.template put_f<1, NT>(st, r, e, v);
+            }
         }
     }
 };

@@ -501,6 +501,92 @@ def run_paper(a, torch, fe) -> dict:
     return {"copy_GBps": copy_gbps, "fp64_matmul_TFLOPs": dgemm_tf, "rows": rows}
 
 
+APPLY_BASES = ("tet_poisson", "tet_cdr", "tet_elasticity", "prism_cdr", "prism_poisson_qp")
+
+
+def run_apply(a, torch, fe, oracle, base: str, dev) -> dict:
+    """Matrix-free operator application y += A x over the whole mesh (element
+    matrices formed in registers, never stored), coloured launches with plain
+    updates; one step = one application. Parity: y at sampled nodes against
+    the oracle's element matrices of every element touching them."""
+    wl = WORKLOADS[base][0]()
+    nodes_np, conn_np = wl.mesh.nodes, wl.mesh.conn
+    n, nv = conn_np.shape
+    n_nodes = nodes_np.shape[0]
+    t0 = time.time()
+    perm, ptr = fe.color_elements(wl.elem, conn_np, n_nodes)
+    log(f"[bench] {n} elements, {n_nodes} nodes, {len(ptr) - 1} colours ({time.time() - t0:.1f}s)")
+    dw = fe.to_device(wl, a.precision, device=dev)
+    p, rule = dw.problem, dw.rule
+    conn = torch.from_numpy(np.ascontiguousarray(conn_np[perm].T.astype(np.int32))).to(dev)
+    coeffs = dw.coeffs
+    if coeffs is not None and wl.coef_mode not in ("uniform", "function"):
+        coeffs = coeffs[:, torch.from_numpy(perm.astype(np.int64)).to(dev)].contiguous()
+    del dw
+    nodes = torch.from_numpy(nodes_np).to(dev).contiguous()
+    nc = 1 if wl.kind == "scalar" else 3
+    dt = torch.float64 if a.precision == "fp64" else torch.float32
+    tsz = 8 if a.precision == "fp64" else 4
+    x64 = np.random.default_rng(7).standard_normal(n_nodes * nc)
+    x = torch.from_numpy(x64).to(device=dev, dtype=dt)
+    y = torch.zeros_like(x)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        fe.apply_indexed(p, wl.elem, nodes, conn, coeffs, rule, x, y, None, color_ptr=ptr)
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(a.steps)]
+    w0 = time.perf_counter()
+    for e0, e1 in ev:
+        e0.record(stream)
+        step()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = np.array([e0.elapsed_time(e1) for e0, e1 in ev])
+    # one clean application for the parity check
+    y.zero_()
+    step()
+    torch.cuda.synchronize()
+    yg = y.double().cpu().numpy()
+    rng = np.random.default_rng(99)
+    snodes = rng.choice(n_nodes, size=min(2000, n_nodes), replace=False)
+    mark = np.zeros(n_nodes, dtype=bool)
+    mark[snodes] = True
+    touch = np.nonzero(mark[conn_np].any(axis=1))[0]
+    cf = None
+    if wl.coeffs is not None and wl.coef_mode == "function":
+        cf = wl.coeffs
+    elif wl.coeffs is not None:
+        cf = wl.coeffs[:, touch]
+        if a.precision == "fp32":
+            cf = cf.astype(np.float32).astype(np.float64)
+    xo = x.double().cpu().numpy()
+    K, _ = oracle.integrate(wl.elem, wl.kind, wl.mesh.coords[:, touch], oracle.quad_rule(wl.elem, wl.n_q),
+                            wl.coef_mode, wl.mask, wl.uniform, cf, threads=max(1, min(16, os.cpu_count() or 1)))
+    dof = (conn_np[touch][:, :, None] * nc + np.arange(nc)[None, None, :]).reshape(len(touch), nv * nc)
+    yr = np.zeros(n_nodes * nc)
+    ya = np.zeros(n_nodes * nc)
+    np.add.at(yr, dof.ravel(), np.einsum("ers,es->er", K, xo[dof]).ravel())
+    np.add.at(ya, dof.ravel(), np.einsum("ers,es->er", np.abs(K), np.abs(xo[dof])).ravel())
+    sd = (snodes[:, None] * nc + np.arange(nc)[None, :]).ravel()
+    err = float((np.abs(yg[sd] - yr[sd]) / np.maximum(ya[sd], 1e-300)).max())
+    tol = 1e-12 if a.precision == "fp64" else 2e-5
+    avg = float(ms.mean()) * 1e-3
+    ncoef = fe.coeff_entries(p, wl.elem, rule.n_q) if wl.coef_mode != "function" else 0
+    bpe = 4 * nv + tsz * ncoef + (24 + 3 * tsz * nc) * n_nodes / n
+    return {"wl": wl, "n_elem": n, "n_nodes": n_nodes, "colours": int(len(ptr) - 1),
+            "ms_avg": float(ms.mean()), "ms_min": float(ms.min()), "wall_s": wall,
+            "elements_per_s": n / avg, "bytes_per_element": bpe,
+            "achieved_GBps": bpe * n / avg / 1e9,
+            "parity": {"sampled_nodes": int(len(snodes)), "max_rel_err_y": err, "tol": tol,
+                       "ok": bool(err <= tol)}}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -508,6 +594,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="tet_poisson",
                     choices=sorted(WORKLOADS) + [w + "_indexed" for w in sorted(WORKLOADS)]
+                    + [w + "_apply" for w in APPLY_BASES]
                     + ["served", "paper"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--tune", action="store_true",
@@ -549,6 +636,28 @@ def main() -> int:
                 "config": {"workload": "paper"}, "paper": res}
         print(json.dumps(line), flush=True)
         return 0
+
+    if a.workload.endswith("_apply"):
+        base = a.workload[: -len("_apply")]
+        r = run_apply(a, torch, fe, oracle, base, dev)
+        line = {"metric": "elements/s of matrix-free operator application (K^e never stored)",
+                "value": r["elements_per_s"], "unit": "elements/s", "n_gpus": 1, "steps": a.steps,
+                "warmup": a.warmup, "ms_per_step": r["wall_s"] * 1e3 / a.steps,
+                "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                "dtype": "f64" if a.precision == "fp64" else "f32 (FP64 Jacobian)",
+                "data": "synthetic",
+                "config": {"workload": a.workload,
+                           "description": WORKLOADS[base][1] + "; y += A x, coloured launches",
+                           "n_elem": r["n_elem"], "n_nodes": r["n_nodes"], "colours": r["colours"],
+                           "precision": a.precision, "bytes_per_element": r["bytes_per_element"],
+                           "parallelism": "single GPU"},
+                "roofline": {"bound": "hbm", "achieved": r["achieved_GBps"], "peak": HBM_PEAK_GBPS,
+                             "unit": "GB/s", "frac": r["achieved_GBps"] / HBM_PEAK_GBPS,
+                             "traffic": None},
+                "cpu_baseline": None, "kernel_ms_avg": r["ms_avg"], "kernel_ms_min": r["ms_min"],
+                "parity": r["parity"]}
+        print(json.dumps(line), flush=True)
+        return 0 if r["parity"]["ok"] else 3
 
     if a.workload == "served":
         from paper_1504_01023_amd import serve

@@ -202,6 +202,46 @@ FE_API int fe_integrate_indexed(const fe_problem *problem, fe_elem_type elem_typ
                                 void *out_F, int64_t ld_out, const fe_variant *variant,
                                 hipStream_t stream);
 
+/* Matrix-free application of the assembled operator, with the element
+ * matrices computed in registers and never stored (Sec. 3.1 leaves open
+ * whether element matrices are stored at all; Sec. 3.2 assembles the element
+ * contributions at their nodes, by colouring for parallel updates):
+ *   y[i] += sum over elements e and local nodes r with conn[r][e] = node(i)
+ *           of (K^e x^e)_r,      x^e = x at the element's nodes,
+ *   b[i] += the same sum of F^e_r            (when b is not NULL).
+ * Inputs as for fe_integrate_indexed (nodes, conn, coeffs with leading
+ * dimension ld_in, rule). x, y, b: device arrays of n_nodes * n_comp values
+ * in the precision of the tier (FP64, or FP32 for FE_FP32_BULK), node-major
+ * (index node * n_comp + component, n_comp = 1 scalar, 3 elasticity); x is
+ * read, y and b are accumulated into (zero them first). K^e and F^e are those
+ * of fe_integrate (same arithmetic, one element per lane), so K^e x^e differs
+ * from a product with stored matrices only by the order of the final sums.
+ * Colouring: color_ptr (host, n_colors + 1 offsets from 0 to n_elem) splits
+ * the elements into colours whose elements share no node (fe_color_elements
+ * computes one; the caller orders conn and coeffs accordingly). Each colour
+ * is one launch with plain read-add-write updates: the result is
+ * deterministic. n_colors = 0: one launch with hardware atomic adds, in
+ * whatever order the elements run (the last bits may vary between runs).
+ * Built for scalar CDR (tetrahedra and prisms) and elasticity on tetrahedra;
+ * other problems return FE_ERR_UNSUPPORTED. Node ids outside [0, n_nodes)
+ * are clamped. Enqueued on `stream`; no allocation. */
+FE_API int fe_apply_indexed(const fe_problem *problem, fe_elem_type elem_type, int64_t n_elem,
+                            const double *nodes, int64_t n_nodes, const int32_t *conn,
+                            int64_t ld_conn, const void *coeffs, int64_t ld_in,
+                            const fe_quad_rule *quad_rule, const void *x, void *y, void *b,
+                            const int64_t *color_ptr, int32_t n_colors, hipStream_t stream);
+
+/* Greedy colouring on the host: elements of one colour share no node. conn
+ * is host memory, conn[v * ld_conn + e] (int32). Writes perm[n_elem] (the
+ * original element ids, colour by colour, increasing within a colour) and
+ * color_ptr[0 .. n_colors] (offsets into perm); color_ptr must hold
+ * max_colors + 1 values. Returns the number of colours, or minus a status
+ * (FE_ERR_CAPACITY when more than max_colors are needed, FE_ERR_INVALID_ARG
+ * for bad arguments or node ids outside [0, n_nodes)). */
+FE_API int fe_color_elements(fe_elem_type elem_type, int64_t n_elem, const int32_t *conn,
+                             int64_t ld_conn, int64_t n_nodes, int32_t *perm, int64_t *color_ptr,
+                             int32_t max_colors);
+
 /* ---------------------------------------------------------------------
  * Sizes and accounting (Sec. 4.1, table "memory_requirements"; Sec. 4.4,
  * table "accesses_and_operations"). Each returns -1 on invalid input.

@@ -6,6 +6,7 @@
 // kernel.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -244,12 +245,13 @@ int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coor
     if ((st = check_symmetry(problem)))
         return st;
     const uint32_t mask = effective_mask(problem);
-    if (form == 1)
+    if (form >= 1)
         coords = nullptr;  // indexed geometry: no per-element coordinates
     if (n_elem > 0) {
-        if ((form == 0 && !coords) || (form == 1 && !conn) || !out_K || !out_F)
+        // form 0: per-element coordinates; 1: indexed; 2: indexed, matrix-free (no K, F)
+        if ((form == 0 && !coords) || (form >= 1 && !conn) || (form < 2 && (!out_K || !out_F)))
             return fail(FE_ERR_INVALID_ARG, "NULL coordinates, connectivity or output pointer");
-        if (form == 1 && ld_conn < n_elem)
+        if (form >= 1 && ld_conn < n_elem)
             return fail(FE_ERR_INVALID_ARG, "connectivity leading dimension smaller than n_elem");
         if (mask && !coeffs)
             return fail(FE_ERR_INVALID_ARG, "coeffs is NULL but coef_mask reads %u slots",
@@ -312,7 +314,7 @@ int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coor
             return false;
         const size_t ca = std::min<size_t>(16, 8 * V), ta = std::min<size_t>(16, tsz * V);
         const size_t ia = std::min<size_t>(16, 4 * V);
-        if (form == 1 && (ld_conn % V || !aligned(conn, ia)))
+        if (form >= 1 && (ld_conn % V || !aligned(conn, ia)))
             return false;
         return aligned(coords, ca) && aligned(out_K, ta) && aligned(out_F, ta) &&
                (!mask || fn || aligned(coeffs, ta));
@@ -328,7 +330,9 @@ int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coor
     k.split = split;
     k.order = order;
     k.nq = rule->n_q;
-    auto usable = [&](const KernelEntry *x) { return x && (form == 0 || x->idx != nullptr); };
+    auto usable = [&](const KernelEntry *x) {
+        return x && (form == 0 || (form == 1 && x->idx != nullptr) || (form == 2 && x->apply != nullptr));
+    };
     const KernelEntry *e = find_kernel(k);
     if (!usable(e)) {
         k.nq = 0;
@@ -449,6 +453,120 @@ int fe_integrate_indexed(const fe_problem *problem, fe_elem_type elem_type, int6
         return st;
     IdxArgs gi{nodes, conn, ld_conn, (uint32_t)n_nodes};
     return launch_indexed(pl, gi, stream);
+}
+
+int fe_apply_indexed(const fe_problem *problem, fe_elem_type elem_type, int64_t n_elem,
+                     const double *nodes, int64_t n_nodes, const int32_t *conn, int64_t ld_conn,
+                     const void *coeffs, int64_t ld_in, const fe_quad_rule *quad_rule,
+                     const void *x, void *y, void *b, const int64_t *color_ptr, int32_t n_colors,
+                     hipStream_t stream)
+{
+    if (n_elem > 0 && (!nodes || n_nodes < 1 || n_nodes > 0x7fffffffLL))
+        return fail(FE_ERR_INVALID_ARG, "need a node array with 1 .. 2^31-1 nodes");
+    if (nodes && ((uintptr_t)nodes % 8))
+        return fail(FE_ERR_UNSUPPORTED, "nodes must be 8-byte aligned");
+    if (n_elem > 0 && (!x || !y))
+        return fail(FE_ERR_INVALID_ARG, "x and y must not be NULL");
+    if (n_colors < 0 || (n_colors > 0 && !color_ptr))
+        return fail(FE_ERR_INVALID_ARG, "n_colors must be >= 0, with color_ptr for n_colors > 0");
+    if (n_colors > 0) {
+        if (color_ptr[0] != 0 || color_ptr[n_colors] != n_elem)
+            return fail(FE_ERR_INVALID_ARG, "color_ptr must run from 0 to n_elem");
+        for (int c = 0; c < n_colors; ++c)
+            if (color_ptr[c + 1] < color_ptr[c])
+                return fail(FE_ERR_INVALID_ARG, "color_ptr must not decrease");
+    }
+    // the matrix-free form exists for the base variant: one element per lane
+    const fe_variant base{256, 1, 2, 1, 0, 1, 1};
+    Plan pl;
+    int st = plan(problem, elem_type, n_elem, nullptr, coeffs, ld_in, quad_rule, nullptr, nullptr,
+                  n_elem, &base, pl, 2, conn, ld_conn);
+    if (st)
+        return st;
+    if (!pl.entry->apply)
+        return fail(FE_ERR_UNSUPPORTED, "no matrix-free form for this problem");
+    const size_t tsz = problem->precision == FE_FP64 ? 8 : 4;
+    if (!aligned(x, tsz) || !aligned(y, tsz) || !aligned(b, tsz))
+        return fail(FE_ERR_UNSUPPORTED, "x, y and b must be aligned to their element size");
+    if (n_elem == 0)
+        return FE_OK;
+    const bool fn = problem->coef_mode == FE_COEF_FUNCTION;
+    const ApplyArgs ap{x, y, b};
+    auto run = [&](int64_t e0, int64_t cnt, int atomic) -> int {
+        if (cnt == 0)
+            return FE_OK;
+        KArgs a = pl.args;
+        a.n_elem = cnt;
+        if (a.coeffs && !fn)
+            a.coeffs = static_cast<const char *>(a.coeffs) + tsz * e0;
+        const IdxArgs gi{nodes, conn + e0, ld_conn, (uint32_t)n_nodes};
+        int64_t grid = (cnt + pl.block - 1) / pl.block;
+        if (grid > 0x7fffffff)
+            grid = 0x7fffffff;
+        pl.entry->apply(a, gi, ap, atomic, (unsigned)grid, pl.block, stream);
+        const hipError_t err = hipGetLastError();
+        if (err != hipSuccess)
+            return fail(FE_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(err));
+        return FE_OK;
+    };
+    if (n_colors == 0)
+        return run(0, n_elem, 1);
+    for (int c = 0; c < n_colors; ++c)
+        if ((st = run(color_ptr[c], color_ptr[c + 1] - color_ptr[c], 0)))
+            return st;
+    return FE_OK;
+}
+
+int fe_color_elements(fe_elem_type elem_type, int64_t n_elem, const int32_t *conn, int64_t ld_conn,
+                      int64_t n_nodes, int32_t *perm, int64_t *color_ptr, int32_t max_colors)
+{
+    if (elem_type != FE_TET4 && elem_type != FE_PRISM6)
+        return -fail(FE_ERR_INVALID_ARG, "bad element type %d", elem_type);
+    if (n_elem < 0 || n_elem > 0x7fffffffLL || n_nodes < 1 || n_nodes > 0x7fffffffLL ||
+        max_colors < 1 || (n_elem > 0 && (!conn || !perm || ld_conn < n_elem)) || !color_ptr)
+        return -fail(FE_ERR_INVALID_ARG, "bad colouring arguments");
+    const int nv = n_shape(elem_type);
+    const int words = (max_colors + 63) / 64;
+    std::vector<uint64_t> used((size_t)n_nodes * words, 0);  // colours taken at each node
+    std::vector<int32_t> color((size_t)n_elem);
+    int n_colors = 0;
+    for (int64_t e = 0; e < n_elem; ++e) {
+        int32_t id[6];
+        for (int v = 0; v < nv; ++v) {
+            id[v] = conn[v * ld_conn + e];
+            if (id[v] < 0 || id[v] >= n_nodes)
+                return -fail(FE_ERR_INVALID_ARG, "element %lld has node id %d outside [0, %lld)",
+                             (long long)e, id[v], (long long)n_nodes);
+        }
+        int c = -1;
+        for (int w = 0; w < words && c < 0; ++w) {
+            uint64_t taken = 0;
+            for (int v = 0; v < nv; ++v)
+                taken |= used[(size_t)id[v] * words + w];
+            if (~taken) {
+                const int cand = 64 * w + __builtin_ctzll(~taken);
+                if (cand < max_colors)
+                    c = cand;
+            }
+        }
+        if (c < 0)
+            return -fail(FE_ERR_CAPACITY, "more than %d colours needed", max_colors);
+        for (int v = 0; v < nv; ++v)
+            used[(size_t)id[v] * words + c / 64] |= 1ull << (c % 64);
+        color[e] = c;
+        n_colors = std::max(n_colors, c + 1);
+    }
+    // elements colour by colour, in their original order within a colour
+    std::vector<int64_t> count((size_t)n_colors + 1, 0);
+    for (int64_t e = 0; e < n_elem; ++e)
+        ++count[color[e] + 1];
+    for (int c = 0; c < n_colors; ++c)
+        count[c + 1] += count[c];
+    for (int c = 0; c <= n_colors; ++c)
+        color_ptr[c] = count[c];
+    for (int64_t e = 0; e < n_elem; ++e)
+        perm[count[color[e]]++] = (int32_t)e;
+    return n_colors;
 }
 
 int fe_integrate(const fe_problem *problem, fe_elem_type elem_type, int64_t n_elem,

@@ -321,12 +321,12 @@ struct VecBlock {
 // y_r += K_rs x_s (and y_s += K_rs x_r for the mirrored entry of a packed
 // symmetric K), and F is added to b when b is requested. The element matrix
 // is never stored. x, y, b are the lane's local arrays.
-template <typename T>
+template <typename T, bool WITH_B>
 struct ApplyBlock : ScalarBlock {
     const T *x;
     T *y;
-    T *b;  // nullptr: no load vector
-    __device__ __forceinline__ bool with_f() const { return b != nullptr; }
+    T *b;  // used when WITH_B
+    __device__ __forceinline__ bool with_f() const { return WITH_B; }
     template <int V, bool NT, typename U>
     __device__ __forceinline__ void put_k(const Streams &, int, int packed, int r, int s, int64_t,
                                           const U (&val)[V]) const
@@ -567,11 +567,23 @@ struct TetScalar {
             run_qp<V, NT, REF>(a, st, ref, X, e0);
     }
 
-    template <int V, bool NT>
+    template <int V, bool NT, class B2>
     __device__ __forceinline__ static void store_K(const Streams &st, int r, int s, int64_t e0,
-                                                   const T (&val)[V], const BL &bl)
+                                                   const T (&val)[V], const B2 &bl)
     {
         bl.template put_k<V, NT>(st, 4, PACKED, r, s, e0, val);
+    }
+
+    // One element from its vertex coordinates, results to bl (matrix-free).
+    template <bool NT, int REF, class B2>
+    __device__ __forceinline__ static void apply_x(const KArgs &a, const Streams &st, const Ref<REF> &ref,
+                                                   const double (&X)[12], int64_t e, const B2 &bl)
+    {
+        const double (&Xv)[1][12] = reinterpret_cast<const double (&)[1][12]>(X);
+        if constexpr (PER_QP)
+            run_qp<1, NT, REF>(a, st, ref, Xv, e, bl);
+        else
+            run_const<1, NT>(a, st, Xv, e, bl);
     }
 
     // Coefficients constant over the element: with the (constant) gradients
@@ -579,10 +591,10 @@ struct TetScalar {
     // carry the whole point sum:
     //   K_rs = det [W g_r . C g_s + (c^{.;0} . g_r) m_s + m_r (c^{0;.} . g_s)
     //               + c^{0;0} M_rs],   F_r = det [W d . g_r + d^0 m_r].
-    template <int V, bool NT>
+    template <int V, bool NT, class B2 = BL>
     __device__ __forceinline__ static void run_const(const KArgs &a, const Streams &st,
                                                      const double (&X)[V][12],
-                                                     int64_t e0, const BL &bl = BL())
+                                                     int64_t e0, const B2 &bl = B2())
     {
         T C[3][3][V], ca[3][V], cb[3][V], c00[V], d[3][V], d0[V];
         if constexpr (DIFF) {
@@ -694,10 +706,10 @@ struct TetScalar {
     //   Cb = sum_q w C_q, Pb_s = sum_q w phi_s c^{.;0}_q, Qb_r = sum_q w phi_r c^{0;.}_q,
     //   Mb_rs = sum_q w c^{0;0}_q phi_r phi_s, Db = sum_q w d_q, fb_r = sum_q w d^0_q phi_r,
     //   K_rs = det (g_r . Cb g_s + g_r . Pb_s + Qb_r . g_s + Mb_rs), F_r = det (Db . g_r + fb_r).
-    template <int V, bool NT, int REF>
+    template <int V, bool NT, int REF, class B2 = BL>
     __device__ __forceinline__ static void run_qp(const KArgs &a, const Streams &st, const Ref<REF> &ref,
                                                   const double (&X)[V][12], int64_t e0,
-                                                  const BL &bl = BL())
+                                                  const B2 &bl = B2())
     {
         const bool wf = bl.with_f();
         T Cb[V][3][3], Pb[V][4][3], Qb[V][4][3], Mb[V][4][4], Db[V][3], fb[V][4];
@@ -722,7 +734,7 @@ struct TetScalar {
             }
         }
         for (int q = 0; q < a.n_q; ++q) {
-            PointCoefs<T, MODE, SL, V, NT, BL> pc(bl);
+            PointCoefs<T, MODE, SL, V, NT, B2> pc(bl);
             if constexpr (MODE == M_FUNC) {
                 // physical point x(xi_q) = X_0 + sum_r phi_r(xi_q) (X_r - X_0)
                 double x[V][3];
@@ -906,10 +918,17 @@ struct TetElastic {
         run_x<V, NT, REF>(a, st, ref, X, e0);
     }
 
-    template <int V, bool NT, int REF>
+    template <bool NT, int REF, class B2>
+    __device__ __forceinline__ static void apply_x(const KArgs &a, const Streams &st, const Ref<REF> &ref,
+                                                   const double (&X)[12], int64_t e, const B2 &bl)
+    {
+        run_x<1, NT, REF>(a, st, ref, reinterpret_cast<const double (&)[1][12]>(X), e, bl);
+    }
+
+    template <int V, bool NT, int REF, class B2 = BL>
     __device__ __forceinline__ static void run_x(const KArgs &a, const Streams &st, const Ref<REF> &ref,
                                                  const double (&X)[V][12], int64_t e0,
-                                                 const BL &bl = BL())
+                                                 const B2 &bl = B2())
     {
         T lb[V], mb[V], fb[V][4][3];
         if constexpr (!PER_QP) {
@@ -1049,13 +1068,13 @@ struct PrismScalar {
         }
     }
 
-    template <bool NT, class R>
+    template <bool NT, class R, class B2 = BL>
     __device__ __forceinline__ static void load_coefs(const KArgs &a, const Streams &st, const R &ref,
                                                       int q, int64_t e, const double (&X0)[3],
                                                       const double (&E)[18], Coefs &c,
-                                                      const BL &bl = BL())
+                                                      const B2 &bl = B2())
     {
-        PointCoefs<T, MODE, SL, 1, NT, BL> pc(bl);
+        PointCoefs<T, MODE, SL, 1, NT, B2> pc(bl);
         if constexpr (MODE == M_FUNC) {
             double x[1][3];
             point_x(X0, E, ref, q, x);
@@ -1125,12 +1144,25 @@ struct PrismScalar {
         body<NT>(a, st, ref, e, X0, X);
     }
 
+    template <bool NT, int REF, class B2>
+    __device__ __forceinline__ static void apply_x(const KArgs &a, const Streams &st, const Ref<REF> &ref,
+                                                   const double (&Xa)[18], int64_t e, const B2 &bl)
+    {
+        double X[18];
+#pragma unroll
+        for (int s = 0; s < 18; ++s)
+            X[s] = Xa[s];
+        const double X0[3] = {X[0], X[1], X[2]};
+        to_edge_vectors<6>(X);
+        body<NT>(a, st, ref, e, X0, X, bl);
+    }
+
     // Point loop and stores for one element, from vertex 0 and the edge
     // vectors X_r - X_0.
-    template <bool NT, class R>
+    template <bool NT, class R, class B2 = BL>
     __device__ __forceinline__ static void body(const KArgs &a, const Streams &st, const R &ref,
                                                 int64_t e, const double (&X0)[3], const double (&X)[18],
-                                                const BL &bl = BL())
+                                                const B2 &bl = B2())
     {
         constexpr int NK = PACKED ? 21 : 36;
         T K[NK], F[6];
@@ -1739,6 +1771,98 @@ __global__ __launch_bounds__(256) void fe_kernel_idx(KArgs a, IdxArgs gi)
                 P::template run<1, NT, REF>(a, st, ref, e);
         }
     }
+}
+
+// Matrix-free application of the assembled operator (indexed geometry, one
+// element per lane): gather the vertex ids, coordinates and nodal values x,
+// compute the element's K (and F) exactly as the storing kernels do but
+// consume them in registers (ApplyBlock), then add the element's K x (and F)
+// to y (and b) at its nodes. ATOMIC: hardware atomic adds, any element
+// order; otherwise plain read-add-write, for launches over one colour of
+// elements that share no node.
+template <typename T, bool ATOMIC>
+__device__ __forceinline__ void add_at(T *p, T v)
+{
+    if constexpr (ATOMIC)
+        unsafeAtomicAdd(p, v);
+    else
+        *p += v;
+}
+
+template <class P, int NV, int NC, typename T, bool NT, int REF, bool ATOMIC, bool WITH_B>
+__global__ __launch_bounds__(256) void fe_apply_kernel(KArgs a, IdxArgs gi, ApplyArgs ap)
+{
+    __shared__ RefLds lds_ref[1];
+    if constexpr (REF == REF_LDS) {
+        const int n_w = a.n_q, n_phi = a.n_q * 6, n_dphi = a.n_q * 18;
+        for (int i = threadIdx.x; i < n_w; i += blockDim.x)
+            lds_ref[0].w[i] = a.w[i];
+        for (int i = threadIdx.x; i < n_phi; i += blockDim.x)
+            (&lds_ref[0].phi[0][0])[i] = (&a.phi[0][0])[i];
+        for (int i = threadIdx.x; i < n_dphi; i += blockDim.x)
+            (&lds_ref[0].dphi[0][0][0])[i] = (&a.dphi[0][0][0])[i];
+        __syncthreads();
+    }
+    const Ref<REF> ref{a, &lds_ref[0]};
+    const Streams st{nullptr, a.coeffs, nullptr, nullptr, a.ld_in, a.ld_out};
+    const T *x = static_cast<const T *>(ap.x);
+    T *y = static_cast<T *>(ap.y);
+    T *b = static_cast<T *>(ap.b);
+    constexpr int N = NV * NC;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < a.n_elem; e += stride) {
+        uint32_t id[NV];
+        double X[3 * NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const uint32_t u = (uint32_t)ld1<NT>(gi.conn + v * gi.ld_conn + e);
+            id[v] = u < gi.n_nodes ? u : gi.n_nodes - 1;  // clamped: never a fault
+            const double *pn = gi.nodes + 3 * (int64_t)id[v];
+            X[3 * v + 0] = pn[0];
+            X[3 * v + 1] = pn[1];
+            X[3 * v + 2] = pn[2];
+        }
+        T xe[N], ye[N], be[N];
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                xe[NC * v + c] = x[(int64_t)NC * id[v] + c];
+                ye[NC * v + c] = T(0);
+                be[NC * v + c] = T(0);
+            }
+        ApplyBlock<T, WITH_B> bl;
+        bl.x = xe;
+        bl.y = ye;
+        bl.b = be;
+        P::template apply_x<NT, REF>(a, st, ref, X, e, bl);
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                add_at<T, ATOMIC>(y + (int64_t)NC * id[v] + c, ye[NC * v + c]);
+                if constexpr (WITH_B)
+                    add_at<T, ATOMIC>(b + (int64_t)NC * id[v] + c, be[NC * v + c]);
+            }
+    }
+}
+
+template <class P, int NV, int NC, typename T, bool NT, int REF>
+void launch_fe_apply(const KArgs &a, const IdxArgs &gi, const ApplyArgs &ap, int atomic,
+                     unsigned grid, unsigned block, hipStream_t stream)
+{
+    if (atomic && ap.b)
+        hipLaunchKernelGGL((fe_apply_kernel<P, NV, NC, T, NT, REF, true, true>), dim3(grid), dim3(block),
+                           0, stream, a, gi, ap);
+    else if (atomic)
+        hipLaunchKernelGGL((fe_apply_kernel<P, NV, NC, T, NT, REF, true, false>), dim3(grid),
+                           dim3(block), 0, stream, a, gi, ap);
+    else if (ap.b)
+        hipLaunchKernelGGL((fe_apply_kernel<P, NV, NC, T, NT, REF, false, true>), dim3(grid),
+                           dim3(block), 0, stream, a, gi, ap);
+    else
+        hipLaunchKernelGGL((fe_apply_kernel<P, NV, NC, T, NT, REF, false, false>), dim3(grid),
+                           dim3(block), 0, stream, a, gi, ap);
 }
 
 template <class P, int V, bool NT, int REF>

@@ -125,12 +125,23 @@ struct IdxArgs {
 typedef void (*IdxLaunchFn)(const KArgs &, const IdxArgs &, unsigned grid, unsigned block,
                             hipStream_t);
 
+// Matrix-free application: nodal vectors in the precision of the tier,
+// node-major (node * components + component).
+struct ApplyArgs {
+    const void *x;  // read
+    void *y;        // y += assembled K x
+    void *b;        // b += assembled F, or nullptr
+};
+typedef void (*ApplyLaunchFn)(const KArgs &, const IdxArgs &, const ApplyArgs &, int atomic,
+                              unsigned grid, unsigned block, hipStream_t);
+
 struct KernelEntry {
     KernelKey key;
     LaunchFn launch;
     const void *func;
     BatchLaunchFn batch;  // persistent batched form, or nullptr
     IdxLaunchFn idx;      // indexed-geometry form, or nullptr
+    ApplyLaunchFn apply;  // matrix-free form (one element per lane), or nullptr
 };
 
 // Registration of compiled kernels (each kernel translation unit registers

@@ -8,10 +8,11 @@
 namespace fe {
 
 // Registers the plain kernel; B = 1 also registers the batched (persistent)
-// form and the indexed-geometry form.
+// form and the indexed-geometry form, and, when the problem class has one,
+// the matrix-free form (ap).
 template <class P, int V, int NT, int REF, int B = 0>
 inline void reg(int elem, int kind, int prec, int terms, int mode, int packed, int nq, int split = 1,
-                int order = 1)
+                int order = 1, ApplyLaunchFn ap = nullptr)
 {
     KernelKey k{elem, kind, prec, terms, mode, packed, V, NT, REF, nq, split, order};
     BatchLaunchFn bl = nullptr;
@@ -22,7 +23,19 @@ inline void reg(int elem, int kind, int prec, int terms, int mode, int packed, i
     }
     register_kernel(KernelEntry{k, &launch_fe_kernel<P, V, NT != 0, REF>,
                                 reinterpret_cast<const void *>(&fe_kernel<P, V, NT != 0, REF>), bl,
-                                il});
+                                il, B != 0 ? ap : nullptr});
+}
+
+// The matrix-free form of a problem class with NV vertices and NC
+// components, for the base variants (one element per lane, with the batched
+// and indexed forms).
+template <class P, int NV, int NC, typename T, int V, int NT, int REF, int B>
+constexpr ApplyLaunchFn apply_form()
+{
+    if constexpr (V == 1 && B != 0)
+        return &launch_fe_apply<P, NV, NC, T, NT != 0, REF>;
+    else
+        return nullptr;
 }
 
 template <typename T>
@@ -31,22 +44,25 @@ constexpr int prec_of() { return std::is_same<T, float>::value ? FE_FP32_BULK : 
 template <typename T, int TERMS, int MODE, int PK, int V, int NT, int B = 0>
 inline void reg_tet_scalar()
 {
-    reg<TetScalar<T, TERMS, MODE, PK>, V, NT, REF_KARG, B>(FE_TET4, FE_SCALAR_CDR, prec_of<T>(), TERMS,
-                                                        MODE, PK, 0);
+    typedef TetScalar<T, TERMS, MODE, PK> P;
+    reg<P, V, NT, REF_KARG, B>(FE_TET4, FE_SCALAR_CDR, prec_of<T>(), TERMS, MODE, PK, 0, 1, 1,
+                               apply_form<P, 4, 1, T, V, NT, REF_KARG, B>());
 }
 
 template <typename T, int MODE, int PK, int V, int NT, int B = 0>
 inline void reg_tet_elastic()
 {
-    reg<TetElastic<T, MODE, PK>, V, NT, REF_KARG, B>(FE_TET4, FE_ELASTICITY, prec_of<T>(), TS_ELAST,
-                                                  MODE, PK, 0);
+    typedef TetElastic<T, MODE, PK> P;
+    reg<P, V, NT, REF_KARG, B>(FE_TET4, FE_ELASTICITY, prec_of<T>(), TS_ELAST, MODE, PK, 0, 1, 1,
+                               apply_form<P, 4, 3, T, V, NT, REF_KARG, B>());
 }
 
 template <typename T, int TERMS, int MODE, int PK, int NQ, int NT, int REF, int B = 0>
 inline void reg_prism_scalar()
 {
-    reg<PrismScalar<T, TERMS, MODE, PK, NQ>, 1, NT, REF, B>(FE_PRISM6, FE_SCALAR_CDR, prec_of<T>(),
-                                                         TERMS, MODE, PK, NQ);
+    typedef PrismScalar<T, TERMS, MODE, PK, NQ> P;
+    reg<P, 1, NT, REF, B>(FE_PRISM6, FE_SCALAR_CDR, prec_of<T>(), TERMS, MODE, PK, NQ, 1, 1,
+                          apply_form<P, 6, 1, T, 1, NT, REF, B>());
 }
 
 // Prism scalar kernels in the SQS / SSQ loop orders (one element per lane).

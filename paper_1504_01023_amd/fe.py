@@ -101,6 +101,9 @@ def lib():
         L.fe_stream_copy.argtypes = [vp, vp, i64, vp]
         L.fe_integrate_indexed.argtypes = [P, i32, i64, vp, i64, vp, i64, vp, i64, R, vp, vp, i64,
                                            V, vp]
+        L.fe_apply_indexed.argtypes = [P, i32, i64, vp, i64, vp, i64, vp, i64, R, vp, vp, vp,
+                                       ctypes.POINTER(ctypes.c_int64), i32, vp]
+        L.fe_color_elements.argtypes = [i32, i64, vp, i64, i64, vp, vp, i32]
         _lib = L
     return _lib
 
@@ -282,6 +285,66 @@ def integrate_indexed(p: Problem, elem, nodes, conn, coeffs, rule: Rule, out_K=N
                                       ctypes.c_void_p(out_F.data_ptr()), ld_out, vptr,
                                       _stream_handle(stream)))
     return out_K, out_F
+
+
+def color_elements(elem, conn, n_nodes: int, max_colors: int = 256):
+    """Greedy colouring on the host (elements of one colour share no node).
+    conn: (n_elem, n_vert) integer array of node ids. Returns (perm, color_ptr):
+    the original element ids colour by colour, and the n_colors + 1 offsets."""
+    e = ELEM.get(elem, elem)
+    c = np.ascontiguousarray(np.asarray(conn).T.astype(np.int32))
+    n = c.shape[1]
+    perm = np.empty(n, dtype=np.int32)
+    ptr = np.empty(max_colors + 1, dtype=np.int64)
+    k = lib().fe_color_elements(e, n, c.ctypes.data_as(ctypes.c_void_p), n, int(n_nodes),
+                                perm.ctypes.data_as(ctypes.c_void_p),
+                                ptr.ctypes.data_as(ctypes.c_void_p), max_colors)
+    if k < 0:
+        _check(-k)
+    return perm, ptr[: k + 1].copy()
+
+
+def apply_indexed(p: Problem, elem, nodes, conn, coeffs, rule: Rule, x, y=None, b=None,
+                  color_ptr=None, n_elem: int | None = None, stream=None):
+    """Matrix-free y += A x (and b += assembled F when b is given) over the
+    elements of conn (n_vert, ld) int32; x, y, b device vectors of n_nodes *
+    components values in the tier's precision. color_ptr: host offsets of the
+    colours (None: one launch with atomic adds). Returns (y, b)."""
+    import torch
+    e = ELEM.get(elem, elem)
+    nv = 4 if e == TET4 else 6
+    ld_conn = conn.shape[1]
+    n = ld_conn if n_elem is None else int(n_elem)
+    dt = _dtype(p)
+    ncomp = 1 if p.kind == SCALAR_CDR else 3
+    ndof = nodes.shape[0] * ncomp
+    if not (nodes.is_cuda and nodes.dtype == torch.float64 and nodes.is_contiguous()
+            and nodes.dim() == 2 and nodes.shape[1] == 3):
+        raise ValueError("nodes must be a contiguous (n_nodes, 3) float64 GPU tensor")
+    _check_tensor(conn, "conn", torch.int32, nv, ld_conn)
+    for name, t in (("x", x), ("y", y), ("b", b)):
+        if t is not None and not (t.is_cuda and t.dtype == dt and t.is_contiguous()
+                                  and t.numel() == ndof):
+            raise ValueError(f"{name} must be a contiguous {dt} GPU vector of {ndof} values")
+    if y is None:
+        y = torch.zeros(ndof, dtype=dt, device=nodes.device)
+    nc = coeff_entries(p, e, rule.n_q)
+    ld_in = coeffs.shape[1] if (coeffs is not None and nc > 0 and coeffs.dim() == 2) else n
+    if nc > 0:
+        _check_coeffs(p, coeffs, dt, nc, ld_in)
+    cptr = ctypes.c_void_p(coeffs.data_ptr()) if (coeffs is not None and nc > 0) else None
+    if color_ptr is None:
+        cp, ncol = None, 0
+    else:
+        cpa = np.ascontiguousarray(color_ptr, dtype=np.int64)
+        cp, ncol = cpa.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(cpa) - 1
+    _check(lib().fe_apply_indexed(ctypes.byref(p), e, n, ctypes.c_void_p(nodes.data_ptr()),
+                                  nodes.shape[0], ctypes.c_void_p(conn.data_ptr()), ld_conn, cptr,
+                                  ld_in, ctypes.byref(rule.c), ctypes.c_void_p(x.data_ptr()),
+                                  ctypes.c_void_p(y.data_ptr()),
+                                  ctypes.c_void_p(b.data_ptr()) if b is not None else None,
+                                  cp, ncol, _stream_handle(stream)))
+    return y, b
 
 
 def autotune(p: Problem, elem, coords, coeffs, rule: Rule, out_K, out_F, reps: int = 5,

@@ -100,3 +100,24 @@ SMALL = {
 @functools.lru_cache(maxsize=None)
 def small(name):
     return SMALL[name]()
+
+
+def apply_reference(wl, precision, x):
+    """Oracle side of the matrix-free tests: the assembled y = A x and load b
+    (from the oracle's element matrices), and the row-wise magnitudes
+    |A| |x| and sum |F| that scale their rounding errors."""
+    coeffs = oracle_coeffs(wl, precision)
+    r = oracle.quad_rule(wl.elem, wl.n_q)
+    y, b = oracle.apply_assembled(wl.elem, wl.kind, wl.mesh.nodes, wl.mesh.conn, r, wl.coef_mode,
+                                  wl.mask, wl.uniform, coeffs, x)
+    K, F = oracle.integrate(wl.elem, wl.kind, wl.mesh.coords, r, wl.coef_mode, wl.mask,
+                            wl.uniform, coeffs, ORACLE_THREADS)
+    nc = 1 if wl.kind == "scalar" else 3
+    conn = wl.mesh.conn
+    n, nv = conn.shape
+    dof = (conn[:, :, None] * nc + np.arange(nc)[None, None, :]).reshape(n, nv * nc)
+    yabs = np.zeros_like(y)
+    babs = np.zeros_like(b)
+    np.add.at(yabs, dof.ravel(), np.einsum("ers,es->er", np.abs(K), np.abs(x[dof])).ravel())
+    np.add.at(babs, dof.ravel(), np.abs(F).ravel())
+    return y, b, yabs, babs

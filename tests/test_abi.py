@@ -228,3 +228,60 @@ def test_vector_problem_sizes_and_validation():
         assert fe.k_entries(bad, "tet4") == -1
         assert _call(bad, coeffs=0x4000) == 2
     assert _call(p, coeffs=None) == 1
+
+
+@pytest.mark.parametrize("elem", ["tet4", "prism6"])
+def test_element_colouring(elem):
+    mesh = inputs.tet_cube(4, 1) if elem == "tet4" else inputs.prism_layers(5, 3, 2)
+    n = mesh.conn.shape[0]
+    perm, ptr = fe.color_elements(elem, mesh.conn, mesh.nodes.shape[0])
+    assert sorted(perm.tolist()) == list(range(n))
+    assert ptr[0] == 0 and ptr[-1] == n and np.all(np.diff(ptr) > 0)
+    for c in range(len(ptr) - 1):
+        ids = perm[ptr[c]:ptr[c + 1]]
+        assert np.all(np.diff(ids) > 0)                      # original order within a colour
+        nodes = mesh.conn[ids].ravel()
+        assert len(np.unique(nodes)) == len(nodes)           # no shared node
+    # a node touches at most 24 Kuhn tets / 12 prisms: greedy needs few colours
+    assert len(ptr) - 1 <= (32 if elem == "tet4" else 16)
+
+
+def test_colouring_errors():
+    mesh = inputs.tet_cube(2, 1)
+    with pytest.raises(fe.FeError) as e:
+        fe.color_elements("tet4", mesh.conn, mesh.nodes.shape[0], max_colors=3)
+    assert e.value.status == 5
+    bad = mesh.conn.copy()
+    bad[3, 1] = mesh.nodes.shape[0]
+    with pytest.raises(fe.FeError) as e:
+        fe.color_elements("tet4", bad, mesh.nodes.shape[0])
+    assert e.value.status == 1
+
+
+def _apply_call(p, color_ptr=None, n_colors=0, x=0x5000, y=0x6000, nodes=0x7000, n_nodes=10,
+                coeffs=None):
+    L = fe.lib()
+    rule = fe.builtin_rule("tet4", 1)
+    cp = None
+    if color_ptr is not None:
+        arr = np.asarray(color_ptr, dtype=np.int64)
+        cp = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        _apply_call.keep = arr
+    return L.fe_apply_indexed(ctypes.byref(p), 0, 10, ctypes.c_void_p(nodes), n_nodes,
+                              ctypes.c_void_p(0x1000), 10,
+                              ctypes.c_void_p(coeffs) if coeffs else None, 10, ctypes.byref(rule.c),
+                              ctypes.c_void_p(x) if x else None, ctypes.c_void_p(y) if y else None,
+                              None, cp, n_colors, None)
+
+
+def test_apply_validation_before_launch():
+    p = fe.problem("scalar", "fp64", "uniform", 0, inputs.identity_diffusion_uniform(), "packed")
+    assert _apply_call(p, x=0) == 1                               # x missing
+    assert _apply_call(p, n_nodes=0) == 1                         # no nodes
+    assert _apply_call(p, color_ptr=[0, 4], n_colors=1) == 1      # does not reach n_elem
+    assert _apply_call(p, color_ptr=[0, 6, 4, 10], n_colors=3) == 1
+    assert _apply_call(p, n_colors=2) == 1                        # colours without offsets
+    v = fe.problem("vector", "fp64", "element", inputs.ALL_VECTOR_MASK, None, "full")
+    assert _apply_call(v, coeffs=0x8000) == 2                     # no matrix-free form
+    e = fe.problem("elasticity", "fp64", "uniform", 0, [1.0, 0.3, 0, 0, 0], "packed")
+    assert _apply_call(e, y=0x6004) == 2                          # misaligned y

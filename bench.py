@@ -548,6 +548,18 @@ def run_apply(a, torch, fe, oracle, base: str, dev) -> dict:
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     ms = np.array([e0.elapsed_time(e1) for e0, e1 in ev])
+    # the same application as one launch with atomic adds (order-dependent
+    # last bits), timed the same way
+    ev_at = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+             for _ in range(a.steps)]
+    for _ in range(a.warmup):
+        fe.apply_indexed(p, wl.elem, nodes, conn, coeffs, rule, x, y, None)
+    for e0, e1 in ev_at:
+        e0.record(stream)
+        fe.apply_indexed(p, wl.elem, nodes, conn, coeffs, rule, x, y, None)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ms_at = np.array([e0.elapsed_time(e1) for e0, e1 in ev_at])
     # one clean application for the parity check
     y.zero_()
     step()
@@ -581,6 +593,7 @@ def run_apply(a, torch, fe, oracle, base: str, dev) -> dict:
     bpe = 4 * nv + tsz * ncoef + (24 + 3 * tsz * nc) * n_nodes / n
     return {"wl": wl, "n_elem": n, "n_nodes": n_nodes, "colours": int(len(ptr) - 1),
             "ms_avg": float(ms.mean()), "ms_min": float(ms.min()), "wall_s": wall,
+            "atomic_ms_avg": float(ms_at.mean()), "atomic_elements_per_s": n / (float(ms_at.mean()) * 1e-3),
             "elements_per_s": n / avg, "bytes_per_element": bpe,
             "achieved_GBps": bpe * n / avg / 1e9,
             "parity": {"sampled_nodes": int(len(snodes)), "max_rel_err_y": err, "tol": tol,
@@ -655,6 +668,7 @@ def main() -> int:
                              "unit": "GB/s", "frac": r["achieved_GBps"] / HBM_PEAK_GBPS,
                              "traffic": None},
                 "cpu_baseline": None, "kernel_ms_avg": r["ms_avg"], "kernel_ms_min": r["ms_min"],
+                "atomic": {"ms_avg": r["atomic_ms_avg"], "elements_per_s": r["atomic_elements_per_s"]},
                 "parity": r["parity"]}
         print(json.dumps(line), flush=True)
         return 0 if r["parity"]["ok"] else 3

@@ -165,6 +165,11 @@ typedef struct fe_variant {
     int32_t loop_order;        /* order of the point and shape-function loops
                                   (Sec. 3.3, Algorithms 2, 4, 6) for prism
                                   scalar kernels: 1 QSS, 2 SQS, 3 SSQ */
+    int32_t lanes;             /* lanes per element (prism scalar QSS): 1, 2, 3
+                                  or 6; the element's points are split between
+                                  its lanes, each forms the Jacobian terms of its
+                                  own points, and the partial K and F are summed
+                                  across the lanes (0 = 1) */
 } fe_variant;
 
 /* ---------------------------------------------------------------------

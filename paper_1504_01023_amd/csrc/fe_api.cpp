@@ -33,7 +33,8 @@ static bool same_key(const KernelKey &a, const KernelKey &b)
 {
     return a.elem == b.elem && a.kind == b.kind && a.prec == b.prec && a.terms == b.terms &&
            a.mode == b.mode && a.packed == b.packed && a.vec == b.vec && a.nt == b.nt &&
-           a.ref == b.ref && a.nq == b.nq && a.split == b.split && a.order == b.order;
+           a.ref == b.ref && a.nq == b.nq && a.split == b.split && a.order == b.order &&
+           a.lanes == b.lanes;
 }
 
 const KernelEntry *find_kernel(const KernelKey &k)
@@ -305,6 +306,7 @@ int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coor
     const int ref = (v.ref_in_lds == 1) ? REF_LDS : REF_KARG;
     const int split = (v.row_split == 2 || v.row_split == 3) ? v.row_split : 1;
     const int order = (v.loop_order == 2 || v.loop_order == 3) ? v.loop_order : 1;
+    const int lanes = (v.lanes == 2 || v.lanes == 3 || v.lanes == 6) ? v.lanes : 1;
 
     // vector width needs aligned rows
     auto vec_ok = [&](int V) {
@@ -329,6 +331,7 @@ int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coor
     k.ref = ref;
     k.split = split;
     k.order = order;
+    k.lanes = lanes;
     k.nq = rule->n_q;
     auto usable = [&](const KernelEntry *x) {
         return x && (form == 0 || (form == 1 && x->idx != nullptr) || (form == 2 && x->apply != nullptr));
@@ -345,6 +348,7 @@ int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coor
         k.ref = REF_KARG;
         k.split = 1;
         k.order = 1;
+        k.lanes = 1;
         k.nq = 0;
         e = find_kernel(k);
     }
@@ -353,9 +357,9 @@ int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coor
     if (!e)
         return fail(FE_ERR_UNSUPPORTED,
                     "no compiled kernel for elem=%d kind=%d prec=%d terms=%d mode=%d packed=%d "
-                    "vec=%d nt=%d ref=%d nq=%d split=%d order=%d",
+                    "vec=%d nt=%d ref=%d nq=%d split=%d order=%d lanes=%d",
                     k.elem, k.kind, k.prec, k.terms, k.mode, k.packed, k.vec, k.nt, k.ref, k.nq,
-                    k.split, k.order);
+                    k.split, k.order, k.lanes);
 
     KArgs &a = pl.args;
     std::memset(&a, 0, sizeof(a));
@@ -382,7 +386,10 @@ int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coor
     fill_reference(elem, *rule, a);
     pl.entry = e;
     pl.block = (unsigned)wg;
-    const int64_t groups = (n_elem + k.vec - 1) / k.vec;
+    // threads: one per group of vec elements, or whole wavefronts of
+    // 64 / lanes elements for the lane-split kernels
+    const int64_t groups = k.lanes > 1 ? (n_elem + 64 / k.lanes - 1) / (64 / k.lanes) * 64
+                                       : (n_elem + k.vec - 1) / k.vec;
     int64_t grid = (groups + wg - 1) / wg;
     if (v.blocks > 0 && v.blocks < grid)
         grid = v.blocks;
@@ -390,7 +397,8 @@ int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coor
         grid = 0x7fffffff;
     pl.grid = (unsigned)(grid > 0 ? grid : 1);
     pl.key = k;
-    pl.variant = fe_variant{wg, k.vec, ref == REF_LDS ? 1 : 2, nt ? 1 : 2, v.blocks, k.split, k.order};
+    pl.variant = fe_variant{wg, k.vec, ref == REF_LDS ? 1 : 2, nt ? 1 : 2, v.blocks, k.split, k.order,
+                            k.lanes};
     return FE_OK;
 }
 

@@ -1166,6 +1166,30 @@ struct PrismScalar {
     {
         constexpr int NK = PACKED ? 21 : 36;
         T K[NK], F[6];
+        accumulate<NT>(a, st, ref, e, X0, X, 0, 1, K, F, bl);
+#pragma unroll
+        for (int r = 0; r < 6; ++r)
+#pragma unroll
+            for (int s = (PACKED ? r : 0); s < 6; ++s) {
+                const T v[1] = {K[PACKED ? pidx(6, r, s) : 6 * r + s]};
+                bl.template put_k<1, NT>(st, 6, PACKED, r, s, e, v);
+            }
+        if (bl.with_f()) {
+#pragma unroll
+            for (int r = 0; r < 6; ++r) {
+                const T v[1] = {F[r]};
+                bl.template put_f<1, NT>(st, r, e, v);
+            }
+        }
+    }
+
+    // The points q0, q0 + qstep, ... of one element, summed into K and F.
+    template <bool NT, class R, class B2, int NK>
+    __device__ __forceinline__ static void accumulate(const KArgs &a, const Streams &st, const R &ref,
+                                                      int64_t e, const double (&X0)[3],
+                                                      const double (&X)[18], int q0, int qstep,
+                                                      T (&K)[NK], T (&F)[6], const B2 &bl)
+    {
 #pragma unroll
         for (int k = 0; k < NK; ++k)
             K[k] = T(0);
@@ -1177,7 +1201,7 @@ struct PrismScalar {
             load_coefs<NT>(a, st, ref, 0, e, X0, X, c, bl);
         const int nq = NQ > 0 ? NQ : a.n_q;
 #pragma unroll(NQ > 0 ? NQ : 1)
-        for (int q = 0; q < nq; ++q) {
+        for (int q = q0; q < nq; q += qstep) {
             if constexpr (PER_QP)
                 load_coefs<NT>(a, st, ref, q, e, X0, X, c, bl);
             T g[6][3], vol;
@@ -1229,19 +1253,50 @@ struct PrismScalar {
                     F[r] += p * c.d0;
             }
         }
+    }
+
+    // G lanes per element (the wavefront-level mapping of the point loop):
+    // lane j of the element's group forms the Jacobian terms and the K, F
+    // contributions of points j, j + G, ...; the partial sums are then added
+    // across the group in lane order (shuffles through the cross-lane
+    // network), and lane j stores the entries with index = j mod G.
+    // `lead` is the group's first lane in the wavefront; `valid` is false for
+    // lanes past the end of the batch, which still join the shuffles.
+    template <int G, bool NT, int REF>
+    __device__ __forceinline__ static void run_lanes(const KArgs &a, const Streams &st,
+                                                     const Ref<REF> &ref, int64_t e, int j, int lead,
+                                                     bool valid)
+    {
+        double Xg[1][18];
+        st.template load_coords<6, 1, NT>(e, Xg);
+        double X[18];
 #pragma unroll
-        for (int r = 0; r < 6; ++r)
+        for (int s = 0; s < 18; ++s)
+            X[s] = Xg[0][s];
+        const double X0[3] = {X[0], X[1], X[2]};
+        to_edge_vectors<6>(X);
+        constexpr int NK = PACKED ? 21 : 36;
+        T K[NK], F[6];
+        accumulate<NT>(a, st, ref, e, X0, X, j, G, K, F, ScalarBlock());
+        T *outK = static_cast<T *>(st.out_K);
+        T *outF = static_cast<T *>(st.out_F);
 #pragma unroll
-            for (int s = (PACKED ? r : 0); s < 6; ++s) {
-                const T v[1] = {K[PACKED ? pidx(6, r, s) : 6 * r + s]};
-                bl.template put_k<1, NT>(st, 6, PACKED, r, s, e, v);
-            }
-        if (bl.with_f()) {
+        for (int k = 0; k < NK; ++k) {
+            T sum = __shfl(K[k], lead);
 #pragma unroll
-            for (int r = 0; r < 6; ++r) {
-                const T v[1] = {F[r]};
-                bl.template put_f<1, NT>(st, r, e, v);
-            }
+            for (int i = 1; i < G; ++i)
+                sum += __shfl(K[k], lead + i);
+            if (valid && k % G == j)
+                st1<NT>(outK + k * st.ld_out + e, sum);
+        }
+#pragma unroll
+        for (int r = 0; r < 6; ++r) {
+            T sum = __shfl(F[r], lead);
+#pragma unroll
+            for (int i = 1; i < G; ++i)
+                sum += __shfl(F[r], lead + i);
+            if (valid && r % G == j)
+                st1<NT>(outF + r * st.ld_out + e, sum);
         }
     }
 };
@@ -1863,6 +1918,47 @@ void launch_fe_apply(const KArgs &a, const IdxArgs &gi, const ApplyArgs &ap, int
     else
         hipLaunchKernelGGL((fe_apply_kernel<P, NV, NC, T, NT, REF, false, false>), dim3(grid),
                            dim3(block), 0, stream, a, gi, ap);
+}
+
+// G lanes per element: each wavefront takes 64 / G consecutive elements
+// (lanes past G * (64 / G) idle); the loop bound is uniform over the
+// wavefront, so every lane reaches every cross-lane exchange.
+template <class P, int G, bool NT, int REF>
+__global__ __launch_bounds__(256) void fe_kernel_lanes(KArgs a)
+{
+    __shared__ RefLds lds_ref[1];
+    if constexpr (REF == REF_LDS) {
+        const int n_w = a.n_q, n_phi = a.n_q * 6, n_dphi = a.n_q * 18;
+        for (int i = threadIdx.x; i < n_w; i += blockDim.x)
+            lds_ref[0].w[i] = a.w[i];
+        for (int i = threadIdx.x; i < n_phi; i += blockDim.x)
+            (&lds_ref[0].phi[0][0])[i] = (&a.phi[0][0])[i];
+        for (int i = threadIdx.x; i < n_dphi; i += blockDim.x)
+            (&lds_ref[0].dphi[0][0][0])[i] = (&a.dphi[0][0][0])[i];
+        __syncthreads();
+    }
+    const Ref<REF> ref{a, &lds_ref[0]};
+    const Streams st{a.coords, a.coeffs, a.out_K, a.out_F, a.ld_in, a.ld_out};
+    constexpr int PER_WAVE = 64 / G;
+    const int lane = threadIdx.x & 63;
+    const int slot = lane / G, j = lane % G;
+    const int lead = (slot < PER_WAVE ? slot : PER_WAVE - 1) * G;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / 64);
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    for (int64_t base = wave * PER_WAVE; base < a.n_elem; base += waves * PER_WAVE) {
+        const int64_t e = base + (slot < PER_WAVE ? slot : PER_WAVE - 1);
+        const bool valid = slot < PER_WAVE && e < a.n_elem;
+        // lanes without an element of their own work on the batch's last
+        // element (in bounds) and store nothing
+        P::template run_lanes<G, NT, REF>(a, st, ref, valid ? e : a.n_elem - 1,
+                                          slot < PER_WAVE ? j : 0, lead, valid);
+    }
+}
+
+template <class P, int G, bool NT, int REF>
+void launch_fe_kernel_lanes(const KArgs &a, unsigned grid, unsigned block, hipStream_t stream)
+{
+    hipLaunchKernelGGL((fe_kernel_lanes<P, G, NT, REF>), dim3(grid), dim3(block), 0, stream, a);
 }
 
 template <class P, int V, bool NT, int REF>

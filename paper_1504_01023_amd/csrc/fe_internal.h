@@ -89,6 +89,7 @@ struct KernelKey {
     int nq;        // compiled point count, 0 = runtime loop
     int split;     // passes over the points (row split of K), 1, 2 or 3
     int order;     // loop order (1 QSS, 2 SQS, 3 SSQ)
+    int lanes;     // lanes per element (1, or 2, 3, 6 for the prism point split)
 };
 
 typedef void (*LaunchFn)(const KArgs &, unsigned grid, unsigned block, hipStream_t);

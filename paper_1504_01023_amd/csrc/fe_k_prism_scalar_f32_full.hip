@@ -27,6 +27,13 @@ int register_all()
     reg_prism_scalar_order<T, TS, MODE, 0, ORDER_SQS, 0>(); reg_prism_scalar_order<T, TS, MODE, 0, ORDER_SSQ, 0>();
     ORDERS(M_QP_MIXED) ORDERS(M_ELEM) ORDERS(M_QP)
 #undef ORDERS
+    // the points of an element split over 2, 3 or 6 lanes
+#define LANES(MODE) \
+    reg_prism_scalar_lanes<T, TS, MODE, 0, 2, 1, REF_KARG>(); \
+    reg_prism_scalar_lanes<T, TS, MODE, 0, 3, 1, REF_KARG>(); \
+    reg_prism_scalar_lanes<T, TS, MODE, 0, 6, 1, REF_KARG>();
+    LANES(M_QP) LANES(M_ELEM)
+#undef LANES
     return 0;
 }
 const int registered = register_all();

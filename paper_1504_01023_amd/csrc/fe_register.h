@@ -14,7 +14,7 @@ template <class P, int V, int NT, int REF, int B = 0>
 inline void reg(int elem, int kind, int prec, int terms, int mode, int packed, int nq, int split = 1,
                 int order = 1, ApplyLaunchFn ap = nullptr)
 {
-    KernelKey k{elem, kind, prec, terms, mode, packed, V, NT, REF, nq, split, order};
+    KernelKey k{elem, kind, prec, terms, mode, packed, V, NT, REF, nq, split, order, 1};
     BatchLaunchFn bl = nullptr;
     IdxLaunchFn il = nullptr;
     if constexpr (B != 0) {
@@ -63,6 +63,18 @@ inline void reg_prism_scalar()
     typedef PrismScalar<T, TERMS, MODE, PK, NQ> P;
     reg<P, 1, NT, REF, B>(FE_PRISM6, FE_SCALAR_CDR, prec_of<T>(), TERMS, MODE, PK, NQ, 1, 1,
                           apply_form<P, 6, 1, T, 1, NT, REF, B>());
+}
+
+// Prism scalar QSS kernels with the points of an element split between G
+// lanes (plain form only).
+template <typename T, int TERMS, int MODE, int PK, int G, int NT, int REF>
+inline void reg_prism_scalar_lanes()
+{
+    typedef PrismScalar<T, TERMS, MODE, PK, 0> P;
+    KernelKey k{FE_PRISM6, FE_SCALAR_CDR, prec_of<T>(), TERMS, MODE, PK, 1, NT, REF, 0, 1, 1, G};
+    register_kernel(KernelEntry{k, &launch_fe_kernel_lanes<P, G, NT != 0, REF>,
+                                reinterpret_cast<const void *>(&fe_kernel_lanes<P, G, NT != 0, REF>),
+                                nullptr, nullptr, nullptr});
 }
 
 // Prism scalar kernels in the SQS / SSQ loop orders (one element per lane).

@@ -105,15 +105,15 @@ int fe_tuning_save(const char *path)
     FILE *f = std::fopen(path, "w");
     if (!f)
         return fail(FE_ERR_INVALID_ARG, "cannot open %s for writing", path);
-    std::fprintf(f, "# libfe tuning table v3: elem kind prec terms mode packed n_q | wg vec ref nt blocks split order\n");
+    std::fprintf(f, "# libfe tuning table v4: elem kind prec terms mode packed n_q | wg vec ref nt blocks split order lanes\n");
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (const auto &kv : table()) {
         const FamilyKey &k = kv.first;
         const fe_variant &v = kv.second;
-        std::fprintf(f, "%d %d %d %d %d %d %d | %d %d %d %d %d %d %d\n", std::get<0>(k),
+        std::fprintf(f, "%d %d %d %d %d %d %d | %d %d %d %d %d %d %d %d\n", std::get<0>(k),
                      std::get<1>(k), std::get<2>(k), std::get<3>(k), std::get<4>(k), std::get<5>(k),
                      std::get<6>(k), v.wg_size, v.elems_per_thread, v.ref_in_lds, v.nontemporal,
-                     v.blocks, v.row_split, v.loop_order);
+                     v.blocks, v.row_split, v.loop_order, v.lanes ? v.lanes : 1);
     }
     std::fclose(f);
     return FE_OK;
@@ -133,16 +133,18 @@ int fe_tuning_load(const char *path)
             continue;
         int a[7];
         fe_variant v{};
-        const int got = std::sscanf(line, "%d %d %d %d %d %d %d | %d %d %d %d %d %d %d", &a[0],
+        const int got = std::sscanf(line, "%d %d %d %d %d %d %d | %d %d %d %d %d %d %d %d", &a[0],
                                     &a[1], &a[2], &a[3], &a[4], &a[5], &a[6], &v.wg_size,
                                     &v.elems_per_thread, &v.ref_in_lds, &v.nontemporal, &v.blocks,
-                                    &v.row_split, &v.loop_order);
-        // tables written before the row-split / loop-order fields
+                                    &v.row_split, &v.loop_order, &v.lanes);
+        // tables written before the row-split / loop-order / lanes fields
         if (got == 12)
             v.row_split = 1;
-        if (got == 12 || got == 13)
+        if (got >= 12 && got <= 13)
             v.loop_order = 1;
-        else if (got != 14) {
+        if (got >= 12 && got <= 14)
+            v.lanes = 1;
+        else if (got != 15) {
             std::fclose(f);
             return fail(FE_ERR_INVALID_ARG, "malformed tuning line: %s", line);
         }
@@ -173,13 +175,13 @@ int fe_autotune(const fe_problem *problem, fe_elem_type elem_type, int64_t n_ele
     // Candidate variants: every compiled (vec, nt, ref, split) of this family,
     // times workgroup sizes and grid shapes (one group per lane, or a
     // persistent grid of 512..8192 workgroups).
-    std::set<std::tuple<int, int, int, int, int>> shapes;
+    std::set<std::tuple<int, int, int, int, int, int>> shapes;
     for (int i = 0; i < kernel_count(); ++i) {
         const KernelKey &k = kernel_at(i)->key;
         if (k.elem == base.key.elem && k.kind == base.key.kind && k.prec == base.key.prec &&
             k.terms == base.key.terms && k.mode == base.key.mode && k.packed == base.key.packed &&
             (k.nq == quad_rule->n_q || k.nq == 0))
-            shapes.insert(std::make_tuple(k.vec, k.nt, k.ref, k.split, k.order));
+            shapes.insert(std::make_tuple(k.vec, k.nt, k.ref, k.split, k.order, k.lanes));
     }
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
@@ -192,7 +194,8 @@ int fe_autotune(const fe_problem *problem, fe_elem_type elem_type, int64_t n_ele
         for (int wg : wgs) {
             for (int gb : grids) {
                 fe_variant v{wg, std::get<0>(sh), std::get<2>(sh) == REF_LDS ? 1 : 2,
-                             std::get<1>(sh) ? 1 : 2, gb, std::get<3>(sh), std::get<4>(sh)};
+                             std::get<1>(sh) ? 1 : 2, gb, std::get<3>(sh), std::get<4>(sh),
+                             std::get<5>(sh)};
                 Plan pl;
                 if (plan(problem, elem_type, n_elem, coords, coeffs, n_elem, quad_rule, out_K,
                          out_F, n_elem, &v, pl) != FE_OK)

@@ -52,11 +52,11 @@ class Variant(ctypes.Structure):
     _fields_ = [("wg_size", ctypes.c_int32), ("elems_per_thread", ctypes.c_int32),
                 ("ref_in_lds", ctypes.c_int32), ("nontemporal", ctypes.c_int32),
                 ("blocks", ctypes.c_int32), ("row_split", ctypes.c_int32),
-                ("loop_order", ctypes.c_int32)]
+                ("loop_order", ctypes.c_int32), ("lanes", ctypes.c_int32)]
 
     def as_tuple(self):
         return (self.wg_size, self.elems_per_thread, self.ref_in_lds, self.nontemporal, self.blocks,
-                self.row_split, self.loop_order)
+                self.row_split, self.loop_order, self.lanes)
 
 
 class FeError(RuntimeError):
@@ -178,9 +178,9 @@ def k_index(p: Problem, elem, row: int, col: int) -> int:
 
 
 def variant(wg_size=0, elems_per_thread=0, ref_in_lds=0, nontemporal=0, blocks=0,
-            row_split=0, loop_order=0) -> Variant:
+            row_split=0, loop_order=0, lanes=0) -> Variant:
     return Variant(wg_size, elems_per_thread, ref_in_lds, nontemporal, blocks, row_split,
-                   loop_order)
+                   loop_order, lanes)
 
 
 # ------------------------------------------------------------------- execution

@@ -189,14 +189,22 @@ def test_tuning_table_roundtrip(tmp_path):
     fe.tuning_clear()
     p = fe.problem("scalar", "fp64", "uniform", 0, None, "packed")
     assert fe.tuning_get(p, "tet4", 1) is None
-    fe.tuning_set(p, "tet4", 1, fe.variant(128, 2, 2, 1, 0, 1, 1))
-    assert fe.tuning_get(p, "tet4", 1) == (128, 2, 2, 1, 0, 1, 1)
+    fe.tuning_set(p, "tet4", 1, fe.variant(128, 2, 2, 1, 0, 1, 1, 3))
+    assert fe.tuning_get(p, "tet4", 1) == (128, 2, 2, 1, 0, 1, 1, 3)
     path = str(tmp_path / "tune.txt")
     fe.tuning_save(path)
     fe.tuning_clear()
     assert fe.tuning_get(p, "tet4", 1) is None
     fe.tuning_load(path)
-    assert fe.tuning_get(p, "tet4", 1) == (128, 2, 2, 1, 0, 1, 1)
+    assert fe.tuning_get(p, "tet4", 1) == (128, 2, 2, 1, 0, 1, 1, 3)
+    fe.tuning_clear()
+    # tables written before the lanes field (and before split / order) still load
+    old = tmp_path / "old.txt"
+    old.write_text("0 0 0 33 0 1 1 | 256 2 2 2 0 1 1\n0 0 0 63 1 0 4 | 64 1 1 1 0\n")
+    fe.tuning_load(str(old))
+    assert fe.tuning_get(p, "tet4", 1) == (256, 2, 2, 2, 0, 1, 1, 1)
+    q = fe.problem("scalar", "fp64", "element", (1 << 20) - 1, None, "full")
+    assert fe.tuning_get(q, "tet4", 4) == (64, 1, 1, 1, 0, 1, 1, 1)
     fe.tuning_clear()
 
 

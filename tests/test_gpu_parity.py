@@ -34,9 +34,12 @@ VARIANTS = [
     for wg in (64, 128, 256) for v in (1, 2, 4) for nt in (1, 2) for ref in (1, 2) for b in (0, 7)
     for sp in (1, 2, 3)
 ]
-# the SQS / SSQ loop orders sum in a different order: parity, not bitwise
+# the SQS / SSQ loop orders and the lane-split point loop sum in a different
+# order: parity, not bitwise
 ORDER_VARIANTS = [dict(wg_size=wg, nontemporal=nt, loop_order=o)
                   for wg in (64, 256) for nt in (1, 2) for o in (2, 3)]
+ORDER_VARIANTS += [dict(wg_size=wg, lanes=g, blocks=b) for wg in (64, 256) for g in (2, 3, 6)
+                   for b in (0, 3)]
 
 
 @pytest.mark.parametrize("name", ["tet_poisson", "tet_cdr", "prism_cdr_qp", "tet_elasticity",
@@ -63,6 +66,23 @@ def test_every_compiled_variant(name):
         assert ek.max() <= 1e-12 and ef.max() <= 1e-12, (kw, ek.max(), ef.max())
         ran += 1
     assert ran >= 4
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 11, 21, 22, 63, 64, 65, 255, 257, 1001])
+@pytest.mark.parametrize("lanes", [0, 2, 3, 6])
+def test_lane_split_ragged_sizes(lanes, n):
+    """Lane-split prism kernels on sizes that end inside a wavefront's group
+    of 64 / G elements, with one and several wavefronts per workgroup."""
+    wl = P.small("prism_cdr")
+    idx = np.arange(n)
+    sub = inputs.Workload(wl.name, wl.elem, wl.kind, wl.n_q, wl.coef_mode, wl.mask, wl.uniform,
+                          wl.k_format,
+                          inputs.Mesh(wl.elem, np.ascontiguousarray(wl.mesh.coords[:, idx]),
+                                      wl.mesh.nodes, wl.mesh.conn[idx], wl.mesh.boundary),
+                          np.ascontiguousarray(wl.coeffs[:, idx]))
+    for wg, blocks in ((64, 0), (256, 0), (128, 1)):
+        K, F = P.gpu_raw(sub, "fp64", variant=fe.variant(wg_size=wg, lanes=lanes, blocks=blocks))
+        P.assert_parity(sub, "fp64", K, F)
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 5, 63, 64, 65, 255, 257, 1001])

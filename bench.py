@@ -617,6 +617,9 @@ def main() -> int:
     ap.add_argument("--save-tuning", default=None, help="write the tuning table here after the run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--parity-sample", type=int, default=20000)
+    ap.add_argument("--ld-align", type=int, default=256,
+                    help="pad the output leading dimension to a multiple of this many elements "
+                         "(0: ld = n_elem)")
     ap.add_argument("--served-requests", type=int, default=1000)
     ap.add_argument("--served-warmup", type=int, default=50)
     ap.add_argument("--served-slots", type=int, default=64)
@@ -699,8 +702,13 @@ def main() -> int:
     p, rule = dw.problem, dw.rule
     nk, nf = fe.k_entries(p, wl.elem), fe.f_entries(p, wl.elem)
     dt = torch.float64 if a.precision == "fp64" else torch.float32
-    K = torch.empty((nk, wl.n_elem), dtype=dt, device=dev)
-    F = torch.empty((nf, wl.n_elem), dtype=dt, device=dev)
+    # output rows padded to whole 2 KB (FP64) / 1 KB (FP32) lines of elements:
+    # every wavefront then writes whole cache lines of every row, which HBM
+    # takes at the copy rate; rows that start mid-line leave partial lines
+    # at both ends of every wavefront's segment and cut the write rate
+    ld_out = (wl.n_elem + a.ld_align - 1) // a.ld_align * a.ld_align if a.ld_align > 0 else wl.n_elem
+    K = torch.empty((nk, ld_out), dtype=dt, device=dev)
+    F = torch.empty((nf, ld_out), dtype=dt, device=dev)
     bpe = fe.bytes_per_element(p, wl.elem, rule.n_q)
     stream = torch.cuda.current_stream()
     nv = 4 if wl.elem == "tet4" else 6
@@ -713,14 +721,16 @@ def main() -> int:
 
     def step():
         if indexed:
-            fe.integrate_indexed(p, wl.elem, nodes, conn, dw.coeffs, rule, out_K=K, out_F=F)
+            fe.integrate_indexed(p, wl.elem, nodes, conn, dw.coeffs, rule, out_K=K, out_F=F,
+                                 n_elem=wl.n_elem)
         else:
-            fe.integrate(p, wl.elem, dw.coords, dw.coeffs, rule, out_K=K, out_F=F)
+            fe.integrate(p, wl.elem, dw.coords, dw.coeffs, rule, out_K=K, out_F=F, n_elem=wl.n_elem)
 
     if a.tuning_file and os.path.exists(a.tuning_file):
         fe.tuning_load(a.tuning_file)
     if a.tune or fe.tuning_get(p, wl.elem, rule.n_q) is None:
-        tuned, tms = fe.autotune(p, wl.elem, dw.coords, dw.coeffs, rule, K, F, reps=5)
+        tuned, tms = fe.autotune(p, wl.elem, dw.coords, dw.coeffs, rule, K, F, reps=5,
+                                 n_elem=wl.n_elem)
         log(f"[bench] autotuned variant (wg, vec, ref, nt, blocks) = {tuned}: {tms:.4f} ms")
     if a.save_tuning:
         fe.tuning_save(a.save_tuning)
@@ -808,7 +818,7 @@ def main() -> int:
                    "description": WORKLOADS[base][1] + (" (indexed geometry: node array + int32 "
                                                         "connectivity)" if indexed else ""),
                    "n_elem": wl.n_elem, "precision": a.precision, "n_q": rule.n_q,
-                   "k_format": wl.k_format, "bytes_per_element": bpe,
+                   "k_format": wl.k_format, "bytes_per_element": bpe, "ld_out": ld_out,
                    "variant_wg_vec_ref_nt_blocks": variant_used, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,

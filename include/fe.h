@@ -178,7 +178,9 @@ typedef struct fe_variant {
  * ------------------------------------------------------------------- */
 
 /* Integrate n_elem elements with leading dimension n_elem for inputs and
- * outputs. coeffs may be NULL when no slot is read from memory.
+ * outputs. (Writes reach HBM fastest when every output row starts on a
+ * cache line: fe_integrate_ex with ld_out a multiple of 64 elements and
+ * 256-byte aligned outputs.) coeffs may be NULL when no slot is read from memory.
  * n_elem == 0 returns FE_OK without enqueuing anything. */
 FE_API int fe_integrate(const fe_problem *problem, fe_elem_type elem_type, int64_t n_elem,
                         const double *coords, const void *coeffs, const fe_quad_rule *quad_rule,
@@ -285,13 +287,13 @@ FE_API int fe_version(void);
  * ------------------------------------------------------------------- */
 
 /* Time every valid variant for this problem on the caller's device buffers
- * (they are overwritten with valid results), keep the fastest in the
- * in-process tuning table and return it in *best (and its mean time in ms).
- * Synchronises `stream`. */
+ * (layouts as for fe_integrate_ex; the outputs are overwritten with valid
+ * results), keep the fastest in the in-process tuning table and return it in
+ * *best (and its mean time in ms). Synchronises `stream`. */
 FE_API int fe_autotune(const fe_problem *problem, fe_elem_type elem_type, int64_t n_elem,
-                       const double *coords, const void *coeffs, const fe_quad_rule *quad_rule,
-                       void *out_K, void *out_F, int reps, fe_variant *best, double *best_ms,
-                       hipStream_t stream);
+                       const double *coords, const void *coeffs, int64_t ld_in,
+                       const fe_quad_rule *quad_rule, void *out_K, void *out_F, int64_t ld_out,
+                       int reps, fe_variant *best, double *best_ms, hipStream_t stream);
 /* Query / set the tuning table entry used by fe_integrate for a problem
  * shape. fe_tuning_get returns FE_ERR_INVALID_ARG when no entry exists. */
 FE_API int fe_tuning_get(const fe_problem *problem, fe_elem_type elem_type, int n_q,

@@ -254,7 +254,10 @@ void complete(fe_server *s, Req &r, int status, double t)
 void layout(const fe_server *s, Req &r)
 {
     const KindInfo &ki = s->kinfo[r.kind];
-    const int64_t ld = (r.n + 3) / 4 * 4;
+    // rows padded to 64 elements: with the arena's 256-byte alignment every
+    // row starts on a cache line, so the kernels' wavefront segments cover
+    // whole lines (partial-line writes cut the HBM write rate markedly)
+    const int64_t ld = (r.n + 63) / 64 * 64;
     r.ld_out = ld;
     if (!r.dev_inputs) {
         r.ld_in = ld;

@@ -158,16 +158,16 @@ int fe_tuning_load(const char *path)
 }
 
 int fe_autotune(const fe_problem *problem, fe_elem_type elem_type, int64_t n_elem,
-                const double *coords, const void *coeffs, const fe_quad_rule *quad_rule,
-                void *out_K, void *out_F, int reps, fe_variant *best, double *best_ms,
-                hipStream_t stream)
+                const double *coords, const void *coeffs, int64_t ld_in,
+                const fe_quad_rule *quad_rule, void *out_K, void *out_F, int64_t ld_out, int reps,
+                fe_variant *best, double *best_ms, hipStream_t stream)
 {
     if (reps < 1)
         reps = 1;
     // Validate the call once with the default variant.
     Plan base;
-    int st = plan(problem, elem_type, n_elem, coords, coeffs, n_elem, quad_rule, out_K, out_F,
-                  n_elem, nullptr, base);
+    int st = plan(problem, elem_type, n_elem, coords, coeffs, ld_in, quad_rule, out_K, out_F,
+                  ld_out, nullptr, base);
     if (st)
         return st;
     if (n_elem == 0)
@@ -197,8 +197,8 @@ int fe_autotune(const fe_problem *problem, fe_elem_type elem_type, int64_t n_ele
                              std::get<1>(sh) ? 1 : 2, gb, std::get<3>(sh), std::get<4>(sh),
                              std::get<5>(sh)};
                 Plan pl;
-                if (plan(problem, elem_type, n_elem, coords, coeffs, n_elem, quad_rule, out_K,
-                         out_F, n_elem, &v, pl) != FE_OK)
+                if (plan(problem, elem_type, n_elem, coords, coeffs, ld_in, quad_rule, out_K,
+                         out_F, ld_out, &v, pl) != FE_OK)
                     continue;
                 if (gb > 0 && (int64_t)gb >= (int64_t)pl.grid && gb != 0)
                     continue;  // same as the one-group-per-thread grid

@@ -92,7 +92,7 @@ def lib():
         L.fe_status_string.argtypes = [i32]
         L.fe_status_string.restype = ctypes.c_char_p
         L.fe_last_error.restype = ctypes.c_char_p
-        L.fe_autotune.argtypes = [P, i32, i64, vp, vp, R, vp, vp, i32, V,
+        L.fe_autotune.argtypes = [P, i32, i64, vp, vp, i64, R, vp, vp, i64, i32, V,
                                   ctypes.POINTER(ctypes.c_double), vp]
         L.fe_tuning_get.argtypes = [P, i32, i32, V]
         L.fe_tuning_set.argtypes = [P, i32, i32, V]
@@ -348,17 +348,20 @@ def apply_indexed(p: Problem, elem, nodes, conn, coeffs, rule: Rule, x, y=None, 
 
 
 def autotune(p: Problem, elem, coords, coeffs, rule: Rule, out_K, out_F, reps: int = 5,
-             stream=None):
-    """Exhaustive search over the compiled variants (synchronises the stream).
-    Returns (variant tuple, mean ms)."""
+             stream=None, n_elem: int | None = None):
+    """Exhaustive search over the compiled variants (synchronises the stream)
+    on n_elem elements (default: all columns of coords), with the leading
+    dimensions of the given tensors. Returns (variant tuple, mean ms)."""
     e = ELEM.get(elem, elem)
     best = Variant()
     ms = ctypes.c_double(0.0)
+    ld_in = coords.shape[1]
+    n = ld_in if n_elem is None else int(n_elem)
     cptr = ctypes.c_void_p(coeffs.data_ptr()) if coeffs is not None else None
-    _check(lib().fe_autotune(ctypes.byref(p), e, coords.shape[1], ctypes.c_void_p(coords.data_ptr()),
-                             cptr, ctypes.byref(rule.c), ctypes.c_void_p(out_K.data_ptr()),
-                             ctypes.c_void_p(out_F.data_ptr()), reps, ctypes.byref(best),
-                             ctypes.byref(ms), _stream_handle(stream)))
+    _check(lib().fe_autotune(ctypes.byref(p), e, n, ctypes.c_void_p(coords.data_ptr()), cptr, ld_in,
+                             ctypes.byref(rule.c), ctypes.c_void_p(out_K.data_ptr()),
+                             ctypes.c_void_p(out_F.data_ptr()), out_K.shape[1], reps,
+                             ctypes.byref(best), ctypes.byref(ms), _stream_handle(stream)))
     return best.as_tuple(), ms.value
 
 

@@ -20,7 +20,7 @@ def kinds():
 
 
 def bytes_of(kind, n):
-    ld = (n + 3) // 4 * 4
+    ld = (n + 63) // 64 * 64
     r = lambda b: (b + 255) // 256 * 256
     if kind == 0:  # tet CDR fp64: coords 12, coeffs 20, K 16, F 4
         return r(8 * 12 * ld) + r(8 * 20 * ld) + r(8 * 16 * ld) + r(8 * 4 * ld)
@@ -49,7 +49,7 @@ def test_all_complete_in_order_with_latency_breakdown():
             c = by_id[rid]
             assert c.t_submit <= c.t_admit <= c.t_ready <= c.t_done
             assert c.n_elem == 1000 + 500 * i
-            assert c.ld_out % 4 == 0 and c.ld_out >= c.n_elem
+            assert c.ld_out % 64 == 0 and c.ld_out >= c.n_elem
         # admission follows arrival order
         adm = [by_id[r].t_admit for r in ids]
         assert adm == sorted(adm)

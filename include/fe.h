@@ -158,7 +158,8 @@ typedef struct fe_variant {
     int32_t elems_per_thread;  /* 1, 2 or 4 contiguous elements (tetrahedra) */
     int32_t ref_in_lds;        /* 1: stage reference tables in LDS; 2: read
                                   them as wave-uniform kernel arguments */
-    int32_t nontemporal;       /* 1: streaming (non-temporal) loads/stores; 2: off */
+    int32_t nontemporal;       /* 1: streaming (non-temporal) loads and stores;
+                                  2: off; 3: streaming stores only */
     int32_t blocks;            /* grid size; 0 = one element group per thread */
     int32_t row_split;         /* passes over the points with the rows of K split
                                   between them (prism elasticity): 1, 2 or 3 */

@@ -302,7 +302,9 @@ int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coor
     if (wg != 64 && wg != 128 && wg != 256)
         return fail(FE_ERR_UNSUPPORTED, "workgroup size %d not supported (64, 128, 256)", wg);
     int vec = v.elems_per_thread ? v.elems_per_thread : (elem == FE_TET4 ? 2 : 1);
-    const int nt = (v.nontemporal == 2) ? 0 : 1;
+    // cache policy: variant 1 (or 0) streaming loads and stores, 2 default,
+    // 3 streaming stores only -> kernel NT 1, 0, 2
+    const int nt = v.nontemporal == 2 ? 0 : (v.nontemporal == 3 ? 2 : 1);
     const int ref = (v.ref_in_lds == 1) ? REF_LDS : REF_KARG;
     const int split = (v.row_split == 2 || v.row_split == 3) ? v.row_split : 1;
     const int order = (v.loop_order == 2 || v.loop_order == 3) ? v.loop_order : 1;
@@ -397,8 +399,8 @@ int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coor
         grid = 0x7fffffff;
     pl.grid = (unsigned)(grid > 0 ? grid : 1);
     pl.key = k;
-    pl.variant = fe_variant{wg, k.vec, ref == REF_LDS ? 1 : 2, nt ? 1 : 2, v.blocks, k.split, k.order,
-                            k.lanes};
+    pl.variant = fe_variant{wg, k.vec, ref == REF_LDS ? 1 : 2, nt == 0 ? 2 : (nt == 2 ? 3 : 1),
+                            v.blocks, k.split, k.order, k.lanes};
     return FE_OK;
 }
 

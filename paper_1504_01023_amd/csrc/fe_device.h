@@ -38,19 +38,21 @@ typedef float f2_t __attribute__((ext_vector_type(2)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------------------ memory
-template <bool NT, typename T>
+// Cache policy of the streams (NT): 0 default; 1 streaming (non-temporal)
+// loads and stores; 2 streaming stores only.
+template <int NT, typename T>
 __device__ __forceinline__ T ld1(const T *p)
 {
-    if constexpr (NT)
+    if constexpr (NT == 1)
         return __builtin_nontemporal_load(p);
     else
         return *p;
 }
 
-template <bool NT, typename T>
+template <int NT, typename T>
 __device__ __forceinline__ void st1(T *p, T v)
 {
-    if constexpr (NT)
+    if constexpr (NT != 0)
         __builtin_nontemporal_store(v, p);
     else
         *p = v;
@@ -58,7 +60,7 @@ __device__ __forceinline__ void st1(T *p, T v)
 
 // Load V consecutive values starting at p. Alignment of p to
 // min(16, V * sizeof(T)) bytes is guaranteed by the host dispatcher.
-template <int V, bool NT>
+template <int V, int NT>
 __device__ __forceinline__ void loadv(const double *p, double (&v)[V])
 {
     if constexpr (V == 1) {
@@ -73,7 +75,7 @@ __device__ __forceinline__ void loadv(const double *p, double (&v)[V])
     }
 }
 
-template <int V, bool NT>
+template <int V, int NT>
 __device__ __forceinline__ void loadv(const float *p, float (&v)[V])
 {
     if constexpr (V == 1) {
@@ -94,7 +96,7 @@ __device__ __forceinline__ void loadv(const float *p, float (&v)[V])
 typedef int int2_t __attribute__((ext_vector_type(2)));
 typedef int int4_t __attribute__((ext_vector_type(4)));
 
-template <int V, bool NT>
+template <int V, int NT>
 __device__ __forceinline__ void loadv(const int32_t *p, int32_t (&v)[V])
 {
     if constexpr (V == 1) {
@@ -112,7 +114,7 @@ __device__ __forceinline__ void loadv(const int32_t *p, int32_t (&v)[V])
     }
 }
 
-template <int V, bool NT>
+template <int V, int NT>
 __device__ __forceinline__ void storev(double *p, const double (&v)[V])
 {
     if constexpr (V == 1) {
@@ -128,7 +130,7 @@ __device__ __forceinline__ void storev(double *p, const double (&v)[V])
     }
 }
 
-template <int V, bool NT>
+template <int V, int NT>
 __device__ __forceinline__ void storev(float *p, const float (&v)[V])
 {
     if constexpr (V == 1) {
@@ -161,7 +163,7 @@ struct Streams {
     int64_t ld_out;
 
     // Vertex coordinates of V consecutive elements: X[i][3 v + d].
-    template <int NV, int V, bool NT>
+    template <int NV, int V, int NT>
     __device__ __forceinline__ void load_coords(int64_t e0, double (&X)[V][3 * NV]) const
     {
 #pragma unroll
@@ -185,7 +187,7 @@ struct StreamsIdx : Streams {
     int64_t ld_conn;
     uint32_t n_nodes;
 
-    template <int NV, int V, bool NT>
+    template <int NV, int V, int NT>
     __device__ __forceinline__ void load_coords(int64_t e0, double (&X)[V][3 * NV]) const
     {
         int32_t id[NV][V];
@@ -219,7 +221,7 @@ __host__ __device__ constexpr int popc_below(uint32_t m, int k)
 __host__ __device__ constexpr int pidx(int N, int r, int s) { return r * N - r * (r - 1) / 2 + (s - r); }
 
 // Value of coefficient slot k at point q for V consecutive elements.
-template <typename T, int MODE, uint32_t DENSE_SLOTS, int V, bool NT>
+template <typename T, int MODE, uint32_t DENSE_SLOTS, int V, int NT>
 __device__ __forceinline__ void coef(const KArgs &a, const Streams &st, int k, int q,
                                      int64_t e0, T (&out)[V])
 {
@@ -255,7 +257,7 @@ __device__ __forceinline__ void coef(const KArgs &a, const Streams &st, int k, i
 // wave-uniform run-time values, so the nine blocks share one copy of the code.
 struct ScalarBlock {
     __device__ __forceinline__ bool with_f() const { return true; }
-    template <typename T, int MODE, uint32_t SL, int V, bool NT>
+    template <typename T, int MODE, uint32_t SL, int V, int NT>
     __device__ __forceinline__ void coef(const KArgs &a, const Streams &st, int k, int q,
                                          int64_t e0, T (&out)[V]) const
     {
@@ -267,13 +269,13 @@ struct ScalarBlock {
     }
     __device__ __forceinline__ int f_index(int r) const { return r; }
     // Results: K entry (r, s) of an N x N matrix and F entry r, for V elements.
-    template <int V, bool NT, typename T>
+    template <int V, int NT, typename T>
     __device__ __forceinline__ void put_k(const Streams &st, int N, int packed, int r, int s,
                                           int64_t e0, const T (&val)[V]) const
     {
         storev<V, NT>(static_cast<T *>(st.out_K) + k_index(N, packed, r, s) * st.ld_out + e0, val);
     }
-    template <int V, bool NT, typename T>
+    template <int V, int NT, typename T>
     __device__ __forceinline__ void put_f(const Streams &st, int r, int64_t e0, const T (&val)[V]) const
     {
         storev<V, NT>(static_cast<T *>(st.out_F) + f_index(r) * st.ld_out + e0, val);
@@ -283,7 +285,7 @@ struct ScalarBlock {
 struct VecBlock {
     int A, B;
     __device__ __forceinline__ bool with_f() const { return B == 0; }
-    template <typename T, int MODE, uint32_t SL, int V, bool NT>
+    template <typename T, int MODE, uint32_t SL, int V, int NT>
     __device__ __forceinline__ void coef(const KArgs &a, const Streams &st, int k, int q,
                                          int64_t e0, T (&out)[V]) const
     {
@@ -303,13 +305,13 @@ struct VecBlock {
         return (3 * r + A) * (3 * NS) + 3 * s + B;
     }
     __device__ __forceinline__ int f_index(int r) const { return 3 * r + A; }
-    template <int V, bool NT, typename T>
+    template <int V, int NT, typename T>
     __device__ __forceinline__ void put_k(const Streams &st, int N, int packed, int r, int s,
                                           int64_t e0, const T (&val)[V]) const
     {
         storev<V, NT>(static_cast<T *>(st.out_K) + k_index(N, packed, r, s) * st.ld_out + e0, val);
     }
-    template <int V, bool NT, typename T>
+    template <int V, int NT, typename T>
     __device__ __forceinline__ void put_f(const Streams &st, int r, int64_t e0, const T (&val)[V]) const
     {
         storev<V, NT>(static_cast<T *>(st.out_F) + f_index(r) * st.ld_out + e0, val);
@@ -327,7 +329,7 @@ struct ApplyBlock : ScalarBlock {
     T *y;
     T *b;  // used when WITH_B
     __device__ __forceinline__ bool with_f() const { return WITH_B; }
-    template <int V, bool NT, typename U>
+    template <int V, int NT, typename U>
     __device__ __forceinline__ void put_k(const Streams &, int, int packed, int r, int s, int64_t,
                                           const U (&val)[V]) const
     {
@@ -336,7 +338,7 @@ struct ApplyBlock : ScalarBlock {
         if (packed && r != s)
             y[s] += val[0] * x[r];
     }
-    template <int V, bool NT, typename U>
+    template <int V, int NT, typename U>
     __device__ __forceinline__ void put_f(const Streams &, int r, int64_t, const U (&val)[V]) const
     {
         b[r] += val[0];
@@ -395,7 +397,7 @@ __device__ __forceinline__ void fn_values(const KArgs &a, const double *p, const
 
 // Coefficient values at one point for V elements: read from memory or
 // uniform (coef), or computed from the coefficient function.
-template <typename T, int MODE, uint32_t SL, int V, bool NT, class BL = ScalarBlock>
+template <typename T, int MODE, uint32_t SL, int V, int NT, class BL = ScalarBlock>
 struct PointCoefs {
     double fv[MODE == M_FUNC ? 20 : 1][V];
     BL bl;
@@ -555,7 +557,7 @@ struct TetScalar {
                           MASS = TERMS & T_MASS, DG = TERMS & T_DGRAD, D0 = TERMS & T_D0;
     static constexpr bool PER_QP = (MODE == M_QP || MODE == M_QP_MIXED || MODE == M_FUNC);
 
-    template <int V, bool NT, int REF, class S>
+    template <int V, int NT, int REF, class S>
     __device__ __forceinline__ static void run(const KArgs &a, const S &st, const Ref<REF> &ref,
                                                int64_t e0)
     {
@@ -567,7 +569,7 @@ struct TetScalar {
             run_qp<V, NT, REF>(a, st, ref, X, e0);
     }
 
-    template <int V, bool NT, class B2>
+    template <int V, int NT, class B2>
     __device__ __forceinline__ static void store_K(const Streams &st, int r, int s, int64_t e0,
                                                    const T (&val)[V], const B2 &bl)
     {
@@ -575,7 +577,7 @@ struct TetScalar {
     }
 
     // One element from its vertex coordinates, results to bl (matrix-free).
-    template <bool NT, int REF, class B2>
+    template <int NT, int REF, class B2>
     __device__ __forceinline__ static void apply_x(const KArgs &a, const Streams &st, const Ref<REF> &ref,
                                                    const double (&X)[12], int64_t e, const B2 &bl)
     {
@@ -591,7 +593,7 @@ struct TetScalar {
     // carry the whole point sum:
     //   K_rs = det [W g_r . C g_s + (c^{.;0} . g_r) m_s + m_r (c^{0;.} . g_s)
     //               + c^{0;0} M_rs],   F_r = det [W d . g_r + d^0 m_r].
-    template <int V, bool NT, class B2 = BL>
+    template <int V, int NT, class B2 = BL>
     __device__ __forceinline__ static void run_const(const KArgs &a, const Streams &st,
                                                      const double (&X)[V][12],
                                                      int64_t e0, const B2 &bl = B2())
@@ -706,7 +708,7 @@ struct TetScalar {
     //   Cb = sum_q w C_q, Pb_s = sum_q w phi_s c^{.;0}_q, Qb_r = sum_q w phi_r c^{0;.}_q,
     //   Mb_rs = sum_q w c^{0;0}_q phi_r phi_s, Db = sum_q w d_q, fb_r = sum_q w d^0_q phi_r,
     //   K_rs = det (g_r . Cb g_s + g_r . Pb_s + Qb_r . g_s + Mb_rs), F_r = det (Db . g_r + fb_r).
-    template <int V, bool NT, int REF, class B2 = BL>
+    template <int V, int NT, int REF, class B2 = BL>
     __device__ __forceinline__ static void run_qp(const KArgs &a, const Streams &st, const Ref<REF> &ref,
                                                   const double (&X)[V][12], int64_t e0,
                                                   const B2 &bl = B2())
@@ -883,7 +885,7 @@ struct TetVector {
     static constexpr bool PER_QP = (MODE == M_QP);
     typedef TetScalar<T, TS_FULL, MODE, 0, VecBlock> P;
 
-    template <int V, bool NT, int REF, class S>
+    template <int V, int NT, int REF, class S>
     __device__ __forceinline__ static void run(const KArgs &a, const S &st, const Ref<REF> &ref,
                                                int64_t e0)
     {
@@ -909,7 +911,7 @@ struct TetElastic {
     static constexpr uint32_t SL = 31u;
     static constexpr bool PER_QP = (MODE == M_QP || MODE == M_QP_MIXED || MODE == M_FUNC);
 
-    template <int V, bool NT, int REF, class S>
+    template <int V, int NT, int REF, class S>
     __device__ __forceinline__ static void run(const KArgs &a, const S &st, const Ref<REF> &ref,
                                                int64_t e0)
     {
@@ -918,14 +920,14 @@ struct TetElastic {
         run_x<V, NT, REF>(a, st, ref, X, e0);
     }
 
-    template <bool NT, int REF, class B2>
+    template <int NT, int REF, class B2>
     __device__ __forceinline__ static void apply_x(const KArgs &a, const Streams &st, const Ref<REF> &ref,
                                                    const double (&X)[12], int64_t e, const B2 &bl)
     {
         run_x<1, NT, REF>(a, st, ref, reinterpret_cast<const double (&)[1][12]>(X), e, bl);
     }
 
-    template <int V, bool NT, int REF, class B2 = BL>
+    template <int V, int NT, int REF, class B2 = BL>
     __device__ __forceinline__ static void run_x(const KArgs &a, const Streams &st, const Ref<REF> &ref,
                                                  const double (&X)[V][12], int64_t e0,
                                                  const B2 &bl = B2())
@@ -1068,7 +1070,7 @@ struct PrismScalar {
         }
     }
 
-    template <bool NT, class R, class B2 = BL>
+    template <int NT, class R, class B2 = BL>
     __device__ __forceinline__ static void load_coefs(const KArgs &a, const Streams &st, const R &ref,
                                                       int q, int64_t e, const double (&X0)[3],
                                                       const double (&E)[18], Coefs &c,
@@ -1128,7 +1130,7 @@ struct PrismScalar {
         }
     }
 
-    template <int V, bool NT, int REF, class S>
+    template <int V, int NT, int REF, class S>
     __device__ __forceinline__ static void run(const KArgs &a, const S &st, const Ref<REF> &ref,
                                                int64_t e)
     {
@@ -1144,7 +1146,7 @@ struct PrismScalar {
         body<NT>(a, st, ref, e, X0, X);
     }
 
-    template <bool NT, int REF, class B2>
+    template <int NT, int REF, class B2>
     __device__ __forceinline__ static void apply_x(const KArgs &a, const Streams &st, const Ref<REF> &ref,
                                                    const double (&Xa)[18], int64_t e, const B2 &bl)
     {
@@ -1159,7 +1161,7 @@ struct PrismScalar {
 
     // Point loop and stores for one element, from vertex 0 and the edge
     // vectors X_r - X_0.
-    template <bool NT, class R, class B2 = BL>
+    template <int NT, class R, class B2 = BL>
     __device__ __forceinline__ static void body(const KArgs &a, const Streams &st, const R &ref,
                                                 int64_t e, const double (&X0)[3], const double (&X)[18],
                                                 const B2 &bl = B2())
@@ -1184,7 +1186,7 @@ struct PrismScalar {
     }
 
     // The points q0, q0 + qstep, ... of one element, summed into K and F.
-    template <bool NT, class R, class B2, int NK>
+    template <int NT, class R, class B2, int NK>
     __device__ __forceinline__ static void accumulate(const KArgs &a, const Streams &st, const R &ref,
                                                       int64_t e, const double (&X0)[3],
                                                       const double (&X)[18], int q0, int qstep,
@@ -1262,7 +1264,7 @@ struct PrismScalar {
     // network), and lane j stores the entries with index = j mod G.
     // `lead` is the group's first lane in the wavefront; `valid` is false for
     // lanes past the end of the batch, which still join the shuffles.
-    template <int G, bool NT, int REF>
+    template <int G, int NT, int REF>
     __device__ __forceinline__ static void run_lanes(const KArgs &a, const Streams &st,
                                                      const Ref<REF> &ref, int64_t e, int j, int lead,
                                                      bool valid)
@@ -1308,7 +1310,7 @@ struct PrismScalar {
 // Jacobian terms are recomputed for each block).
 template <typename T, int MODE, int NQ>
 struct PrismVector {
-    template <int V, bool NT, int REF, class S>
+    template <int V, int NT, int REF, class S>
     __device__ __forceinline__ static void run(const KArgs &a, const S &st, const Ref<REF> &ref,
                                                int64_t e)
     {
@@ -1418,7 +1420,7 @@ struct PrismScalarOrder {
         return x;
     }
 
-    template <int V, bool NT, int REF, class S>
+    template <int V, int NT, int REF, class S>
     __device__ __forceinline__ static void run(const KArgs &a, const S &st, const Ref<REF> &ref,
                                                int64_t e)
     {
@@ -1518,7 +1520,7 @@ struct PrismElastic {
     static constexpr bool PER_QP = (MODE == M_QP || MODE == M_QP_MIXED || MODE == M_FUNC);
     static constexpr int NP = 171;  // packed entries of the 18 x 18 matrix
 
-    template <int V, bool NT>
+    template <int V, int NT>
     __device__ __forceinline__ static void store_block(const Streams &st, int64_t e, int k0,
                                                        int k1, const T *Kp)
     {
@@ -1544,7 +1546,7 @@ struct PrismElastic {
 
     // Shape functions R0..R1-1 as test functions (rows 3*R0 .. 3*R1-1 of K):
     // accumulate H over the points, transform to K, store.
-    template <int R0, int R1, bool WITH_F, bool NT, int REF>
+    template <int R0, int R1, bool WITH_F, int NT, int REF>
     __device__ __forceinline__ static void const_pass(const KArgs &a, const Streams &st,
                                                       const Ref<REF> &ref, const double (&X)[18],
                                                       int64_t e, T lam, T mu, const T (&f)[3])
@@ -1618,7 +1620,7 @@ struct PrismElastic {
         }
     }
 
-    template <int V, bool NT, int REF, class S>
+    template <int V, int NT, int REF, class S>
     __device__ __forceinline__ static void run(const KArgs &a, const S &st, const Ref<REF> &ref,
                                                int64_t e)
     {
@@ -1707,7 +1709,7 @@ struct PrismElastic {
 // Grid: element groups of V contiguous elements, one group per lane, with a
 // grid-stride loop so a launch may use fewer workgroups than groups. The
 // last, partial group is processed element by element.
-template <class P, int V, bool NT, int REF>
+template <class P, int V, int NT, int REF>
 __global__ __launch_bounds__(256) void fe_kernel(KArgs a)
 {
     __shared__ RefLds lds_ref[1];
@@ -1740,7 +1742,7 @@ __global__ __launch_bounds__(256) void fe_kernel(KArgs a)
 // kind in the device table (chunk c by block c mod gridDim), so requests of
 // different sizes share one launch. Chunk starts are multiples of V, so every
 // element is processed by the same code path as in a plain launch.
-template <class P, int V, bool NT, int REF>
+template <class P, int V, int NT, int REF>
 __global__ __launch_bounds__(256) void fe_batch_kernel(KArgs a, const BatchHeader *__restrict__ hdr,
                                                        const Chunk *__restrict__ chunks, int kind)
 {
@@ -1780,7 +1782,7 @@ __global__ __launch_bounds__(256) void fe_batch_kernel(KArgs a, const BatchHeade
     }
 }
 
-template <class P, int V, bool NT, int REF>
+template <class P, int V, int NT, int REF>
 void launch_fe_batch_kernel(const KArgs &a, const BatchHeader *hdr, const Chunk *chunks, int kind,
                             unsigned grid, unsigned block, hipStream_t stream)
 {
@@ -1789,7 +1791,7 @@ void launch_fe_batch_kernel(const KArgs &a, const BatchHeader *hdr, const Chunk 
 }
 
 // Indexed-geometry form of fe_kernel.
-template <class P, int V, bool NT, int REF>
+template <class P, int V, int NT, int REF>
 __global__ __launch_bounds__(256) void fe_kernel_idx(KArgs a, IdxArgs gi)
 {
     __shared__ RefLds lds_ref[1];
@@ -1844,7 +1846,7 @@ __device__ __forceinline__ void add_at(T *p, T v)
         *p += v;
 }
 
-template <class P, int NV, int NC, typename T, bool NT, int REF, bool ATOMIC, bool WITH_B>
+template <class P, int NV, int NC, typename T, int NT, int REF, bool ATOMIC, bool WITH_B>
 __global__ __launch_bounds__(256) void fe_apply_kernel(KArgs a, IdxArgs gi, ApplyArgs ap)
 {
     __shared__ RefLds lds_ref[1];
@@ -1902,7 +1904,7 @@ __global__ __launch_bounds__(256) void fe_apply_kernel(KArgs a, IdxArgs gi, Appl
     }
 }
 
-template <class P, int NV, int NC, typename T, bool NT, int REF>
+template <class P, int NV, int NC, typename T, int NT, int REF>
 void launch_fe_apply(const KArgs &a, const IdxArgs &gi, const ApplyArgs &ap, int atomic,
                      unsigned grid, unsigned block, hipStream_t stream)
 {
@@ -1923,7 +1925,7 @@ void launch_fe_apply(const KArgs &a, const IdxArgs &gi, const ApplyArgs &ap, int
 // G lanes per element: each wavefront takes 64 / G consecutive elements
 // (lanes past G * (64 / G) idle); the loop bound is uniform over the
 // wavefront, so every lane reaches every cross-lane exchange.
-template <class P, int G, bool NT, int REF>
+template <class P, int G, int NT, int REF>
 __global__ __launch_bounds__(256) void fe_kernel_lanes(KArgs a)
 {
     __shared__ RefLds lds_ref[1];
@@ -1955,20 +1957,20 @@ __global__ __launch_bounds__(256) void fe_kernel_lanes(KArgs a)
     }
 }
 
-template <class P, int G, bool NT, int REF>
+template <class P, int G, int NT, int REF>
 void launch_fe_kernel_lanes(const KArgs &a, unsigned grid, unsigned block, hipStream_t stream)
 {
     hipLaunchKernelGGL((fe_kernel_lanes<P, G, NT, REF>), dim3(grid), dim3(block), 0, stream, a);
 }
 
-template <class P, int V, bool NT, int REF>
+template <class P, int V, int NT, int REF>
 void launch_fe_kernel_idx(const KArgs &a, const IdxArgs &gi, unsigned grid, unsigned block,
                           hipStream_t stream)
 {
     hipLaunchKernelGGL((fe_kernel_idx<P, V, NT, REF>), dim3(grid), dim3(block), 0, stream, a, gi);
 }
 
-template <class P, int V, bool NT, int REF>
+template <class P, int V, int NT, int REF>
 void launch_fe_kernel(const KArgs &a, unsigned grid, unsigned block, hipStream_t stream)
 {
     hipLaunchKernelGGL((fe_kernel<P, V, NT, REF>), dim3(grid), dim3(block), 0, stream, a);

@@ -17,7 +17,7 @@ int register_all()
     // staging of the reference tables
 #define TUNE(MODE, PK) \
     reg_prism_scalar<T, TS, MODE, PK, 0, 0, REF_KARG>(); reg_prism_scalar<T, TS, MODE, PK, 0, 1, REF_LDS>(); \
-    reg_prism_scalar<T, TS, MODE, PK, 0, 0, REF_LDS>();
+    reg_prism_scalar<T, TS, MODE, PK, 0, 0, REF_LDS>(); reg_prism_scalar<T, TS, MODE, PK, 0, 2, REF_KARG>();
     TUNE(M_QP, 0) TUNE(M_ELEM, 0) TUNE(M_UNIFORM, 1) TUNE(M_UNIFORM, 0) TUNE(M_FUNC, 0)
 #undef TUNE
     // the SQS and SSQ loop orders, for the order comparison (the paper's

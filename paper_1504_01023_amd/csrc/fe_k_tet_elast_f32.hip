@@ -12,7 +12,8 @@ int register_all()
 #undef BASE
 #define TUNE(MODE, PK) \
     reg_tet_elastic<T, MODE, PK, 2, 1, 1>(); reg_tet_elastic<T, MODE, PK, 4, 1>(); \
-    reg_tet_elastic<T, MODE, PK, 1, 0>(); reg_tet_elastic<T, MODE, PK, 2, 0>();
+    reg_tet_elastic<T, MODE, PK, 1, 0>(); reg_tet_elastic<T, MODE, PK, 2, 0>(); \
+    reg_tet_elastic<T, MODE, PK, 1, 2>(); reg_tet_elastic<T, MODE, PK, 2, 2>();
     TUNE(M_ELEM, 1) TUNE(M_ELEM, 0) TUNE(M_UNIFORM, 1)
 #undef TUNE
     return 0;

@@ -15,11 +15,14 @@ int register_all()
 #undef BASE
     reg_tet_scalar<T, TS, M_FUNC, 0, 2, 1>();
     reg_tet_scalar<T, TS, M_FUNC, 0, 2, 0>();
-    // tuning variants: elements per lane and cache policy
+    // tuning variants: elements per lane and cache policy (default,
+    // streaming, streaming stores only)
 #define TUNE(MODE, PK) \
     reg_tet_scalar<T, TS, MODE, PK, 2, 1, 1>(); reg_tet_scalar<T, TS, MODE, PK, 4, 1>(); \
     reg_tet_scalar<T, TS, MODE, PK, 1, 0>(); reg_tet_scalar<T, TS, MODE, PK, 2, 0, 1>(); \
-    reg_tet_scalar<T, TS, MODE, PK, 4, 0>();
+    reg_tet_scalar<T, TS, MODE, PK, 4, 0>(); \
+    reg_tet_scalar<T, TS, MODE, PK, 1, 2>(); reg_tet_scalar<T, TS, MODE, PK, 2, 2>(); \
+    reg_tet_scalar<T, TS, MODE, PK, 4, 2>();
     TUNE(M_UNIFORM, 1) TUNE(M_UNIFORM, 0) TUNE(M_ELEM, 0) TUNE(M_ELEM, 1) TUNE(M_QP, 0)
 #undef TUNE
     reg_tet_scalar<T, TS, M_QP_MIXED, 0, 2, 1>();

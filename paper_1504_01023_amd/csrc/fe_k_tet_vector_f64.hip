@@ -12,6 +12,7 @@ int register_all()
     // exceed the register file)
     reg_tet_vector<T, M_ELEM, 1, 1>(); reg_tet_vector<T, M_ELEM, 2, 1>();
     reg_tet_vector<T, M_ELEM, 1, 0>(); reg_tet_vector<T, M_ELEM, 2, 0>();
+    reg_tet_vector<T, M_ELEM, 1, 2>(); reg_tet_vector<T, M_ELEM, 2, 2>();
     reg_tet_vector<T, M_QP, 1, 1>(); reg_tet_vector<T, M_QP, 1, 0>();
     return 0;
 }

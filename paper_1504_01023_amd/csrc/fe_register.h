@@ -18,11 +18,11 @@ inline void reg(int elem, int kind, int prec, int terms, int mode, int packed, i
     BatchLaunchFn bl = nullptr;
     IdxLaunchFn il = nullptr;
     if constexpr (B != 0) {
-        bl = &launch_fe_batch_kernel<P, V, NT != 0, REF>;
-        il = &launch_fe_kernel_idx<P, V, NT != 0, REF>;
+        bl = &launch_fe_batch_kernel<P, V, NT, REF>;
+        il = &launch_fe_kernel_idx<P, V, NT, REF>;
     }
-    register_kernel(KernelEntry{k, &launch_fe_kernel<P, V, NT != 0, REF>,
-                                reinterpret_cast<const void *>(&fe_kernel<P, V, NT != 0, REF>), bl,
+    register_kernel(KernelEntry{k, &launch_fe_kernel<P, V, NT, REF>,
+                                reinterpret_cast<const void *>(&fe_kernel<P, V, NT, REF>), bl,
                                 il, B != 0 ? ap : nullptr});
 }
 
@@ -33,7 +33,7 @@ template <class P, int NV, int NC, typename T, int V, int NT, int REF, int B>
 constexpr ApplyLaunchFn apply_form()
 {
     if constexpr (V == 1 && B != 0)
-        return &launch_fe_apply<P, NV, NC, T, NT != 0, REF>;
+        return &launch_fe_apply<P, NV, NC, T, NT, REF>;
     else
         return nullptr;
 }
@@ -72,8 +72,8 @@ inline void reg_prism_scalar_lanes()
 {
     typedef PrismScalar<T, TERMS, MODE, PK, 0> P;
     KernelKey k{FE_PRISM6, FE_SCALAR_CDR, prec_of<T>(), TERMS, MODE, PK, 1, NT, REF, 0, 1, 1, G};
-    register_kernel(KernelEntry{k, &launch_fe_kernel_lanes<P, G, NT != 0, REF>,
-                                reinterpret_cast<const void *>(&fe_kernel_lanes<P, G, NT != 0, REF>),
+    register_kernel(KernelEntry{k, &launch_fe_kernel_lanes<P, G, NT, REF>,
+                                reinterpret_cast<const void *>(&fe_kernel_lanes<P, G, NT, REF>),
                                 nullptr, nullptr, nullptr});
 }
 

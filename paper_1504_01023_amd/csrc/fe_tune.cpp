@@ -193,9 +193,10 @@ int fe_autotune(const fe_problem *problem, fe_elem_type elem_type, int64_t n_ele
     for (const auto &sh : shapes) {
         for (int wg : wgs) {
             for (int gb : grids) {
+                const int ntk = std::get<1>(sh);  // kernel policy 0, 1, 2
                 fe_variant v{wg, std::get<0>(sh), std::get<2>(sh) == REF_LDS ? 1 : 2,
-                             std::get<1>(sh) ? 1 : 2, gb, std::get<3>(sh), std::get<4>(sh),
-                             std::get<5>(sh)};
+                             ntk == 0 ? 2 : (ntk == 2 ? 3 : 1), gb, std::get<3>(sh),
+                             std::get<4>(sh), std::get<5>(sh)};
                 Plan pl;
                 if (plan(problem, elem_type, n_elem, coords, coeffs, ld_in, quad_rule, out_K,
                          out_F, ld_out, &v, pl) != FE_OK)

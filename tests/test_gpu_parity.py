@@ -31,7 +31,7 @@ def test_small_parity(name, precision):
 
 VARIANTS = [
     dict(wg_size=wg, elems_per_thread=v, nontemporal=nt, ref_in_lds=ref, blocks=b, row_split=sp)
-    for wg in (64, 128, 256) for v in (1, 2, 4) for nt in (1, 2) for ref in (1, 2) for b in (0, 7)
+    for wg in (64, 128, 256) for v in (1, 2, 4) for nt in (1, 2, 3) for ref in (1, 2) for b in (0, 7)
     for sp in (1, 2, 3)
 ]
 # the SQS / SSQ loop orders and the lane-split point loop sum in a different

@@ -700,6 +700,19 @@ def main() -> int:
     log(f"[bench] generated {a.workload}: {wl.n_elem} elements in {time.time() - t0:.1f}s")
     dw = fe.to_device(wl, a.precision, device=dev)
     p, rule = dw.problem, dw.rule
+    if a.ld_align > 0:
+        # input rows padded like the outputs, so wavefront segments of the
+        # input rows are whole cache lines too (no line fetched twice)
+        ld_in = (wl.n_elem + a.ld_align - 1) // a.ld_align * a.ld_align
+
+        def padded(t):
+            out = torch.zeros((t.shape[0], ld_in), dtype=t.dtype, device=dev)
+            out[:, : wl.n_elem] = t
+            return out
+
+        dw.coords = padded(dw.coords)
+        if dw.coeffs is not None and wl.coef_mode != "function":
+            dw.coeffs = padded(dw.coeffs)
     nk, nf = fe.k_entries(p, wl.elem), fe.f_entries(p, wl.elem)
     dt = torch.float64 if a.precision == "fp64" else torch.float32
     # output rows padded to whole 2 KB (FP64) / 1 KB (FP32) lines of elements:
@@ -818,7 +831,8 @@ def main() -> int:
                    "description": WORKLOADS[base][1] + (" (indexed geometry: node array + int32 "
                                                         "connectivity)" if indexed else ""),
                    "n_elem": wl.n_elem, "precision": a.precision, "n_q": rule.n_q,
-                   "k_format": wl.k_format, "bytes_per_element": bpe, "ld_out": ld_out,
+                   "k_format": wl.k_format, "bytes_per_element": bpe,
+                   "ld_in": int(dw.coords.shape[1]), "ld_out": ld_out,
                    "variant_wg_vec_ref_nt_blocks": variant_used, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,

@@ -146,9 +146,25 @@ def cpu_baseline(wl, min_s: float = 10.0, max_s: float = 30.0):
         if el >= min_s or el > max_s:
             break
     el = time.perf_counter() - t0
+    # one thread on the first 500,000 elements, for the per-core rate
+    n1 = min(wl.n_elem, 500_000)
+    t1 = time.perf_counter()
+    oracle.integrate_workload(wl, threads=1, elements=np.arange(n1))
+    single = n1 / (time.perf_counter() - t1)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": done / el, "unit": "elements/s", "cores": threads, "kind": "oracle",
             "sample": f"{done} elements ({passes} pass(es) over the {wl.n_elem}-element workload, "
-                      f"chunks of {chunk}), {el:.1f} s wall"}
+                      f"chunks of {chunk}), {el:.1f} s wall",
+            "single_thread_value": single, "single_thread_sample": f"first {n1} elements",
+            "cpu_model": model}
 
 
 # ---------------------------------------------------------------- serving
@@ -411,6 +427,14 @@ PAPER_CASES = [
 ORDER_CODE = {"QSS": 1, "SQS": 2, "SSQ": 3}
 
 
+def model_bound_ns(words: float, ops: float, stream_gbps: float, dgemm_tflops: float) -> float:
+    """The execution-time estimate of Sec. 4.5 (the table of execution
+    times): the longer of the time to move 8-byte words at the STREAM rate
+    and the time to perform the operations at the DGEMM rate, in ns per
+    element."""
+    return max(8.0 * words / stream_gbps, ops / (dgemm_tflops * 1e3))
+
+
 def run_paper(a, torch, fe) -> dict:
     import oracle
     dev = torch.device("cuda:0")
@@ -485,9 +509,7 @@ def run_paper(a, torch, fe) -> dict:
             Kg = fe.unpack_full(Ks, N, False)
             ek = float(np.sqrt(((Kg - Ko) ** 2).sum(axis=(1, 2)) / (Ko ** 2).sum(axis=(1, 2))).max())
             ns = ms * 1e6 / wl.n_elem
-            bound_mem = 8 * words / copy_gbps
-            bound_op = ops[order] / (dgemm_tf * 1e3)
-            bound = max(bound_mem, bound_op)
+            bound = model_bound_ns(words, ops[order], copy_gbps, dgemm_tf)
             rows.append({"case": name, "order": order, "n_elem": wl.n_elem, "ns_per_element": ns,
                          "elements_per_s": wl.n_elem / (ms * 1e-3),
                          "GBps": 8 * words * wl.n_elem / (ms * 1e-3) / 1e9,

@@ -523,6 +523,8 @@ def run_paper(a, torch, fe) -> dict:
     return {"copy_GBps": copy_gbps, "fp64_matmul_TFLOPs": dgemm_tf, "rows": rows}
 
 
+NATURAL_BASES = ("tet_poisson", "tet_poisson_qp", "tet_cdr", "tet_elasticity", "prism_cdr",
+                 "prism_poisson_qp")
 APPLY_BASES = ("tet_poisson", "tet_cdr", "tet_elasticity", "prism_cdr", "prism_poisson_qp")
 
 
@@ -630,6 +632,7 @@ def main() -> int:
     ap.add_argument("--workload", default="tet_poisson",
                     choices=sorted(WORKLOADS) + [w + "_indexed" for w in sorted(WORKLOADS)]
                     + [w + "_apply" for w in APPLY_BASES]
+                    + [w + "_natural" for w in NATURAL_BASES]
                     + ["served", "paper"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--tune", action="store_true",
@@ -716,13 +719,15 @@ def main() -> int:
         return 0
 
     indexed = a.workload.endswith("_indexed")
-    base = a.workload[: -len("_indexed")] if indexed else a.workload
+    natural = a.workload.endswith("_natural")
+    base = a.workload[: -len("_indexed")] if indexed else (
+        a.workload[: -len("_natural")] if natural else a.workload)
     t0 = time.time()
     wl = WORKLOADS[base][0]()
     log(f"[bench] generated {a.workload}: {wl.n_elem} elements in {time.time() - t0:.1f}s")
     dw = fe.to_device(wl, a.precision, device=dev)
     p, rule = dw.problem, dw.rule
-    if a.ld_align > 0:
+    if a.ld_align > 0 and not natural:
         # input rows padded like the outputs, so wavefront segments of the
         # input rows are whole cache lines too (no line fetched twice)
         ld_in = (wl.n_elem + a.ld_align - 1) // a.ld_align * a.ld_align
@@ -754,8 +759,21 @@ def main() -> int:
         conn = torch.from_numpy(np.ascontiguousarray(wl.mesh.conn.T.astype(np.int32))).to(dev)
         bpe = bpe - 24 * nv + 4 * nv + 24.0 * wl.mesh.nodes.shape[0] / wl.n_elem
 
+    if natural:
+        # element-contiguous inputs and outputs; K and F below are row views
+        # of the natural-order outputs for the parity sample
+        x_nat = dw.coords.t().contiguous()
+        c_nat = dw.coeffs
+        if c_nat is not None and wl.coef_mode != "function":
+            c_nat = c_nat.t().contiguous()
+        K_nat = torch.empty((wl.n_elem, nk), dtype=dt, device=dev)
+        F_nat = torch.empty((wl.n_elem, nf), dtype=dt, device=dev)
+        K, F = K_nat.t(), F_nat.t()
+
     def step():
-        if indexed:
+        if natural:
+            fe.integrate_natural(p, wl.elem, x_nat, c_nat, rule, out_K=K_nat, out_F=F_nat)
+        elif indexed:
             fe.integrate_indexed(p, wl.elem, nodes, conn, dw.coeffs, rule, out_K=K, out_F=F,
                                  n_elem=wl.n_elem)
         else:
@@ -763,13 +781,15 @@ def main() -> int:
 
     if a.tuning_file and os.path.exists(a.tuning_file):
         fe.tuning_load(a.tuning_file)
-    if a.tune or fe.tuning_get(p, wl.elem, rule.n_q) is None:
+    if not natural and (a.tune or fe.tuning_get(p, wl.elem, rule.n_q) is None):
         tuned, tms = fe.autotune(p, wl.elem, dw.coords, dw.coeffs, rule, K, F, reps=5,
                                  n_elem=wl.n_elem)
         log(f"[bench] autotuned variant (wg, vec, ref, nt, blocks) = {tuned}: {tms:.4f} ms")
     if a.save_tuning:
         fe.tuning_save(a.save_tuning)
     variant_used = fe.tuning_get(p, wl.elem, rule.n_q)
+    if natural:
+        variant_used = "natural order: tiles of 64 elements, one wavefront, LDS transposition"
 
     for _ in range(a.warmup):
         step()
@@ -851,7 +871,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": a.workload,
                    "description": WORKLOADS[base][1] + (" (indexed geometry: node array + int32 "
-                                                        "connectivity)" if indexed else ""),
+                                                        "connectivity)" if indexed else "")
+                   + (" (natural element-contiguous order, LDS-tiled)" if natural else ""),
                    "n_elem": wl.n_elem, "precision": a.precision, "n_q": rule.n_q,
                    "k_format": wl.k_format, "bytes_per_element": bpe,
                    "ld_in": int(dw.coords.shape[1]), "ld_out": ld_out,

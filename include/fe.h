@@ -210,6 +210,25 @@ FE_API int fe_integrate_indexed(const fe_problem *problem, fe_elem_type elem_typ
                                 void *out_F, int64_t ld_out, const fe_variant *variant,
                                 hipStream_t stream);
 
+/* Natural (element-contiguous) order, the organisation of the element data
+ * that Sec. 4.2 discusses (Fig. 1): every element's values are contiguous,
+ * element after element:
+ *   coords  [e * 3 NV + 3 v + d]              FP64
+ *   coeffs  [e * C + j] per element, [e * C + j * n_q + q] per point
+ *           (C = fe_coeff_entries; the compact slots of coef_mask)
+ *   out_K   [e * fe_k_entries + k],  out_F [e * fe_f_entries + i]
+ * A workgroup of one wavefront copies a tile of 64 elements' inputs to LDS
+ * with coalesced loads, runs the same per-element code as fe_integrate on
+ * the tile (bitwise identical results), and writes the tile's outputs back as
+ * contiguous blocks. Built for scalar CDR (tetrahedra, prisms) and elasticity
+ * on tetrahedra while one tile's data fit in 64 KiB of LDS (it covers the
+ * paper's four cases of table "accesses_and_operations"); otherwise, and for
+ * other problems, FE_ERR_UNSUPPORTED. Pointers aligned to their element size. */
+FE_API int fe_integrate_natural(const fe_problem *problem, fe_elem_type elem_type, int64_t n_elem,
+                                const double *coords, const void *coeffs,
+                                const fe_quad_rule *quad_rule, void *out_K, void *out_F,
+                                hipStream_t stream);
+
 /* Matrix-free application of the assembled operator, with the element
  * matrices computed in registers and never stored (Sec. 3.1 leaves open
  * whether element matrices are stored at all; Sec. 3.2 assembles the element

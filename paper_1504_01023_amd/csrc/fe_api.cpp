@@ -527,6 +527,44 @@ int fe_apply_indexed(const fe_problem *problem, fe_elem_type elem_type, int64_t 
     return FE_OK;
 }
 
+int fe_integrate_natural(const fe_problem *problem, fe_elem_type elem_type, int64_t n_elem,
+                         const double *coords, const void *coeffs, const fe_quad_rule *quad_rule,
+                         void *out_K, void *out_F, hipStream_t stream)
+{
+    // the natural-order form exists for the base variant: one element per lane
+    const fe_variant base{AOS_TILE, 1, 2, 1, 0, 1, 1, 1};
+    Plan pl;
+    int st = plan(problem, elem_type, n_elem, coords, coeffs, n_elem, quad_rule, out_K, out_F,
+                  n_elem, &base, pl);
+    if (st)
+        return st;
+    if (!pl.entry->aos)
+        return fail(FE_ERR_UNSUPPORTED, "no natural-order form for this problem");
+    const bool fn = problem->coef_mode == FE_COEF_FUNCTION;
+    AosArgs ao{};
+    ao.tsize = problem->precision == FE_FP64 ? 8 : 4;
+    ao.coef_rows = fn ? 0 : (int32_t)fe_coeff_entries(problem, elem_type, quad_rule->n_q);
+    ao.k_rows = (int32_t)fe_k_entries(problem, elem_type);
+    ao.f_rows = (int32_t)fe_f_entries(problem, elem_type);
+    const int nv = elem_type == FE_TET4 ? 4 : 6;
+    const size_t lds = (size_t)AOS_TILE * (8 * 3 * nv + (size_t)ao.tsize * (ao.coef_rows + ao.k_rows +
+                                                                            ao.f_rows));
+    if (lds > 64 * 1024)
+        return fail(FE_ERR_UNSUPPORTED,
+                    "natural order needs %zu bytes of LDS per tile of %d elements (limit 65536)", lds,
+                    AOS_TILE);
+    if (n_elem == 0)
+        return FE_OK;
+    int64_t grid = (n_elem + AOS_TILE - 1) / AOS_TILE;
+    if (grid > 0x7fffffff)
+        grid = 0x7fffffff;
+    pl.entry->aos(pl.args, ao, (unsigned)grid, lds, stream);
+    const hipError_t err = hipGetLastError();
+    if (err != hipSuccess)
+        return fail(FE_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(err));
+    return FE_OK;
+}
+
 int fe_color_elements(fe_elem_type elem_type, int64_t n_elem, const int32_t *conn, int64_t ld_conn,
                       int64_t n_nodes, int32_t *perm, int64_t *color_ptr, int32_t max_colors)
 {

@@ -1963,6 +1963,92 @@ void launch_fe_kernel_lanes(const KArgs &a, unsigned grid, unsigned block, hipSt
     hipLaunchKernelGGL((fe_kernel_lanes<P, G, NT, REF>), dim3(grid), dim3(block), 0, stream, a);
 }
 
+// Natural-order inputs and outputs (the element-contiguous organisation
+// of Sec. 4.2 and its Fig. 1): a workgroup of one wavefront takes a tile of
+// AOS_TILE consecutive elements, copies the tile's contiguous input block to
+// LDS with coalesced loads, transposed to rows (row-major by value, element
+// fastest), runs the unchanged per-element code on that LDS tile (the
+// stream pointers are LDS addresses, the leading dimension AOS_TILE), and
+// writes the tile's K and F back as contiguous element-major blocks with
+// coalesced stores. LDS tile: [3 NV rows FP64 | coef rows | K rows | F rows].
+template <class P, int NV, int NT, int REF>
+__global__ __launch_bounds__(64) void fe_kernel_aos(KArgs a, AosArgs ao)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    __shared__ RefLds lds_ref[1];
+    if constexpr (REF == REF_LDS) {
+        const int n_w = a.n_q, n_phi = a.n_q * 6, n_dphi = a.n_q * 18;
+        for (int i = threadIdx.x; i < n_w; i += blockDim.x)
+            lds_ref[0].w[i] = a.w[i];
+        for (int i = threadIdx.x; i < n_phi; i += blockDim.x)
+            (&lds_ref[0].phi[0][0])[i] = (&a.phi[0][0])[i];
+        for (int i = threadIdx.x; i < n_dphi; i += blockDim.x)
+            (&lds_ref[0].dphi[0][0][0])[i] = (&a.dphi[0][0][0])[i];
+        __syncthreads();
+    }
+    const Ref<REF> ref{a, &lds_ref[0]};
+    constexpr int NC3 = 3 * NV;
+    double *l_x = reinterpret_cast<double *>(lds_raw);
+    unsigned char *l_c = lds_raw + sizeof(double) * NC3 * AOS_TILE;
+    unsigned char *l_k = l_c + (size_t)ao.tsize * ao.coef_rows * AOS_TILE;
+    unsigned char *l_f = l_k + (size_t)ao.tsize * ao.k_rows * AOS_TILE;
+    const Streams st{l_x, l_c, l_k, l_f, AOS_TILE, AOS_TILE};
+    const int lane = threadIdx.x;
+    for (int64_t t0 = (int64_t)blockIdx.x * AOS_TILE; t0 < a.n_elem; t0 += (int64_t)gridDim.x * AOS_TILE) {
+        const int n = (int)(a.n_elem - t0 < AOS_TILE ? a.n_elem - t0 : AOS_TILE);
+        // tile inputs: element-major in memory, row-major in LDS
+        const double *gx = a.coords + t0 * NC3;
+        for (int i = lane; i < n * NC3; i += AOS_TILE)
+            l_x[(i % NC3) * AOS_TILE + i / NC3] = ld1<NT>(gx + i);
+        const int cr = ao.coef_rows;
+        if (ao.tsize == 8) {
+            const double *gc = static_cast<const double *>(a.coeffs) + t0 * cr;
+            double *lc = reinterpret_cast<double *>(l_c);
+            for (int i = lane; i < n * cr; i += AOS_TILE)
+                lc[(i % cr) * AOS_TILE + i / cr] = ld1<NT>(gc + i);
+        } else {
+            const float *gc = static_cast<const float *>(a.coeffs) + t0 * cr;
+            float *lc = reinterpret_cast<float *>(l_c);
+            for (int i = lane; i < n * cr; i += AOS_TILE)
+                lc[(i % cr) * AOS_TILE + i / cr] = ld1<NT>(gc + i);
+        }
+        __syncthreads();
+        if (lane < n)
+            P::template run<1, 0, REF>(a, st, ref, (int64_t)lane);
+        __syncthreads();
+        // tile outputs: row-major in LDS, element-major in memory
+        const int kr = ao.k_rows, fr = ao.f_rows;
+        if (ao.tsize == 8) {
+            double *gk = static_cast<double *>(a.out_K) + t0 * kr;
+            double *gf = static_cast<double *>(a.out_F) + t0 * fr;
+            const double *lk = reinterpret_cast<const double *>(l_k);
+            const double *lf = reinterpret_cast<const double *>(l_f);
+            for (int i = lane; i < n * kr; i += AOS_TILE)
+                st1<NT>(gk + i, lk[(i % kr) * AOS_TILE + i / kr]);
+            for (int i = lane; i < n * fr; i += AOS_TILE)
+                st1<NT>(gf + i, lf[(i % fr) * AOS_TILE + i / fr]);
+        } else {
+            float *gk = static_cast<float *>(a.out_K) + t0 * kr;
+            float *gf = static_cast<float *>(a.out_F) + t0 * fr;
+            const float *lk = reinterpret_cast<const float *>(l_k);
+            const float *lf = reinterpret_cast<const float *>(l_f);
+            for (int i = lane; i < n * kr; i += AOS_TILE)
+                st1<NT>(gk + i, lk[(i % kr) * AOS_TILE + i / kr]);
+            for (int i = lane; i < n * fr; i += AOS_TILE)
+                st1<NT>(gf + i, lf[(i % fr) * AOS_TILE + i / fr]);
+        }
+        __syncthreads();
+    }
+}
+
+template <class P, int NV, int NT, int REF>
+void launch_fe_kernel_aos(const KArgs &a, const AosArgs &ao, unsigned grid, size_t lds_bytes,
+                          hipStream_t stream)
+{
+    hipLaunchKernelGGL((fe_kernel_aos<P, NV, NT, REF>), dim3(grid), dim3(AOS_TILE), lds_bytes, stream,
+                       a, ao);
+}
+
 template <class P, int V, int NT, int REF>
 void launch_fe_kernel_idx(const KArgs &a, const IdxArgs &gi, unsigned grid, unsigned block,
                           hipStream_t stream)

@@ -136,6 +136,18 @@ struct ApplyArgs {
 typedef void (*ApplyLaunchFn)(const KArgs &, const IdxArgs &, const ApplyArgs &, int atomic,
                               unsigned grid, unsigned block, hipStream_t);
 
+// Natural-order (element-contiguous) inputs and outputs: every element's
+// coordinates, coefficients, K and F are contiguous, element after element.
+struct AosArgs {
+    int32_t coef_rows;  // coefficient values per element
+    int32_t k_rows;     // K entries per element
+    int32_t f_rows;     // F entries per element
+    int32_t tsize;      // bytes per coefficient / output value
+};
+typedef void (*AosLaunchFn)(const KArgs &, const AosArgs &, unsigned grid, size_t lds_bytes,
+                            hipStream_t);
+constexpr int AOS_TILE = 64;  // elements per workgroup tile (one wavefront)
+
 struct KernelEntry {
     KernelKey key;
     LaunchFn launch;
@@ -143,6 +155,7 @@ struct KernelEntry {
     BatchLaunchFn batch;  // persistent batched form, or nullptr
     IdxLaunchFn idx;      // indexed-geometry form, or nullptr
     ApplyLaunchFn apply;  // matrix-free form (one element per lane), or nullptr
+    AosLaunchFn aos;      // natural-order form (one element per lane), or nullptr
 };
 
 // Registration of compiled kernels (each kernel translation unit registers

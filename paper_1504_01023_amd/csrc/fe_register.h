@@ -12,7 +12,7 @@ namespace fe {
 // the matrix-free form (ap).
 template <class P, int V, int NT, int REF, int B = 0>
 inline void reg(int elem, int kind, int prec, int terms, int mode, int packed, int nq, int split = 1,
-                int order = 1, ApplyLaunchFn ap = nullptr)
+                int order = 1, ApplyLaunchFn ap = nullptr, AosLaunchFn ao = nullptr)
 {
     KernelKey k{elem, kind, prec, terms, mode, packed, V, NT, REF, nq, split, order, 1};
     BatchLaunchFn bl = nullptr;
@@ -23,7 +23,18 @@ inline void reg(int elem, int kind, int prec, int terms, int mode, int packed, i
     }
     register_kernel(KernelEntry{k, &launch_fe_kernel<P, V, NT, REF>,
                                 reinterpret_cast<const void *>(&fe_kernel<P, V, NT, REF>), bl,
-                                il, B != 0 ? ap : nullptr});
+                                il, B != 0 ? ap : nullptr, B != 0 ? ao : nullptr});
+}
+
+// The natural-order form of a problem class with NV vertices, for the base
+// variants (one element per lane, with the batched and indexed forms).
+template <class P, int NV, int V, int NT, int REF, int B>
+constexpr AosLaunchFn aos_form()
+{
+    if constexpr (V == 1 && B != 0)
+        return &launch_fe_kernel_aos<P, NV, NT, REF>;
+    else
+        return nullptr;
 }
 
 // The matrix-free form of a problem class with NV vertices and NC
@@ -46,7 +57,8 @@ inline void reg_tet_scalar()
 {
     typedef TetScalar<T, TERMS, MODE, PK> P;
     reg<P, V, NT, REF_KARG, B>(FE_TET4, FE_SCALAR_CDR, prec_of<T>(), TERMS, MODE, PK, 0, 1, 1,
-                               apply_form<P, 4, 1, T, V, NT, REF_KARG, B>());
+                               apply_form<P, 4, 1, T, V, NT, REF_KARG, B>(),
+                               aos_form<P, 4, V, NT, REF_KARG, B>());
 }
 
 template <typename T, int MODE, int PK, int V, int NT, int B = 0>
@@ -54,7 +66,8 @@ inline void reg_tet_elastic()
 {
     typedef TetElastic<T, MODE, PK> P;
     reg<P, V, NT, REF_KARG, B>(FE_TET4, FE_ELASTICITY, prec_of<T>(), TS_ELAST, MODE, PK, 0, 1, 1,
-                               apply_form<P, 4, 3, T, V, NT, REF_KARG, B>());
+                               apply_form<P, 4, 3, T, V, NT, REF_KARG, B>(),
+                               aos_form<P, 4, V, NT, REF_KARG, B>());
 }
 
 template <typename T, int TERMS, int MODE, int PK, int NQ, int NT, int REF, int B = 0>
@@ -62,7 +75,7 @@ inline void reg_prism_scalar()
 {
     typedef PrismScalar<T, TERMS, MODE, PK, NQ> P;
     reg<P, 1, NT, REF, B>(FE_PRISM6, FE_SCALAR_CDR, prec_of<T>(), TERMS, MODE, PK, NQ, 1, 1,
-                          apply_form<P, 6, 1, T, 1, NT, REF, B>());
+                          apply_form<P, 6, 1, T, 1, NT, REF, B>(), aos_form<P, 6, 1, NT, REF, B>());
 }
 
 // Prism scalar QSS kernels with the points of an element split between G
@@ -74,7 +87,7 @@ inline void reg_prism_scalar_lanes()
     KernelKey k{FE_PRISM6, FE_SCALAR_CDR, prec_of<T>(), TERMS, MODE, PK, 1, NT, REF, 0, 1, 1, G};
     register_kernel(KernelEntry{k, &launch_fe_kernel_lanes<P, G, NT, REF>,
                                 reinterpret_cast<const void *>(&fe_kernel_lanes<P, G, NT, REF>),
-                                nullptr, nullptr, nullptr});
+                                nullptr, nullptr, nullptr, nullptr});
 }
 
 // Prism scalar kernels in the SQS / SSQ loop orders (one element per lane).

@@ -104,6 +104,7 @@ def lib():
         L.fe_apply_indexed.argtypes = [P, i32, i64, vp, i64, vp, i64, vp, i64, R, vp, vp, vp,
                                        ctypes.POINTER(ctypes.c_int64), i32, vp]
         L.fe_color_elements.argtypes = [i32, i64, vp, i64, i64, vp, vp, i32]
+        L.fe_integrate_natural.argtypes = [P, i32, i64, vp, vp, R, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -284,6 +285,44 @@ def integrate_indexed(p: Problem, elem, nodes, conn, coeffs, rule: Rule, out_K=N
                                       ctypes.c_void_p(out_K.data_ptr()),
                                       ctypes.c_void_p(out_F.data_ptr()), ld_out, vptr,
                                       _stream_handle(stream)))
+    return out_K, out_F
+
+
+def integrate_natural(p: Problem, elem, coords, coeffs, rule: Rule, out_K=None, out_F=None,
+                      stream=None):
+    """Natural (element-contiguous) order: coords (n, 3 n_vert) FP64, coeffs
+    (n, coeff_entries) or the function parameters, outputs (n, k_entries) and
+    (n, f_entries), all contiguous device tensors. Returns (out_K, out_F)."""
+    import torch
+    e = ELEM.get(elem, elem)
+    nv = 4 if e == TET4 else 6
+    n = coords.shape[0]
+    dt = _dtype(p)
+    nk, nf = k_entries(p, e), f_entries(p, e)
+    if not (coords.is_cuda and coords.dtype == torch.float64 and coords.is_contiguous()
+            and coords.dim() == 2 and coords.shape[1] == 3 * nv):
+        raise ValueError(f"coords must be a contiguous (n, {3 * nv}) float64 GPU tensor")
+    if out_K is None:
+        out_K = torch.empty((n, nk), dtype=dt, device=coords.device)
+    if out_F is None:
+        out_F = torch.empty((n, nf), dtype=dt, device=coords.device)
+    for name, t, c in (("out_K", out_K, nk), ("out_F", out_F, nf)):
+        if not (t.is_cuda and t.dtype == dt and t.is_contiguous() and tuple(t.shape) == (n, c)):
+            raise ValueError(f"{name} must be a contiguous ({n}, {c}) {dt} GPU tensor")
+    nc = coeff_entries(p, e, rule.n_q)
+    cptr = None
+    if nc > 0:
+        if coeffs is None:
+            raise ValueError("this problem reads coefficients from memory; coeffs is None")
+        if p.coef_mode == COEF_FUNCTION:
+            _check_coeffs(p, coeffs, dt, nc, n)
+        elif not (coeffs.is_cuda and coeffs.dtype == dt and coeffs.is_contiguous()
+                  and tuple(coeffs.shape) == (n, nc)):
+            raise ValueError(f"coeffs must be a contiguous ({n}, {nc}) {dt} GPU tensor")
+        cptr = ctypes.c_void_p(coeffs.data_ptr())
+    _check(lib().fe_integrate_natural(ctypes.byref(p), e, n, ctypes.c_void_p(coords.data_ptr()), cptr,
+                                      ctypes.byref(rule.c), ctypes.c_void_p(out_K.data_ptr()),
+                                      ctypes.c_void_p(out_F.data_ptr()), _stream_handle(stream)))
     return out_K, out_F
 
 

@@ -546,9 +546,18 @@ int fe_integrate_natural(const fe_problem *problem, fe_elem_type elem_type, int6
     ao.coef_rows = fn ? 0 : (int32_t)fe_coeff_entries(problem, elem_type, quad_rule->n_q);
     ao.k_rows = (int32_t)fe_k_entries(problem, elem_type);
     ao.f_rows = (int32_t)fe_f_entries(problem, elem_type);
+    auto magic = [](int32_t d) -> uint32_t {
+        return d > 0 ? (uint32_t)(((uint64_t)1 << 32) / (uint64_t)d + 1) : 0u;
+    };
+    ao.coef_magic = magic(ao.coef_rows);
+    ao.k_magic = magic(ao.k_rows);
+    ao.f_magic = magic(ao.f_rows);
     const int nv = elem_type == FE_TET4 ? 4 : 6;
-    const size_t lds = (size_t)AOS_TILE * (8 * 3 * nv + (size_t)ao.tsize * (ao.coef_rows + ao.k_rows +
-                                                                            ao.f_rows));
+    // the outputs reuse the inputs' LDS (every input of an element is read
+    // before its first output is written, and a tile is one wavefront)
+    const size_t in_b = 8 * 3 * nv + (size_t)ao.tsize * ao.coef_rows;
+    const size_t out_b = (size_t)ao.tsize * (ao.k_rows + ao.f_rows);
+    const size_t lds = (size_t)AOS_TILE * (in_b > out_b ? in_b : out_b);
     if (lds > 64 * 1024)
         return fail(FE_ERR_UNSUPPORTED,
                     "natural order needs %zu bytes of LDS per tile of %d elements (limit 65536)", lds,

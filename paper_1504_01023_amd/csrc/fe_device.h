@@ -1970,7 +1970,13 @@ void launch_fe_kernel_lanes(const KArgs &a, unsigned grid, unsigned block, hipSt
 // fastest), runs the unchanged per-element code on that LDS tile (the
 // stream pointers are LDS addresses, the leading dimension AOS_TILE), and
 // writes the tile's K and F back as contiguous element-major blocks with
-// coalesced stores. LDS tile: [3 NV rows FP64 | coef rows | K rows | F rows].
+// coalesced stores. LDS tile: inputs [3 NV rows FP64 | coef rows], and the
+// outputs [K rows | F rows] over the same bytes: the problem classes read
+// every input of an element before they write its first output, and the
+// one wavefront executes its instructions in order, so no lane's output
+// overwrites an input another lane has still to read.
+__device__ __forceinline__ uint32_t div_magic(uint32_t i, uint32_t magic) { return __umulhi(i, magic); }
+
 template <class P, int NV, int NT, int REF>
 __global__ __launch_bounds__(64) void fe_kernel_aos(KArgs a, AosArgs ao)
 {
@@ -1990,7 +1996,7 @@ __global__ __launch_bounds__(64) void fe_kernel_aos(KArgs a, AosArgs ao)
     constexpr int NC3 = 3 * NV;
     double *l_x = reinterpret_cast<double *>(lds_raw);
     unsigned char *l_c = lds_raw + sizeof(double) * NC3 * AOS_TILE;
-    unsigned char *l_k = l_c + (size_t)ao.tsize * ao.coef_rows * AOS_TILE;
+    unsigned char *l_k = lds_raw;
     unsigned char *l_f = l_k + (size_t)ao.tsize * ao.k_rows * AOS_TILE;
     const Streams st{l_x, l_c, l_k, l_f, AOS_TILE, AOS_TILE};
     const int lane = threadIdx.x;
@@ -2004,13 +2010,17 @@ __global__ __launch_bounds__(64) void fe_kernel_aos(KArgs a, AosArgs ao)
         if (ao.tsize == 8) {
             const double *gc = static_cast<const double *>(a.coeffs) + t0 * cr;
             double *lc = reinterpret_cast<double *>(l_c);
-            for (int i = lane; i < n * cr; i += AOS_TILE)
-                lc[(i % cr) * AOS_TILE + i / cr] = ld1<NT>(gc + i);
+            for (int i = lane; i < n * cr; i += AOS_TILE) {
+                const int q = (int)div_magic((uint32_t)i, ao.coef_magic);
+                lc[(i - q * cr) * AOS_TILE + q] = ld1<NT>(gc + i);
+            }
         } else {
             const float *gc = static_cast<const float *>(a.coeffs) + t0 * cr;
             float *lc = reinterpret_cast<float *>(l_c);
-            for (int i = lane; i < n * cr; i += AOS_TILE)
-                lc[(i % cr) * AOS_TILE + i / cr] = ld1<NT>(gc + i);
+            for (int i = lane; i < n * cr; i += AOS_TILE) {
+                const int q = (int)div_magic((uint32_t)i, ao.coef_magic);
+                lc[(i - q * cr) * AOS_TILE + q] = ld1<NT>(gc + i);
+            }
         }
         __syncthreads();
         if (lane < n)
@@ -2023,19 +2033,27 @@ __global__ __launch_bounds__(64) void fe_kernel_aos(KArgs a, AosArgs ao)
             double *gf = static_cast<double *>(a.out_F) + t0 * fr;
             const double *lk = reinterpret_cast<const double *>(l_k);
             const double *lf = reinterpret_cast<const double *>(l_f);
-            for (int i = lane; i < n * kr; i += AOS_TILE)
-                st1<NT>(gk + i, lk[(i % kr) * AOS_TILE + i / kr]);
-            for (int i = lane; i < n * fr; i += AOS_TILE)
-                st1<NT>(gf + i, lf[(i % fr) * AOS_TILE + i / fr]);
+            for (int i = lane; i < n * kr; i += AOS_TILE) {
+                const int q = (int)div_magic((uint32_t)i, ao.k_magic);
+                st1<NT>(gk + i, lk[(i - q * kr) * AOS_TILE + q]);
+            }
+            for (int i = lane; i < n * fr; i += AOS_TILE) {
+                const int q = (int)div_magic((uint32_t)i, ao.f_magic);
+                st1<NT>(gf + i, lf[(i - q * fr) * AOS_TILE + q]);
+            }
         } else {
             float *gk = static_cast<float *>(a.out_K) + t0 * kr;
             float *gf = static_cast<float *>(a.out_F) + t0 * fr;
             const float *lk = reinterpret_cast<const float *>(l_k);
             const float *lf = reinterpret_cast<const float *>(l_f);
-            for (int i = lane; i < n * kr; i += AOS_TILE)
-                st1<NT>(gk + i, lk[(i % kr) * AOS_TILE + i / kr]);
-            for (int i = lane; i < n * fr; i += AOS_TILE)
-                st1<NT>(gf + i, lf[(i % fr) * AOS_TILE + i / fr]);
+            for (int i = lane; i < n * kr; i += AOS_TILE) {
+                const int q = (int)div_magic((uint32_t)i, ao.k_magic);
+                st1<NT>(gk + i, lk[(i - q * kr) * AOS_TILE + q]);
+            }
+            for (int i = lane; i < n * fr; i += AOS_TILE) {
+                const int q = (int)div_magic((uint32_t)i, ao.f_magic);
+                st1<NT>(gf + i, lf[(i - q * fr) * AOS_TILE + q]);
+            }
         }
         __syncthreads();
     }

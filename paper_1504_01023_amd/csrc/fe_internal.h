@@ -143,6 +143,9 @@ struct AosArgs {
     int32_t k_rows;     // K entries per element
     int32_t f_rows;     // F entries per element
     int32_t tsize;      // bytes per coefficient / output value
+    // ceil(2^32 / rows): i / rows = umulhi(i, magic) exactly for the tile
+    // indices used (i < 2^16, rows < 2^16)
+    uint32_t coef_magic, k_magic, f_magic;
 };
 typedef void (*AosLaunchFn)(const KArgs &, const AosArgs &, unsigned grid, size_t lds_bytes,
                             hipStream_t);

@@ -230,6 +230,23 @@ static int check_rule(const fe_quad_rule *r)
 
 static bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
+// K is symmetric whatever the per-element data: no convection term, and the
+// diffusion tensor uniform and symmetric (the mass term is symmetric).
+static bool symmetric_full(const fe_problem *p, int elem)
+{
+    if (elem != FE_PRISM6 || p->kind != FE_SCALAR_CDR || p->coef_mode == FE_COEF_FUNCTION)
+        return false;
+    if (needed_terms(p) & (T_CONVA | T_CONVB))
+        return false;
+    if (effective_mask(p) & slots_of_terms(T_DIFF))
+        return false;
+    for (int i = 0; i < 3; ++i)
+        for (int j = i + 1; j < 3; ++j)
+            if (p->uniform[4 * (i + 1) + 1 + j] != p->uniform[4 * (j + 1) + 1 + i])
+                return false;
+    return true;
+}
+
 // ---------------------------------------------------------------- planning
 int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coords,
          const void *coeffs, int64_t ld_in, const fe_quad_rule *rule, void *out_K, void *out_F,
@@ -289,6 +306,20 @@ int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coor
     else
         k.mode = per_qp ? M_QP_MIXED : M_ELEM_MIXED;
     k.packed = (problem->k_format == FE_K_SYM_PACKED) ? 1 : 0;
+    if (k.packed == 0 && symmetric_full(problem, elem)) {
+        // a symmetric prism problem asked for full K: accumulate the upper
+        // triangle only, where such kernels are built
+        KernelKey s = k;
+        s.packed = 2;
+        for (int i = 0; i < kernel_count(); ++i) {
+            const KernelKey &x = kernel_at(i)->key;
+            if (x.elem == s.elem && x.kind == s.kind && x.prec == s.prec && x.terms == s.terms &&
+                x.mode == s.mode && x.packed == 2) {
+                k.packed = 2;
+                break;
+            }
+        }
+    }
 
     // variant: forced, tuned, or default
     fe_variant v{};
@@ -338,10 +369,22 @@ int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coor
     auto usable = [&](const KernelEntry *x) {
         return x && (form == 0 || (form == 1 && x->idx != nullptr) || (form == 2 && x->apply != nullptr));
     };
+    const int nq_rule = k.nq;
     const KernelEntry *e = find_kernel(k);
     if (!usable(e)) {
         k.nq = 0;
         e = find_kernel(k);
+    }
+    if (!usable(e) && k.packed == 2) {
+        // the symmetric accumulation is built for some variants only (QSS,
+        // one lane per element): the plain full-K kernel of this variant
+        k.packed = 0;
+        k.nq = nq_rule;
+        e = find_kernel(k);
+        if (!usable(e)) {
+            k.nq = 0;
+            e = find_kernel(k);
+        }
     }
     if (!usable(e) && !forced) {
         // fall back to the always-built base variant

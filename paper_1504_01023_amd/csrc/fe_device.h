@@ -1038,7 +1038,9 @@ struct TetElastic {
 
 // ========================================================== prism, scalar
 // Algorithm 2 (QSS, geometry per point): for every point the Jacobian terms
-// and global derivatives are formed, then the S x S update. With
+// and global derivatives are formed, then the S x S update. PACKED: 0 full
+// K, 1 packed upper triangle, 2 a symmetric problem asked for full K (the
+// upper triangle is accumulated, both halves stored). With
 // u_r = vol g_r, p_r = vol phi_r, t_s = C g_s + phi_s c^{.;0} and
 // sigma_s = c^{0;.} . g_s + c^{0;0} phi_s:  K_rs += u_r . t_s + p_r sigma_s,
 // F_r += u_r . d + p_r d^0.
@@ -1174,7 +1176,15 @@ struct PrismScalar {
 #pragma unroll
             for (int s = (PACKED ? r : 0); s < 6; ++s) {
                 const T v[1] = {K[PACKED ? pidx(6, r, s) : 6 * r + s]};
-                bl.template put_k<1, NT>(st, 6, PACKED, r, s, e, v);
+                if constexpr (PACKED == 2) {
+                    // symmetric problem stored in full: the upper triangle
+                    // is accumulated, both halves are stored
+                    bl.template put_k<1, NT>(st, 6, 0, r, s, e, v);
+                    if (s != r)
+                        bl.template put_k<1, NT>(st, 6, 0, s, r, e, v);
+                } else {
+                    bl.template put_k<1, NT>(st, 6, PACKED, r, s, e, v);
+                }
             }
         if (bl.with_f()) {
 #pragma unroll
@@ -1277,6 +1287,7 @@ struct PrismScalar {
             X[s] = Xg[0][s];
         const double X0[3] = {X[0], X[1], X[2]};
         to_edge_vectors<6>(X);
+        static_assert(PACKED != 2, "lane-split kernels store packed or full accumulations");
         constexpr int NK = PACKED ? 21 : 36;
         T K[NK], F[6];
         accumulate<NT>(a, st, ref, e, X0, X, j, G, K, F, ScalarBlock());

@@ -27,6 +27,12 @@ int register_all()
     reg_prism_scalar_order<T, TS, MODE, 0, ORDER_SQS, 0>(); reg_prism_scalar_order<T, TS, MODE, 0, ORDER_SSQ, 0>();
     ORDERS(M_QP_MIXED) ORDERS(M_ELEM) ORDERS(M_QP)
 #undef ORDERS
+    // symmetric problems asked for full K: upper triangle accumulated
+#define SYMFULL(MODE) \
+    reg_prism_scalar<T, TS, MODE, 2, 0, 1, REF_KARG, 1>(); reg_prism_scalar<T, TS, MODE, 2, 0, 0, REF_KARG>(); \
+    reg_prism_scalar<T, TS, MODE, 2, 0, 2, REF_KARG>(); reg_prism_scalar<T, TS, MODE, 2, 0, 1, REF_LDS>();
+    SYMFULL(M_UNIFORM) SYMFULL(M_QP_MIXED) SYMFULL(M_ELEM_MIXED)
+#undef SYMFULL
     // the points of an element split over 2, 3 or 6 lanes
 #define LANES(MODE) \
     reg_prism_scalar_lanes<T, TS, MODE, 0, 2, 1, REF_KARG>(); \

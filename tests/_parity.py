@@ -92,6 +92,7 @@ SMALL = {
     "prism_elasticity": lambda: inputs.prism_elasticity(6, 6, seed=14),
     "tet_cdr_fn": lambda: inputs.tet_cdr_fn(6, seed=15),
     "prism_cdr_fn": lambda: inputs.prism_cdr_fn(8, 6, seed=16),
+    "prism_poisson_qp": lambda: inputs.prism_poisson_qp_rhs(8, 5, seed=19),
     "tet_vector": lambda: inputs.tet_vector(6, seed=17),
     "prism_vector": lambda: inputs.prism_vector(7, 5, seed=18),
 }

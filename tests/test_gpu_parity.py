@@ -296,3 +296,18 @@ def test_indexed_geometry_clamps_bad_ids():
     torch.cuda.synchronize()
     good = np.setdiff1d(np.arange(wl.n_elem), [5, 7])
     P.assert_parity(wl, "fp64", K.cpu().numpy(), F.cpu().numpy(), elements=good)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_symmetric_full_storage(precision):
+    """A symmetric prism problem asked for full K accumulates the upper
+    triangle and stores both halves: the stored matrix is exactly symmetric,
+    and matches the oracle and the plain full-K (SQS order) kernel."""
+    wl = P.small("prism_poisson_qp")
+    K, F = P.gpu_raw(wl, precision)
+    Kf, _ = P.to_full(K, F, wl)
+    assert np.array_equal(Kf, np.transpose(Kf, (0, 2, 1)))
+    P.assert_parity(wl, precision, K, F)
+    K2, F2 = P.gpu_raw(wl, precision, variant=fe.variant(loop_order=2))
+    tol = P.TOL[precision]
+    assert np.abs(K2 - K).max() <= tol * np.abs(K).max() * 10

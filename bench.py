@@ -533,7 +533,12 @@ def run_apply(a, torch, fe, oracle, base: str, dev) -> dict:
     matrices formed in registers, never stored), coloured launches with plain
     updates; one step = one application. Parity: y at sampled nodes against
     the oracle's element matrices of every element touching them."""
+    from paper_1504_01023_amd import inputs
     wl = WORKLOADS[base][0]()
+    if a.apply_order != "generator":
+        t0 = time.time()
+        wl = inputs.reordered(wl, a.apply_order)
+        log(f"[bench] {a.apply_order} node and element order ({time.time() - t0:.1f}s)")
     nodes_np, conn_np = wl.mesh.nodes, wl.mesh.conn
     n, nv = conn_np.shape
     n_nodes = nodes_np.shape[0]
@@ -642,6 +647,9 @@ def main() -> int:
     ap.add_argument("--save-tuning", default=None, help="write the tuning table here after the run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--parity-sample", type=int, default=20000)
+    ap.add_argument("--apply-order", default="morton", choices=["morton", "generator"],
+                    help="node and element order of the matrix-free runs: Z-order renumbering, "
+                         "or the generator's lexicographic order")
     ap.add_argument("--ld-align", type=int, default=256,
                     help="pad the output leading dimension to a multiple of this many elements "
                          "(0: ld = n_elem)")
@@ -690,6 +698,7 @@ def main() -> int:
                 "config": {"workload": a.workload,
                            "description": WORKLOADS[base][1] + "; y += A x, coloured launches",
                            "n_elem": r["n_elem"], "n_nodes": r["n_nodes"], "colours": r["colours"],
+                           "node_element_order": a.apply_order,
                            "precision": a.precision, "bytes_per_element": r["bytes_per_element"],
                            "parallelism": "single GPU"},
                 "roofline": {"bound": "hbm", "achieved": r["achieved_GBps"], "peak": HBM_PEAK_GBPS,

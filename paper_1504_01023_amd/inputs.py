@@ -67,6 +67,35 @@ def _soa(nodes: np.ndarray, conn: np.ndarray) -> np.ndarray:
     return out
 
 
+def _morton_keys(points: np.ndarray, bits: int = 10) -> np.ndarray:
+    """Z-order (Morton) keys of points quantised to 2^bits cells per axis of
+    their bounding box."""
+    lo = points.min(axis=0)
+    span = np.maximum(points.max(axis=0) - lo, 1e-300)
+    q = np.minimum(((points - lo) / span * (1 << bits)).astype(np.int64), (1 << bits) - 1)
+    key = np.zeros(points.shape[0], dtype=np.int64)
+    for b in range(bits):
+        for d in range(3):
+            key |= ((q[:, d] >> b) & 1) << (3 * b + d)
+    return key
+
+
+def morton_order(mesh: Mesh) -> tuple[Mesh, np.ndarray]:
+    """The same mesh with nodes renumbered and elements reordered along a
+    Z-order curve (nodes by position, elements by centroid), so that elements
+    close in the element order touch nodes close in memory. Returns the new
+    mesh and the element permutation (new element i is old element perm[i])
+    for reordering per-element data."""
+    node_perm = np.argsort(_morton_keys(mesh.nodes), kind="stable")
+    new_id = np.empty_like(node_perm)
+    new_id[node_perm] = np.arange(node_perm.size)
+    nodes = np.ascontiguousarray(mesh.nodes[node_perm])
+    conn = new_id[mesh.conn]
+    perm = np.argsort(_morton_keys(nodes[conn].mean(axis=1)), kind="stable")
+    conn = np.ascontiguousarray(conn[perm])
+    return Mesh(mesh.elem, _soa(nodes, conn), nodes, conn, mesh.boundary[node_perm]), perm
+
+
 def tet_cube(N: int, seed: int | np.random.Generator, jitter: float = 0.1) -> Mesh:
     """Unit cube as N^3 cells, each split into 6 Kuhn tetrahedra (6 N^3 elements).
 
@@ -506,6 +535,19 @@ def prism_vector(n: int, L: int, seed: int = 7, sliver: bool = True) -> Workload
     coeffs = vector_per_element(mesh.n_elem, rng)
     return Workload("prism_vector", "prism6", "vector", 6, "element", ALL_VECTOR_MASK,
                     np.zeros(N_SCALAR_SLOTS), "full", mesh, coeffs)
+
+
+def reordered(wl: Workload, order: str = "morton") -> Workload:
+    """A workload on the Z-order renumbered mesh, per-element or per-point
+    coefficients permuted with the elements."""
+    if order != "morton":
+        return wl
+    mesh, perm = morton_order(wl.mesh)
+    coeffs = wl.coeffs
+    if coeffs is not None and wl.coef_mode in ("element", "qp"):
+        coeffs = np.ascontiguousarray(coeffs[:, perm])
+    return Workload(wl.name, wl.elem, wl.kind, wl.n_q, wl.coef_mode, wl.mask, wl.uniform,
+                    wl.k_format, mesh, coeffs)
 
 
 N_FN_PARAMS = 122

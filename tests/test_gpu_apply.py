@@ -14,7 +14,7 @@ torch = pytest.importorskip("torch")
 # rounding of the assembled sums, relative to |A| |x| row by row
 TOL = {"fp64": 1e-12, "fp32": 2e-5}
 CASES = ["tet_poisson", "tet_poisson_qp", "tet_cdr", "tet_cdr_fn", "tet_elasticity", "prism_cdr_qp",
-         "prism_cdr", "prism_cdr_fn"]
+         "prism_cdr", "prism_cdr_fn", "tet_cdr_morton", "prism_cdr_qp_morton"]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -26,7 +26,10 @@ def _device():
 
 
 def _setup(name, precision):
-    wl = P.small(name)
+    if name.endswith("_morton"):
+        wl = inputs.reordered(P.small(name[: -len("_morton")]))
+    else:
+        wl = P.small(name)
     perm, ptr = fe.color_elements(wl.elem, wl.mesh.conn, wl.mesh.nodes.shape[0])
     dw = fe.to_device(wl, precision)
     conn = torch.from_numpy(np.ascontiguousarray(wl.mesh.conn[perm].T.astype(np.int32))).cuda()

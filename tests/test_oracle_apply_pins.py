@@ -101,3 +101,23 @@ def test_elasticity_rigid_modes_in_the_kernel():
         y, _ = _apply(wl.mesh, "elasticity", rule, "element", inputs.ALL_ELAST_MASK, None,
                       wl.coeffs, u.ravel())
         assert np.abs(y).max() < 1e-11 * np.abs(wl.coeffs[0]).max()
+
+
+def test_reordering_leaves_the_operator_unchanged():
+    # Z-order renumbering of nodes and elements is a relabelling: the
+    # assembled operator applied to the relabelled vector is the relabelled
+    # result, and every element matrix is bit-identical
+    wl = inputs.tet_cdr(3, seed=12)
+    mesh, perm = inputs.morton_order(wl.mesh)
+    wr = inputs.reordered(wl)
+    rule = oracle.quad_rule("tet4", 4)
+    x = np.random.default_rng(13).standard_normal(wl.mesh.nodes.shape[0])
+    y, _ = _apply(wl.mesh, "scalar", rule, "element", inputs.ALL_SCALAR_MASK, None, wl.coeffs, x)
+    # node i of the new numbering is old node node_perm[i]
+    node_perm = np.array([np.nonzero((wl.mesh.nodes == p).all(axis=1))[0][0] for p in mesh.nodes])
+    yr, _ = _apply(wr.mesh, "scalar", rule, "element", inputs.ALL_SCALAR_MASK, None, wr.coeffs,
+                   x[node_perm])
+    np.testing.assert_allclose(yr, y[node_perm], rtol=0, atol=1e-13 * np.abs(y).max())
+    K0, _ = oracle.integrate_workload(wl)
+    K1, _ = oracle.integrate_workload(wr)
+    assert np.array_equal(K1, K0[perm])

@@ -269,6 +269,15 @@ FE_API int fe_color_elements(fe_elem_type elem_type, int64_t n_elem, const int32
                              int64_t ld_conn, int64_t n_nodes, int32_t *perm, int64_t *color_ptr,
                              int32_t max_colors);
 
+/* Diagnostic for the signed-determinant convention (det J is used as it
+ * is; inverted elements are integrated as written): adds to *count (device
+ * int64, zero it first) the number of elements whose det J is not positive
+ * at some point of the rule (at the one constant value for tetrahedra).
+ * Coordinates as for fe_integrate_ex. Enqueued on `stream`. */
+FE_API int fe_count_inverted(fe_elem_type elem_type, int64_t n_elem, const double *coords,
+                             int64_t ld_in, const fe_quad_rule *quad_rule, int64_t *count,
+                             hipStream_t stream);
+
 /* ---------------------------------------------------------------------
  * Sizes and accounting (Sec. 4.1, table "memory_requirements"; Sec. 4.4,
  * table "accesses_and_operations"). Each returns -1 on invalid input.

@@ -198,3 +198,28 @@ def apply_assembled(elem: str, kind: str, nodes, conn, rule, coef_mode: str = "u
     np.add.at(y, dof.ravel(), ye.ravel())
     np.add.at(b, dof.ravel(), F.ravel())
     return y, b
+
+
+def jacobian_dets(elem: str, coords, rule):
+    """det J of the reference-to-physical map at every rule point, (n, n_q).
+
+    J_ik = sum_r X_{r,i} dphi_r/dxi_k (Sec. 2.2, the change of variables of
+    the reference element); the determinant is numpy's."""
+    coords = np.asarray(coords, dtype=np.float64)
+    nv = 4 if elem == "tet4" else 6
+    n = coords.shape[1]
+    X = coords.reshape(nv, 3, n).transpose(2, 0, 1)          # (n, vertex, i)
+    xi = np.asarray(rule[0], dtype=np.float64).reshape(-1, 3)
+    dets = np.empty((n, xi.shape[0]))
+    for q in range(xi.shape[0]):
+        _, dphi = shape(elem, xi[q])
+        J = np.einsum("eri,rk->eik", X, dphi)
+        dets[:, q] = np.linalg.det(J)
+    return dets
+
+
+def count_inverted(elem: str, coords, rule) -> int:
+    """Number of elements whose det J is not positive at some rule point
+    (the signed-determinant convention integrates them as written)."""
+    d = jacobian_dets(elem, coords, rule)
+    return int(np.count_nonzero((~(d > 0.0)).any(axis=1)))

@@ -210,7 +210,7 @@ static int check_symmetry(const fe_problem *p)
     return FE_OK;
 }
 
-static int check_rule(const fe_quad_rule *r)
+int check_rule(const fe_quad_rule *r)
 {
     if (!r)
         return fail(FE_ERR_INVALID_ARG, "quad_rule is NULL");

@@ -27,6 +27,8 @@ int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coor
          const int32_t *conn = nullptr, int64_t ld_conn = 0);
 int launch(const Plan &pl, hipStream_t stream);
 void fill_reference(int elem, const fe_quad_rule &rule, KArgs &a);
+// NULL rule, point count outside 1..FE_MAX_QP, non-finite points or weights
+int check_rule(const fe_quad_rule *r);
 
 // Tuning table: variant per (kernel family, point count).
 int tuning_lookup(const KernelKey &family, int n_q, fe_variant &out);

@@ -105,6 +105,7 @@ def lib():
                                        ctypes.POINTER(ctypes.c_int64), i32, vp]
         L.fe_color_elements.argtypes = [i32, i64, vp, i64, i64, vp, vp, i32]
         L.fe_integrate_natural.argtypes = [P, i32, i64, vp, vp, R, vp, vp, vp]
+        L.fe_count_inverted.argtypes = [i32, i64, vp, i64, R, vp, vp]
         _lib = L
     return _lib
 
@@ -384,6 +385,27 @@ def apply_indexed(p: Problem, elem, nodes, conn, coeffs, rule: Rule, x, y=None, 
                                   ctypes.c_void_p(b.data_ptr()) if b is not None else None,
                                   cp, ncol, _stream_handle(stream)))
     return y, b
+
+
+def count_inverted(elem, coords, rule: Rule, n_elem: int | None = None, count=None,
+                   stream=None):
+    """Enqueue the count of elements whose det J is not positive at some rule
+    point. coords: (3 n_vert, ld) FP64 device tensor. Adds to ``count`` (a
+    one-element int64 device tensor, zeroed here when not given) and returns
+    it."""
+    import torch
+    e = ELEM.get(elem, elem)
+    ld_in = coords.shape[1]
+    n = ld_in if n_elem is None else int(n_elem)
+    _check_tensor(coords, "coords", torch.float64, 3 * (4 if e == TET4 else 6), ld_in)
+    if count is None:
+        count = torch.zeros(1, dtype=torch.int64, device=coords.device)
+    if not (count.is_cuda and count.dtype == torch.int64 and count.numel() == 1):
+        raise ValueError("count must be a one-element int64 GPU tensor")
+    _check(lib().fe_count_inverted(e, n, ctypes.c_void_p(coords.data_ptr()), ld_in,
+                                   ctypes.byref(rule.c), ctypes.c_void_p(count.data_ptr()),
+                                   _stream_handle(stream)))
+    return count
 
 
 def autotune(p: Problem, elem, coords, coeffs, rule: Rule, out_K, out_F, reps: int = 5,

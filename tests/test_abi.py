@@ -293,3 +293,24 @@ def test_apply_validation_before_launch():
     assert _apply_call(v, coeffs=0x8000) == 2                     # no matrix-free form
     e = fe.problem("elasticity", "fp64", "uniform", 0, [1.0, 0.3, 0, 0, 0], "packed")
     assert _apply_call(e, y=0x6004) == 2                          # misaligned y
+
+
+def test_count_inverted_validation_before_launch():
+    L = fe.lib()
+    r = fe.builtin_rule("prism6", 6)
+    vp = ctypes.c_void_p
+    call = lambda elem=1, n=10, coords=0x4000, ld=16, rule=r, count=0x8000: \
+        L.fe_count_inverted(elem, n, vp(coords) if coords else None, ld,
+                            ctypes.byref(rule.c) if rule is not None else None,
+                            vp(count) if count else None, None)
+    assert call(elem=3) == 1
+    assert call(n=-1) == 1
+    assert call(coords=0) == 1
+    assert call(count=0) == 1
+    assert call(ld=9) == 1
+    assert call(rule=None) == 1
+    assert call(rule=fe.Rule(np.zeros((9, 3)), np.ones(9))) == 2
+    assert call(rule=fe.Rule(np.full((1, 3), np.inf), [1.0])) == 1
+    assert call(coords=0x4004) == 2
+    # nothing to count: no pointer is touched
+    assert call(n=0, coords=0, count=0) == 0

@@ -269,6 +269,43 @@ FE_API int fe_color_elements(fe_elem_type elem_type, int64_t n_elem, const int32
                              int64_t ld_conn, int64_t n_nodes, int32_t *perm, int64_t *color_ptr,
                              int32_t max_colors);
 
+/* Sparsity pattern of the assembled matrix (Sec. 3.2: the global matrix is
+ * the sum of the element matrices at their nodes), built on the host. conn
+ * is host memory as for fe_color_elements. Row R = n_comp * node +
+ * component (n_comp 1 or 3); a node's rows hold every component of every
+ * node that shares an element with it (itself included), columns
+ * ascending, and the rows of one node's components have the same columns.
+ * Writes row_ptr[0 .. n_nodes * n_comp] (host) and, when col_idx is not
+ * NULL, col_idx[0 .. nnz) (host, int32). Returns nnz, or minus a status:
+ * FE_ERR_CAPACITY when col_idx is given and nnz > max_nnz,
+ * FE_ERR_INVALID_ARG for bad arguments or node ids outside [0, n_nodes).
+ * Call once with col_idx = NULL to learn nnz. */
+FE_API int64_t fe_csr_pattern(fe_elem_type elem_type, int64_t n_elem, const int32_t *conn,
+                              int64_t ld_conn, int64_t n_nodes, int32_t n_comp, int64_t *row_ptr,
+                              int32_t *col_idx, int64_t max_nnz);
+
+/* Assembly of the global matrix and load vector into CSR storage, with the
+ * element matrices computed in registers and never stored (Sec. 3.1, 3.2):
+ *   values[p] += K^e_rs for every element e and local dofs r, s whose
+ *                global row and column meet at entry p,
+ *   b[i]      += F^e_r at the element's dofs          (when b is not NULL).
+ * Inputs as for fe_apply_indexed. row_ptr (n_nodes * n_comp + 1 values,
+ * int64), col_idx (nnz, int32), values (nnz) and b (n_nodes * n_comp): device
+ * memory; row_ptr and col_idx as fe_csr_pattern writes them (a pattern with
+ * fewer entries drops the missing couplings; reads and writes stay inside
+ * [0, nnz)). values and b are in the precision of the tier and are
+ * accumulated into (zero them first). A packed symmetric K is added to both
+ * triangles. Colouring as for fe_apply_indexed: per colour, plain
+ * read-add-write (deterministic); n_colors = 0, hardware atomic adds. Built
+ * for the problems fe_apply_indexed supports; others return
+ * FE_ERR_UNSUPPORTED. Enqueued on `stream`; no allocation. */
+FE_API int fe_assemble_csr(const fe_problem *problem, fe_elem_type elem_type, int64_t n_elem,
+                           const double *nodes, int64_t n_nodes, const int32_t *conn,
+                           int64_t ld_conn, const void *coeffs, int64_t ld_in,
+                           const fe_quad_rule *quad_rule, const int64_t *row_ptr,
+                           const int32_t *col_idx, int64_t nnz, void *values, void *b,
+                           const int64_t *color_ptr, int32_t n_colors, hipStream_t stream);
+
 /* Diagnostic for the signed-determinant convention (det J is used as it
  * is; inverted elements are integrated as written): adds to *count (device
  * int64, zero it first) the number of elements whose det J is not positive

@@ -5,8 +5,11 @@ benchmark's CPU-baseline leg import this package. It never touches the GPU and
 shares nothing with the GPU library; the inputs it is given come from the
 seeded generators.
 
-Every function here marshals arguments only; the arithmetic is in
-fe_oracle.c (Algorithm 1 of the paper, written out plainly).
+The element integrals are in fe_oracle.c (Algorithm 1 of the paper, written
+out plainly); the functions here marshal their arguments. Two small pieces
+are plain NumPy beside it: the scatter of element matrices into the
+assembled operator (apply_assembled, assemble_dense) and det J at the rule points
+(jacobian_dets, count_inverted).
 """
 from __future__ import annotations
 
@@ -198,6 +201,31 @@ def apply_assembled(elem: str, kind: str, nodes, conn, rule, coef_mode: str = "u
     np.add.at(y, dof.ravel(), ye.ravel())
     np.add.at(b, dof.ravel(), F.ravel())
     return y, b
+
+
+def assemble_dense(elem: str, kind: str, nodes, conn, rule, coef_mode: str = "uniform",
+                   mask: int = 0, uniform=None, coeffs=None, threads: int = 1):
+    """The assembled global matrix and load vector, dense (small meshes
+    only), from the element matrices (Sec. 3.2: the sum of the element
+    contributions at their nodes):
+
+        A = sum_e P_e^T K^e P_e,    b = sum_e P_e^T F^e
+
+    with unknowns node-major (node * n_comp + component); the scatter is
+    numpy's add.at. Returns (A (n_dof, n_dof), b (n_dof,)), float64."""
+    nodes = np.asarray(nodes, dtype=np.float64)
+    conn = np.asarray(conn, dtype=np.int64)
+    n, nv = conn.shape
+    nc = 1 if kind == "scalar" else 3
+    coords = np.ascontiguousarray(nodes[conn].transpose(1, 2, 0).reshape(nv * 3, n))
+    K, F = integrate(elem, kind, coords, rule, coef_mode, mask, uniform, coeffs, threads)
+    dof = (conn[:, :, None] * nc + np.arange(nc)[None, None, :]).reshape(n, nv * nc)
+    nd = nodes.shape[0] * nc
+    A = np.zeros((nd, nd))
+    b = np.zeros(nd)
+    np.add.at(A, (dof[:, :, None], dof[:, None, :]), K)
+    np.add.at(b, dof, F)
+    return A, b
 
 
 def jacobian_dets(elem: str, coords, rule):

@@ -508,18 +508,22 @@ int fe_integrate_indexed(const fe_problem *problem, fe_elem_type elem_type, int6
     return launch_indexed(pl, gi, stream);
 }
 
-int fe_apply_indexed(const fe_problem *problem, fe_elem_type elem_type, int64_t n_elem,
-                     const double *nodes, int64_t n_nodes, const int32_t *conn, int64_t ld_conn,
-                     const void *coeffs, int64_t ld_in, const fe_quad_rule *quad_rule,
-                     const void *x, void *y, void *b, const int64_t *color_ptr, int32_t n_colors,
-                     hipStream_t stream)
+// The consumers of indexed geometry that never store K: the matrix-free
+// application (ap.x, ap.y) and the assembly into a CSR matrix (ap.vals).
+// With colours, one launch per colour with plain read-add-write; without,
+// one launch with atomic adds.
+static int indexed_consumer(const fe_problem *problem, fe_elem_type elem_type, int64_t n_elem,
+                            const double *nodes, int64_t n_nodes, const int32_t *conn,
+                            int64_t ld_conn, const void *coeffs, int64_t ld_in,
+                            const fe_quad_rule *quad_rule, const ApplyArgs &ap, bool csr,
+                            const int64_t *color_ptr, int32_t n_colors, hipStream_t stream)
 {
+    const void *x = ap.x;
+    void *y = ap.y, *b = ap.b;
     if (n_elem > 0 && (!nodes || n_nodes < 1 || n_nodes > 0x7fffffffLL))
         return fail(FE_ERR_INVALID_ARG, "need a node array with 1 .. 2^31-1 nodes");
     if (nodes && ((uintptr_t)nodes % 8))
         return fail(FE_ERR_UNSUPPORTED, "nodes must be 8-byte aligned");
-    if (n_elem > 0 && (!x || !y))
-        return fail(FE_ERR_INVALID_ARG, "x and y must not be NULL");
     if (n_colors < 0 || (n_colors > 0 && !color_ptr))
         return fail(FE_ERR_INVALID_ARG, "n_colors must be >= 0, with color_ptr for n_colors > 0");
     if (n_colors > 0) {
@@ -537,14 +541,14 @@ int fe_apply_indexed(const fe_problem *problem, fe_elem_type elem_type, int64_t 
     if (st)
         return st;
     if (!pl.entry->apply)
-        return fail(FE_ERR_UNSUPPORTED, "no matrix-free form for this problem");
+        return fail(FE_ERR_UNSUPPORTED, csr ? "no assembly form for this problem"
+                                                : "no matrix-free form for this problem");
     const size_t tsz = problem->precision == FE_FP64 ? 8 : 4;
-    if (!aligned(x, tsz) || !aligned(y, tsz) || !aligned(b, tsz))
-        return fail(FE_ERR_UNSUPPORTED, "x, y and b must be aligned to their element size");
+    if (!aligned(x, tsz) || !aligned(y, tsz) || !aligned(b, tsz) || !aligned(ap.vals, tsz))
+        return fail(FE_ERR_UNSUPPORTED, "nodal vectors and values must be aligned to their element size");
     if (n_elem == 0)
         return FE_OK;
     const bool fn = problem->coef_mode == FE_COEF_FUNCTION;
-    const ApplyArgs ap{x, y, b};
     auto run = [&](int64_t e0, int64_t cnt, int atomic) -> int {
         if (cnt == 0)
             return FE_OK;
@@ -568,6 +572,44 @@ int fe_apply_indexed(const fe_problem *problem, fe_elem_type elem_type, int64_t 
         if ((st = run(color_ptr[c], color_ptr[c + 1] - color_ptr[c], 0)))
             return st;
     return FE_OK;
+}
+
+int fe_apply_indexed(const fe_problem *problem, fe_elem_type elem_type, int64_t n_elem,
+                     const double *nodes, int64_t n_nodes, const int32_t *conn, int64_t ld_conn,
+                     const void *coeffs, int64_t ld_in, const fe_quad_rule *quad_rule,
+                     const void *x, void *y, void *b, const int64_t *color_ptr, int32_t n_colors,
+                     hipStream_t stream)
+{
+    if (n_elem > 0 && (!x || !y))
+        return fail(FE_ERR_INVALID_ARG, "x and y must not be NULL");
+    ApplyArgs ap{};
+    ap.x = x;
+    ap.y = y;
+    ap.b = b;
+    return indexed_consumer(problem, elem_type, n_elem, nodes, n_nodes, conn, ld_conn, coeffs,
+                            ld_in, quad_rule, ap, false, color_ptr, n_colors, stream);
+}
+
+int fe_assemble_csr(const fe_problem *problem, fe_elem_type elem_type, int64_t n_elem,
+                    const double *nodes, int64_t n_nodes, const int32_t *conn, int64_t ld_conn,
+                    const void *coeffs, int64_t ld_in, const fe_quad_rule *quad_rule,
+                    const int64_t *row_ptr, const int32_t *col_idx, int64_t nnz, void *values,
+                    void *b, const int64_t *color_ptr, int32_t n_colors, hipStream_t stream)
+{
+    if (n_elem > 0 && (!row_ptr || !col_idx || !values))
+        return fail(FE_ERR_INVALID_ARG, "row_ptr, col_idx and values must not be NULL");
+    if (nnz < 0 || nnz > 0x7fffffffffffLL)
+        return fail(FE_ERR_INVALID_ARG, "nnz out of range");
+    if (!aligned(row_ptr, 8) || !aligned(col_idx, 4))
+        return fail(FE_ERR_UNSUPPORTED, "row_ptr and col_idx must be aligned to their element size");
+    ApplyArgs ap{};
+    ap.b = b;
+    ap.row_ptr = row_ptr;
+    ap.col_idx = col_idx;
+    ap.nnz = nnz;
+    ap.vals = values;  // non-null whenever a kernel is launched: selects the assembly form
+    return indexed_consumer(problem, elem_type, n_elem, nodes, n_nodes, conn, ld_conn, coeffs,
+                            ld_in, quad_rule, ap, true, color_ptr, n_colors, stream);
 }
 
 int fe_integrate_natural(const fe_problem *problem, fe_elem_type elem_type, int64_t n_elem,
@@ -667,6 +709,83 @@ int fe_color_elements(fe_elem_type elem_type, int64_t n_elem, const int32_t *con
     for (int64_t e = 0; e < n_elem; ++e)
         perm[count[color[e]]++] = (int32_t)e;
     return n_colors;
+}
+
+int64_t fe_csr_pattern(fe_elem_type elem_type, int64_t n_elem, const int32_t *conn,
+                       int64_t ld_conn, int64_t n_nodes, int32_t n_comp, int64_t *row_ptr,
+                       int32_t *col_idx, int64_t max_nnz)
+{
+    if (elem_type != FE_TET4 && elem_type != FE_PRISM6)
+        return -fail(FE_ERR_INVALID_ARG, "bad element type %d", elem_type);
+    if (n_comp != 1 && n_comp != 3)
+        return -fail(FE_ERR_INVALID_ARG, "n_comp must be 1 or 3");
+    if (n_elem < 0 || n_elem > 0x7fffffffLL || n_nodes < 1 ||
+        n_nodes * n_comp > 0x7fffffffLL || (n_elem > 0 && (!conn || ld_conn < n_elem)) ||
+        !row_ptr || max_nnz < 0)
+        return -fail(FE_ERR_INVALID_ARG, "bad pattern arguments");
+    const int nv = n_shape(elem_type);
+    // elements at each node
+    std::vector<int64_t> at((size_t)n_nodes + 1, 0);
+    for (int v = 0; v < nv; ++v)
+        for (int64_t e = 0; e < n_elem; ++e) {
+            const int32_t id = conn[v * ld_conn + e];
+            if (id < 0 || id >= n_nodes)
+                return -fail(FE_ERR_INVALID_ARG, "element %lld has node id %d outside [0, %lld)",
+                             (long long)e, id, (long long)n_nodes);
+            ++at[(size_t)id + 1];
+        }
+    for (int64_t i = 0; i < n_nodes; ++i)
+        at[i + 1] += at[i];
+    std::vector<int32_t> elems((size_t)at[n_nodes]);
+    {
+        std::vector<int64_t> fill(at.begin(), at.end() - 1);
+        for (int64_t e = 0; e < n_elem; ++e)
+            for (int v = 0; v < nv; ++v)
+                elems[fill[conn[v * ld_conn + e]]++] = (int32_t)e;
+    }
+    // node neighbours (the node itself included), ascending
+    std::vector<int64_t> nb_ptr((size_t)n_nodes + 1, 0);
+    std::vector<int32_t> nb;
+    std::vector<int32_t> mark((size_t)n_nodes, -1);
+    nb.reserve((size_t)at[n_nodes] * 2);
+    for (int64_t i = 0; i < n_nodes; ++i) {
+        const size_t first = nb.size();
+        for (int64_t k = at[i]; k < at[i + 1]; ++k)
+            for (int v = 0; v < nv; ++v) {
+                const int32_t j = conn[v * ld_conn + elems[k]];
+                if (mark[j] != (int32_t)i) {
+                    mark[j] = (int32_t)i;
+                    nb.push_back(j);
+                }
+            }
+        std::sort(nb.begin() + first, nb.end());
+        nb_ptr[i + 1] = (int64_t)nb.size();
+    }
+    // rows of the components of a node: the same columns, every component of
+    // every neighbour
+    const int64_t nc = n_comp;
+    int64_t nnz = 0;
+    row_ptr[0] = 0;
+    for (int64_t i = 0; i < n_nodes; ++i) {
+        const int64_t len = nc * (nb_ptr[i + 1] - nb_ptr[i]);
+        for (int64_t a = 0; a < nc; ++a) {
+            nnz += len;
+            row_ptr[nc * i + a + 1] = nnz;
+        }
+    }
+    if (!col_idx)
+        return nnz;
+    if (nnz > max_nnz)
+        return -fail(FE_ERR_CAPACITY, "the pattern has %lld entries; col_idx holds %lld",
+                     (long long)nnz, (long long)max_nnz);
+    for (int64_t i = 0; i < n_nodes; ++i)
+        for (int64_t a = 0; a < nc; ++a) {
+            int32_t *out = col_idx + row_ptr[nc * i + a];
+            for (int64_t k = nb_ptr[i]; k < nb_ptr[i + 1]; ++k)
+                for (int64_t b = 0; b < nc; ++b)
+                    *out++ = (int32_t)(nc * nb[k] + b);
+        }
+    return nnz;
 }
 
 int fe_integrate(const fe_problem *problem, fe_elem_type elem_type, int64_t n_elem,

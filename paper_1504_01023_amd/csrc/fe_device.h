@@ -345,6 +345,60 @@ struct ApplyBlock : ScalarBlock {
     }
 };
 
+// Assembly into a CSR matrix (one element per lane): each entry of K is added
+// to the global entry of its (row, column) as it is produced, and to the
+// mirrored entry for a packed symmetric K; F is added to b. The element
+// matrix is never stored. Element dof r = NC v + alpha sits in global row
+// NC id[v] + alpha; rp[v] is where row NC id[v] starts, len[v] its length
+// (the rows of a node's components have equal length and the same columns),
+// off[v][u] the position of column NC id[u] in it, or -1 when the pattern
+// lacks it (the entry is then dropped; nothing is written outside vals).
+template <typename T, bool ATOMIC>
+__device__ __forceinline__ void add_at(T *p, T v)
+{
+    if constexpr (ATOMIC)
+        unsafeAtomicAdd(p, v);
+    else
+        *p += v;
+}
+
+template <typename T, int NV, int NC, bool ATOMIC, bool WITH_B>
+struct CsrBlock : ScalarBlock {
+    T *vals;
+    T *b;  // used when WITH_B
+    int64_t nnz;
+    uint32_t id[NV];
+    int64_t rp[NV];
+    int32_t len[NV];
+    int32_t off[NV][NV];
+    __device__ __forceinline__ bool with_f() const { return WITH_B; }
+    __device__ __forceinline__ void add(int r, int s, T v) const
+    {
+        const int vr = r / NC, al = r % NC, vs = s / NC, be = s % NC;
+        const int o = off[vr][vs];
+        if (o < 0)
+            return;
+        const int64_t p = rp[vr] + (int64_t)al * len[vr] + o + be;
+        if (p < nnz)
+            add_at<T, ATOMIC>(vals + p, v);
+    }
+    template <int V, int NT, typename U>
+    __device__ __forceinline__ void put_k(const Streams &, int, int packed, int r, int s, int64_t,
+                                          const U (&val)[V]) const
+    {
+        static_assert(V == 1, "assembly is one element per lane");
+        add(r, s, val[0]);
+        if (packed && r != s)
+            add(s, r, val[0]);
+    }
+    template <int V, int NT, typename U>
+    __device__ __forceinline__ void put_f(const Streams &, int r, int64_t, const U (&val)[V]) const
+    {
+        if constexpr (WITH_B)
+            add_at<T, ATOMIC>(b + (int64_t)NC * id[r / NC] + r % NC, val[0]);
+    }
+};
+
 // Coefficient functions: slot k's value at the physical point x is
 // alpha_k + beta_k sin(2 pi (omega_k . x) + theta_k), parameters p[6k..6k+5]
 // (read with wave-uniform scalar loads); with p[121] != 0 the diffusion block
@@ -1841,6 +1895,38 @@ __global__ __launch_bounds__(256) void fe_kernel_idx(KArgs a, IdxArgs gi)
     }
 }
 
+// Vertex ids (clamped into the node array: never a fault) and coordinates
+// of element e.
+template <int NV, int NT>
+__device__ __forceinline__ void gather_vertices(const IdxArgs &gi, int64_t e, uint32_t (&id)[NV],
+                                                double (&X)[3 * NV])
+{
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const uint32_t u = (uint32_t)ld1<NT>(gi.conn + v * gi.ld_conn + e);
+        id[v] = u < gi.n_nodes ? u : gi.n_nodes - 1;
+        const double *pn = gi.nodes + 3 * (int64_t)id[v];
+        X[3 * v + 0] = pn[0];
+        X[3 * v + 1] = pn[1];
+        X[3 * v + 2] = pn[2];
+    }
+}
+
+template <int REF>
+__device__ __forceinline__ void stage_reference(const KArgs &a, RefLds &lds)
+{
+    if constexpr (REF == REF_LDS) {
+        const int n_w = a.n_q, n_phi = a.n_q * 6, n_dphi = a.n_q * 18;
+        for (int i = threadIdx.x; i < n_w; i += blockDim.x)
+            lds.w[i] = a.w[i];
+        for (int i = threadIdx.x; i < n_phi; i += blockDim.x)
+            (&lds.phi[0][0])[i] = (&a.phi[0][0])[i];
+        for (int i = threadIdx.x; i < n_dphi; i += blockDim.x)
+            (&lds.dphi[0][0][0])[i] = (&a.dphi[0][0][0])[i];
+        __syncthreads();
+    }
+}
+
 // Matrix-free application of the assembled operator (indexed geometry, one
 // element per lane): gather the vertex ids, coordinates and nodal values x,
 // compute the element's K (and F) exactly as the storing kernels do but
@@ -1848,29 +1934,11 @@ __global__ __launch_bounds__(256) void fe_kernel_idx(KArgs a, IdxArgs gi)
 // to y (and b) at its nodes. ATOMIC: hardware atomic adds, any element
 // order; otherwise plain read-add-write, for launches over one colour of
 // elements that share no node.
-template <typename T, bool ATOMIC>
-__device__ __forceinline__ void add_at(T *p, T v)
-{
-    if constexpr (ATOMIC)
-        unsafeAtomicAdd(p, v);
-    else
-        *p += v;
-}
-
 template <class P, int NV, int NC, typename T, int NT, int REF, bool ATOMIC, bool WITH_B>
 __global__ __launch_bounds__(256) void fe_apply_kernel(KArgs a, IdxArgs gi, ApplyArgs ap)
 {
     __shared__ RefLds lds_ref[1];
-    if constexpr (REF == REF_LDS) {
-        const int n_w = a.n_q, n_phi = a.n_q * 6, n_dphi = a.n_q * 18;
-        for (int i = threadIdx.x; i < n_w; i += blockDim.x)
-            lds_ref[0].w[i] = a.w[i];
-        for (int i = threadIdx.x; i < n_phi; i += blockDim.x)
-            (&lds_ref[0].phi[0][0])[i] = (&a.phi[0][0])[i];
-        for (int i = threadIdx.x; i < n_dphi; i += blockDim.x)
-            (&lds_ref[0].dphi[0][0][0])[i] = (&a.dphi[0][0][0])[i];
-        __syncthreads();
-    }
+    stage_reference<REF>(a, lds_ref[0]);
     const Ref<REF> ref{a, &lds_ref[0]};
     const Streams st{nullptr, a.coeffs, nullptr, nullptr, a.ld_in, a.ld_out};
     const T *x = static_cast<const T *>(ap.x);
@@ -1881,15 +1949,7 @@ __global__ __launch_bounds__(256) void fe_apply_kernel(KArgs a, IdxArgs gi, Appl
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < a.n_elem; e += stride) {
         uint32_t id[NV];
         double X[3 * NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const uint32_t u = (uint32_t)ld1<NT>(gi.conn + v * gi.ld_conn + e);
-            id[v] = u < gi.n_nodes ? u : gi.n_nodes - 1;  // clamped: never a fault
-            const double *pn = gi.nodes + 3 * (int64_t)id[v];
-            X[3 * v + 0] = pn[0];
-            X[3 * v + 1] = pn[1];
-            X[3 * v + 2] = pn[2];
-        }
+        gather_vertices<NV, NT>(gi, e, id, X);
         T xe[N], ye[N], be[N];
 #pragma unroll
         for (int v = 0; v < NV; ++v)
@@ -1915,10 +1975,70 @@ __global__ __launch_bounds__(256) void fe_apply_kernel(KArgs a, IdxArgs gi, Appl
     }
 }
 
+// Assembly into a CSR matrix (indexed geometry, one element per lane):
+// gather the element as the matrix-free kernel does, find where its
+// couplings sit in the rows of its nodes (one pass over each row's
+// columns), then compute K (and F) and add every entry there (CsrBlock).
+// ATOMIC as for the matrix-free kernel.
+template <class P, int NV, int NC, typename T, int NT, int REF, bool ATOMIC, bool WITH_B>
+__global__ __launch_bounds__(256) void fe_csr_kernel(KArgs a, IdxArgs gi, ApplyArgs ap)
+{
+    __shared__ RefLds lds_ref[1];
+    stage_reference<REF>(a, lds_ref[0]);
+    const Ref<REF> ref{a, &lds_ref[0]};
+    const Streams st{nullptr, a.coeffs, nullptr, nullptr, a.ld_in, a.ld_out};
+    const int64_t nnz = ap.nnz;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < a.n_elem; e += stride) {
+        CsrBlock<T, NV, NC, ATOMIC, WITH_B> bl;
+        bl.vals = static_cast<T *>(ap.vals);
+        bl.b = static_cast<T *>(ap.b);
+        bl.nnz = nnz;
+        double X[3 * NV];
+        gather_vertices<NV, NT>(gi, e, bl.id, X);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            // row bounds clamped into [0, nnz]: never a fault
+            const int64_t row = (int64_t)NC * bl.id[v];
+            int64_t r0 = ap.row_ptr[row], r1 = ap.row_ptr[row + 1];
+            r0 = r0 < 0 ? 0 : (r0 > nnz ? nnz : r0);
+            r1 = r1 < r0 ? r0 : (r1 > nnz ? nnz : r1);
+            bl.rp[v] = r0;
+            bl.len[v] = (int32_t)(r1 - r0);
+#pragma unroll
+            for (int u = 0; u < NV; ++u)
+                bl.off[v][u] = -1;
+            for (int64_t j = r0; j < r1; j += NC) {
+                const int32_t c = ap.col_idx[j];
+#pragma unroll
+                for (int u = 0; u < NV; ++u)
+                    if (c == (int32_t)(NC * bl.id[u]))
+                        bl.off[v][u] = (int32_t)(j - r0);
+            }
+        }
+        P::template apply_x<NT, REF>(a, st, ref, X, e, bl);
+    }
+}
+
 template <class P, int NV, int NC, typename T, int NT, int REF>
 void launch_fe_apply(const KArgs &a, const IdxArgs &gi, const ApplyArgs &ap, int atomic,
                      unsigned grid, unsigned block, hipStream_t stream)
 {
+    if (ap.vals) {
+        if (atomic && ap.b)
+            hipLaunchKernelGGL((fe_csr_kernel<P, NV, NC, T, NT, REF, true, true>), dim3(grid),
+                               dim3(block), 0, stream, a, gi, ap);
+        else if (atomic)
+            hipLaunchKernelGGL((fe_csr_kernel<P, NV, NC, T, NT, REF, true, false>), dim3(grid),
+                               dim3(block), 0, stream, a, gi, ap);
+        else if (ap.b)
+            hipLaunchKernelGGL((fe_csr_kernel<P, NV, NC, T, NT, REF, false, true>), dim3(grid),
+                               dim3(block), 0, stream, a, gi, ap);
+        else
+            hipLaunchKernelGGL((fe_csr_kernel<P, NV, NC, T, NT, REF, false, false>), dim3(grid),
+                               dim3(block), 0, stream, a, gi, ap);
+        return;
+    }
     if (atomic && ap.b)
         hipLaunchKernelGGL((fe_apply_kernel<P, NV, NC, T, NT, REF, true, true>), dim3(grid), dim3(block),
                            0, stream, a, gi, ap);

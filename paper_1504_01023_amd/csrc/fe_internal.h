@@ -132,6 +132,14 @@ struct ApplyArgs {
     const void *x;  // read
     void *y;        // y += assembled K x
     void *b;        // b += assembled F, or nullptr
+    // Assembly into a CSR matrix instead (vals != nullptr; x and y unused):
+    // vals[row_ptr[R] .. row_ptr[R + 1]) hold row R's entries, columns
+    // col_idx[] ascending, each node's components in consecutive rows with
+    // the same columns (the pattern fe_csr_pattern builds).
+    const int64_t *row_ptr;
+    const int32_t *col_idx;
+    int64_t nnz;
+    void *vals;
 };
 typedef void (*ApplyLaunchFn)(const KArgs &, const IdxArgs &, const ApplyArgs &, int atomic,
                               unsigned grid, unsigned block, hipStream_t);

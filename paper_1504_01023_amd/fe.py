@@ -106,6 +106,10 @@ def lib():
         L.fe_color_elements.argtypes = [i32, i64, vp, i64, i64, vp, vp, i32]
         L.fe_integrate_natural.argtypes = [P, i32, i64, vp, vp, R, vp, vp, vp]
         L.fe_count_inverted.argtypes = [i32, i64, vp, i64, R, vp, vp]
+        L.fe_csr_pattern.argtypes = [i32, i64, vp, i64, i64, i32, vp, vp, i64]
+        L.fe_csr_pattern.restype = i64
+        L.fe_assemble_csr.argtypes = [P, i32, i64, vp, i64, vp, i64, vp, i64, R, vp, vp, i64, vp,
+                                      vp, ctypes.POINTER(ctypes.c_int64), i32, vp]
         _lib = L
     return _lib
 
@@ -385,6 +389,81 @@ def apply_indexed(p: Problem, elem, nodes, conn, coeffs, rule: Rule, x, y=None, 
                                   ctypes.c_void_p(b.data_ptr()) if b is not None else None,
                                   cp, ncol, _stream_handle(stream)))
     return y, b
+
+
+def csr_pattern(elem, conn, n_nodes: int, n_comp: int = 1):
+    """Sparsity pattern of the assembled matrix, built on the host. conn:
+    (n_elem, n_vert) integer array of node ids. Returns (row_ptr int64
+    (n_nodes * n_comp + 1,), col_idx int32 (nnz,)) numpy arrays."""
+    e = ELEM.get(elem, elem)
+    c = np.ascontiguousarray(np.asarray(conn).T.astype(np.int32))
+    n = c.shape[1]
+    row_ptr = np.empty(int(n_nodes) * n_comp + 1, dtype=np.int64)
+    args = (e, n, c.ctypes.data_as(ctypes.c_void_p), n, int(n_nodes), int(n_comp),
+            row_ptr.ctypes.data_as(ctypes.c_void_p))
+    nnz = lib().fe_csr_pattern(*args, None, 0)
+    if nnz < 0:
+        _check(-nnz)
+    col_idx = np.empty(nnz, dtype=np.int32)
+    got = lib().fe_csr_pattern(*args, col_idx.ctypes.data_as(ctypes.c_void_p), nnz)
+    if got < 0:
+        _check(-got)
+    return row_ptr, col_idx
+
+
+def assemble_csr(p: Problem, elem, nodes, conn, coeffs, rule: Rule, row_ptr, col_idx,
+                 values=None, b=None, color_ptr=None, n_elem: int | None = None, stream=None,
+                 with_b: bool = False):
+    """Assemble the global matrix into CSR values (values += sum of the
+    element matrices at their couplings) and, when b is given or with_b,
+    the load vector. row_ptr (int64) and col_idx (int32) are device tensors
+    of the pattern csr_pattern builds; values (nnz,) and b (n_nodes *
+    components,) device vectors in the tier's precision, zeroed here when not
+    given. color_ptr as for apply_indexed. Returns (values, b)."""
+    import torch
+    e = ELEM.get(elem, elem)
+    nv = 4 if e == TET4 else 6
+    ld_conn = conn.shape[1]
+    n = ld_conn if n_elem is None else int(n_elem)
+    dt = _dtype(p)
+    ncomp = 1 if p.kind == SCALAR_CDR else 3
+    ndof = nodes.shape[0] * ncomp
+    if not (nodes.is_cuda and nodes.dtype == torch.float64 and nodes.is_contiguous()
+            and nodes.dim() == 2 and nodes.shape[1] == 3):
+        raise ValueError("nodes must be a contiguous (n_nodes, 3) float64 GPU tensor")
+    _check_tensor(conn, "conn", torch.int32, nv, ld_conn)
+    if not (row_ptr.is_cuda and row_ptr.dtype == torch.int64 and row_ptr.is_contiguous()
+            and row_ptr.numel() == ndof + 1):
+        raise ValueError(f"row_ptr must be a contiguous int64 GPU vector of {ndof + 1} values")
+    if not (col_idx.is_cuda and col_idx.dtype == torch.int32 and col_idx.is_contiguous()):
+        raise ValueError("col_idx must be a contiguous int32 GPU vector")
+    nnz = col_idx.numel()
+    if values is None:
+        values = torch.zeros(nnz, dtype=dt, device=nodes.device)
+    if b is None and with_b:
+        b = torch.zeros(ndof, dtype=dt, device=nodes.device)
+    for name, t, size in (("values", values, nnz), ("b", b, ndof)):
+        if t is not None and not (t.is_cuda and t.dtype == dt and t.is_contiguous()
+                                  and t.numel() == size):
+            raise ValueError(f"{name} must be a contiguous {dt} GPU vector of {size} values")
+    nc = coeff_entries(p, e, rule.n_q)
+    ld_in = coeffs.shape[1] if (coeffs is not None and nc > 0 and coeffs.dim() == 2) else n
+    if nc > 0:
+        _check_coeffs(p, coeffs, dt, nc, ld_in)
+    cptr = ctypes.c_void_p(coeffs.data_ptr()) if (coeffs is not None and nc > 0) else None
+    if color_ptr is None:
+        cp, ncol = None, 0
+    else:
+        cpa = np.ascontiguousarray(color_ptr, dtype=np.int64)
+        cp, ncol = cpa.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(cpa) - 1
+    _check(lib().fe_assemble_csr(ctypes.byref(p), e, n, ctypes.c_void_p(nodes.data_ptr()),
+                                 nodes.shape[0], ctypes.c_void_p(conn.data_ptr()), ld_conn, cptr,
+                                 ld_in, ctypes.byref(rule.c), ctypes.c_void_p(row_ptr.data_ptr()),
+                                 ctypes.c_void_p(col_idx.data_ptr()), nnz,
+                                 ctypes.c_void_p(values.data_ptr()),
+                                 ctypes.c_void_p(b.data_ptr()) if b is not None else None,
+                                 cp, ncol, _stream_handle(stream)))
+    return values, b
 
 
 def count_inverted(elem, coords, rule: Rule, n_elem: int | None = None, count=None,

@@ -122,3 +122,24 @@ def apply_reference(wl, precision, x):
     np.add.at(yabs, dof.ravel(), np.einsum("ers,es->er", np.abs(K), np.abs(x[dof])).ravel())
     np.add.at(babs, dof.ravel(), np.abs(F).ravel())
     return y, b, yabs, babs
+
+
+def assembly_reference(wl, precision):
+    """Oracle side of the CSR assembly tests: the dense assembled matrix and
+    load vector, and the entry-wise sums of |K^e| and |F^e| that scale their
+    rounding errors."""
+    coeffs = oracle_coeffs(wl, precision)
+    r = oracle.quad_rule(wl.elem, wl.n_q)
+    A, b = oracle.assemble_dense(wl.elem, wl.kind, wl.mesh.nodes, wl.mesh.conn, r, wl.coef_mode,
+                                 wl.mask, wl.uniform, coeffs)
+    K, F = oracle.integrate(wl.elem, wl.kind, wl.mesh.coords, r, wl.coef_mode, wl.mask,
+                            wl.uniform, coeffs, ORACLE_THREADS)
+    nc = 1 if wl.kind == "scalar" else 3
+    conn = wl.mesh.conn
+    n, nv = conn.shape
+    dof = (conn[:, :, None] * nc + np.arange(nc)[None, None, :]).reshape(n, nv * nc)
+    Aabs = np.zeros_like(A)
+    babs = np.zeros_like(b)
+    np.add.at(Aabs, (dof[:, :, None], dof[:, None, :]), np.abs(K))
+    np.add.at(babs, dof, np.abs(F))
+    return A, b, Aabs, babs

@@ -314,3 +314,65 @@ def test_count_inverted_validation_before_launch():
     assert call(coords=0x4004) == 2
     # nothing to count: no pointer is touched
     assert call(n=0, coords=0, count=0) == 0
+
+
+@pytest.mark.parametrize("elem,n_comp", [("tet4", 1), ("tet4", 3), ("prism6", 1), ("prism6", 3)])
+def test_csr_pattern_matches_brute_force(elem, n_comp):
+    mesh = inputs.tet_cube(3, 2) if elem == "tet4" else inputs.prism_layers(3, 3, 2)
+    nn = mesh.nodes.shape[0]
+    row_ptr, col_idx = fe.csr_pattern(elem, mesh.conn, nn, n_comp)
+    share = [set() for _ in range(nn)]
+    for el in mesh.conn:
+        for i in el:
+            share[i].update(int(j) for j in el)
+    want_ptr = [0]
+    want_cols = []
+    for i in range(nn):
+        cols = [n_comp * j + b for j in sorted(share[i]) for b in range(n_comp)]
+        for _ in range(n_comp):
+            want_cols += cols
+            want_ptr.append(len(want_cols))
+    assert np.array_equal(row_ptr, np.array(want_ptr, dtype=np.int64))
+    assert np.array_equal(col_idx, np.array(want_cols, dtype=np.int32))
+
+
+def test_csr_pattern_errors_and_isolated_nodes():
+    L = fe.lib()
+    conn = np.ascontiguousarray(np.array([[0, 1, 2, 3]], dtype=np.int32).T)   # one tet, SoA
+    vp = ctypes.c_void_p
+    rp = np.zeros(6 * 3 + 1, dtype=np.int64)
+    ci = np.zeros(200, dtype=np.int32)
+    call = lambda n_nodes=6, n_comp=1, cap=200, c=conn, cols=True: L.fe_csr_pattern(
+        0, 1, c.ctypes.data_as(vp), 1, n_nodes, n_comp, rp.ctypes.data_as(vp),
+        ci.ctypes.data_as(vp) if cols else None, cap)
+    # nodes 4 and 5 touch no element: empty rows
+    assert call(cols=False) == 16
+    assert call() == 16
+    assert list(rp[:7]) == [0, 4, 8, 12, 16, 16, 16]
+    assert call(n_comp=3) == 144
+    assert call(n_comp=2) == -1
+    assert call(n_nodes=3) == -1            # node id 3 outside [0, 3)
+    assert call(cap=15) == -5               # col_idx too small
+    assert fe.lib().fe_last_error()
+
+
+def _csr_call(p, rows=0x5000, cols=0x6000, nnz=100, vals=0x7000, b=None, n=10, coeffs=None):
+    L = fe.lib()
+    rule = fe.builtin_rule("tet4", 1)
+    v = lambda a: ctypes.c_void_p(a) if a else None
+    return L.fe_assemble_csr(ctypes.byref(p), 0, n, ctypes.c_void_p(0x8000), 10,
+                             ctypes.c_void_p(0x1000), 10, v(coeffs), 10, ctypes.byref(rule.c),
+                             v(rows), v(cols), nnz, v(vals), v(b), None, 0, None)
+
+
+def test_assemble_csr_validation_before_launch():
+    p = fe.problem("scalar", "fp64", "uniform", 0, inputs.identity_diffusion_uniform(), "packed")
+    assert _csr_call(p, rows=0) == 1
+    assert _csr_call(p, cols=0) == 1
+    assert _csr_call(p, vals=0) == 1
+    assert _csr_call(p, nnz=-1) == 1
+    assert _csr_call(p, rows=0x5004) == 2                          # misaligned row_ptr
+    assert _csr_call(p, vals=0x7004) == 2                          # misaligned values
+    v = fe.problem("vector", "fp64", "element", inputs.ALL_VECTOR_MASK, None, "full")
+    assert _csr_call(v, coeffs=0x9000) == 2                        # no assembly form
+    assert _csr_call(p, rows=0, cols=0, vals=0, n=0) == 0          # nothing to do

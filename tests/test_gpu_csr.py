@@ -1,0 +1,170 @@
+"""GPU parity of the assembly into CSR storage (fe_assemble_csr, element
+matrices never stored) against the oracle's dense assembled matrix and load
+vector, coloured (deterministic) and atomic, FP64 and FP32; accumulation,
+ragged element counts, and the full-size tetrahedral mesh (exact symmetry,
+zero row sums, sampled rows against the oracle)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1504_01023_amd import fe, inputs
+from tests import _parity as P
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+# rounding of the assembled sums, relative to sum_e |K^e| entry by entry,
+# floored at the largest such sum in the row (an entry whose contributions
+# all vanish still carries rounding of the size of the element matrices)
+TOL = {"fp64": 1e-12, "fp32": 2e-5}
+CASES = ["tet_poisson", "tet_poisson_qp", "tet_cdr", "tet_cdr_fn", "tet_elasticity", "prism_cdr_qp",
+         "prism_cdr", "prism_cdr_fn", "prism_poisson_qp", "tet_cdr_morton"]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    fe.lib()
+    yield
+
+
+def _setup(wl, precision, colour=True):
+    nn = wl.mesh.nodes.shape[0]
+    nc = 1 if wl.kind == "scalar" else 3
+    if colour:
+        perm, ptr = fe.color_elements(wl.elem, wl.mesh.conn, nn)
+    else:
+        perm, ptr = np.arange(wl.n_elem), None
+    dw = fe.to_device(wl, precision)
+    conn = torch.from_numpy(np.ascontiguousarray(wl.mesh.conn[perm].T.astype(np.int32))).cuda()
+    coeffs = dw.coeffs
+    if coeffs is not None and wl.coef_mode not in ("uniform", "function"):
+        coeffs = coeffs[:, torch.from_numpy(perm.astype(np.int64)).cuda()].contiguous()
+    nodes = torch.from_numpy(wl.mesh.nodes).cuda().contiguous()
+    rp, ci = fe.csr_pattern(wl.elem, wl.mesh.conn, nn, nc)
+    return dw, conn, coeffs, nodes, rp, ci, ptr
+
+
+def _dense(rp, ci, vals):
+    n = len(rp) - 1
+    A = np.zeros((n, n))
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    A[rows, ci] = vals.double().cpu().numpy()
+    return A
+
+
+def _check(A, b, ref, precision, rp, ci):
+    Ar, br, Aabs, babs = ref
+    tol = TOL[precision]
+    inside = np.zeros(Ar.shape, dtype=bool)
+    inside[np.repeat(np.arange(len(rp) - 1), np.diff(rp)), ci] = True
+    assert not np.any(Ar[~inside]), "the pattern misses a coupling"
+    scale = np.maximum(Aabs, Aabs.max(axis=1, keepdims=True))
+    e = np.abs(A - Ar)[inside] / np.maximum(scale[inside], 1e-300)
+    assert e.max() <= tol, f"A rel err {e.max():.3e}"
+    if b is not None:
+        eb = np.abs(b.double().cpu().numpy() - br) / np.maximum(babs, 1e-300)
+        assert eb.max() <= tol, f"b rel err {eb.max():.3e}"
+
+
+def _small(name):
+    if name.endswith("_morton"):
+        return inputs.reordered(P.small(name[: -len("_morton")]))
+    return P.small(name)
+
+
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_coloured_and_atomic_match_oracle(name, precision):
+    wl = _small(name)
+    dw, conn, coeffs, nodes, rp, ci, ptr = _setup(wl, precision)
+    print(f"[csr] {name} {precision} n={wl.n_elem} nnz={len(ci)} colours={len(ptr) - 1}", flush=True)
+    ref = P.assembly_reference(wl, precision)
+    rpd = torch.from_numpy(rp).cuda()
+    cid = torch.from_numpy(ci).cuda()
+    run = lambda cp: fe.assemble_csr(dw.problem, wl.elem, nodes, conn, coeffs, dw.rule, rpd, cid,
+                                     color_ptr=cp, with_b=True)
+    v1, b1 = run(ptr)
+    v2, b2 = run(ptr)
+    v3, b3 = run(None)
+    torch.cuda.synchronize()
+    _check(_dense(rp, ci, v1), b1, ref, precision, rp, ci)
+    _check(_dense(rp, ci, v3), b3, ref, precision, rp, ci)
+    assert torch.equal(v1, v2) and torch.equal(b1, b2)
+
+
+def test_accumulates_ragged_and_without_load():
+    wl = P.small("tet_cdr")
+    dw, conn, coeffs, nodes, rp, ci, _ = _setup(wl, "fp64", colour=False)
+    rpd = torch.from_numpy(rp).cuda()
+    cid = torch.from_numpy(ci).cuda()
+    m = wl.n_elem - 37
+    sub = inputs.Workload(wl.name, wl.elem, wl.kind, wl.n_q, wl.coef_mode, wl.mask, wl.uniform,
+                          wl.k_format, inputs.Mesh(wl.elem, wl.mesh.coords[:, :m], wl.mesh.nodes,
+                                                   wl.mesh.conn[:m], wl.mesh.boundary),
+                          wl.coeffs[:, :m])
+    ref = P.assembly_reference(sub, "fp64")
+    vals, b = fe.assemble_csr(dw.problem, wl.elem, nodes, conn, coeffs, dw.rule, rpd, cid,
+                              n_elem=m)
+    assert b is None
+    torch.cuda.synchronize()
+    _check(_dense(rp, ci, vals), None, ref, "fp64", rp, ci)
+    # a second call adds to the same values
+    fe.assemble_csr(dw.problem, wl.elem, nodes, conn, coeffs, dw.rule, rpd, cid, values=vals,
+                    n_elem=m)
+    torch.cuda.synchronize()
+    Ar, br, Aabs, babs = ref
+    _check(_dense(rp, ci, vals), None, (2 * Ar, br, 2 * Aabs, babs), "fp64", rp, ci)
+    # nothing to assemble leaves the values alone
+    before = vals.clone()
+    fe.assemble_csr(dw.problem, wl.elem, nodes, conn, coeffs, dw.rule, rpd, cid, values=vals,
+                    n_elem=0)
+    torch.cuda.synchronize()
+    assert torch.equal(vals, before)
+
+
+def test_full_size_tet_poisson():
+    # the headline mesh (10,110,954 tetrahedra), Laplacian with d^0 = 1,
+    # packed symmetric K, coloured: every entry and its mirror receive the
+    # same contributions in the same order, so A is exactly symmetric
+    wl = inputs.tet_poisson(119, 1)
+    nn = wl.mesh.nodes.shape[0]
+    dw, conn, coeffs, nodes, rp, ci, ptr = _setup(wl, "fp64")
+    print(f"[csr] full n={wl.n_elem} nodes={nn} nnz={len(ci)} colours={len(ptr) - 1}", flush=True)
+    rpd = torch.from_numpy(rp).cuda()
+    cid = torch.from_numpy(ci).cuda()
+    vals, b = fe.assemble_csr(dw.problem, wl.elem, nodes, conn, coeffs, dw.rule, rpd, cid,
+                              color_ptr=ptr, with_b=True)
+    torch.cuda.synchronize()
+    v = vals.cpu().numpy()
+    rows = np.repeat(np.arange(nn), np.diff(rp))
+    # exact symmetry: entry (i, j) equals entry (j, i)
+    key = rows.astype(np.int64) * nn + ci
+    tkey = ci.astype(np.int64) * nn + rows
+    pos = np.searchsorted(key, tkey)
+    assert np.array_equal(key[pos], tkey)
+    assert np.array_equal(v[pos], v)
+    # zero row sums of the Laplacian, relative to the row's magnitude
+    rs = np.add.reduceat(v, rp[:-1])
+    ra = np.add.reduceat(np.abs(v), rp[:-1])
+    assert np.abs(rs).max() <= 1e-12 * ra.max()
+    assert b.sum().item() == pytest.approx(1.0, rel=1e-12)
+    # sampled rows against the oracle's element matrices of the elements at the node
+    rng = np.random.default_rng(41)
+    rule = oracle.quad_rule("tet4", 1)
+    for node in rng.choice(nn, 20, replace=False):
+        els = np.nonzero((wl.mesh.conn == node).any(axis=1))[0]
+        K, _ = oracle.integrate("tet4", "scalar", wl.mesh.coords[:, els], rule, "uniform", 0,
+                                wl.uniform)
+        row = np.zeros(nn)
+        rowabs = np.zeros(nn)
+        for k, e in enumerate(els):
+            r = int(np.nonzero(wl.mesh.conn[e] == node)[0][0])
+            np.add.at(row, wl.mesh.conn[e], K[k, r])
+            np.add.at(rowabs, wl.mesh.conn[e], np.abs(K[k, r]))
+        lo, hi = rp[node], rp[node + 1]
+        got = np.zeros(nn)
+        got[ci[lo:hi]] = v[lo:hi]
+        assert np.all(np.abs(got - row) <= 1e-12 * np.maximum(rowabs, rowabs.max()))

@@ -528,11 +528,14 @@ NATURAL_BASES = ("tet_poisson", "tet_poisson_qp", "tet_cdr", "tet_elasticity", "
 APPLY_BASES = ("tet_poisson", "tet_cdr", "tet_elasticity", "prism_cdr", "prism_poisson_qp")
 
 
-def run_apply(a, torch, fe, oracle, base: str, dev) -> dict:
+def run_apply(a, torch, fe, oracle, base: str, dev, csr: bool = False) -> dict:
     """Matrix-free operator application y += A x over the whole mesh (element
     matrices formed in registers, never stored), coloured launches with plain
     updates; one step = one application. Parity: y at sampled nodes against
-    the oracle's element matrices of every element touching them."""
+    the oracle's element matrices of every element touching them.
+
+    csr: the assembly of the global matrix into CSR storage instead (one
+    step = one assembly, values += A); parity: the sampled nodes' rows."""
     from paper_1504_01023_amd import inputs
     wl = WORKLOADS[base][0]()
     if a.apply_order != "generator":
@@ -560,9 +563,27 @@ def run_apply(a, torch, fe, oracle, base: str, dev) -> dict:
     x = torch.from_numpy(x64).to(device=dev, dtype=dt)
     y = torch.zeros_like(x)
     stream = torch.cuda.current_stream()
+    if csr:
+        t0 = time.time()
+        rp, ci = fe.csr_pattern(wl.elem, conn_np, n_nodes, nc)
+        log(f"[bench] CSR pattern: {len(ci)} entries ({time.time() - t0:.1f}s)")
+        rpd = torch.from_numpy(rp).to(dev)
+        cid = torch.from_numpy(ci).to(dev)
+        vals = torch.zeros(len(ci), dtype=dt, device=dev)
+        ip, inc = fe.node_incidence(wl.elem, conn_np[perm], n_nodes)
+        ipd = torch.from_numpy(ip).to(dev)
+        incd = torch.from_numpy(inc).to(dev)
 
-    def step():
-        fe.apply_indexed(p, wl.elem, nodes, conn, coeffs, rule, x, y, None, color_ptr=ptr)
+    def step(cp=ptr):
+        if csr:
+            fe.assemble_csr(p, wl.elem, nodes, conn, coeffs, rule, rpd, cid, values=vals,
+                            color_ptr=cp)
+        else:
+            fe.apply_indexed(p, wl.elem, nodes, conn, coeffs, rule, x, y, None, color_ptr=cp)
+
+    def step_rows():
+        fe.assemble_csr_rows(p, wl.elem, nodes, conn, coeffs, rule, rpd, cid, ipd, incd,
+                             values=vals)
 
     for _ in range(a.warmup):
         step()
@@ -582,18 +603,33 @@ def run_apply(a, torch, fe, oracle, base: str, dev) -> dict:
     ev_at = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
              for _ in range(a.steps)]
     for _ in range(a.warmup):
-        fe.apply_indexed(p, wl.elem, nodes, conn, coeffs, rule, x, y, None)
+        step(None)
     for e0, e1 in ev_at:
         e0.record(stream)
-        fe.apply_indexed(p, wl.elem, nodes, conn, coeffs, rule, x, y, None)
+        step(None)
         e1.record(stream)
     torch.cuda.synchronize()
     ms_at = np.array([e0.elapsed_time(e1) for e0, e1 in ev_at])
-    # one clean application for the parity check
-    y.zero_()
+    ms_rows = None
+    if csr:
+        # by row ownership (one lane per node, no colours, no atomics)
+        ev_r = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                for _ in range(a.steps)]
+        for _ in range(a.warmup):
+            step_rows()
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        for e0, e1 in ev_r:
+            e0.record(stream)
+            step_rows()
+            e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        ms_rows = np.array([e0.elapsed_time(e1) for e0, e1 in ev_r])
+    # one clean application (assembly) for the parity check
+    (vals if csr else y).zero_()
     step()
     torch.cuda.synchronize()
-    yg = y.double().cpu().numpy()
     rng = np.random.default_rng(99)
     snodes = rng.choice(n_nodes, size=min(2000, n_nodes), replace=False)
     mark = np.zeros(n_nodes, dtype=bool)
@@ -606,26 +642,58 @@ def run_apply(a, torch, fe, oracle, base: str, dev) -> dict:
         cf = wl.coeffs[:, touch]
         if a.precision == "fp32":
             cf = cf.astype(np.float32).astype(np.float64)
-    xo = x.double().cpu().numpy()
     K, _ = oracle.integrate(wl.elem, wl.kind, wl.mesh.coords[:, touch], oracle.quad_rule(wl.elem, wl.n_q),
                             wl.coef_mode, wl.mask, wl.uniform, cf, threads=max(1, min(16, os.cpu_count() or 1)))
     dof = (conn_np[touch][:, :, None] * nc + np.arange(nc)[None, None, :]).reshape(len(touch), nv * nc)
-    yr = np.zeros(n_nodes * nc)
-    ya = np.zeros(n_nodes * nc)
-    np.add.at(yr, dof.ravel(), np.einsum("ers,es->er", K, xo[dof]).ravel())
-    np.add.at(ya, dof.ravel(), np.einsum("ers,es->er", np.abs(K), np.abs(xo[dof])).ravel())
     sd = (snodes[:, None] * nc + np.arange(nc)[None, :]).ravel()
-    err = float((np.abs(yg[sd] - yr[sd]) / np.maximum(ya[sd], 1e-300)).max())
     tol = 1e-12 if a.precision == "fp64" else 2e-5
-    avg = float(ms.mean()) * 1e-3
     ncoef = fe.coeff_entries(p, wl.elem, rule.n_q) if wl.coef_mode != "function" else 0
-    bpe = 4 * nv + tsz * ncoef + (24 + 3 * tsz * nc) * n_nodes / n
+    if csr:
+        # rows of the sampled unknowns: the oracle's element matrices added at
+        # their couplings, against the GPU's CSR rows; rounding relative to
+        # the row's largest sum of |K^e|
+        import scipy.sparse as sp
+        nd = n_nodes * nc
+        rows = np.repeat(dof[:, :, None], dof.shape[1], axis=2).ravel()
+        cols = np.repeat(dof[:, None, :], dof.shape[1], axis=1).ravel()
+        R = sp.csr_matrix((K.ravel(), (rows, cols)), shape=(nd, nd))[sd]
+        Ra = sp.csr_matrix((np.abs(K).ravel(), (rows, cols)), shape=(nd, nd))[sd]
+        den = np.maximum(Ra.max(axis=1).toarray().ravel(), 1e-300)
+        err = 0.0
+        for mode in ("coloured", "rows"):
+            if mode == "rows":
+                vals.zero_()
+                step_rows()
+                torch.cuda.synchronize()
+            G = sp.csr_matrix((vals.double().cpu().numpy(), ci, rp), shape=(nd, nd))[sd]
+            D = abs(G - R)
+            err = max(err, float((D.max(axis=1).toarray().ravel() / den).max()))
+        nnz = len(ci)
+        # inputs once, the pattern once, every value read and written once
+        bpe = 4 * nv + tsz * ncoef + (24 * n_nodes + 8 * (nd + 1) + (4 + 2 * tsz) * nnz) / n
+    else:
+        yg = y.double().cpu().numpy()
+        xo = x.double().cpu().numpy()
+        yr = np.zeros(n_nodes * nc)
+        ya = np.zeros(n_nodes * nc)
+        np.add.at(yr, dof.ravel(), np.einsum("ers,es->er", K, xo[dof]).ravel())
+        np.add.at(ya, dof.ravel(), np.einsum("ers,es->er", np.abs(K), np.abs(xo[dof])).ravel())
+        err = float((np.abs(yg[sd] - yr[sd]) / np.maximum(ya[sd], 1e-300)).max())
+        bpe = 4 * nv + tsz * ncoef + (24 + 3 * tsz * nc) * n_nodes / n
+    if csr:
+        # the value is the row-ownership assembly; the coloured one beside it
+        ms, ms_col = ms_rows, ms
+    avg = float(ms.mean()) * 1e-3
     return {"wl": wl, "n_elem": n, "n_nodes": n_nodes, "colours": int(len(ptr) - 1),
             "ms_avg": float(ms.mean()), "ms_min": float(ms.min()), "wall_s": wall,
+            "coloured_ms_avg": float(ms_col.mean()) if csr else None,
+            "coloured_elements_per_s": n / (float(ms_col.mean()) * 1e-3) if csr else None,
             "atomic_ms_avg": float(ms_at.mean()), "atomic_elements_per_s": n / (float(ms_at.mean()) * 1e-3),
             "elements_per_s": n / avg, "bytes_per_element": bpe,
             "achieved_GBps": bpe * n / avg / 1e9,
-            "parity": {"sampled_nodes": int(len(snodes)), "max_rel_err_y": err, "tol": tol,
+            "nnz": int(len(ci)) if csr else None,
+            "parity": {"sampled_nodes": int(len(snodes)),
+                       ("max_rel_err_rows" if csr else "max_rel_err_y"): err, "tol": tol,
                        "ok": bool(err <= tol)}}
 
 
@@ -637,6 +705,7 @@ def main() -> int:
     ap.add_argument("--workload", default="tet_poisson",
                     choices=sorted(WORKLOADS) + [w + "_indexed" for w in sorted(WORKLOADS)]
                     + [w + "_apply" for w in APPLY_BASES]
+                    + [w + "_csr" for w in APPLY_BASES]
                     + [w + "_natural" for w in NATURAL_BASES]
                     + ["served", "paper"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
@@ -686,18 +755,22 @@ def main() -> int:
         print(json.dumps(line), flush=True)
         return 0
 
-    if a.workload.endswith("_apply"):
-        base = a.workload[: -len("_apply")]
-        r = run_apply(a, torch, fe, oracle, base, dev)
-        line = {"metric": "elements/s of matrix-free operator application (K^e never stored)",
+    if a.workload.endswith("_apply") or a.workload.endswith("_csr"):
+        csr = a.workload.endswith("_csr")
+        base = a.workload[: -len("_csr" if csr else "_apply")]
+        r = run_apply(a, torch, fe, oracle, base, dev, csr)
+        line = {"metric": ("elements/s of assembly into CSR storage (K^e never stored)" if csr else
+                           "elements/s of matrix-free operator application (K^e never stored)"),
                 "value": r["elements_per_s"], "unit": "elements/s", "n_gpus": 1, "steps": a.steps,
                 "warmup": a.warmup, "ms_per_step": r["wall_s"] * 1e3 / a.steps,
                 "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
                 "dtype": "f64" if a.precision == "fp64" else "f32 (FP64 Jacobian)",
                 "data": "synthetic",
                 "config": {"workload": a.workload,
-                           "description": WORKLOADS[base][1] + "; y += A x, coloured launches",
+                           "description": WORKLOADS[base][1] + ("; values += A, one lane per node (row ownership)"
+                                                                if csr else "; y += A x, coloured launches"),
                            "n_elem": r["n_elem"], "n_nodes": r["n_nodes"], "colours": r["colours"],
+                           "nnz": r["nnz"],
                            "node_element_order": a.apply_order,
                            "precision": a.precision, "bytes_per_element": r["bytes_per_element"],
                            "parallelism": "single GPU"},
@@ -706,6 +779,8 @@ def main() -> int:
                              "traffic": None},
                 "cpu_baseline": None, "kernel_ms_avg": r["ms_avg"], "kernel_ms_min": r["ms_min"],
                 "atomic": {"ms_avg": r["atomic_ms_avg"], "elements_per_s": r["atomic_elements_per_s"]},
+                "coloured": ({"ms_avg": r["coloured_ms_avg"],
+                              "elements_per_s": r["coloured_elements_per_s"]} if csr else None),
                 "parity": r["parity"]}
         print(json.dumps(line), flush=True)
         return 0 if r["parity"]["ok"] else 3

@@ -306,6 +306,31 @@ FE_API int fe_assemble_csr(const fe_problem *problem, fe_elem_type elem_type, in
                            const int32_t *col_idx, int64_t nnz, void *values, void *b,
                            const int64_t *color_ptr, int32_t n_colors, hipStream_t stream);
 
+/* Elements at each node, built on the host for fe_assemble_csr_rows. conn
+ * is host memory as for fe_color_elements. Writes inc_ptr[0 .. n_nodes]
+ * (host) and, when inc is not NULL, inc[0 .. n_elem * n_vert) (host): the
+ * elements at node i are inc[inc_ptr[i] .. inc_ptr[i + 1]), in increasing
+ * element order, each coded element * n_vert + local vertex (n_elem *
+ * n_vert must fit in int32). Returns n_elem * n_vert, or minus
+ * FE_ERR_INVALID_ARG for bad arguments or node ids outside [0, n_nodes). */
+FE_API int64_t fe_node_incidence(fe_elem_type elem_type, int64_t n_elem, const int32_t *conn,
+                                 int64_t ld_conn, int64_t n_nodes, int64_t *inc_ptr, int32_t *inc);
+
+/* The same assembly as fe_assemble_csr by row ownership: one lane per node
+ * adds the node's rows, walking the elements at the node (inc_ptr, inc:
+ * device copies of what fe_node_incidence writes) and computing each
+ * element's K and F once per vertex (Sec. 3.2 assembles at the nodes; here
+ * the node, not the element, is the unit of parallel work). No colours and
+ * no atomic operations: each row is written by one lane, in the order of
+ * inc, so the result is deterministic. Other arguments as for
+ * fe_assemble_csr. Enqueued on `stream`; no allocation. */
+FE_API int fe_assemble_csr_rows(const fe_problem *problem, fe_elem_type elem_type, int64_t n_elem,
+                                const double *nodes, int64_t n_nodes, const int32_t *conn,
+                                int64_t ld_conn, const void *coeffs, int64_t ld_in,
+                                const fe_quad_rule *quad_rule, const int64_t *row_ptr,
+                                const int32_t *col_idx, int64_t nnz, void *values, void *b,
+                                const int64_t *inc_ptr, const int32_t *inc, hipStream_t stream);
+
 /* Diagnostic for the signed-determinant convention (det J is used as it
  * is; inverted elements are integrated as written): adds to *count (device
  * int64, zero it first) the number of elements whose det J is not positive

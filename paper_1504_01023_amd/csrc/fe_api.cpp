@@ -612,6 +612,60 @@ int fe_assemble_csr(const fe_problem *problem, fe_elem_type elem_type, int64_t n
                             ld_in, quad_rule, ap, true, color_ptr, n_colors, stream);
 }
 
+int fe_assemble_csr_rows(const fe_problem *problem, fe_elem_type elem_type, int64_t n_elem,
+                         const double *nodes, int64_t n_nodes, const int32_t *conn,
+                         int64_t ld_conn, const void *coeffs, int64_t ld_in,
+                         const fe_quad_rule *quad_rule, const int64_t *row_ptr,
+                         const int32_t *col_idx, int64_t nnz, void *values, void *b,
+                         const int64_t *inc_ptr, const int32_t *inc, hipStream_t stream)
+{
+    if (n_elem > 0 && (!nodes || n_nodes < 1 || n_nodes > 0x7fffffffLL))
+        return fail(FE_ERR_INVALID_ARG, "need a node array with 1 .. 2^31-1 nodes");
+    if (n_elem > 0 && (!row_ptr || !col_idx || !values || !inc_ptr || !inc))
+        return fail(FE_ERR_INVALID_ARG, "row_ptr, col_idx, values, inc_ptr and inc must not be NULL");
+    if (nnz < 0 || nnz > 0x7fffffffffffLL)
+        return fail(FE_ERR_INVALID_ARG, "nnz out of range");
+    if (elem_type == FE_TET4 || elem_type == FE_PRISM6) {
+        if (n_elem > 0x7fffffffLL / n_shape(elem_type))
+            return fail(FE_ERR_INVALID_ARG, "element * vertex codes must fit in int32");
+    }
+    if (!aligned(nodes, 8) || !aligned(row_ptr, 8) || !aligned(col_idx, 4) ||
+        !aligned(inc_ptr, 8) || !aligned(inc, 4))
+        return fail(FE_ERR_UNSUPPORTED, "pointers must be aligned to their element size");
+    // the assembly form exists for the base variant: one element per lane
+    const fe_variant base{256, 1, 2, 1, 0, 1, 1};
+    Plan pl;
+    int st = plan(problem, elem_type, n_elem, nullptr, coeffs, ld_in, quad_rule, nullptr, nullptr,
+                  n_elem, &base, pl, 2, conn, ld_conn);
+    if (st)
+        return st;
+    if (!pl.entry->apply)
+        return fail(FE_ERR_UNSUPPORTED, "no assembly form for this problem");
+    const size_t tsz = problem->precision == FE_FP64 ? 8 : 4;
+    if (!aligned(values, tsz) || !aligned(b, tsz))
+        return fail(FE_ERR_UNSUPPORTED, "values and b must be aligned to their element size");
+    if (n_elem == 0)
+        return FE_OK;
+    ApplyArgs ap{};
+    ap.b = b;
+    ap.row_ptr = row_ptr;
+    ap.col_idx = col_idx;
+    ap.nnz = nnz;
+    ap.vals = values;
+    ap.inc_ptr = inc_ptr;
+    ap.inc = inc;
+    ap.n_own = n_nodes;
+    const IdxArgs gi{nodes, conn, ld_conn, (uint32_t)n_nodes};
+    int64_t grid = (n_nodes + pl.block - 1) / pl.block;
+    if (grid > 0x7fffffff)
+        grid = 0x7fffffff;
+    pl.entry->apply(pl.args, gi, ap, 0, (unsigned)grid, pl.block, stream);
+    const hipError_t err = hipGetLastError();
+    if (err != hipSuccess)
+        return fail(FE_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(err));
+    return FE_OK;
+}
+
 int fe_integrate_natural(const fe_problem *problem, fe_elem_type elem_type, int64_t n_elem,
                          const double *coords, const void *coeffs, const fe_quad_rule *quad_rule,
                          void *out_K, void *out_F, hipStream_t stream)
@@ -709,6 +763,36 @@ int fe_color_elements(fe_elem_type elem_type, int64_t n_elem, const int32_t *con
     for (int64_t e = 0; e < n_elem; ++e)
         perm[count[color[e]]++] = (int32_t)e;
     return n_colors;
+}
+
+int64_t fe_node_incidence(fe_elem_type elem_type, int64_t n_elem, const int32_t *conn,
+                          int64_t ld_conn, int64_t n_nodes, int64_t *inc_ptr, int32_t *inc)
+{
+    if (elem_type != FE_TET4 && elem_type != FE_PRISM6)
+        return -fail(FE_ERR_INVALID_ARG, "bad element type %d", elem_type);
+    const int nv = n_shape(elem_type);
+    if (n_elem < 0 || n_elem > 0x7fffffffLL / nv || n_nodes < 1 || n_nodes > 0x7fffffffLL ||
+        (n_elem > 0 && (!conn || ld_conn < n_elem)) || !inc_ptr)
+        return -fail(FE_ERR_INVALID_ARG, "bad incidence arguments");
+    for (int64_t i = 0; i <= n_nodes; ++i)
+        inc_ptr[i] = 0;
+    for (int v = 0; v < nv; ++v)
+        for (int64_t e = 0; e < n_elem; ++e) {
+            const int32_t id = conn[v * ld_conn + e];
+            if (id < 0 || id >= n_nodes)
+                return -fail(FE_ERR_INVALID_ARG, "element %lld has node id %d outside [0, %lld)",
+                             (long long)e, id, (long long)n_nodes);
+            ++inc_ptr[id + 1];
+        }
+    for (int64_t i = 0; i < n_nodes; ++i)
+        inc_ptr[i + 1] += inc_ptr[i];
+    if (inc) {
+        std::vector<int64_t> fill(inc_ptr, inc_ptr + n_nodes);
+        for (int64_t e = 0; e < n_elem; ++e)
+            for (int v = 0; v < nv; ++v)
+                inc[fill[conn[v * ld_conn + e]]++] = (int32_t)(e * nv + v);
+    }
+    return inc_ptr[n_nodes];
 }
 
 int64_t fe_csr_pattern(fe_elem_type elem_type, int64_t n_elem, const int32_t *conn,

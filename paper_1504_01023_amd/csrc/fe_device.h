@@ -345,14 +345,18 @@ struct ApplyBlock : ScalarBlock {
     }
 };
 
-// Assembly into a CSR matrix (one element per lane): each entry of K is added
-// to the global entry of its (row, column) as it is produced, and to the
-// mirrored entry for a packed symmetric K; F is added to b. The element
-// matrix is never stored. Element dof r = NC v + alpha sits in global row
-// NC id[v] + alpha; rp[v] is where row NC id[v] starts, len[v] its length
-// (the rows of a node's components have equal length and the same columns),
-// off[v][u] the position of column NC id[u] in it, or -1 when the pattern
-// lacks it (the entry is then dropped; nothing is written outside vals).
+// Assembly into a CSR matrix (one element per lane): each entry of K goes to
+// the global entry of its (row, column), and to the mirrored entry for a
+// packed symmetric K; F goes to b. The element matrix is never stored.
+// Element dof r = NC v + alpha sits in global row NC id[v] + alpha; rp[v] is
+// where row NC id[v] starts, len[v] its length (the rows of a node's
+// components have equal length and the same columns), off[v][u] the
+// position of column NC id[u] in it, or -1 when the pattern lacks it (the
+// entry is then dropped; nothing is written outside vals).
+// DEFER: the entries are collected in the lane's array kv (and fv) and
+// added by the kernel afterwards, all loads before all stores (the plain
+// read-add-write of a coloured launch; small K only); otherwise each entry
+// is added as it is produced.
 template <typename T, bool ATOMIC>
 __device__ __forceinline__ void add_at(T *p, T v)
 {
@@ -362,25 +366,38 @@ __device__ __forceinline__ void add_at(T *p, T v)
         *p += v;
 }
 
-template <typename T, int NV, int NC, bool ATOMIC, bool WITH_B>
+template <typename T, int NV, int NC, bool ATOMIC, bool WITH_B, bool DEFER>
 struct CsrBlock : ScalarBlock {
+    static constexpr int N = NV * NC;
     T *vals;
-    T *b;  // used when WITH_B
+    T *b;   // used when WITH_B
+    T *kv;  // DEFER: N x N entries
+    T *fv;  // DEFER: N entries
     int64_t nnz;
     uint32_t id[NV];
     int64_t rp[NV];
     int32_t len[NV];
     int32_t off[NV][NV];
     __device__ __forceinline__ bool with_f() const { return WITH_B; }
-    __device__ __forceinline__ void add(int r, int s, T v) const
+    // position of entry (r, s) in vals, or -1
+    __device__ __forceinline__ int64_t pos(int r, int s) const
     {
         const int vr = r / NC, al = r % NC, vs = s / NC, be = s % NC;
         const int o = off[vr][vs];
         if (o < 0)
-            return;
+            return -1;
         const int64_t p = rp[vr] + (int64_t)al * len[vr] + o + be;
-        if (p < nnz)
-            add_at<T, ATOMIC>(vals + p, v);
+        return p < nnz ? p : -1;
+    }
+    __device__ __forceinline__ void add(int r, int s, T v) const
+    {
+        if constexpr (DEFER) {
+            kv[r * N + s] = v;
+        } else {
+            const int64_t p = pos(r, s);
+            if (p >= 0)
+                add_at<T, ATOMIC>(vals + p, v);
+        }
     }
     template <int V, int NT, typename U>
     __device__ __forceinline__ void put_k(const Streams &, int, int packed, int r, int s, int64_t,
@@ -394,8 +411,70 @@ struct CsrBlock : ScalarBlock {
     template <int V, int NT, typename U>
     __device__ __forceinline__ void put_f(const Streams &, int r, int64_t, const U (&val)[V]) const
     {
-        if constexpr (WITH_B)
-            add_at<T, ATOMIC>(b + (int64_t)NC * id[r / NC] + r % NC, val[0]);
+        if constexpr (WITH_B) {
+            if constexpr (DEFER)
+                fv[r] = val[0];
+            else
+                add_at<T, ATOMIC>(b + (int64_t)NC * id[r / NC] + r % NC, val[0]);
+        }
+    }
+    // DEFER: add the collected entries, every load issued before any store
+    __device__ __forceinline__ void flush() const
+    {
+        int64_t p[N * N];
+        T old[N * N];
+#pragma unroll
+        for (int r = 0; r < N; ++r)
+#pragma unroll
+            for (int s = 0; s < N; ++s) {
+                p[r * N + s] = pos(r, s);
+                old[r * N + s] = p[r * N + s] >= 0 ? vals[p[r * N + s]] : T(0);
+            }
+        T oldb[N];
+        if constexpr (WITH_B) {
+#pragma unroll
+            for (int r = 0; r < N; ++r)
+                oldb[r] = b[(int64_t)NC * id[r / NC] + r % NC];
+        }
+#pragma unroll
+        for (int k = 0; k < N * N; ++k)
+            if (p[k] >= 0)
+                vals[p[k]] = old[k] + kv[k];
+        if constexpr (WITH_B) {
+#pragma unroll
+            for (int r = 0; r < N; ++r)
+                b[(int64_t)NC * id[r / NC] + r % NC] = oldb[r] + fv[r];
+        }
+    }
+};
+
+// Row ownership (one node per lane): of element e's K and F only the rows
+// of the owning node's local vertex lv are kept, kr[alpha][s] = K_{NC lv +
+// alpha, s} (a packed symmetric K also gives them from the mirrored
+// entries) and fr[alpha] = F_{NC lv + alpha}; the kernel adds them to the
+// node's rows.
+template <typename T, int NV, int NC>
+struct RowBlock : ScalarBlock {
+    static constexpr int N = NV * NC;
+    int lv;
+    T *kr;  // NC x N
+    T *fr;  // NC
+    __device__ __forceinline__ bool with_f() const { return true; }
+    template <int V, int NT, typename U>
+    __device__ __forceinline__ void put_k(const Streams &, int, int packed, int r, int s, int64_t,
+                                          const U (&val)[V]) const
+    {
+        static_assert(V == 1, "assembly is one element per lane");
+        if (r / NC == lv)
+            kr[(r % NC) * N + s] = val[0];
+        if (packed && r != s && s / NC == lv)
+            kr[(s % NC) * N + r] = val[0];
+    }
+    template <int V, int NT, typename U>
+    __device__ __forceinline__ void put_f(const Streams &, int r, int64_t, const U (&val)[V]) const
+    {
+        if (r / NC == lv)
+            fr[r % NC] = val[0];
     }
 };
 
@@ -1988,11 +2067,23 @@ __global__ __launch_bounds__(256) void fe_csr_kernel(KArgs a, IdxArgs gi, ApplyA
     const Ref<REF> ref{a, &lds_ref[0]};
     const Streams st{nullptr, a.coeffs, nullptr, nullptr, a.ld_in, a.ld_out};
     const int64_t nnz = ap.nnz;
+    constexpr int N = NV * NC;
+    constexpr bool DEFER = !ATOMIC && N * N <= 36;
+    constexpr int SB = 16;  // columns loaded together in the row scans
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < a.n_elem; e += stride) {
-        CsrBlock<T, NV, NC, ATOMIC, WITH_B> bl;
+        CsrBlock<T, NV, NC, ATOMIC, WITH_B, DEFER> bl;
+        T kv[DEFER ? N * N : 1], fv[DEFER ? N : 1];
+#pragma unroll
+        for (int k = 0; k < (DEFER ? N * N : 1); ++k)
+            kv[k] = T(0);
+#pragma unroll
+        for (int k = 0; k < (DEFER ? N : 1); ++k)
+            fv[k] = T(0);
         bl.vals = static_cast<T *>(ap.vals);
         bl.b = static_cast<T *>(ap.b);
+        bl.kv = kv;
+        bl.fv = fv;
         bl.nnz = nnz;
         double X[3 * NV];
         gather_vertices<NV, NT>(gi, e, bl.id, X);
@@ -2008,15 +2099,175 @@ __global__ __launch_bounds__(256) void fe_csr_kernel(KArgs a, IdxArgs gi, ApplyA
 #pragma unroll
             for (int u = 0; u < NV; ++u)
                 bl.off[v][u] = -1;
-            for (int64_t j = r0; j < r1; j += NC) {
-                const int32_t c = ap.col_idx[j];
+            for (int64_t j0 = r0; j0 < r1; j0 += SB * NC) {
+                int32_t c[SB];
 #pragma unroll
-                for (int u = 0; u < NV; ++u)
-                    if (c == (int32_t)(NC * bl.id[u]))
-                        bl.off[v][u] = (int32_t)(j - r0);
+                for (int t = 0; t < SB; ++t) {
+                    const int64_t j = j0 + (int64_t)t * NC;
+                    c[t] = j < r1 ? ap.col_idx[j] : -1;
+                }
+#pragma unroll
+                for (int t = 0; t < SB; ++t)
+#pragma unroll
+                    for (int u = 0; u < NV; ++u)
+                        if (c[t] == (int32_t)(NC * bl.id[u]))
+                            bl.off[v][u] = (int32_t)(j0 - r0) + t * NC;
             }
         }
         P::template apply_x<NT, REF>(a, st, ref, X, e, bl);
+        if constexpr (DEFER)
+            bl.flush();
+    }
+}
+
+// Assembly into a CSR matrix by row ownership (one node per lane, no
+// colours and no atomics): node i's lane loads the node columns of its
+// rows (the first RC in registers), then for each element at the node
+// gathers it, finds where the element's nodes sit in the row, computes K
+// and F keeping only the node's rows (RowBlock) and adds them; every
+// element is computed once per vertex. Each row is written by one lane
+// only, so the result does not depend on the schedule.
+template <class P, int NV, int NC, typename T, int NT, int REF, bool WITH_B>
+__global__ __launch_bounds__(256) void fe_csr_rows_kernel(KArgs a, IdxArgs gi, ApplyArgs ap)
+{
+    __shared__ RefLds lds_ref[1];
+    stage_reference<REF>(a, lds_ref[0]);
+    const Ref<REF> ref{a, &lds_ref[0]};
+    const Streams st{nullptr, a.coeffs, nullptr, nullptr, a.ld_in, a.ld_out};
+    constexpr int N = NV * NC;
+    constexpr int RC = 32;  // node columns of a row held in registers
+    const int64_t nnz = ap.nnz;
+    T *vals = static_cast<T *>(ap.vals);
+    T *b = static_cast<T *>(ap.b);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ap.n_own; i += stride) {
+        // row bounds clamped into [0, nnz]: never a fault
+        int64_t r0 = ap.row_ptr[NC * i], r1 = ap.row_ptr[NC * i + 1];
+        r0 = r0 < 0 ? 0 : (r0 > nnz ? nnz : r0);
+        r1 = r1 < r0 ? r0 : (r1 > nnz ? nnz : r1);
+        const int64_t len = r1 - r0;
+        int32_t cols[RC];
+#pragma unroll
+        for (int k = 0; k < RC; ++k)
+            cols[k] = (int64_t)k * NC < len ? ap.col_idx[r0 + (int64_t)k * NC] : -1;
+        T fb[NC];
+#pragma unroll
+        for (int al = 0; al < NC; ++al)
+            fb[al] = T(0);
+        const int64_t k0 = ap.inc_ptr[i], k1 = ap.inc_ptr[i + 1];
+        // software pipeline over the node's elements: the code of element
+        // k + 2 and the vertex ids of element k + 1 are loaded while
+        // element k is processed
+        auto code_at = [&](int64_t k) -> uint32_t {
+            return k < k1 ? (uint32_t)ap.inc[k] : 0u;
+        };
+        auto ids_of = [&](uint32_t code, uint32_t (&id)[NV]) {
+            const int64_t e = code / NV < a.n_elem ? code / NV : 0;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const uint32_t u = (uint32_t)ld1<NT>(gi.conn + v * gi.ld_conn + e);
+                id[v] = u < gi.n_nodes ? u : gi.n_nodes - 1;  // clamped: never a fault
+            }
+        };
+        uint32_t c_cur = code_at(k0), c_next = code_at(k0 + 1);
+        uint32_t id_cur[NV];
+        ids_of(c_cur, id_cur);
+        for (int64_t k = k0; k < k1; ++k) {
+            const uint32_t code = c_cur;
+            uint32_t id[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                id[v] = id_cur[v];
+            const uint32_t c_after = code_at(k + 2);
+            if (k + 1 < k1)
+                ids_of(c_next, id_cur);
+            c_cur = c_next;
+            c_next = c_after;
+            const int64_t e = code / NV;
+            if (e >= a.n_elem)
+                continue;
+            RowBlock<T, NV, NC> bl;
+            bl.lv = (int)(code % NV);
+            T kr[NC * N], fr[NC];
+#pragma unroll
+            for (int j = 0; j < NC * N; ++j)
+                kr[j] = T(0);
+#pragma unroll
+            for (int al = 0; al < NC; ++al)
+                fr[al] = T(0);
+            bl.kr = kr;
+            bl.fr = fr;
+            double X[3 * NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const double *pn = gi.nodes + 3 * (int64_t)id[v];
+                X[3 * v + 0] = pn[0];
+                X[3 * v + 1] = pn[1];
+                X[3 * v + 2] = pn[2];
+            }
+            // offset of each element node's first column in the row, or -1
+            int32_t slot[NV];
+#pragma unroll
+            for (int u = 0; u < NV; ++u)
+                slot[u] = -1;
+#pragma unroll
+            for (int c = 0; c < RC; ++c)
+#pragma unroll
+                for (int u = 0; u < NV; ++u)
+                    if (cols[c] == (int32_t)(NC * id[u]))
+                        slot[u] = c * NC;
+            for (int64_t j = (int64_t)RC * NC; j < len; j += NC) {
+                const int32_t c = ap.col_idx[r0 + j];
+#pragma unroll
+                for (int u = 0; u < NV; ++u)
+                    if (c == (int32_t)(NC * id[u]))
+                        slot[u] = (int32_t)j;
+            }
+            if constexpr (NC == 1) {
+                // the row's current values are loaded before the element is
+                // computed, so the loads overlap the arithmetic
+                int64_t p[N];
+                T old[N];
+#pragma unroll
+                for (int s = 0; s < N; ++s) {
+                    const int64_t q = r0 + slot[s];
+                    p[s] = (slot[s] >= 0 && q < nnz) ? q : -1;
+                    old[s] = p[s] >= 0 ? vals[p[s]] : T(0);
+                }
+                P::template apply_x<NT, REF>(a, st, ref, X, e, bl);
+#pragma unroll
+                for (int s = 0; s < N; ++s)
+                    if (p[s] >= 0)
+                        vals[p[s]] = old[s] + kr[s];
+            } else {
+                P::template apply_x<NT, REF>(a, st, ref, X, e, bl);
+                // row by row: the row's loads, then its stores
+#pragma unroll
+                for (int al = 0; al < NC; ++al) {
+                    int64_t p[N];
+                    T old[N];
+#pragma unroll
+                    for (int s = 0; s < N; ++s) {
+                        const int o = slot[s / NC];
+                        const int64_t q = r0 + (int64_t)al * len + o + s % NC;
+                        p[s] = (o >= 0 && q < nnz) ? q : -1;
+                        old[s] = p[s] >= 0 ? vals[p[s]] : T(0);
+                    }
+#pragma unroll
+                    for (int s = 0; s < N; ++s)
+                        if (p[s] >= 0)
+                            vals[p[s]] = old[s] + kr[al * N + s];
+                }
+            }
+#pragma unroll
+            for (int al = 0; al < NC; ++al)
+                fb[al] += fr[al];
+        }
+        if constexpr (WITH_B) {
+#pragma unroll
+            for (int al = 0; al < NC; ++al)
+                b[NC * i + al] += fb[al];
+        }
     }
 }
 
@@ -2024,6 +2275,15 @@ template <class P, int NV, int NC, typename T, int NT, int REF>
 void launch_fe_apply(const KArgs &a, const IdxArgs &gi, const ApplyArgs &ap, int atomic,
                      unsigned grid, unsigned block, hipStream_t stream)
 {
+    if (ap.vals && ap.inc) {
+        if (ap.b)
+            hipLaunchKernelGGL((fe_csr_rows_kernel<P, NV, NC, T, NT, REF, true>), dim3(grid),
+                               dim3(block), 0, stream, a, gi, ap);
+        else
+            hipLaunchKernelGGL((fe_csr_rows_kernel<P, NV, NC, T, NT, REF, false>), dim3(grid),
+                               dim3(block), 0, stream, a, gi, ap);
+        return;
+    }
     if (ap.vals) {
         if (atomic && ap.b)
             hipLaunchKernelGGL((fe_csr_kernel<P, NV, NC, T, NT, REF, true, true>), dim3(grid),

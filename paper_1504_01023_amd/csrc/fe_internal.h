@@ -140,6 +140,12 @@ struct ApplyArgs {
     const int32_t *col_idx;
     int64_t nnz;
     void *vals;
+    // Row ownership (inc != nullptr; the launch then runs over nodes): the
+    // elements at node i are inc[inc_ptr[i] .. inc_ptr[i + 1]), each coded
+    // element * n_vert + local vertex; the node's thread adds its rows.
+    const int64_t *inc_ptr;
+    const int32_t *inc;
+    int64_t n_own;  // nodes in this launch
 };
 typedef void (*ApplyLaunchFn)(const KArgs &, const IdxArgs &, const ApplyArgs &, int atomic,
                               unsigned grid, unsigned block, hipStream_t);

@@ -110,6 +110,10 @@ def lib():
         L.fe_csr_pattern.restype = i64
         L.fe_assemble_csr.argtypes = [P, i32, i64, vp, i64, vp, i64, vp, i64, R, vp, vp, i64, vp,
                                       vp, ctypes.POINTER(ctypes.c_int64), i32, vp]
+        L.fe_node_incidence.argtypes = [i32, i64, vp, i64, i64, vp, vp]
+        L.fe_node_incidence.restype = i64
+        L.fe_assemble_csr_rows.argtypes = [P, i32, i64, vp, i64, vp, i64, vp, i64, R, vp, vp, i64,
+                                           vp, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -411,15 +415,26 @@ def csr_pattern(elem, conn, n_nodes: int, n_comp: int = 1):
     return row_ptr, col_idx
 
 
-def assemble_csr(p: Problem, elem, nodes, conn, coeffs, rule: Rule, row_ptr, col_idx,
-                 values=None, b=None, color_ptr=None, n_elem: int | None = None, stream=None,
-                 with_b: bool = False):
-    """Assemble the global matrix into CSR values (values += sum of the
-    element matrices at their couplings) and, when b is given or with_b,
-    the load vector. row_ptr (int64) and col_idx (int32) are device tensors
-    of the pattern csr_pattern builds; values (nnz,) and b (n_nodes *
-    components,) device vectors in the tier's precision, zeroed here when not
-    given. color_ptr as for apply_indexed. Returns (values, b)."""
+def node_incidence(elem, conn, n_nodes: int):
+    """Elements at each node, built on the host. conn: (n_elem, n_vert)
+    integer array of node ids. Returns (inc_ptr int64 (n_nodes + 1,), inc
+    int32 (n_elem * n_vert,)) numpy arrays, inc coded element * n_vert +
+    local vertex."""
+    e = ELEM.get(elem, elem)
+    c = np.ascontiguousarray(np.asarray(conn).T.astype(np.int32))
+    n = c.shape[1]
+    inc_ptr = np.empty(int(n_nodes) + 1, dtype=np.int64)
+    inc = np.empty(n * c.shape[0], dtype=np.int32)
+    got = lib().fe_node_incidence(e, n, c.ctypes.data_as(ctypes.c_void_p), n, int(n_nodes),
+                                  inc_ptr.ctypes.data_as(ctypes.c_void_p),
+                                  inc.ctypes.data_as(ctypes.c_void_p))
+    if got < 0:
+        _check(-got)
+    return inc_ptr, inc
+
+
+def _csr_args(p: Problem, elem, nodes, conn, coeffs, rule: Rule, row_ptr, col_idx, values, b,
+              n_elem, with_b):
     import torch
     e = ELEM.get(elem, elem)
     nv = 4 if e == TET4 else 6
@@ -451,18 +466,50 @@ def assemble_csr(p: Problem, elem, nodes, conn, coeffs, rule: Rule, row_ptr, col
     if nc > 0:
         _check_coeffs(p, coeffs, dt, nc, ld_in)
     cptr = ctypes.c_void_p(coeffs.data_ptr()) if (coeffs is not None and nc > 0) else None
+    head = (ctypes.byref(p), e, n, ctypes.c_void_p(nodes.data_ptr()), nodes.shape[0],
+            ctypes.c_void_p(conn.data_ptr()), ld_conn, cptr, ld_in, ctypes.byref(rule.c),
+            ctypes.c_void_p(row_ptr.data_ptr()), ctypes.c_void_p(col_idx.data_ptr()), nnz,
+            ctypes.c_void_p(values.data_ptr()),
+            ctypes.c_void_p(b.data_ptr()) if b is not None else None)
+    return head, values, b
+
+
+def assemble_csr(p: Problem, elem, nodes, conn, coeffs, rule: Rule, row_ptr, col_idx,
+                 values=None, b=None, color_ptr=None, n_elem: int | None = None, stream=None,
+                 with_b: bool = False):
+    """Assemble the global matrix into CSR values (values += sum of the
+    element matrices at their couplings) and, when b is given or with_b,
+    the load vector. row_ptr (int64) and col_idx (int32) are device tensors
+    of the pattern csr_pattern builds; values (nnz,) and b (n_nodes *
+    components,) device vectors in the tier's precision, zeroed here when not
+    given. color_ptr as for apply_indexed. Returns (values, b)."""
+    head, values, b = _csr_args(p, elem, nodes, conn, coeffs, rule, row_ptr, col_idx, values, b,
+                                n_elem, with_b)
     if color_ptr is None:
         cp, ncol = None, 0
     else:
         cpa = np.ascontiguousarray(color_ptr, dtype=np.int64)
         cp, ncol = cpa.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(cpa) - 1
-    _check(lib().fe_assemble_csr(ctypes.byref(p), e, n, ctypes.c_void_p(nodes.data_ptr()),
-                                 nodes.shape[0], ctypes.c_void_p(conn.data_ptr()), ld_conn, cptr,
-                                 ld_in, ctypes.byref(rule.c), ctypes.c_void_p(row_ptr.data_ptr()),
-                                 ctypes.c_void_p(col_idx.data_ptr()), nnz,
-                                 ctypes.c_void_p(values.data_ptr()),
-                                 ctypes.c_void_p(b.data_ptr()) if b is not None else None,
-                                 cp, ncol, _stream_handle(stream)))
+    _check(lib().fe_assemble_csr(*head, cp, ncol, _stream_handle(stream)))
+    return values, b
+
+
+def assemble_csr_rows(p: Problem, elem, nodes, conn, coeffs, rule: Rule, row_ptr, col_idx,
+                      inc_ptr, inc, values=None, b=None, n_elem: int | None = None, stream=None,
+                      with_b: bool = False):
+    """The same assembly by row ownership (one lane per node, no colours, no
+    atomics). inc_ptr (int64, n_nodes + 1) and inc (int32) are device copies
+    of node_incidence's arrays. Returns (values, b)."""
+    import torch
+    head, values, b = _csr_args(p, elem, nodes, conn, coeffs, rule, row_ptr, col_idx, values, b,
+                                n_elem, with_b)
+    if not (inc_ptr.is_cuda and inc_ptr.dtype == torch.int64 and inc_ptr.is_contiguous()
+            and inc_ptr.numel() == nodes.shape[0] + 1):
+        raise ValueError("inc_ptr must be a contiguous int64 GPU vector of n_nodes + 1 values")
+    if not (inc.is_cuda and inc.dtype == torch.int32 and inc.is_contiguous()):
+        raise ValueError("inc must be a contiguous int32 GPU vector")
+    _check(lib().fe_assemble_csr_rows(*head, ctypes.c_void_p(inc_ptr.data_ptr()),
+                                      ctypes.c_void_p(inc.data_ptr()), _stream_handle(stream)))
     return values, b
 
 

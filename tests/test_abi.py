@@ -376,3 +376,41 @@ def test_assemble_csr_validation_before_launch():
     v = fe.problem("vector", "fp64", "element", inputs.ALL_VECTOR_MASK, None, "full")
     assert _csr_call(v, coeffs=0x9000) == 2                        # no assembly form
     assert _csr_call(p, rows=0, cols=0, vals=0, n=0) == 0          # nothing to do
+
+
+@pytest.mark.parametrize("elem", ["tet4", "prism6"])
+def test_node_incidence_matches_brute_force(elem):
+    mesh = inputs.tet_cube(3, 3) if elem == "tet4" else inputs.prism_layers(3, 3, 3)
+    nn = mesh.nodes.shape[0]
+    ip, inc = fe.node_incidence(elem, mesh.conn, nn)
+    nv = mesh.conn.shape[1]
+    want_ptr = [0]
+    want = []
+    for i in range(nn):
+        for e in range(mesh.n_elem):
+            for v in range(nv):
+                if mesh.conn[e, v] == i:
+                    want.append(e * nv + v)
+        want_ptr.append(len(want))
+    assert np.array_equal(ip, np.array(want_ptr, dtype=np.int64))
+    assert np.array_equal(inc, np.array(want, dtype=np.int32))
+
+
+def test_assemble_csr_rows_validation_before_launch():
+    L = fe.lib()
+    p = fe.problem("scalar", "fp64", "uniform", 0, inputs.identity_diffusion_uniform(), "packed")
+    rule = fe.builtin_rule("tet4", 1)
+    v = lambda a: ctypes.c_void_p(a) if a else None
+    call = lambda inc=0x9000, incp=0xa000, vals=0x7000, n=10: L.fe_assemble_csr_rows(
+        ctypes.byref(p), 0, n, v(0x8000), 10, v(0x1000), 10, None, 10, ctypes.byref(rule.c),
+        v(0x5000), v(0x6000), 100, v(vals), None, v(incp), v(inc), None)
+    assert call(inc=0) == 1
+    assert call(incp=0) == 1
+    assert call(vals=0) == 1
+    assert call(inc=0x9002) == 2
+    assert call(vals=0x7004) == 2
+    assert call(inc=0, incp=0, vals=0, n=0) == 0
+    conn = np.zeros((1, 4), dtype=np.int32)
+    assert L.fe_node_incidence(0, 1, conn.ctypes.data_as(ctypes.c_void_p), 1, 0,
+                               np.zeros(2, dtype=np.int64).ctypes.data_as(ctypes.c_void_p),
+                               None) == -1

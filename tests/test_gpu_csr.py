@@ -1,8 +1,9 @@
-"""GPU parity of the assembly into CSR storage (fe_assemble_csr, element
-matrices never stored) against the oracle's dense assembled matrix and load
-vector, coloured (deterministic) and atomic, FP64 and FP32; accumulation,
-ragged element counts, and the full-size tetrahedral mesh (exact symmetry,
-zero row sums, sampled rows against the oracle)."""
+"""GPU parity of the assembly into CSR storage (fe_assemble_csr and
+fe_assemble_csr_rows, element matrices never stored) against the oracle's
+dense assembled matrix and load vector: coloured (deterministic), atomic and
+by row ownership (deterministic), FP64 and FP32; accumulation, ragged
+element counts, and the full-size tetrahedral mesh (exact symmetry, zero row
+sums, sampled rows against the oracle)."""
 import numpy as np
 import pytest
 
@@ -44,7 +45,9 @@ def _setup(wl, precision, colour=True):
         coeffs = coeffs[:, torch.from_numpy(perm.astype(np.int64)).cuda()].contiguous()
     nodes = torch.from_numpy(wl.mesh.nodes).cuda().contiguous()
     rp, ci = fe.csr_pattern(wl.elem, wl.mesh.conn, nn, nc)
-    return dw, conn, coeffs, nodes, rp, ci, ptr
+    ip, inc = fe.node_incidence(wl.elem, wl.mesh.conn[perm], nn)
+    rows = (torch.from_numpy(ip).cuda(), torch.from_numpy(inc).cuda())
+    return dw, conn, coeffs, nodes, rp, ci, ptr, rows
 
 
 def _dense(rp, ci, vals):
@@ -79,7 +82,7 @@ def _small(name):
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_coloured_and_atomic_match_oracle(name, precision):
     wl = _small(name)
-    dw, conn, coeffs, nodes, rp, ci, ptr = _setup(wl, precision)
+    dw, conn, coeffs, nodes, rp, ci, ptr, rows = _setup(wl, precision)
     print(f"[csr] {name} {precision} n={wl.n_elem} nnz={len(ci)} colours={len(ptr) - 1}", flush=True)
     ref = P.assembly_reference(wl, precision)
     rpd = torch.from_numpy(rp).cuda()
@@ -89,15 +92,21 @@ def test_coloured_and_atomic_match_oracle(name, precision):
     v1, b1 = run(ptr)
     v2, b2 = run(ptr)
     v3, b3 = run(None)
+    own = lambda: fe.assemble_csr_rows(dw.problem, wl.elem, nodes, conn, coeffs, dw.rule, rpd, cid,
+                                       *rows, with_b=True)
+    v4, b4 = own()
+    v5, b5 = own()
     torch.cuda.synchronize()
     _check(_dense(rp, ci, v1), b1, ref, precision, rp, ci)
     _check(_dense(rp, ci, v3), b3, ref, precision, rp, ci)
+    _check(_dense(rp, ci, v4), b4, ref, precision, rp, ci)
     assert torch.equal(v1, v2) and torch.equal(b1, b2)
+    assert torch.equal(v4, v5) and torch.equal(b4, b5)
 
 
 def test_accumulates_ragged_and_without_load():
     wl = P.small("tet_cdr")
-    dw, conn, coeffs, nodes, rp, ci, _ = _setup(wl, "fp64", colour=False)
+    dw, conn, coeffs, nodes, rp, ci, _, _ = _setup(wl, "fp64", colour=False)
     rpd = torch.from_numpy(rp).cuda()
     cid = torch.from_numpy(ci).cuda()
     m = wl.n_elem - 37
@@ -125,24 +134,50 @@ def test_accumulates_ragged_and_without_load():
     assert torch.equal(vals, before)
 
 
-def test_full_size_tet_poisson():
+def test_ragged_rows_mode():
+    # row ownership over the first m elements: the incidence lists only those
+    wl = P.small("prism_cdr")
+    m = wl.n_elem - 37
+    dw, conn, coeffs, nodes, rp, ci, _, _ = _setup(wl, "fp64", colour=False)
+    ip, inc = fe.node_incidence(wl.elem, wl.mesh.conn[:m], wl.mesh.nodes.shape[0])
+    sub = inputs.Workload(wl.name, wl.elem, wl.kind, wl.n_q, wl.coef_mode, wl.mask, wl.uniform,
+                          wl.k_format, inputs.Mesh(wl.elem, wl.mesh.coords[:, :m], wl.mesh.nodes,
+                                                   wl.mesh.conn[:m], wl.mesh.boundary),
+                          wl.coeffs[:, :m])
+    ref = P.assembly_reference(sub, "fp64")
+    vals, b = fe.assemble_csr_rows(dw.problem, wl.elem, nodes, conn, coeffs, dw.rule,
+                                   torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda(),
+                                   torch.from_numpy(ip).cuda(), torch.from_numpy(inc).cuda(),
+                                   n_elem=m, with_b=True)
+    torch.cuda.synchronize()
+    _check(_dense(rp, ci, vals), b, ref, "fp64", rp, ci)
+
+
+@pytest.mark.parametrize("mode", ["coloured", "rows"])
+def test_full_size_tet_poisson(mode):
     # the headline mesh (10,110,954 tetrahedra), Laplacian with d^0 = 1,
-    # packed symmetric K, coloured: every entry and its mirror receive the
-    # same contributions in the same order, so A is exactly symmetric
+    # packed symmetric K: in both deterministic modes every entry and its
+    # mirror receive the same contributions in the same order, so A is
+    # exactly symmetric
     wl = inputs.tet_poisson(119, 1)
     nn = wl.mesh.nodes.shape[0]
-    dw, conn, coeffs, nodes, rp, ci, ptr = _setup(wl, "fp64")
-    print(f"[csr] full n={wl.n_elem} nodes={nn} nnz={len(ci)} colours={len(ptr) - 1}", flush=True)
+    dw, conn, coeffs, nodes, rp, ci, ptr, rows = _setup(wl, "fp64")
+    print(f"[csr] full {mode} n={wl.n_elem} nodes={nn} nnz={len(ci)} colours={len(ptr) - 1}",
+          flush=True)
     rpd = torch.from_numpy(rp).cuda()
     cid = torch.from_numpy(ci).cuda()
-    vals, b = fe.assemble_csr(dw.problem, wl.elem, nodes, conn, coeffs, dw.rule, rpd, cid,
-                              color_ptr=ptr, with_b=True)
+    if mode == "coloured":
+        vals, b = fe.assemble_csr(dw.problem, wl.elem, nodes, conn, coeffs, dw.rule, rpd, cid,
+                                  color_ptr=ptr, with_b=True)
+    else:
+        vals, b = fe.assemble_csr_rows(dw.problem, wl.elem, nodes, conn, coeffs, dw.rule, rpd,
+                                       cid, *rows, with_b=True)
     torch.cuda.synchronize()
     v = vals.cpu().numpy()
-    rows = np.repeat(np.arange(nn), np.diff(rp))
+    rows_of = np.repeat(np.arange(nn), np.diff(rp))
     # exact symmetry: entry (i, j) equals entry (j, i)
-    key = rows.astype(np.int64) * nn + ci
-    tkey = ci.astype(np.int64) * nn + rows
+    key = rows_of.astype(np.int64) * nn + ci
+    tkey = ci.astype(np.int64) * nn + rows_of
     pos = np.searchsorted(key, tkey)
     assert np.array_equal(key[pos], tkey)
     assert np.array_equal(v[pos], v)

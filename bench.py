@@ -524,7 +524,8 @@ def run_paper(a, torch, fe) -> dict:
 
 
 NATURAL_BASES = ("tet_poisson", "tet_poisson_qp", "tet_cdr", "tet_elasticity", "prism_cdr",
-                 "prism_poisson_qp")
+                 "prism_poisson_qp", "prism_cdr_qp", "prism_elasticity", "tet_vector",
+                 "prism_vector")
 APPLY_BASES = ("tet_poisson", "tet_cdr", "tet_elasticity", "prism_cdr", "prism_poisson_qp")
 
 

@@ -693,14 +693,28 @@ int fe_integrate_natural(const fe_problem *problem, fe_elem_type elem_type, int6
     ao.f_magic = magic(ao.f_rows);
     const int nv = elem_type == FE_TET4 ? 4 : 6;
     // the outputs reuse the inputs' LDS (every input of an element is read
-    // before its first output is written, and a tile is one wavefront)
+    // before its first output is written, and a tile is one wavefront),
+    // except for the 3-component problems, whose block loop reads
+    // coefficients after storing earlier blocks: their outputs follow the
+    // inputs
     const size_t in_b = 8 * 3 * nv + (size_t)ao.tsize * ao.coef_rows;
     const size_t out_b = (size_t)ao.tsize * (ao.k_rows + ao.f_rows);
-    const size_t lds = (size_t)AOS_TILE * (in_b > out_b ? in_b : out_b);
-    if (lds > 64 * 1024)
+    const bool separate = problem->kind == FE_VECTOR_CDR;
+    const size_t lds = (size_t)AOS_TILE * (separate ? in_b + out_b : (in_b > out_b ? in_b : out_b));
+    // the device's LDS per workgroup (160 KiB on gfx950; 64 KiB when it
+    // cannot be queried) less the kernel's static reference tables
+    size_t lds_max = 64 * 1024;
+    int dev = 0, attr = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&attr, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+        attr > 0)
+        lds_max = (size_t)attr;
+    (void)hipGetLastError();
+    const size_t lds_dyn_max = lds_max > 2048 ? lds_max - 2048 : 0;
+    if (lds > lds_dyn_max)
         return fail(FE_ERR_UNSUPPORTED,
-                    "natural order needs %zu bytes of LDS per tile of %d elements (limit 65536)", lds,
-                    AOS_TILE);
+                    "natural order needs %zu bytes of LDS per tile of %d elements (limit %zu)", lds,
+                    AOS_TILE, lds_dyn_max);
     if (n_elem == 0)
         return FE_OK;
     int64_t grid = (n_elem + AOS_TILE - 1) / AOS_TILE;

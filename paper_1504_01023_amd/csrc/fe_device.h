@@ -1016,6 +1016,8 @@ struct TetScalar {
 template <typename T, int MODE>
 struct TetVector {
     static constexpr bool PER_QP = (MODE == M_QP);
+    // each block's coefficients are read after earlier blocks are stored
+    static constexpr bool INTERLEAVED_IO = true;
     typedef TetScalar<T, TS_FULL, MODE, 0, VecBlock> P;
 
     template <int V, int NT, int REF, class S>
@@ -1454,6 +1456,8 @@ struct PrismScalar {
 // Jacobian terms are recomputed for each block).
 template <typename T, int MODE, int NQ>
 struct PrismVector {
+    // each block's coefficients are read after earlier blocks are stored
+    static constexpr bool INTERLEAVED_IO = true;
     template <int V, int NT, int REF, class S>
     __device__ __forceinline__ static void run(const KArgs &a, const S &st, const Ref<REF> &ref,
                                                int64_t e)
@@ -2365,8 +2369,18 @@ void launch_fe_kernel_lanes(const KArgs &a, unsigned grid, unsigned block, hipSt
 // outputs [K rows | F rows] over the same bytes: the problem classes read
 // every input of an element before they write its first output, and the
 // one wavefront executes its instructions in order, so no lane's output
-// overwrites an input another lane has still to read.
+// overwrites an input another lane has still to read (except those marked
+// INTERLEAVED_IO below, whose outputs get bytes of their own).
 __device__ __forceinline__ uint32_t div_magic(uint32_t i, uint32_t magic) { return __umulhi(i, magic); }
+
+// Problem classes whose block loop reads the next block's coefficients
+// after storing earlier blocks (INTERLEAVED_IO) break that order; for them
+// the outputs follow the inputs in LDS instead of sharing their bytes.
+template <class P, class = void>
+struct aos_separate : std::false_type {};
+template <class P>
+struct aos_separate<P, std::void_t<decltype(P::INTERLEAVED_IO)>>
+    : std::integral_constant<bool, P::INTERLEAVED_IO> {};
 
 template <class P, int NV, int NT, int REF>
 __global__ __launch_bounds__(64) void fe_kernel_aos(KArgs a, AosArgs ao)
@@ -2387,7 +2401,8 @@ __global__ __launch_bounds__(64) void fe_kernel_aos(KArgs a, AosArgs ao)
     constexpr int NC3 = 3 * NV;
     double *l_x = reinterpret_cast<double *>(lds_raw);
     unsigned char *l_c = lds_raw + sizeof(double) * NC3 * AOS_TILE;
-    unsigned char *l_k = lds_raw;
+    unsigned char *l_k =
+        aos_separate<P>::value ? l_c + (size_t)ao.tsize * ao.coef_rows * AOS_TILE : lds_raw;
     unsigned char *l_f = l_k + (size_t)ao.tsize * ao.k_rows * AOS_TILE;
     const Streams st{l_x, l_c, l_k, l_f, AOS_TILE, AOS_TILE};
     const int lane = threadIdx.x;

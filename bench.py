@@ -357,7 +357,7 @@ def run_served(a, torch, fe, serve) -> dict:
     rng = np.random.default_rng(55)
     sample_ids = set(int(x) for x in rng.choice(n_meas, size=min(20, n_meas), replace=False))
     with serve.Server(kinds, max_slots=a.served_slots, hbm_budget_bytes=budget, max_chunks=2048,
-                      chunk_elems=4096, blocks_per_kind=0) as srv:
+                      chunk_elems=4096, blocks_per_kind=a.served_blocks_per_kind) as srv:
         # warm-up
         for r in reqs[:n_warm]:
             cp, kp, ld = host_ptrs(r)
@@ -726,6 +726,8 @@ def main() -> int:
                     help="pad the output leading dimension to a multiple of this many elements "
                          "(0: ld = n_elem)")
     ap.add_argument("--served-requests", type=int, default=1000)
+    ap.add_argument("--served-blocks-per-kind", type=int, default=0,
+                    help="workgroups of each kind's persistent batched kernel (0: the library's default)")
     ap.add_argument("--served-warmup", type=int, default=50)
     ap.add_argument("--served-slots", type=int, default=64)
     ap.add_argument("--served-rho", type=float, nargs="*", default=[0.5, 0.7, 0.9])

@@ -424,7 +424,7 @@ typedef struct fe_batch fe_batch;
 
 /* Create a batcher for n_kinds kinds (1..FE_MAX_BATCH_KINDS) with a table of
  * max_chunks chunks of chunk_elems elements (a multiple of 4) and
- * blocks_per_kind workgroups per persistent kernel (0 = 1024). Allocates the
+ * blocks_per_kind workgroups per persistent kernel (0 = 4096). Allocates the
  * device and pinned host tables and captures the graphs on the current
  * device. Kernel variants come from the tuning table as at creation. */
 FE_API int fe_batch_create(const fe_batch_kind *kinds, int n_kinds, int max_chunks,
@@ -468,7 +468,7 @@ typedef struct fe_server_config {
     int32_t max_slots;           /* requests admitted and not yet complete */
     int64_t hbm_budget_bytes;    /* device arena for inputs and outputs */
     int32_t max_chunks;          /* chunks per launch (tick) */
-    int32_t blocks_per_kind;     /* persistent workgroups per kind (0 = 1024) */
+    int32_t blocks_per_kind;     /* persistent workgroups per kind (0 = 4096) */
     int64_t chunk_elems;         /* elements per chunk, multiple of 4 */
     int32_t backend;             /* FE_SERVER_GPU or FE_SERVER_FAKE */
     int32_t reserved;

@@ -527,7 +527,7 @@ NATURAL_BASES = ("tet_poisson", "tet_poisson_qp", "tet_cdr", "tet_elasticity", "
                  "prism_poisson_qp", "prism_cdr_qp", "prism_elasticity", "tet_vector",
                  "prism_vector")
 APPLY_BASES = ("tet_poisson", "tet_cdr", "tet_elasticity", "prism_cdr", "prism_poisson_qp",
-               "prism_elasticity")
+               "prism_elasticity", "tet_vector", "prism_vector")
 
 
 def run_apply(a, torch, fe, oracle, base: str, dev, csr: bool = False) -> dict:

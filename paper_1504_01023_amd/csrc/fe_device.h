@@ -320,6 +320,27 @@ struct VecBlock {
     }
 };
 
+// The (A, B) block of a 3-component problem handed to a consumer of whole
+// element matrices (matrix-free application, assembly): block entry (r, s)
+// is entry (3r + A, 3s + B) of the full 3NS x 3NS matrix, F entry r of a
+// B = 0 block is entry 3r + A. Coefficient addressing is VecBlock's.
+template <class IN>
+struct VecConsumer : VecBlock {
+    const IN *in;
+    __device__ __forceinline__ bool with_f() const { return B == 0 && in->with_f(); }
+    template <int V, int NT, typename U>
+    __device__ __forceinline__ void put_k(const Streams &st, int NS, int, int r, int s, int64_t e0,
+                                          const U (&val)[V]) const
+    {
+        in->template put_k<V, NT>(st, 3 * NS, 0, 3 * r + A, 3 * s + B, e0, val);
+    }
+    template <int V, int NT, typename U>
+    __device__ __forceinline__ void put_f(const Streams &st, int r, int64_t e0, const U (&val)[V]) const
+    {
+        in->template put_f<V, NT>(st, 3 * r + A, e0, val);
+    }
+};
+
 // Matrix-free consumer of one element's results (one element per lane): K
 // is applied to the element's nodal values x as its entries are produced,
 // y_r += K_rs x_s (and y_s += K_rs x_r for the mirrored entry of a packed
@@ -1037,6 +1058,25 @@ struct TetVector {
                 P::template run_const<V, NT>(a, st, X, e0, bl);
         }
     }
+
+    // Matrix-free and assembly consumers: the nine blocks handed to bl.
+    template <int NT, int REF, class B2>
+    __device__ __forceinline__ static void apply_x(const KArgs &a, const Streams &st, const Ref<REF> &ref,
+                                                   const double (&X)[12], int64_t e, const B2 &bl)
+    {
+        const double (&Xv)[1][12] = reinterpret_cast<const double (&)[1][12]>(X);
+#pragma unroll 1
+        for (int b = 0; b < 9; ++b) {
+            VecConsumer<B2> vb;
+            vb.A = b / 3;
+            vb.B = b % 3;
+            vb.in = &bl;
+            if constexpr (PER_QP)
+                P::template run_qp<1, NT, REF>(a, st, ref, Xv, e, vb);
+            else
+                P::template run_const<1, NT>(a, st, Xv, e, vb);
+        }
+    }
 };
 
 // ================================================= tetrahedron, elasticity
@@ -1477,6 +1517,27 @@ struct PrismVector {
         for (int b = 0; b < 9; ++b)
             PrismScalar<T, TS_FULL, MODE, 0, NQ, VecBlock>::template body<NT>(a, st, ref, e, X0, X,
                                                                                VecBlock{b / 3, b % 3});
+    }
+
+    // Matrix-free and assembly consumers: the nine blocks handed to bl.
+    template <int NT, int REF, class B2>
+    __device__ __forceinline__ static void apply_x(const KArgs &a, const Streams &st, const Ref<REF> &ref,
+                                                   const double (&Xa)[18], int64_t e, const B2 &bl)
+    {
+        double X[18];
+#pragma unroll
+        for (int s = 0; s < 18; ++s)
+            X[s] = Xa[s];
+        const double X0[3] = {X[0], X[1], X[2]};
+        to_edge_vectors<6>(X);
+#pragma unroll 1
+        for (int b = 0; b < 9; ++b) {
+            VecConsumer<B2> vb;
+            vb.A = b / 3;
+            vb.B = b % 3;
+            vb.in = &bl;
+            PrismScalar<T, TS_FULL, MODE, 0, NQ, VecBlock>::template body<NT>(a, st, ref, e, X0, X, vb);
+        }
     }
 };
 

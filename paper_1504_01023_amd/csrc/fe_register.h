@@ -8,9 +8,9 @@
 namespace fe {
 
 // Registers the plain kernel; B = 1 also registers the batched (persistent)
-// form and the indexed-geometry form, and, when the problem class has one,
-// the matrix-free form (ap). The natural-order form (ao) is registered as
-// given.
+// form and the indexed-geometry form. The consumer form (ap: matrix-free
+// application and assembly) and the natural-order form (ao) are registered
+// as given.
 template <class P, int V, int NT, int REF, int B = 0>
 inline void reg(int elem, int kind, int prec, int terms, int mode, int packed, int nq, int split = 1,
                 int order = 1, ApplyLaunchFn ap = nullptr, AosLaunchFn ao = nullptr)
@@ -24,7 +24,7 @@ inline void reg(int elem, int kind, int prec, int terms, int mode, int packed, i
     }
     register_kernel(KernelEntry{k, &launch_fe_kernel<P, V, NT, REF>,
                                 reinterpret_cast<const void *>(&fe_kernel<P, V, NT, REF>), bl,
-                                il, B != 0 ? ap : nullptr, ao});
+                                il, ap, ao});
 }
 
 // The natural-order form of a problem class with NV vertices, for the base
@@ -117,7 +117,8 @@ template <typename T, int MODE, int V, int NT>
 inline void reg_tet_vector()
 {
     typedef TetVector<T, MODE> P;
-    reg<P, V, NT, REF_KARG>(FE_TET4, FE_VECTOR_CDR, prec_of<T>(), TS_FULL, MODE, 0, 0, 1, 1, nullptr,
+    reg<P, V, NT, REF_KARG>(FE_TET4, FE_VECTOR_CDR, prec_of<T>(), TS_FULL, MODE, 0, 0, 1, 1,
+                            apply_form<P, 4, 3, T, V, NT, REF_KARG, V == 1 && NT == 1>(),
                             aos_form<P, 4, V, NT, REF_KARG, V == 1 && NT == 1>());
 }
 
@@ -125,7 +126,8 @@ template <typename T, int MODE, int NQ, int NT, int REF>
 inline void reg_prism_vector()
 {
     typedef PrismVector<T, MODE, NQ> P;
-    reg<P, 1, NT, REF>(FE_PRISM6, FE_VECTOR_CDR, prec_of<T>(), TS_FULL, MODE, 0, NQ, 1, 1, nullptr,
+    reg<P, 1, NT, REF>(FE_PRISM6, FE_VECTOR_CDR, prec_of<T>(), TS_FULL, MODE, 0, NQ, 1, 1,
+                       apply_form<P, 6, 3, T, 1, NT, REF, NT == 1 && REF == REF_KARG>(),
                        aos_form<P, 6, 1, NT, REF, NT == 1 && REF == REF_KARG>());
 }
 

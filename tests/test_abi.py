@@ -267,15 +267,15 @@ def test_colouring_errors():
 
 
 def _apply_call(p, color_ptr=None, n_colors=0, x=0x5000, y=0x6000, nodes=0x7000, n_nodes=10,
-                coeffs=None):
+                coeffs=None, elem=0):
     L = fe.lib()
-    rule = fe.builtin_rule("tet4", 1)
+    rule = fe.builtin_rule("tet4", 1) if elem == 0 else fe.builtin_rule("prism6", 6)
     cp = None
     if color_ptr is not None:
         arr = np.asarray(color_ptr, dtype=np.int64)
         cp = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
         _apply_call.keep = arr
-    return L.fe_apply_indexed(ctypes.byref(p), 0, 10, ctypes.c_void_p(nodes), n_nodes,
+    return L.fe_apply_indexed(ctypes.byref(p), elem, 10, ctypes.c_void_p(nodes), n_nodes,
                               ctypes.c_void_p(0x1000), 10,
                               ctypes.c_void_p(coeffs) if coeffs else None, 10, ctypes.byref(rule.c),
                               ctypes.c_void_p(x) if x else None, ctypes.c_void_p(y) if y else None,
@@ -289,8 +289,9 @@ def test_apply_validation_before_launch():
     assert _apply_call(p, color_ptr=[0, 4], n_colors=1) == 1      # does not reach n_elem
     assert _apply_call(p, color_ptr=[0, 6, 4, 10], n_colors=3) == 1
     assert _apply_call(p, n_colors=2) == 1                        # colours without offsets
-    v = fe.problem("vector", "fp64", "element", inputs.ALL_VECTOR_MASK, None, "full")
-    assert _apply_call(v, coeffs=0x8000) == 2                     # no matrix-free form
+    # prism elasticity with per-point coefficients has no matrix-free form
+    pq = fe.problem("elasticity", "fp64", "qp", inputs.ALL_ELAST_MASK, None, "packed")
+    assert _apply_call(pq, coeffs=0x8000, elem=1) == 2
     e = fe.problem("elasticity", "fp64", "uniform", 0, [1.0, 0.3, 0, 0, 0], "packed")
     assert _apply_call(e, y=0x6004) == 2                          # misaligned y
 
@@ -356,11 +357,12 @@ def test_csr_pattern_errors_and_isolated_nodes():
     assert fe.lib().fe_last_error()
 
 
-def _csr_call(p, rows=0x5000, cols=0x6000, nnz=100, vals=0x7000, b=None, n=10, coeffs=None):
+def _csr_call(p, rows=0x5000, cols=0x6000, nnz=100, vals=0x7000, b=None, n=10, coeffs=None,
+              elem=0):
     L = fe.lib()
-    rule = fe.builtin_rule("tet4", 1)
+    rule = fe.builtin_rule("tet4", 1) if elem == 0 else fe.builtin_rule("prism6", 6)
     v = lambda a: ctypes.c_void_p(a) if a else None
-    return L.fe_assemble_csr(ctypes.byref(p), 0, n, ctypes.c_void_p(0x8000), 10,
+    return L.fe_assemble_csr(ctypes.byref(p), elem, n, ctypes.c_void_p(0x8000), 10,
                              ctypes.c_void_p(0x1000), 10, v(coeffs), 10, ctypes.byref(rule.c),
                              v(rows), v(cols), nnz, v(vals), v(b), None, 0, None)
 
@@ -373,8 +375,8 @@ def test_assemble_csr_validation_before_launch():
     assert _csr_call(p, nnz=-1) == 1
     assert _csr_call(p, rows=0x5004) == 2                          # misaligned row_ptr
     assert _csr_call(p, vals=0x7004) == 2                          # misaligned values
-    v = fe.problem("vector", "fp64", "element", inputs.ALL_VECTOR_MASK, None, "full")
-    assert _csr_call(v, coeffs=0x9000) == 2                        # no assembly form
+    pq = fe.problem("elasticity", "fp64", "qp", inputs.ALL_ELAST_MASK, None, "packed")
+    assert _csr_call(pq, coeffs=0x9000, elem=1) == 2               # no assembly form
     assert _csr_call(p, rows=0, cols=0, vals=0, n=0) == 0          # nothing to do
 
 

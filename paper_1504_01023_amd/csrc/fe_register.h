@@ -112,12 +112,14 @@ inline void reg_prism_elastic()
 }
 
 // General 3-component CDR (coefficients per element or per point, full K).
-// (natural order for the streaming one-element-per-lane variants)
+// (batched, indexed, consumer and natural-order forms for the streaming
+// one-element-per-lane variants)
 template <typename T, int MODE, int V, int NT>
 inline void reg_tet_vector()
 {
     typedef TetVector<T, MODE> P;
-    reg<P, V, NT, REF_KARG>(FE_TET4, FE_VECTOR_CDR, prec_of<T>(), TS_FULL, MODE, 0, 0, 1, 1,
+    reg<P, V, NT, REF_KARG, V == 1 && NT == 1>(FE_TET4, FE_VECTOR_CDR, prec_of<T>(), TS_FULL, MODE, 0,
+                                              0, 1, 1,
                             apply_form<P, 4, 3, T, V, NT, REF_KARG, V == 1 && NT == 1>(),
                             aos_form<P, 4, V, NT, REF_KARG, V == 1 && NT == 1>());
 }
@@ -126,7 +128,8 @@ template <typename T, int MODE, int NQ, int NT, int REF>
 inline void reg_prism_vector()
 {
     typedef PrismVector<T, MODE, NQ> P;
-    reg<P, 1, NT, REF>(FE_PRISM6, FE_VECTOR_CDR, prec_of<T>(), TS_FULL, MODE, 0, NQ, 1, 1,
+    reg<P, 1, NT, REF, NT == 1 && REF == REF_KARG>(FE_PRISM6, FE_VECTOR_CDR, prec_of<T>(), TS_FULL,
+                                                   MODE, 0, NQ, 1, 1,
                        apply_form<P, 6, 3, T, 1, NT, REF, NT == 1 && REF == REF_KARG>(),
                        aos_form<P, 6, 1, NT, REF, NT == 1 && REF == REF_KARG>());
 }

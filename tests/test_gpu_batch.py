@@ -27,9 +27,11 @@ def _requests(seed):
         lambda s: inputs.tet_elasticity(int(rng.integers(2, 6)), seed=s),
         lambda s: inputs.prism_cdr_element(int(rng.integers(2, 8)), int(rng.integers(2, 6)), seed=s),
         lambda s: inputs.prism_elasticity(int(rng.integers(2, 6)), int(rng.integers(2, 5)), seed=s),
+        lambda s: inputs.tet_vector(int(rng.integers(2, 5)), seed=s),
+        lambda s: inputs.prism_vector(int(rng.integers(2, 5)), int(rng.integers(2, 4)), seed=s),
     ]
-    for i in range(14):
-        k = int(rng.integers(0, 4))
+    for i in range(18):
+        k = int(rng.integers(0, len(makers)))
         prec = "fp64" if rng.random() < 0.5 else "fp32"
         reqs.append((k, prec, makers[k](100 + i)))
     return reqs
@@ -39,7 +41,7 @@ def _kind_list():
     ks = []
     for prec in ("fp64", "fp32"):
         for wl in (P.small("tet_cdr"), P.small("tet_elasticity"), P.small("prism_cdr"),
-                   P.small("prism_elasticity")):
+                   P.small("prism_elasticity"), P.small("tet_vector"), P.small("prism_vector")):
             ks.append((fe.problem_for(wl, prec), wl.elem, fe.builtin_rule(wl.elem, wl.n_q)))
     return ks
 
@@ -50,7 +52,7 @@ def test_batch_matches_plain_bitwise_and_oracle():
     reqs = _requests(7)
     outs, plain = [], []
     for k, prec, wl in reqs:
-        kind = k + (0 if prec == "fp64" else 4)
+        kind = k + (0 if prec == "fp64" else 6)
         dw = fe.to_device(wl, prec)
         p = kinds[kind][0]
         nk, nf = fe.k_entries(p, wl.elem), fe.f_entries(p, wl.elem)

@@ -261,7 +261,7 @@ def test_variants_are_bitwise_identical(name):
 
 
 @pytest.mark.parametrize("name", ["tet_poisson", "tet_cdr", "tet_elasticity", "prism_cdr_qp",
-                                  "prism_elasticity"])
+                                  "prism_elasticity", "tet_vector", "prism_vector"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_indexed_geometry(name, precision):
     """Coordinates gathered from the node array through the connectivity give

@@ -250,8 +250,8 @@ FE_API int fe_integrate_natural(const fe_problem *problem, fe_elem_type elem_typ
  * is one launch with plain read-add-write updates: the result is
  * deterministic. n_colors = 0: one launch with hardware atomic adds, in
  * whatever order the elements run (the last bits may vary between runs).
- * Built for every problem class (prism elasticity with element-constant
- * coefficients only); others return FE_ERR_UNSUPPORTED. Node ids outside [0, n_nodes)
+ * Built for every problem class; coefficient modes a class lacks return
+ * FE_ERR_UNSUPPORTED. Node ids outside [0, n_nodes)
  * are clamped. Enqueued on `stream`; no allocation. */
 FE_API int fe_apply_indexed(const fe_problem *problem, fe_elem_type elem_type, int64_t n_elem,
                             const double *nodes, int64_t n_nodes, const int32_t *conn,

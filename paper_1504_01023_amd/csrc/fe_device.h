@@ -1858,35 +1858,119 @@ struct PrismElastic {
         }
     }
 
-    // Matrix-free and assembly consumers (element-constant coefficients):
-    // absolute vertex coordinates in, K and F handed to bl one row block per
-    // pass over the points (six passes: at most 51 live accumulators next to
-    // the consumer's own arrays).
+    // Per-point coefficients, rows 3*R0 .. 3*R1-1 of K (and F when WITH_F)
+    // for a consumer: lambda_q, mu_q and f_q at every point.
+    template <int R0, int R1, bool WITH_F, int NT, int REF, class B2>
+    __device__ __forceinline__ static void qp_pass(const KArgs &a, const Streams &st,
+                                                   const Ref<REF> &ref, const double (&X)[18],
+                                                   int64_t e, const B2 &bl)
+    {
+        constexpr int K0 = pidx(18, 3 * R0, 3 * R0);
+        constexpr int K1 = R1 == 6 ? NP : pidx(18, 3 * R1, 3 * R1);
+        T Kp[K1 - K0], F[18];
+#pragma unroll
+        for (int k = 0; k < K1 - K0; ++k)
+            Kp[k] = T(0);
+#pragma unroll
+        for (int k = 0; k < 18; ++k)
+            F[k] = T(0);
+        const int nq = NQ > 0 ? NQ : a.n_q;
+#pragma unroll(NQ > 0 ? NQ : 1)
+        for (int q = 0; q < nq; ++q) {
+            T E[1], nu[1], f[3][1];
+            coef<T, MODE, SL, 1, NT>(a, st, 0, q, e, E);
+            coef<T, MODE, SL, 1, NT>(a, st, 1, q, e, nu);
+            if constexpr (WITH_F) {
+#pragma unroll
+                for (int al = 0; al < 3; ++al)
+                    coef<T, MODE, SL, 1, NT>(a, st, 2 + al, q, e, f[al]);
+            }
+            T lam, mu;
+            lame<T>(E[0], nu[0], lam, mu);
+            T g[6][3], vol;
+            point_geometry<6, T>(X, ref, q, g, vol);
+            const T vl = vol * lam, vm = vol * mu;
+            if constexpr (WITH_F) {
+#pragma unroll
+                for (int r = 0; r < 6; ++r) {
+                    const T pq = vol * (T)ref.phi(q, r);
+#pragma unroll
+                    for (int al = 0; al < 3; ++al)
+                        F[3 * r + al] += pq * f[al][0];
+                }
+            }
+#pragma unroll
+            for (int r = R0; r < R1; ++r)
+#pragma unroll
+                for (int s = r; s < 6; ++s) {
+                    const T dot = vm * (g[r][0] * g[s][0] + g[r][1] * g[s][1] + g[r][2] * g[s][2]);
+#pragma unroll
+                    for (int al = 0; al < 3; ++al)
+#pragma unroll
+                        for (int be = (s == r ? al : 0); be < 3; ++be) {
+                            T x = vl * g[r][al] * g[s][be] + vm * g[r][be] * g[s][al];
+                            if (al == be)
+                                x += dot;
+                            Kp[pidx(18, 3 * r + al, 3 * s + be) - K0] += x;
+                        }
+                }
+        }
+#pragma unroll
+        for (int r = R0; r < R1; ++r)
+#pragma unroll
+            for (int s = r; s < 6; ++s)
+#pragma unroll
+                for (int al = 0; al < 3; ++al)
+#pragma unroll
+                    for (int be = (s == r ? al : 0); be < 3; ++be) {
+                        const T v[1] = {Kp[pidx(18, 3 * r + al, 3 * s + be) - K0]};
+                        bl.template put_k<1, NT>(st, 18, 1, 3 * r + al, 3 * s + be, e, v);
+                    }
+        if constexpr (WITH_F) {
+#pragma unroll
+            for (int k = 0; k < 18; ++k) {
+                const T v[1] = {F[k]};
+                bl.template put_f<1, NT>(st, k, e, v);
+            }
+        }
+    }
+
+    // Matrix-free and assembly consumers: absolute vertex coordinates in, K
+    // and F handed to bl one row block per pass over the points (six passes:
+    // at most 51 live accumulators next to the consumer's own arrays).
     template <int NT, int REF, class B2>
     __device__ __forceinline__ static void apply_x(const KArgs &a, const Streams &st, const Ref<REF> &ref,
                                                    const double (&Xa)[18], int64_t e, const B2 &bl)
     {
-        static_assert(!PER_QP, "the consumer forms take element-constant coefficients");
         double X[18];
 #pragma unroll
         for (int s = 0; s < 18; ++s)
             X[s] = Xa[s];
         to_edge_vectors<6>(X);
-        T E[1], nu[1], fc[3][1];
-        coef<T, MODE, SL, 1, NT>(a, st, 0, 0, e, E);
-        coef<T, MODE, SL, 1, NT>(a, st, 1, 0, e, nu);
+        if constexpr (PER_QP) {
+            qp_pass<0, 1, true, NT, REF, B2>(a, st, ref, X, e, bl);
+            qp_pass<1, 2, false, NT, REF, B2>(a, st, ref, X, e, bl);
+            qp_pass<2, 3, false, NT, REF, B2>(a, st, ref, X, e, bl);
+            qp_pass<3, 4, false, NT, REF, B2>(a, st, ref, X, e, bl);
+            qp_pass<4, 5, false, NT, REF, B2>(a, st, ref, X, e, bl);
+            qp_pass<5, 6, false, NT, REF, B2>(a, st, ref, X, e, bl);
+        } else {
+            T E[1], nu[1], fc[3][1];
+            coef<T, MODE, SL, 1, NT>(a, st, 0, 0, e, E);
+            coef<T, MODE, SL, 1, NT>(a, st, 1, 0, e, nu);
 #pragma unroll
-        for (int al = 0; al < 3; ++al)
-            coef<T, MODE, SL, 1, NT>(a, st, 2 + al, 0, e, fc[al]);
-        T lam, mu;
-        lame<T>(E[0], nu[0], lam, mu);
-        const T fv[3] = {fc[0][0], fc[1][0], fc[2][0]};
-        const_pass<0, 1, true, NT, REF, B2>(a, st, ref, X, e, lam, mu, fv, &bl);
-        const_pass<1, 2, false, NT, REF, B2>(a, st, ref, X, e, lam, mu, fv, &bl);
-        const_pass<2, 3, false, NT, REF, B2>(a, st, ref, X, e, lam, mu, fv, &bl);
-        const_pass<3, 4, false, NT, REF, B2>(a, st, ref, X, e, lam, mu, fv, &bl);
-        const_pass<4, 5, false, NT, REF, B2>(a, st, ref, X, e, lam, mu, fv, &bl);
-        const_pass<5, 6, false, NT, REF, B2>(a, st, ref, X, e, lam, mu, fv, &bl);
+            for (int al = 0; al < 3; ++al)
+                coef<T, MODE, SL, 1, NT>(a, st, 2 + al, 0, e, fc[al]);
+            T lam, mu;
+            lame<T>(E[0], nu[0], lam, mu);
+            const T fv[3] = {fc[0][0], fc[1][0], fc[2][0]};
+            const_pass<0, 1, true, NT, REF, B2>(a, st, ref, X, e, lam, mu, fv, &bl);
+            const_pass<1, 2, false, NT, REF, B2>(a, st, ref, X, e, lam, mu, fv, &bl);
+            const_pass<2, 3, false, NT, REF, B2>(a, st, ref, X, e, lam, mu, fv, &bl);
+            const_pass<3, 4, false, NT, REF, B2>(a, st, ref, X, e, lam, mu, fv, &bl);
+            const_pass<4, 5, false, NT, REF, B2>(a, st, ref, X, e, lam, mu, fv, &bl);
+            const_pass<5, 6, false, NT, REF, B2>(a, st, ref, X, e, lam, mu, fv, &bl);
+        }
     }
 
     template <int V, int NT, int REF, class S>

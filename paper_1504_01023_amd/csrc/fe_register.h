@@ -103,12 +103,8 @@ template <typename T, int MODE, int PK, int NQ, int NT, int REF, int B = 0, int 
 inline void reg_prism_elastic()
 {
     typedef PrismElastic<T, MODE, PK, NQ, SPLIT> P;
-    constexpr bool PER_QP = (MODE == M_QP || MODE == M_QP_MIXED || MODE == M_FUNC);
-    ApplyLaunchFn ap = nullptr;
-    if constexpr (!PER_QP)
-        ap = apply_form<P, 6, 3, T, 1, NT, REF, B>();
     reg<P, 1, NT, REF, B>(FE_PRISM6, FE_ELASTICITY, prec_of<T>(), TS_ELAST, MODE, PK, NQ, SPLIT, 1,
-                          ap, aos_form<P, 6, 1, NT, REF, B>());
+                          apply_form<P, 6, 3, T, 1, NT, REF, B>(), aos_form<P, 6, 1, NT, REF, B>());
 }
 
 // General 3-component CDR (coefficients per element or per point, full K).

@@ -2,6 +2,7 @@
 through the C ABI and through the oracle, and compare per element."""
 from __future__ import annotations
 
+import dataclasses
 import functools
 import os
 
@@ -95,7 +96,22 @@ SMALL = {
     "prism_poisson_qp": lambda: inputs.prism_poisson_qp_rhs(8, 5, seed=19),
     "tet_vector": lambda: inputs.tet_vector(6, seed=17),
     "prism_vector": lambda: inputs.prism_vector(7, 5, seed=18),
+    "prism_elasticity_qp": lambda: _elasticity_per_point(inputs.prism_elasticity(5, 4, seed=20)),
 }
+
+
+def _elasticity_per_point(wl):
+    """The same mesh with E, nu, f varying over the points of the rule
+    (rows j * n_q + q): the element values scaled by 1 + 0.1 (q / n_q) per
+    point, nu kept below 0.45 + 0.045."""
+    n_q = 6
+    c = wl.coeffs
+    rows = []
+    for j in range(c.shape[0]):
+        for q in range(n_q):
+            rows.append(c[j] * (1.0 + 0.1 * q / n_q))
+    return dataclasses.replace(wl, name="prism_elasticity_qp", n_q=n_q, coef_mode="qp",
+                               coeffs=np.ascontiguousarray(np.array(rows)))
 
 
 @functools.lru_cache(maxsize=None)

@@ -289,9 +289,9 @@ def test_apply_validation_before_launch():
     assert _apply_call(p, color_ptr=[0, 4], n_colors=1) == 1      # does not reach n_elem
     assert _apply_call(p, color_ptr=[0, 6, 4, 10], n_colors=3) == 1
     assert _apply_call(p, n_colors=2) == 1                        # colours without offsets
-    # prism elasticity with per-point coefficients has no matrix-free form
-    pq = fe.problem("elasticity", "fp64", "qp", inputs.ALL_ELAST_MASK, None, "packed")
-    assert _apply_call(pq, coeffs=0x8000, elem=1) == 2
+    # coefficient functions exist for scalar problems only
+    vf = fe.problem("vector", "fp64", "function", inputs.ALL_VECTOR_MASK, None, "full")
+    assert _apply_call(vf, coeffs=0x8000) == 2
     e = fe.problem("elasticity", "fp64", "uniform", 0, [1.0, 0.3, 0, 0, 0], "packed")
     assert _apply_call(e, y=0x6004) == 2                          # misaligned y
 
@@ -375,8 +375,8 @@ def test_assemble_csr_validation_before_launch():
     assert _csr_call(p, nnz=-1) == 1
     assert _csr_call(p, rows=0x5004) == 2                          # misaligned row_ptr
     assert _csr_call(p, vals=0x7004) == 2                          # misaligned values
-    pq = fe.problem("elasticity", "fp64", "qp", inputs.ALL_ELAST_MASK, None, "packed")
-    assert _csr_call(pq, coeffs=0x9000, elem=1) == 2               # no assembly form
+    vf = fe.problem("vector", "fp64", "function", inputs.ALL_VECTOR_MASK, None, "full")
+    assert _csr_call(vf, coeffs=0x9000) == 2                       # not built
     assert _csr_call(p, rows=0, cols=0, vals=0, n=0) == 0          # nothing to do
 
 

@@ -14,7 +14,8 @@ torch = pytest.importorskip("torch")
 # rounding of the assembled sums, relative to |A| |x| row by row
 TOL = {"fp64": 1e-12, "fp32": 2e-5}
 CASES = ["tet_poisson", "tet_poisson_qp", "tet_cdr", "tet_cdr_fn", "tet_elasticity", "prism_cdr_qp",
-         "prism_cdr", "prism_cdr_fn", "prism_elasticity", "tet_vector", "prism_vector", "tet_cdr_morton",
+         "prism_cdr", "prism_cdr_fn", "prism_elasticity", "prism_elasticity_qp", "tet_vector", "prism_vector",
+         "tet_cdr_morton",
          "prism_cdr_qp_morton"]
 
 

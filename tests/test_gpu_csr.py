@@ -20,7 +20,8 @@ torch = pytest.importorskip("torch")
 # all vanish still carries rounding of the size of the element matrices)
 TOL = {"fp64": 1e-12, "fp32": 2e-5}
 CASES = ["tet_poisson", "tet_poisson_qp", "tet_cdr", "tet_cdr_fn", "tet_elasticity", "prism_cdr_qp",
-         "prism_cdr", "prism_cdr_fn", "prism_poisson_qp", "prism_elasticity", "tet_vector", "prism_vector",
+         "prism_cdr", "prism_cdr_fn", "prism_poisson_qp", "prism_elasticity", "prism_elasticity_qp",
+         "tet_vector", "prism_vector",
          "tet_cdr_morton"]
 
 

@@ -587,6 +587,23 @@ def run_apply(a, torch, fe, oracle, base: str, dev, csr: bool = False) -> dict:
         fe.assemble_csr_rows(p, wl.elem, nodes, conn, coeffs, rule, rpd, cid, ipd, incd,
                              values=vals)
 
+    if csr:
+        # element-contiguous inputs and outputs for the stored schedule
+        x_nat = torch.from_numpy(np.ascontiguousarray(
+            nodes_np[conn_np[perm]].reshape(n, 3 * nv))).to(dev)
+        c_nat = coeffs
+        if coeffs is not None and wl.coef_mode not in ("uniform", "function"):
+            c_nat = coeffs.t().contiguous()
+        Kst = torch.empty((n, fe.k_entries(p, wl.elem)), dtype=dt, device=dev)
+        Fst = torch.empty((n, fe.f_entries(p, wl.elem)), dtype=dt, device=dev)
+
+    def step_stored():
+        # integrate with K, F stored element by element, then assemble the
+        # stored matrices by rows
+        fe.integrate_natural(p, wl.elem, x_nat, c_nat, rule, out_K=Kst, out_F=Fst)
+        fe.assemble_csr_stored(p, wl.elem, conn, n_nodes, Kst, Fst, rpd, cid, ipd, incd,
+                               values=vals, elem_major=True)
+
     for _ in range(a.warmup):
         step()
     torch.cuda.synchronize()
@@ -628,6 +645,16 @@ def run_apply(a, torch, fe, oracle, base: str, dev, csr: bool = False) -> dict:
         torch.cuda.synchronize()
         wall = time.perf_counter() - w0
         ms_rows = np.array([e0.elapsed_time(e1) for e0, e1 in ev_r])
+        ev_s = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                for _ in range(a.steps)]
+        for _ in range(a.warmup):
+            step_stored()
+        for e0, e1 in ev_s:
+            e0.record(stream)
+            step_stored()
+            e1.record(stream)
+        torch.cuda.synchronize()
+        ms_stored = np.array([e0.elapsed_time(e1) for e0, e1 in ev_s])
     # one clean application (assembly) for the parity check
     (vals if csr else y).zero_()
     step()
@@ -689,6 +716,8 @@ def run_apply(a, torch, fe, oracle, base: str, dev, csr: bool = False) -> dict:
     return {"wl": wl, "n_elem": n, "n_nodes": n_nodes, "colours": int(len(ptr) - 1),
             "ms_avg": float(ms.mean()), "ms_min": float(ms.min()), "ms_median": float(np.median(ms)),
             "wall_s": wall,
+            "stored_ms_avg": float(ms_stored.mean()) if csr else None,
+            "stored_elements_per_s": n / (float(ms_stored.mean()) * 1e-3) if csr else None,
             "coloured_ms_avg": float(ms_col.mean()) if csr else None,
             "coloured_elements_per_s": n / (float(ms_col.mean()) * 1e-3) if csr else None,
             "atomic_ms_avg": float(ms_at.mean()), "atomic_elements_per_s": n / (float(ms_at.mean()) * 1e-3),
@@ -787,6 +816,10 @@ def main() -> int:
                 "atomic": {"ms_avg": r["atomic_ms_avg"], "elements_per_s": r["atomic_elements_per_s"]},
                 "coloured": ({"ms_avg": r["coloured_ms_avg"],
                               "elements_per_s": r["coloured_elements_per_s"]} if csr else None),
+                "stored": ({"ms_avg": r["stored_ms_avg"], "elements_per_s": r["stored_elements_per_s"],
+                            "what": "fe_integrate_natural (K, F stored element by element) + "
+                                    "fe_assemble_csr_stored"}
+                           if csr else None),
                 "parity": r["parity"]}
         print(json.dumps(line), flush=True)
         return 0 if r["parity"]["ok"] else 3

@@ -332,6 +332,28 @@ FE_API int fe_assemble_csr_rows(const fe_problem *problem, fe_elem_type elem_typ
                                 const int32_t *col_idx, int64_t nnz, void *values, void *b,
                                 const int64_t *inc_ptr, const int32_t *inc, hipStream_t stream);
 
+/* Assembly of stored element matrices into CSR storage (Sec. 3.2: the
+ * global matrix is the sum of the element contributions at their nodes), the
+ * step after an integration entry point has stored K and F (device, the
+ * problem's precision and k_format): elem_major = 0, rows as fe_integrate
+ * writes them, K [k * ld + e] and F [i * ld + e]; elem_major = 1,
+ * element-contiguous as fe_integrate_natural writes them, K [e * nk + k] and
+ * F [e * nf + i] (ld ignored; the faster input here: a lane reads an
+ * element's entries from one or two cache lines). conn [v * ld_conn + e]
+ * (device, int32), row_ptr, col_idx,
+ * values and b as for fe_assemble_csr, inc_ptr and inc as for
+ * fe_assemble_csr_rows. One lane per node adds the node's rows from the
+ * stored matrices of the elements at the node (no colours, no atomic
+ * operations, nothing recomputed): with the same incidence lists the values
+ * equal those of fe_assemble_csr_rows bit for bit. F may be NULL when b is
+ * NULL. Enqueued on `stream`; no allocation. */
+FE_API int fe_assemble_csr_stored(const fe_problem *problem, fe_elem_type elem_type, int64_t n_elem,
+                                  const int32_t *conn, int64_t ld_conn, int64_t n_nodes,
+                                  const void *K, const void *F, int64_t ld, int32_t elem_major,
+                                  const int64_t *row_ptr,
+                                  const int32_t *col_idx, int64_t nnz, void *values, void *b,
+                                  const int64_t *inc_ptr, const int32_t *inc, hipStream_t stream);
+
 /* Diagnostic for the signed-determinant convention (det J is used as it
  * is; inverted elements are integrated as written): adds to *count (device
  * int64, zero it first) the number of elements whose det J is not positive

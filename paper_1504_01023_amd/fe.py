@@ -110,6 +110,8 @@ def lib():
         L.fe_csr_pattern.restype = i64
         L.fe_assemble_csr.argtypes = [P, i32, i64, vp, i64, vp, i64, vp, i64, R, vp, vp, i64, vp,
                                       vp, ctypes.POINTER(ctypes.c_int64), i32, vp]
+        L.fe_assemble_csr_stored.argtypes = [P, i32, i64, vp, i64, i64, vp, vp, i64, i32, vp, vp,
+                                             i64, vp, vp, vp, vp, vp]
         L.fe_node_incidence.argtypes = [i32, i64, vp, i64, i64, vp, vp]
         L.fe_node_incidence.restype = i64
         L.fe_assemble_csr_rows.argtypes = [P, i32, i64, vp, i64, vp, i64, vp, i64, R, vp, vp, i64,
@@ -510,6 +512,59 @@ def assemble_csr_rows(p: Problem, elem, nodes, conn, coeffs, rule: Rule, row_ptr
         raise ValueError("inc must be a contiguous int32 GPU vector")
     _check(lib().fe_assemble_csr_rows(*head, ctypes.c_void_p(inc_ptr.data_ptr()),
                                       ctypes.c_void_p(inc.data_ptr()), _stream_handle(stream)))
+    return values, b
+
+
+def assemble_csr_stored(p: Problem, elem, conn, n_nodes: int, K, F, row_ptr, col_idx, inc_ptr, inc,
+                        values=None, b=None, n_elem: int | None = None, stream=None,
+                        with_b: bool = False, elem_major: bool = False):
+    """Assemble stored element matrices into CSR values, one lane per node.
+    K, F: (k_entries, ld) and (f_entries, ld) device tensors as fe.integrate
+    returns them, or with elem_major (n_elem, k_entries) and (n_elem,
+    f_entries) as fe.integrate_natural returns them. conn (n_vert, ld_conn)
+    int32; row_ptr, col_idx, inc_ptr, inc device tensors as for
+    assemble_csr_rows. Returns (values, b)."""
+    import torch
+    e = ELEM.get(elem, elem)
+    nv = 4 if e == TET4 else 6
+    ld_conn = conn.shape[1]
+    n = ld_conn if n_elem is None else int(n_elem)
+    dt = _dtype(p)
+    ncomp = 1 if p.kind == SCALAR_CDR else 3
+    ndof = int(n_nodes) * ncomp
+    _check_tensor(conn, "conn", torch.int32, nv, ld_conn)
+    if elem_major:
+        ld = 0
+        _check_tensor(K, "K", dt, n, k_entries(p, e))
+        if F is not None:
+            _check_tensor(F, "F", dt, n, f_entries(p, e))
+    else:
+        ld = K.shape[1]
+        _check_tensor(K, "K", dt, k_entries(p, e), ld)
+        if F is not None:
+            _check_tensor(F, "F", dt, f_entries(p, e), ld)
+    nnz = col_idx.numel()
+    if values is None:
+        values = torch.zeros(nnz, dtype=dt, device=K.device)
+    if b is None and with_b:
+        b = torch.zeros(ndof, dtype=dt, device=K.device)
+    for name, t, size in (("values", values, nnz), ("b", b, ndof)):
+        if t is not None and not (t.is_cuda and t.dtype == dt and t.is_contiguous()
+                                  and t.numel() == size):
+            raise ValueError(f"{name} must be a contiguous {dt} GPU vector of {size} values")
+    for name, t, d in (("row_ptr", row_ptr, torch.int64), ("col_idx", col_idx, torch.int32),
+                       ("inc_ptr", inc_ptr, torch.int64), ("inc", inc, torch.int32)):
+        if not (t.is_cuda and t.dtype == d and t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous {d} GPU vector")
+    vp = ctypes.c_void_p
+    _check(lib().fe_assemble_csr_stored(ctypes.byref(p), e, n, vp(conn.data_ptr()), ld_conn,
+                                        int(n_nodes), vp(K.data_ptr()),
+                                        vp(F.data_ptr()) if F is not None else None, ld,
+                                        int(bool(elem_major)), vp(row_ptr.data_ptr()), vp(col_idx.data_ptr()), nnz,
+                                        vp(values.data_ptr()),
+                                        vp(b.data_ptr()) if b is not None else None,
+                                        vp(inc_ptr.data_ptr()), vp(inc.data_ptr()),
+                                        _stream_handle(stream)))
     return values, b
 
 

@@ -416,3 +416,19 @@ def test_assemble_csr_rows_validation_before_launch():
     assert L.fe_node_incidence(0, 1, conn.ctypes.data_as(ctypes.c_void_p), 1, 0,
                                np.zeros(2, dtype=np.int64).ctypes.data_as(ctypes.c_void_p),
                                None) == -1
+
+
+def test_assemble_csr_stored_validation_before_launch():
+    L = fe.lib()
+    p = fe.problem("scalar", "fp64", "uniform", 0, inputs.identity_diffusion_uniform(), "packed")
+    v = lambda a: ctypes.c_void_p(a) if a else None
+    call = lambda K=0x2000, F=0x3000, b=0x4000, ld=10, n=10, inc=0x9000, nn=10: \
+        L.fe_assemble_csr_stored(ctypes.byref(p), 0, n, v(0x1000), 10, nn, v(K), v(F), ld, 0,
+                                 v(0x5000), v(0x6000), 100, v(0x7000), v(b), v(0xa000), v(inc), None)
+    assert call(K=0) == 1
+    assert call(F=0) == 1              # F needed with b
+    assert call(inc=0) == 1
+    assert call(ld=9) == 1
+    assert call(nn=0) == 1
+    assert call(K=0x2004) == 2         # misaligned
+    assert call(n=0, K=0, F=0, inc=0) == 0

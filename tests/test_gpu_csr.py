@@ -98,12 +98,25 @@ def test_coloured_and_atomic_match_oracle(name, precision):
                                        *rows, with_b=True)
     v4, b4 = own()
     v5, b5 = own()
+    # stored element matrices, assembled by row ownership
+    Ks, Fs = fe.integrate_indexed(dw.problem, wl.elem, nodes, conn, coeffs, dw.rule)
+    v6, b6 = fe.assemble_csr_stored(dw.problem, wl.elem, conn, wl.mesh.nodes.shape[0], Ks, Fs, rpd,
+                                    cid, *rows, with_b=True)
     torch.cuda.synchronize()
     _check(_dense(rp, ci, v1), b1, ref, precision, rp, ci)
     _check(_dense(rp, ci, v3), b3, ref, precision, rp, ci)
     _check(_dense(rp, ci, v4), b4, ref, precision, rp, ci)
+    _check(_dense(rp, ci, v6), b6, ref, precision, rp, ci)
     assert torch.equal(v1, v2) and torch.equal(b1, b2)
     assert torch.equal(v4, v5) and torch.equal(b4, b5)
+    # same element arithmetic, same incidence order: the same bits
+    assert torch.equal(v4, v6) and torch.equal(b4, b6)
+    # the same matrices element-contiguous
+    v7, b7 = fe.assemble_csr_stored(dw.problem, wl.elem, conn, wl.mesh.nodes.shape[0],
+                                    Ks.t().contiguous(), Fs.t().contiguous(), rpd, cid, *rows,
+                                    with_b=True, elem_major=True)
+    torch.cuda.synchronize()
+    assert torch.equal(v6, v7) and torch.equal(b6, b7)
 
 
 def test_accumulates_ragged_and_without_load():

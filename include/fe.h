@@ -297,7 +297,9 @@ FE_API int64_t fe_csr_pattern(fe_elem_type elem_type, int64_t n_elem, const int3
  * [0, nnz)). values and b are in the precision of the tier and are
  * accumulated into (zero them first). A packed symmetric K is added to both
  * triangles. Colouring as for fe_apply_indexed: per colour, plain
- * read-add-write (deterministic); n_colors = 0, hardware atomic adds. Built
+ * read-add-write (deterministic); n_colors = 0, hardware atomic adds. An
+ * element that repeats a node id is degenerate (det J = 0, non-finite K) and
+ * its entries are unspecified; nothing outside values and b is written. Built
  * for the problems fe_apply_indexed supports; others return
  * FE_ERR_UNSUPPORTED. Enqueued on `stream`; no allocation. */
 FE_API int fe_assemble_csr(const fe_problem *problem, fe_elem_type elem_type, int64_t n_elem,

@@ -69,18 +69,45 @@ __global__ __launch_bounds__(256) void assemble_stored_kernel(AsmArgs g)
         for (int al = 0; al < NC; ++al)
             fb[al] = T(0);
         const int64_t k0 = g.inc_ptr[i], k1 = g.inc_ptr[i + 1];
-        for (int64_t k = k0; k < k1; ++k) {
-            const uint32_t code = (uint32_t)g.inc[k];
-            const int64_t e = code / NV;
-            if (e >= g.n_elem)
-                continue;
-            const int lv = (int)(code % NV);
-            uint32_t id[NV];
+        // software pipeline over the node's elements: the code of element
+        // k + 2 and the vertex ids of element k + 1 are loaded while element
+        // k is processed; element k's K entries are loaded before its
+        // positions in the row are searched
+        auto code_at = [&](int64_t k) -> uint32_t { return k < k1 ? (uint32_t)g.inc[k] : 0u; };
+        auto ids_of = [&](uint32_t code, uint32_t (&id)[NV]) {
+            const int64_t e = code / NV < g.n_elem ? code / NV : 0;
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 const uint32_t u = (uint32_t)g.conn[v * g.ld_conn + e];
                 id[v] = u < g.n_nodes ? u : g.n_nodes - 1;  // clamped: never a fault
             }
+        };
+        uint32_t c_cur = code_at(k0), c_next = code_at(k0 + 1);
+        uint32_t id_cur[NV];
+        ids_of(c_cur, id_cur);
+        for (int64_t k = k0; k < k1; ++k) {
+            const uint32_t code = c_cur;
+            uint32_t id[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                id[v] = id_cur[v];
+            const int64_t e = code / NV;
+            const int lv = (int)(code % NV);
+            const bool valid = e < g.n_elem;
+            const int64_t ee = valid ? e : 0;
+            T kv[NC][N];
+#pragma unroll
+            for (int al = 0; al < NC; ++al)
+#pragma unroll
+                for (int s = 0; s < N; ++s)
+                    kv[al][s] = K[(int64_t)k_row(N, PACKED, NC * lv + al, s) * g.ks + ee * g.es];
+            const uint32_t c_after = code_at(k + 2);
+            if (k + 1 < k1)
+                ids_of(c_next, id_cur);
+            c_cur = c_next;
+            c_next = c_after;
+            if (!valid)
+                continue;
             int32_t slot[NV];
 #pragma unroll
             for (int u = 0; u < NV; ++u)
@@ -100,12 +127,10 @@ __global__ __launch_bounds__(256) void assemble_stored_kernel(AsmArgs g)
             }
 #pragma unroll
             for (int al = 0; al < NC; ++al) {
-                const int r = NC * lv + al;
-                T kv[N], old[N];
+                T old[N];
                 int64_t p[N];
 #pragma unroll
                 for (int s = 0; s < N; ++s) {
-                    kv[s] = K[(int64_t)k_row(N, PACKED, r, s) * g.ks + e * g.es];
                     const int o = slot[s / NC];
                     const int64_t q = r0 + (int64_t)al * len + o + s % NC;
                     p[s] = (o >= 0 && q < nnz) ? q : -1;
@@ -114,9 +139,9 @@ __global__ __launch_bounds__(256) void assemble_stored_kernel(AsmArgs g)
 #pragma unroll
                 for (int s = 0; s < N; ++s)
                     if (p[s] >= 0)
-                        vals[p[s]] = old[s] + kv[s];
+                        vals[p[s]] = old[s] + kv[al][s];
                 if constexpr (WITH_B)
-                    fb[al] += F[(int64_t)r * g.fs + e * g.fes];
+                    fb[al] += F[(int64_t)(NC * lv + al) * g.fs + e * g.fes];
             }
         }
         if constexpr (WITH_B) {

@@ -432,3 +432,25 @@ def test_assemble_csr_stored_validation_before_launch():
     assert call(nn=0) == 1
     assert call(K=0x2004) == 2         # misaligned
     assert call(n=0, K=0, F=0, inc=0) == 0
+
+
+def test_product_path_fails_loudly_without_the_library(tmp_path):
+    # with libfe.so absent the binding raises; nothing falls back to the oracle
+    import subprocess
+    import sys
+    code = (
+        "import paper_1504_01023_amd.fe as fe\n"
+        f"fe.LIB_PATH = {str(tmp_path / 'libfe.so')!r}\n"
+        "fe._lib = None\n"
+        "try:\n"
+        "    fe.lib()\n"
+        "except RuntimeError as e:\n"
+        "    print('raised', 'missing' in str(e))\n"
+        "import sys\n"
+        "print('oracle imported', 'oracle' in sys.modules)\n"
+    )
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
+                         timeout=120)
+    assert "raised True" in out.stdout, out.stdout + out.stderr
+    assert "oracle imported False" in out.stdout, out.stdout

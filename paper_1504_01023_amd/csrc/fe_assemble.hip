@@ -152,21 +152,140 @@ __global__ __launch_bounds__(256) void assemble_stored_kernel(AsmArgs g)
     }
 }
 
+// Scalar problems (one unknown per node). The first RC entries of the node's
+// row stay in registers from the first element at the node to the last,
+// starting from their stored values, so the loop over the elements carries
+// no load-add-store through memory; the K row and vertex ids of the next
+// element load while the current one is added. Every element adds to each
+// held entry either its K value or -0 (x + (-0) is x for every x, -0
+// included), so each entry receives the same additions in the same order as
+// the read-add-write form above and the results are bitwise the same.
+// Entries beyond the first RC keep the read-add-write form.
+template <int NV, typename T, bool PACKED, bool WITH_B>
+__global__ __launch_bounds__(256) void assemble_scalar_kernel(AsmArgs g)
+{
+    constexpr int RC = 32;
+    const T *K = static_cast<const T *>(g.K);
+    const T *F = static_cast<const T *>(g.F);
+    T *vals = static_cast<T *>(g.vals);
+    T *b = static_cast<T *>(g.b);
+    const int64_t nnz = g.nnz;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.n_own; i += stride) {
+        // row bounds clamped into [0, nnz]: never a fault
+        int64_t r0 = g.row_ptr[i], r1 = g.row_ptr[i + 1];
+        r0 = r0 < 0 ? 0 : (r0 > nnz ? nnz : r0);
+        r1 = r1 < r0 ? r0 : (r1 > nnz ? nnz : r1);
+        const int64_t len = r1 - r0;
+        int32_t cols[RC];
+        T acc[RC];
+#pragma unroll
+        for (int c = 0; c < RC; ++c) {
+            const bool in = c < len;
+            cols[c] = in ? g.col_idx[r0 + c] : -1;
+            acc[c] = in ? vals[r0 + c] : T(0);
+        }
+        T fb = T(0);
+        const int64_t k0 = g.inc_ptr[i], k1 = g.inc_ptr[i + 1];
+        auto code_at = [&](int64_t k) -> uint32_t { return k < k1 ? (uint32_t)g.inc[k] : 0u; };
+        auto load = [&](uint32_t code, uint32_t (&id)[NV], T (&kv)[NV]) {
+            const int64_t e = code / NV < g.n_elem ? code / NV : 0;
+            const int lv = (int)(code % NV);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const uint32_t u = (uint32_t)g.conn[v * g.ld_conn + e];
+                id[v] = u < g.n_nodes ? u : g.n_nodes - 1;  // clamped: never a fault
+            }
+#pragma unroll
+            for (int s = 0; s < NV; ++s)
+                kv[s] = K[(int64_t)k_row(NV, PACKED, lv, s) * g.ks + e * g.es];
+        };
+        uint32_t c_cur = code_at(k0), c_next = code_at(k0 + 1);
+        uint32_t id_cur[NV];
+        T kv_cur[NV];
+        load(c_cur, id_cur, kv_cur);
+        for (int64_t k = k0; k < k1; ++k) {
+            const uint32_t code = c_cur;
+            uint32_t id[NV];
+            T kv[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                id[v] = id_cur[v];
+                kv[v] = kv_cur[v];
+            }
+            const uint32_t c_after = code_at(k + 2);
+            if (k + 1 < k1)
+                load(c_next, id_cur, kv_cur);
+            c_cur = c_next;
+            c_next = c_after;
+            const int64_t e = code / NV;
+            if (e >= g.n_elem)
+                continue;
+            // held entries in chunks of 8; a chunk no lane of the wave has
+            // entries in (its columns are all -1) is skipped by the whole wave
+#pragma unroll
+            for (int q = 0; q < RC / 8; ++q) {
+                if (q > 0 && !__any(len > 8 * q))
+                    break;
+#pragma unroll
+                for (int c = 8 * q; c < 8 * q + 8; ++c) {
+                    T add = T(-0.0);
+#pragma unroll
+                    for (int u = 0; u < NV; ++u)
+                        if (cols[c] == (int32_t)id[u])
+                            add = kv[u];
+                    acc[c] += add;
+                    // keeps each column's compares beside their selects (all
+                    // compares hoisted together need more mask registers than
+                    // there are)
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+            for (int64_t j = RC; j < len; ++j) {
+                const int32_t c = g.col_idx[r0 + j];
+#pragma unroll
+                for (int u = 0; u < NV; ++u)
+                    if (c == (int32_t)id[u])
+                        vals[r0 + j] = vals[r0 + j] + kv[u];
+            }
+            if constexpr (WITH_B)
+                fb += F[(int64_t)(code % NV) * g.fs + e * g.fes];
+        }
+        // written back where a column is held (cols[c] is -1 for c >= len; a
+        // negative column matches no node, so its entry is unchanged)
+#pragma unroll
+        for (int c = 0; c < RC; ++c)
+            if (cols[c] >= 0)
+                vals[r0 + c] = acc[c];
+        if constexpr (WITH_B)
+            b[i] += fb;
+    }
+}
+
+// Scalar problems take the register-row kernel, 3-component ones the
+// read-add-write kernel.
+template <int NV, int NC, typename T, bool PACKED, bool WITH_B>
+void launch_one(const AsmArgs &g, unsigned grid, hipStream_t stream)
+{
+    if constexpr (NC == 1)
+        hipLaunchKernelGGL((assemble_scalar_kernel<NV, T, PACKED, WITH_B>), dim3(grid), dim3(256), 0,
+                           stream, g);
+    else
+        hipLaunchKernelGGL((assemble_stored_kernel<NV, NC, T, PACKED, WITH_B>), dim3(grid), dim3(256),
+                           0, stream, g);
+}
+
 template <int NV, int NC, typename T>
 void launch(const AsmArgs &g, bool packed, unsigned grid, hipStream_t stream)
 {
     if (packed && g.b)
-        hipLaunchKernelGGL((assemble_stored_kernel<NV, NC, T, true, true>), dim3(grid), dim3(256), 0,
-                           stream, g);
+        launch_one<NV, NC, T, true, true>(g, grid, stream);
     else if (packed)
-        hipLaunchKernelGGL((assemble_stored_kernel<NV, NC, T, true, false>), dim3(grid), dim3(256), 0,
-                           stream, g);
+        launch_one<NV, NC, T, true, false>(g, grid, stream);
     else if (g.b)
-        hipLaunchKernelGGL((assemble_stored_kernel<NV, NC, T, false, true>), dim3(grid), dim3(256), 0,
-                           stream, g);
+        launch_one<NV, NC, T, false, true>(g, grid, stream);
     else
-        hipLaunchKernelGGL((assemble_stored_kernel<NV, NC, T, false, false>), dim3(grid), dim3(256),
-                           0, stream, g);
+        launch_one<NV, NC, T, false, false>(g, grid, stream);
 }
 
 bool aligned_to(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }

@@ -2335,7 +2335,14 @@ __global__ __launch_bounds__(256) void fe_csr_kernel(KArgs a, IdxArgs gi, ApplyA
 // gathers it, finds where the element's nodes sit in the row, computes K
 // and F keeping only the node's rows (RowBlock) and adds them; every
 // element is computed once per vertex. Each row is written by one lane
-// only, so the result does not depend on the schedule.
+// only, so the result does not depend on the schedule. For scalar tets
+// (REG_ROW) the first RC entries of the row stay in registers from the
+// first element to the last, starting from their stored values, and are
+// written once: each element adds its K value or -0 to every held entry
+// (x + (-0) is x for every x), the same additions in the same order as a
+// read-add-write. Entries beyond the first RC, and the rows of prisms
+// (whose element arithmetic already fills the registers), are added
+// through memory.
 template <class P, int NV, int NC, typename T, int NT, int REF, bool WITH_B>
 __global__ __launch_bounds__(256) void fe_csr_rows_kernel(KArgs a, IdxArgs gi, ApplyArgs ap)
 {
@@ -2345,6 +2352,7 @@ __global__ __launch_bounds__(256) void fe_csr_rows_kernel(KArgs a, IdxArgs gi, A
     const Streams st{nullptr, a.coeffs, nullptr, nullptr, a.ld_in, a.ld_out};
     constexpr int N = NV * NC;
     constexpr int RC = 32;  // node columns of a row held in registers
+    constexpr bool REG_ROW = NC == 1 && NV == 4;
     const int64_t nnz = ap.nnz;
     T *vals = static_cast<T *>(ap.vals);
     T *b = static_cast<T *>(ap.b);
@@ -2356,9 +2364,15 @@ __global__ __launch_bounds__(256) void fe_csr_rows_kernel(KArgs a, IdxArgs gi, A
         r1 = r1 < r0 ? r0 : (r1 > nnz ? nnz : r1);
         const int64_t len = r1 - r0;
         int32_t cols[RC];
+        T acc[REG_ROW ? RC : 1];
 #pragma unroll
         for (int k = 0; k < RC; ++k)
             cols[k] = (int64_t)k * NC < len ? ap.col_idx[r0 + (int64_t)k * NC] : -1;
+        if constexpr (REG_ROW) {
+#pragma unroll
+            for (int k = 0; k < RC; ++k)
+                acc[k] = k < len ? vals[r0 + k] : T(0);
+        }
         T fb[NC];
 #pragma unroll
         for (int al = 0; al < NC; ++al)
@@ -2414,63 +2428,102 @@ __global__ __launch_bounds__(256) void fe_csr_rows_kernel(KArgs a, IdxArgs gi, A
                 X[3 * v + 1] = pn[1];
                 X[3 * v + 2] = pn[2];
             }
-            // offset of each element node's first column in the row, or -1
-            int32_t slot[NV];
+            if constexpr (REG_ROW) {
+                P::template apply_x<NT, REF>(a, st, ref, X, e, bl);
+                // held entries in chunks of 8; a chunk no lane of the wave
+                // has entries in (its columns are all -1) is skipped by the
+                // whole wave
 #pragma unroll
-            for (int u = 0; u < NV; ++u)
-                slot[u] = -1;
+                for (int q = 0; q < RC / 8; ++q) {
+                    if (q > 0 && !__any(len > 8 * q))
+                        break;
 #pragma unroll
-            for (int c = 0; c < RC; ++c)
+                    for (int c = 8 * q; c < 8 * q + 8; ++c) {
+                        T add = T(-0.0);
 #pragma unroll
-                for (int u = 0; u < NV; ++u)
-                    if (cols[c] == (int32_t)(NC * id[u]))
-                        slot[u] = c * NC;
-            for (int64_t j = (int64_t)RC * NC; j < len; j += NC) {
-                const int32_t c = ap.col_idx[r0 + j];
-#pragma unroll
-                for (int u = 0; u < NV; ++u)
-                    if (c == (int32_t)(NC * id[u]))
-                        slot[u] = (int32_t)j;
-            }
-            if constexpr (NC == 1) {
-                // the row's current values are loaded before the element is
-                // computed, so the loads overlap the arithmetic
-                int64_t p[N];
-                T old[N];
-#pragma unroll
-                for (int s = 0; s < N; ++s) {
-                    const int64_t q = r0 + slot[s];
-                    p[s] = (slot[s] >= 0 && q < nnz) ? q : -1;
-                    old[s] = p[s] >= 0 ? vals[p[s]] : T(0);
+                        for (int u = 0; u < NV; ++u)
+                            if (cols[c] == (int32_t)id[u])
+                                add = kr[u];
+                        acc[c] += add;
+                        // keeps each column's compares beside their selects
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
                 }
-                P::template apply_x<NT, REF>(a, st, ref, X, e, bl);
+                for (int64_t j = RC; j < len; ++j) {
+                    const int32_t c = ap.col_idx[r0 + j];
 #pragma unroll
-                for (int s = 0; s < N; ++s)
-                    if (p[s] >= 0)
-                        vals[p[s]] = old[s] + kr[s];
+                    for (int u = 0; u < NV; ++u)
+                        if (c == (int32_t)id[u])
+                            vals[r0 + j] = vals[r0 + j] + kr[u];
+                }
             } else {
-                P::template apply_x<NT, REF>(a, st, ref, X, e, bl);
-                // row by row: the row's loads, then its stores
+                // offset of each element node's first column in the row, or -1
+                int32_t slot[NV];
 #pragma unroll
-                for (int al = 0; al < NC; ++al) {
+                for (int u = 0; u < NV; ++u)
+                    slot[u] = -1;
+#pragma unroll
+                for (int c = 0; c < RC; ++c)
+#pragma unroll
+                    for (int u = 0; u < NV; ++u)
+                        if (cols[c] == (int32_t)(NC * id[u]))
+                            slot[u] = c * NC;
+                for (int64_t j = (int64_t)RC * NC; j < len; j += NC) {
+                    const int32_t c = ap.col_idx[r0 + j];
+#pragma unroll
+                    for (int u = 0; u < NV; ++u)
+                        if (c == (int32_t)(NC * id[u]))
+                            slot[u] = (int32_t)j;
+                }
+                if constexpr (NC == 1) {
+                    // the row's current values are loaded before the element
+                    // is computed, so the loads overlap the arithmetic
                     int64_t p[N];
                     T old[N];
 #pragma unroll
                     for (int s = 0; s < N; ++s) {
-                        const int o = slot[s / NC];
-                        const int64_t q = r0 + (int64_t)al * len + o + s % NC;
-                        p[s] = (o >= 0 && q < nnz) ? q : -1;
+                        const int64_t q = r0 + slot[s];
+                        p[s] = (slot[s] >= 0 && q < nnz) ? q : -1;
                         old[s] = p[s] >= 0 ? vals[p[s]] : T(0);
                     }
+                    P::template apply_x<NT, REF>(a, st, ref, X, e, bl);
 #pragma unroll
                     for (int s = 0; s < N; ++s)
                         if (p[s] >= 0)
-                            vals[p[s]] = old[s] + kr[al * N + s];
+                            vals[p[s]] = old[s] + kr[s];
+                } else {
+                    P::template apply_x<NT, REF>(a, st, ref, X, e, bl);
+                    // row by row: the row's loads, then its stores
+#pragma unroll
+                    for (int al = 0; al < NC; ++al) {
+                        int64_t p[N];
+                        T old[N];
+#pragma unroll
+                        for (int s = 0; s < N; ++s) {
+                            const int o = slot[s / NC];
+                            const int64_t q = r0 + (int64_t)al * len + o + s % NC;
+                            p[s] = (o >= 0 && q < nnz) ? q : -1;
+                            old[s] = p[s] >= 0 ? vals[p[s]] : T(0);
+                        }
+#pragma unroll
+                        for (int s = 0; s < N; ++s)
+                            if (p[s] >= 0)
+                                vals[p[s]] = old[s] + kr[al * N + s];
+                    }
                 }
             }
 #pragma unroll
             for (int al = 0; al < NC; ++al)
                 fb[al] += fr[al];
+        }
+        if constexpr (REG_ROW) {
+            // written back where a column is held (cols[c] is -1 for c >=
+            // len; a negative column matches no node, so its entry is
+            // unchanged)
+#pragma unroll
+            for (int c = 0; c < RC; ++c)
+                if (cols[c] >= 0)
+                    vals[r0 + c] = acc[c];
         }
         if constexpr (WITH_B) {
 #pragma unroll

@@ -43,6 +43,18 @@ __device__ __forceinline__ int k_row(int N, bool packed, int r, int s)
     return lo * N - lo * (lo - 1) / 2 + (hi - lo);
 }
 
+// Workgroups are handed to the chip's 8 XCDs in turn (workgroup b to XCD
+// b mod 8), and each XCD has its own L2. The logical workgroup index gives
+// every XCD one contiguous range of nodes, so neighbouring nodes, which share
+// elements and vertex data, are read through the same L2. A bijection of
+// [0, G): XCD x takes q + 1 consecutive indices if x < G mod 8, else q
+// (q = G / 8).
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t G)
+{
+    const int64_t x = b % 8, k = b / 8, q = G / 8, r = G % 8;
+    return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
 template <int NV, int NC, typename T, bool PACKED, bool WITH_B>
 __global__ __launch_bounds__(256) void assemble_stored_kernel(AsmArgs g)
 {
@@ -171,7 +183,8 @@ __global__ __launch_bounds__(256) void assemble_scalar_kernel(AsmArgs g)
     T *b = static_cast<T *>(g.b);
     const int64_t nnz = g.nnz;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.n_own; i += stride) {
+    for (int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x; i < g.n_own;
+         i += stride) {
         // row bounds clamped into [0, nnz]: never a fault
         int64_t r0 = g.row_ptr[i], r1 = g.row_ptr[i + 1];
         r0 = r0 < 0 ? 0 : (r0 > nnz ? nnz : r0);

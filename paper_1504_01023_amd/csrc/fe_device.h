@@ -2329,6 +2329,18 @@ __global__ __launch_bounds__(256) void fe_csr_kernel(KArgs a, IdxArgs gi, ApplyA
     }
 }
 
+// Workgroups are handed to the chip's 8 XCDs in turn (workgroup b to XCD
+// b mod 8), and each XCD has its own L2. The logical workgroup index gives
+// every XCD one contiguous range of nodes, so neighbouring nodes, which share
+// elements and vertex data, are read through the same L2. A bijection of
+// [0, G): XCD x takes q + 1 consecutive indices if x < G mod 8, else q
+// (q = G / 8).
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t G)
+{
+    const int64_t x = b % 8, k = b / 8, q = G / 8, r = G % 8;
+    return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
 // Assembly into a CSR matrix by row ownership (one node per lane, no
 // colours and no atomics): node i's lane loads the node columns of its
 // rows (the first RC in registers), then for each element at the node
@@ -2357,7 +2369,10 @@ __global__ __launch_bounds__(256) void fe_csr_rows_kernel(KArgs a, IdxArgs gi, A
     T *vals = static_cast<T *>(ap.vals);
     T *b = static_cast<T *>(ap.b);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ap.n_own; i += stride) {
+    // scalar tets: workgroup b takes the nodes of logical workgroup
+    // xcd_block(b) (one contiguous range of nodes per XCD, see xcd_block)
+    const int64_t blk = REG_ROW ? xcd_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+    for (int64_t i = blk * blockDim.x + threadIdx.x; i < ap.n_own; i += stride) {
         // row bounds clamped into [0, nnz]: never a fault
         int64_t r0 = ap.row_ptr[NC * i], r1 = ap.row_ptr[NC * i + 1];
         r0 = r0 < 0 ? 0 : (r0 > nnz ? nnz : r0);

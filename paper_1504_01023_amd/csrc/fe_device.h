@@ -2215,6 +2215,18 @@ __device__ __forceinline__ void stage_reference(const KArgs &a, RefLds &lds)
     }
 }
 
+// Workgroups are handed to the chip's 8 XCDs in turn (workgroup b to XCD
+// b mod 8), and each XCD has its own L2. The logical workgroup index gives
+// every XCD one contiguous range of the work (nodes, or elements in mesh
+// order), so neighbours, which share elements and vertex data, are read
+// through the same L2. A bijection of [0, G): XCD x takes q + 1 consecutive
+// indices if x < G mod 8, else q (q = G / 8).
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t G)
+{
+    const int64_t x = b % 8, k = b / 8, q = G / 8, r = G % 8;
+    return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
 // Matrix-free application of the assembled operator (indexed geometry, one
 // element per lane): gather the vertex ids, coordinates and nodal values x,
 // compute the element's K (and F) exactly as the storing kernels do but
@@ -2234,7 +2246,8 @@ __global__ __launch_bounds__(256) void fe_apply_kernel(KArgs a, IdxArgs gi, Appl
     T *b = static_cast<T *>(ap.b);
     constexpr int N = NV * NC;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < a.n_elem; e += stride) {
+    for (int64_t e = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x; e < a.n_elem;
+         e += stride) {
         uint32_t id[NV];
         double X[3 * NV];
         gather_vertices<NV, NT>(gi, e, id, X);
@@ -2327,18 +2340,6 @@ __global__ __launch_bounds__(256) void fe_csr_kernel(KArgs a, IdxArgs gi, ApplyA
         if constexpr (DEFER)
             bl.flush();
     }
-}
-
-// Workgroups are handed to the chip's 8 XCDs in turn (workgroup b to XCD
-// b mod 8), and each XCD has its own L2. The logical workgroup index gives
-// every XCD one contiguous range of nodes, so neighbouring nodes, which share
-// elements and vertex data, are read through the same L2. A bijection of
-// [0, G): XCD x takes q + 1 consecutive indices if x < G mod 8, else q
-// (q = G / 8).
-__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t G)
-{
-    const int64_t x = b % 8, k = b / 8, q = G / 8, r = G % 8;
-    return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
 }
 
 // Assembly into a CSR matrix by row ownership (one node per lane, no

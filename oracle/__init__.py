@@ -5,8 +5,9 @@ benchmark's CPU-baseline leg import this package. It never touches the GPU and
 shares nothing with the GPU library; the inputs it is given come from the
 seeded generators.
 
-The element integrals are in fe_oracle.c (Algorithm 1 of the paper, written
-out plainly); the functions here marshal their arguments. Two small pieces
+The element integrals are in fe_oracle.c (the quadrature sums that define
+K and F, eqs. "sm_local" and "lv_local" with the rule of eq. "quadrature",
+written out term by term); the functions here marshal their arguments. Two small pieces
 are plain NumPy beside it: the scatter of element matrices into the
 assembled operator (apply_assembled, assemble_dense) and det J at the rule points
 (jacobian_dets, count_inverted).

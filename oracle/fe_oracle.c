@@ -8,16 +8,17 @@
  * table or constant with the GPU library: shape functions, quadrature rules
  * and the element loop are written out here independently.
  *
- * What it computes. For every element e, the quadrature sum (Sec. 2.3, eq.
- * "quadrature", with the change of variables of eq. "change_of_variables")
- * applied to the element stiffness matrix and load vector of eqs. "sm_local"
- * and "lv_local", using the rule the caller passes, in the order of the
- * generic procedure of Algorithm 1: read parameters and geometry, initialise,
- * then one loop over points for Jacobian terms, vol and global derivatives,
- * one loop for the coefficients, and the five nested loops (point, test
- * function, trial function, derivative index of each) that update A^e and
- * b^e. Nothing is hoisted or fused. Index 0 of the derivative index is the
- * function value, 1..3 the x, y, z derivatives (Algorithm 1).
+ * What it computes. For every element e, the element stiffness matrix and
+ * load vector of eqs. "sm_local" and "lv_local" (Sec. 2.2) as their
+ * definition gives them after the change of variables to the reference
+ * element (eq. "change_of_variables") and the quadrature rule the caller
+ * passes (eq. "quadrature", Sec. 2.3):
+ *   K[r][s] = sum_q vol_q sum_{a,b} c^{a;b}(x_q) Phi_r[a](x_q) Phi_s[b](x_q),
+ *   F[r]    = sum_q vol_q sum_a d^a(x_q) Phi_r[a](x_q),
+ * vol_q = det J(xi_q) w_q, Phi_r = (phi_r, its x, y, z derivatives); for
+ * 3-component problems every coefficient also carries the component indices
+ * of the test and trial functions. Each term is evaluated as written, point
+ * by point; nothing is hoisted, reduced in advance or fused.
  *
  * Readings where the paper is silent (stated again in the design notes):
  *  - first coefficient index pairs with the test function (row r), the second
@@ -197,20 +198,6 @@ int oracle_shape(int elem, const double *xi, double *phi, double *dphi)
  * with A[i][j] the raw value of slot 4(i+1)+1+j (symmetric positive
  * definite for p[120] > 0).
  * ---------------------------------------------------------------------- */
-static void physical_point(int elem, const double xi[3], const double X[6][3], double x[3])
-{
-    double ph[6], dph[6][3];
-    if (elem == OR_TET4)
-        tet4_shape(xi, ph, dph);
-    else
-        prism6_shape(xi, ph, dph);
-    for (int i = 0; i < 3; ++i) {
-        x[i] = 0.0;
-        for (int r = 0; r < n_shape(elem); ++r)
-            x[i] += ph[r] * X[r][i];
-    }
-}
-
 static double fn_raw(const double *p, int k, const double x[3])
 {
     const double *a = p + 6 * k;
@@ -257,15 +244,6 @@ typedef struct {
     const double *fn; /* coefficient-function parameters (OR_FUNCTION) */
 } job_t;
 
-typedef struct {
-    /* per-thread scratch, sized by n_q */
-    double *vol;   /* [n_q] */
-    double *phi;   /* [4][6][n_q]: phi[(d*6 + r)*n_q + q] */
-    double *par;   /* [n_q][OR_MAX_SLOTS] slot values */
-    double *c;     /* scalar: [4][4][n_q]; elasticity: [4][4][3][3][n_q] */
-    double *d;     /* scalar: [4][n_q];    elasticity: [4][3][n_q] */
-} scratch_t;
-
 /* Jacobian terms at one point: J[i][k] = dx_i/dxi_k. Because the reference
  * derivatives of the shape functions sum to zero, x(xi) = X_0 + sum_r
  * phi_r(xi) (X_r - X_0) and J[i][k] = sum_r (X[r][i] - X[0][i]) dphi_r/dxi_k
@@ -306,144 +284,170 @@ static void jacobian_terms(int ns, const double X[6][3], const double dphi[6][3]
 
 static double kd(int a, int b) { return a == b ? 1.0 : 0.0; }
 
-static void integrate_element(const job_t *jb, scratch_t *sc, int64_t e)
+/* What the integrands of eqs. "sm_local" and "lv_local" need at one point of
+ * the rule, after the change of variables (eq. "change_of_variables"): the
+ * factor vol = det J(xi_q) w_q of the quadrature sum (eq. "quadrature", det J
+ * signed), the physical point x(xi_q), and for every shape function r the
+ * 4-vector Phi_r = (phi_r, d phi_r/dx, d phi_r/dy, d phi_r/dz), the global
+ * derivatives being J^{-T} times the reference ones. */
+typedef struct {
+    double vol;
+    double x[3];
+    double Phi[6][4];
+} point_t;
+
+static void point_values(int elem, const double X[6][3], const double xi[3], double w,
+                         point_t *pt)
+{
+    const int ns = n_shape(elem);
+    double ph[6], dph[6][3], Jinv[3][3], det;
+    if (elem == OR_TET4)
+        tet4_shape(xi, ph, dph);
+    else
+        prism6_shape(xi, ph, dph);
+    jacobian_terms(ns, X, dph, &det, Jinv);
+    pt->vol = det * w;
+    for (int i = 0; i < 3; ++i) {
+        pt->x[i] = 0.0;
+        for (int r = 0; r < ns; ++r)
+            pt->x[i] += ph[r] * X[r][i];
+    }
+    for (int r = 0; r < ns; ++r) {
+        pt->Phi[r][0] = ph[r];
+        for (int i = 0; i < 3; ++i) {
+            double g = 0.0;
+            for (int k = 0; k < 3; ++k)
+                g += dph[r][k] * Jinv[k][i];
+            pt->Phi[r][1 + i] = g;
+        }
+    }
+}
+
+/* The coefficients of the weak form (eq. "weak_form") at one point, as
+ * c[a][b][alpha][beta] and d[a][alpha] over the derivative indices a, b
+ * (0: the function, 1..3: x, y, z) and the components alpha, beta of the
+ * test and trial functions. Scalar problems use component 0 only. */
+typedef struct {
+    double c[4][4][3][3];
+    double d[4][3];
+} coef_t;
+
+/* Slot values at point q of element e: read from memory (per element or per
+ * point), computed from the coefficient function at x, or the uniform
+ * values. */
+static void slot_values(const job_t *jb, int64_t e, int q, const double x[3], double *par)
+{
+    for (int k = 0; k < jb->n_slots; ++k) {
+        const int j = jb->slot_col[k];
+        double v = (jb->kind == OR_VECTOR) ? 0.0 : jb->uniform[k];
+        if (j >= 0) {
+            if (jb->coef_mode == OR_FUNCTION)
+                v = fn_raw(jb->fn, k, x);
+            else if (jb->coef_mode == OR_PER_QP)
+                v = jb->coeffs[((int64_t)j * jb->n_q + q) * jb->ldc + e];
+            else
+                v = jb->coeffs[(int64_t)j * jb->ldc + e];
+        }
+        par[k] = v;
+    }
+    if (jb->coef_mode == OR_FUNCTION)
+        fn_spd_diffusion(jb->fn, par);
+}
+
+static void coefficients(const job_t *jb, const double *p, coef_t *cf)
+{
+    memset(cf, 0, sizeof(*cf));
+    if (jb->kind == OR_SCALAR) {
+        for (int a = 0; a < 4; ++a) {
+            for (int b = 0; b < 4; ++b)
+                cf->c[a][b][0][0] = p[4 * a + b];
+            cf->d[a][0] = p[16 + a];
+        }
+    } else if (jb->kind == OR_VECTOR) {
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b)
+                for (int al = 0; al < 3; ++al)
+                    for (int be = 0; be < 3; ++be)
+                        cf->c[a][b][al][be] = p[(4 * a + b) * 9 + 3 * al + be];
+        for (int a = 0; a < 4; ++a)
+            for (int al = 0; al < 3; ++al)
+                cf->d[a][al] = p[144 + 3 * a + al];
+    } else {
+        /* isotropic elasticity: only the derivative-derivative terms, the
+         * tensor of (i, alpha), (j, beta) with i = a - 1, j = b - 1 */
+        const double E = p[0], nu = p[1];
+        const double lambda = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+        const double mu = E / (2.0 * (1.0 + nu));
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+                for (int al = 0; al < 3; ++al)
+                    for (int be = 0; be < 3; ++be)
+                        cf->c[1 + i][1 + j][al][be] =
+                            lambda * kd(i, al) * kd(j, be) +
+                            mu * (kd(i, j) * kd(al, be) + kd(i, be) * kd(j, al));
+        for (int al = 0; al < 3; ++al)
+            cf->d[0][al] = p[2 + al];
+    }
+}
+
+/* The integrand of eq. "sm_local" for test function (r, alpha) and trial
+ * function (s, beta): sum over a, b of c^{a;b}_{alpha beta} Phi_r[a] Phi_s[b]. */
+static double stiffness_integrand(const coef_t *cf, const double Phi_r[4], const double Phi_s[4],
+                                  int al, int be)
+{
+    double v = 0.0;
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b)
+            v += cf->c[a][b][al][be] * Phi_r[a] * Phi_s[b];
+    return v;
+}
+
+/* The integrand of eq. "lv_local" for test function (r, alpha): sum over a of
+ * d^a_alpha Phi_r[a]. */
+static double load_integrand(const coef_t *cf, const double Phi_r[4], int al)
+{
+    double v = 0.0;
+    for (int a = 0; a < 4; ++a)
+        v += cf->d[a][al] * Phi_r[a];
+    return v;
+}
+
+/* K and F of element e: the quadrature sums over the rule's points of vol
+ * times the integrands, for every unknown (r, alpha), number 3 r + alpha
+ * (r for scalar problems). */
+static void integrate_element(const job_t *jb, int64_t e)
 {
     const int ns = n_shape(jb->elem);
     const int nc = (jb->kind == OR_SCALAR) ? 1 : 3;
     const int N = ns * nc;
-    const int nq = jb->n_q;
     double *Ke = jb->K + (size_t)e * N * N;
     double *Fe = jb->F + (size_t)e * N;
 
-    /* read geometry data for the element */
     double X[6][3];
     for (int v = 0; v < ns; ++v)
         for (int d = 0; d < 3; ++d)
             X[v][d] = jb->coords[(int64_t)(v * 3 + d) * jb->ld + e];
-
-    /* read problem dependent parameters specific to the element, or compute
-     * the coefficients from the parameters of the coefficient function */
-    for (int q = 0; q < nq; ++q) {
-        double x[3] = {0.0, 0.0, 0.0};
-        if (jb->coef_mode == OR_FUNCTION)
-            physical_point(jb->elem, &jb->xi[3 * q], X, x);
-        for (int k = 0; k < jb->n_slots; ++k) {
-            const int j = jb->slot_col[k];
-            double v = (jb->kind == OR_VECTOR) ? 0.0 : jb->uniform[k];
-            if (j >= 0) {
-                if (jb->coef_mode == OR_FUNCTION)
-                    v = fn_raw(jb->fn, k, x);
-                else if (jb->coef_mode == OR_PER_QP)
-                    v = jb->coeffs[((int64_t)j * nq + q) * jb->ldc + e];
-                else
-                    v = jb->coeffs[(int64_t)j * jb->ldc + e];
-            }
-            sc->par[q * OR_MAX_SLOTS + k] = v;
-        }
-        if (jb->coef_mode == OR_FUNCTION)
-            fn_spd_diffusion(jb->fn, &sc->par[q * OR_MAX_SLOTS]);
-    }
-
-    /* initialise A^e and b^e */
     for (int i = 0; i < N * N; ++i)
         Ke[i] = 0.0;
     for (int i = 0; i < N; ++i)
         Fe[i] = 0.0;
 
-    /* loop over points: Jacobian terms, vol, global derivatives */
-    for (int q = 0; q < nq; ++q) {
-        double ph[6], dph[6][3], Jinv[3][3], det;
-        if (jb->elem == OR_TET4)
-            tet4_shape(&jb->xi[3 * q], ph, dph);
-        else
-            prism6_shape(&jb->xi[3 * q], ph, dph);
-        jacobian_terms(ns, X, dph, &det, Jinv);
-        sc->vol[q] = det * jb->w[q];
-        for (int r = 0; r < ns; ++r) {
-            sc->phi[(0 * 6 + r) * nq + q] = ph[r];
-            for (int i = 0; i < 3; ++i) {
-                double s = 0.0;
-                for (int k = 0; k < 3; ++k)
-                    s += dph[r][k] * Jinv[k][i];
-                sc->phi[((1 + i) * 6 + r) * nq + q] = s;
+    for (int q = 0; q < jb->n_q; ++q) {
+        point_t pt;
+        point_values(jb->elem, X, &jb->xi[3 * q], jb->w[q], &pt);
+        double par[OR_MAX_SLOTS];
+        slot_values(jb, e, q, pt.x, par);
+        coef_t cf;
+        coefficients(jb, par, &cf);
+        for (int r = 0; r < ns; ++r)
+            for (int al = 0; al < nc; ++al) {
+                const int row = nc * r + al;
+                for (int s = 0; s < ns; ++s)
+                    for (int be = 0; be < nc; ++be)
+                        Ke[row * N + nc * s + be] +=
+                            pt.vol * stiffness_integrand(&cf, pt.Phi[r], pt.Phi[s], al, be);
+                Fe[row] += pt.vol * load_integrand(&cf, pt.Phi[r], al);
             }
-        }
-    }
-
-    /* loop over points: coefficients c and d at the points */
-    for (int q = 0; q < nq; ++q) {
-        const double *p = &sc->par[q * OR_MAX_SLOTS];
-        if (jb->kind == OR_SCALAR) {
-            for (int a = 0; a < 4; ++a) {
-                for (int b = 0; b < 4; ++b)
-                    sc->c[(a * 4 + b) * nq + q] = p[4 * a + b];
-                sc->d[a * nq + q] = p[16 + a];
-            }
-        } else if (jb->kind == OR_VECTOR) {
-            for (int a = 0; a < 4; ++a)
-                for (int b = 0; b < 4; ++b)
-                    for (int al = 0; al < 3; ++al)
-                        for (int be = 0; be < 3; ++be)
-                            sc->c[(((a * 4 + b) * 3 + al) * 3 + be) * nq + q] =
-                                p[(4 * a + b) * 9 + 3 * al + be];
-            for (int a = 0; a < 4; ++a)
-                for (int al = 0; al < 3; ++al)
-                    sc->d[(a * 3 + al) * nq + q] = p[144 + 3 * a + al];
-        } else {
-            const double E = p[0], nu = p[1];
-            const double lambda = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
-            const double mu = E / (2.0 * (1.0 + nu));
-            for (int a = 0; a < 4; ++a)
-                for (int b = 0; b < 4; ++b)
-                    for (int al = 0; al < 3; ++al)
-                        for (int be = 0; be < 3; ++be) {
-                            double v = 0.0;
-                            if (a > 0 && b > 0) {
-                                const int i = a - 1, j = b - 1;
-                                v = lambda * kd(i, al) * kd(j, be) +
-                                    mu * (kd(i, j) * kd(al, be) + kd(i, be) * kd(j, al));
-                            }
-                            sc->c[(((a * 4 + b) * 3 + al) * 3 + be) * nq + q] = v;
-                        }
-            for (int a = 0; a < 4; ++a)
-                for (int al = 0; al < 3; ++al)
-                    sc->d[(a * 3 + al) * nq + q] = (a == 0) ? p[2 + al] : 0.0;
-        }
-    }
-
-    /* five nested loops: point, test function, trial function, derivative
-     * index of the test function, derivative index of the trial function */
-    for (int q = 0; q < nq; ++q) {
-        const double vol = sc->vol[q];
-        for (int r = 0; r < ns; ++r) {
-            for (int s = 0; s < ns; ++s) {
-                if (nc == 1) {
-                    for (int a = 0; a < 4; ++a)
-                        for (int b = 0; b < 4; ++b)
-                            Ke[r * N + s] += vol * sc->c[(a * 4 + b) * nq + q] *
-                                             sc->phi[(a * 6 + r) * nq + q] *
-                                             sc->phi[(b * 6 + s) * nq + q];
-                } else {
-                    for (int al = 0; al < 3; ++al)
-                        for (int be = 0; be < 3; ++be)
-                            for (int a = 0; a < 4; ++a)
-                                for (int b = 0; b < 4; ++b)
-                                    Ke[(3 * r + al) * N + 3 * s + be] +=
-                                        vol * sc->c[(((a * 4 + b) * 3 + al) * 3 + be) * nq + q] *
-                                        sc->phi[(a * 6 + r) * nq + q] *
-                                        sc->phi[(b * 6 + s) * nq + q];
-                }
-            }
-            if (nc == 1) {
-                for (int a = 0; a < 4; ++a)
-                    Fe[r] += vol * sc->d[a * nq + q] * sc->phi[(a * 6 + r) * nq + q];
-            } else {
-                for (int al = 0; al < 3; ++al)
-                    for (int a = 0; a < 4; ++a)
-                        Fe[3 * r + al] += vol * sc->d[(a * 3 + al) * nq + q] *
-                                          sc->phi[(a * 6 + r) * nq + q];
-            }
-        }
     }
 }
 
@@ -456,25 +460,9 @@ typedef struct {
 static void *run_range(void *arg)
 {
     range_t *rg = (range_t *)arg;
-    const int nq = rg->jb->n_q;
-    scratch_t sc;
-    sc.vol = (double *)malloc(sizeof(double) * nq);
-    sc.phi = (double *)malloc(sizeof(double) * 4 * 6 * nq);
-    sc.par = (double *)malloc(sizeof(double) * OR_MAX_SLOTS * nq);
-    sc.c = (double *)malloc(sizeof(double) * 4 * 4 * 9 * nq);
-    sc.d = (double *)malloc(sizeof(double) * 4 * 3 * nq);
-    if (!sc.vol || !sc.phi || !sc.par || !sc.c || !sc.d) {
-        rg->status = OR_ENOMEM;
-    } else {
-        for (int64_t e = rg->e0; e < rg->e1; ++e)
-            integrate_element(rg->jb, &sc, e);
-        rg->status = OR_OK;
-    }
-    free(sc.vol);
-    free(sc.phi);
-    free(sc.par);
-    free(sc.c);
-    free(sc.d);
+    for (int64_t e = rg->e0; e < rg->e1; ++e)
+        integrate_element(rg->jb, e);
+    rg->status = OR_OK;
     return NULL;
 }
 

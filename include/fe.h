@@ -454,8 +454,10 @@ FE_API int fe_batch_create(const fe_batch_kind *kinds, int n_kinds, int max_chun
                            int64_t chunk_elems, int blocks_per_kind, fe_batch **out);
 /* Append a request (device pointers, layouts as for fe_integrate_ex) to the
  * pending table. FE_ERR_CAPACITY when its chunks do not fit (launch first);
- * FE_ERR_UNSUPPORTED when its leading dimensions or alignment do not suit
- * the kind's elements-per-lane. Nothing is enqueued until fe_batch_launch. */
+ * FE_ERR_UNSUPPORTED when a pointer is not aligned to its element size. A
+ * request whose leading dimensions or pointers do not suit the kind's
+ * elements per lane is processed element by element (same results, bit for
+ * bit). Nothing is enqueued until fe_batch_launch. */
 FE_API int fe_batch_add(fe_batch *b, int kind, int64_t n_elem, const double *coords,
                         const void *coeffs, int64_t ld_in, void *out_K, void *out_F,
                         int64_t ld_out);

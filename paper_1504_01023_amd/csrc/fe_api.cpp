@@ -451,8 +451,7 @@ int launch(const Plan &pl, hipStream_t stream)
 {
     if (pl.args.n_elem == 0)
         return FE_OK;
-    pl.entry->launch(pl.args, pl.grid, pl.block, stream);
-    const hipError_t err = hipGetLastError();
+    const hipError_t err = pl.entry->launch(pl.args, pl.grid, pl.block, stream);
     if (err != hipSuccess)
         return fail(FE_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(err));
     return FE_OK;
@@ -462,8 +461,7 @@ int launch_indexed(const Plan &pl, const IdxArgs &gi, hipStream_t stream)
 {
     if (pl.args.n_elem == 0)
         return FE_OK;
-    pl.entry->idx(pl.args, gi, pl.grid, pl.block, stream);
-    const hipError_t err = hipGetLastError();
+    const hipError_t err = pl.entry->idx(pl.args, gi, pl.grid, pl.block, stream);
     if (err != hipSuccess)
         return fail(FE_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(err));
     return FE_OK;
@@ -560,8 +558,7 @@ static int indexed_consumer(const fe_problem *problem, fe_elem_type elem_type, i
         int64_t grid = (cnt + pl.block - 1) / pl.block;
         if (grid > 0x7fffffff)
             grid = 0x7fffffff;
-        pl.entry->apply(a, gi, ap, atomic, (unsigned)grid, pl.block, stream);
-        const hipError_t err = hipGetLastError();
+        const hipError_t err = pl.entry->apply(a, gi, ap, atomic, (unsigned)grid, pl.block, stream);
         if (err != hipSuccess)
             return fail(FE_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(err));
         return FE_OK;
@@ -659,8 +656,7 @@ int fe_assemble_csr_rows(const fe_problem *problem, fe_elem_type elem_type, int6
     int64_t grid = (n_nodes + pl.block - 1) / pl.block;
     if (grid > 0x7fffffff)
         grid = 0x7fffffff;
-    pl.entry->apply(pl.args, gi, ap, 0, (unsigned)grid, pl.block, stream);
-    const hipError_t err = hipGetLastError();
+    const hipError_t err = pl.entry->apply(pl.args, gi, ap, 0, (unsigned)grid, pl.block, stream);
     if (err != hipSuccess)
         return fail(FE_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(err));
     return FE_OK;
@@ -705,11 +701,13 @@ int fe_integrate_natural(const fe_problem *problem, fe_elem_type elem_type, int6
     // cannot be queried) less the kernel's static reference tables
     size_t lds_max = 64 * 1024;
     int dev = 0, attr = 0;
+    const hipError_t pending = hipPeekAtLastError();
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&attr, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
         attr > 0)
         lds_max = (size_t)attr;
-    (void)hipGetLastError();
+    else if (pending == hipSuccess)
+        (void)hipGetLastError();  // clear only what the failed query left
     const size_t lds_dyn_max = lds_max > 2048 ? lds_max - 2048 : 0;
     // Two forms (measured on MI355X): the LDS tile suits records with few
     // coefficient rows (uniform data, a per-point right-hand side); records
@@ -725,8 +723,7 @@ int fe_integrate_natural(const fe_problem *problem, fe_elem_type elem_type, int6
     int64_t grid = ao.direct ? (n_elem + 255) / 256 : (n_elem + AOS_TILE - 1) / AOS_TILE;
     if (grid > 0x7fffffff)
         grid = 0x7fffffff;
-    pl.entry->aos(pl.args, ao, (unsigned)grid, ao.direct ? 0 : lds, stream);
-    const hipError_t err = hipGetLastError();
+    const hipError_t err = pl.entry->aos(pl.args, ao, (unsigned)grid, ao.direct ? 0 : lds, stream);
     if (err != hipSuccess)
         return fail(FE_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(err));
     return FE_OK;

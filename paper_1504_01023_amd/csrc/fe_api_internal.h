@@ -33,4 +33,17 @@ int check_rule(const fe_quad_rule *r);
 // Tuning table: variant per (kernel family, point count).
 int tuning_lookup(const KernelKey &family, int n_q, fe_variant &out);
 
+// Persistent batched launches (fe_batch.cpp): the resolved plan of kind k
+// (its grid and the chunk size set), the validation of one request of that
+// kind (*wide: its rows and pointers suit the kind's elements per lane), and
+// chunk c of a request.
+int batch_kind_plan(const fe_batch_kind &bk, int k, int64_t chunk_elems, int blocks_per_kind,
+                    Plan &out);
+int batch_check_request(const Plan &pl, int kind, int64_t n_elem, const double *coords,
+                        const void *coeffs, int64_t ld_in, const void *out_K, const void *out_F,
+                        int64_t ld_out, bool *wide);
+Chunk batch_chunk(int64_t c, int64_t chunk_elems, int64_t n_elem, const double *coords,
+                  const void *coeffs, int64_t ld_in, void *out_K, void *out_F, int64_t ld_out,
+                  bool wide);
+
 }  // namespace fe

@@ -278,27 +278,27 @@ __global__ __launch_bounds__(256) void assemble_scalar_kernel(AsmArgs g)
 // Scalar problems take the register-row kernel, 3-component ones the
 // read-add-write kernel.
 template <int NV, int NC, typename T, bool PACKED, bool WITH_B>
-void launch_one(const AsmArgs &g, unsigned grid, hipStream_t stream)
+hipError_t launch_one(const AsmArgs &g, unsigned grid, hipStream_t stream)
 {
     if constexpr (NC == 1)
-        hipLaunchKernelGGL((assemble_scalar_kernel<NV, T, PACKED, WITH_B>), dim3(grid), dim3(256), 0,
+        return launch_kernel(&assemble_scalar_kernel<NV, T, PACKED, WITH_B>, dim3(grid), dim3(256), 0,
                            stream, g);
     else
-        hipLaunchKernelGGL((assemble_stored_kernel<NV, NC, T, PACKED, WITH_B>), dim3(grid), dim3(256),
+        return launch_kernel(&assemble_stored_kernel<NV, NC, T, PACKED, WITH_B>, dim3(grid), dim3(256),
                            0, stream, g);
 }
 
 template <int NV, int NC, typename T>
-void launch(const AsmArgs &g, bool packed, unsigned grid, hipStream_t stream)
+hipError_t launch(const AsmArgs &g, bool packed, unsigned grid, hipStream_t stream)
 {
     if (packed && g.b)
-        launch_one<NV, NC, T, true, true>(g, grid, stream);
+        return launch_one<NV, NC, T, true, true>(g, grid, stream);
     else if (packed)
-        launch_one<NV, NC, T, true, false>(g, grid, stream);
+        return launch_one<NV, NC, T, true, false>(g, grid, stream);
     else if (g.b)
-        launch_one<NV, NC, T, false, true>(g, grid, stream);
+        return launch_one<NV, NC, T, false, true>(g, grid, stream);
     else
-        launch_one<NV, NC, T, false, false>(g, grid, stream);
+        return launch_one<NV, NC, T, false, false>(g, grid, stream);
 }
 
 bool aligned_to(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
@@ -361,19 +361,19 @@ extern "C" int fe_assemble_csr_stored(const fe_problem *problem, fe_elem_type el
     if (grid > 0x7fffffff)
         grid = 0x7fffffff;
     const bool fp64 = problem->precision == FE_FP64;
+    hipError_t err;
     if (nv == 4 && nc == 1)
-        fp64 ? launch<4, 1, double>(g, packed, (unsigned)grid, stream)
-             : launch<4, 1, float>(g, packed, (unsigned)grid, stream);
+        err = fp64 ? launch<4, 1, double>(g, packed, (unsigned)grid, stream)
+                   : launch<4, 1, float>(g, packed, (unsigned)grid, stream);
     else if (nv == 4)
-        fp64 ? launch<4, 3, double>(g, packed, (unsigned)grid, stream)
-             : launch<4, 3, float>(g, packed, (unsigned)grid, stream);
+        err = fp64 ? launch<4, 3, double>(g, packed, (unsigned)grid, stream)
+                   : launch<4, 3, float>(g, packed, (unsigned)grid, stream);
     else if (nc == 1)
-        fp64 ? launch<6, 1, double>(g, packed, (unsigned)grid, stream)
-             : launch<6, 1, float>(g, packed, (unsigned)grid, stream);
+        err = fp64 ? launch<6, 1, double>(g, packed, (unsigned)grid, stream)
+                   : launch<6, 1, float>(g, packed, (unsigned)grid, stream);
     else
-        fp64 ? launch<6, 3, double>(g, packed, (unsigned)grid, stream)
-             : launch<6, 3, float>(g, packed, (unsigned)grid, stream);
-    const hipError_t err = hipGetLastError();
+        err = fp64 ? launch<6, 3, double>(g, packed, (unsigned)grid, stream)
+                   : launch<6, 3, float>(g, packed, (unsigned)grid, stream);
     if (err != hipSuccess)
         return fail(FE_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(err));
     return FE_OK;

@@ -44,6 +44,93 @@ struct Buffer {
 
 }  // namespace
 
+namespace fe {
+
+int batch_kind_plan(const fe_batch_kind &bk, int k, int64_t chunk_elems, int blocks_per_kind,
+                    Plan &out)
+{
+    const fe_quad_rule rule{bk.n_q, bk.xi, bk.w};
+    // Resolve the kernel for this kind (validation, tuned variant, reference
+    // tables) with an empty batch.
+    int st = plan(&bk.problem, bk.elem_type, 0, nullptr, nullptr, 0, &rule, nullptr, nullptr, 0,
+                  nullptr, out);
+    if (st)
+        return st;
+    if (!out.entry->batch) {
+        // The tuned variant has no batched form: keep its workgroup and
+        // width with streaming memory operations, else the base variant.
+        const fe_variant tuned = out.variant;
+        const fe_variant alts[2] = {
+            {tuned.wg_size, tuned.elems_per_thread, tuned.ref_in_lds, 1, 0, tuned.row_split, 1},
+            {256, 1, 2, 1, 0, 1, 1}};
+        for (const fe_variant &v : alts) {
+            Plan alt;
+            if (plan(&bk.problem, bk.elem_type, 0, nullptr, nullptr, 0, &rule, nullptr, nullptr, 0,
+                     &v, alt) == FE_OK && alt.entry->batch) {
+                out = alt;
+                break;
+            }
+        }
+    }
+    if (!out.entry->batch)
+        return fail(FE_ERR_UNSUPPORTED, "kind %d has no batched kernel (elem=%d kind=%d mode=%d)",
+                    k, out.key.elem, out.key.kind, out.key.mode);
+    // 4096 workgroups per kind: most batches take one or two passes of the
+    // tile loop (a long grid-stride loop streams more slowly; measured on
+    // MI355X: resident served throughput +8% over 1024)
+    out.grid = blocks_per_kind > 0 ? (unsigned)blocks_per_kind : 4096u;
+    out.args.n_elem = chunk_elems;  // the kernel's tile count per chunk
+    return FE_OK;
+}
+
+int batch_check_request(const Plan &pl, int kind, int64_t n_elem, const double *coords,
+                        const void *coeffs, int64_t ld_in, const void *out_K, const void *out_F,
+                        int64_t ld_out, bool *wide)
+{
+    bool reads_coeffs = false;
+    for (int s = 0; s < 20; ++s)
+        reads_coeffs = reads_coeffs || pl.args.col[s] >= 0;
+    if (!coords || !out_K || !out_F || (reads_coeffs && !coeffs))
+        return fail(FE_ERR_INVALID_ARG, "NULL input or output pointer");
+    if (ld_in < n_elem || ld_out < n_elem)
+        return fail(FE_ERR_INVALID_ARG, "leading dimension smaller than n_elem");
+    const size_t tsize = pl.key.prec == FE_FP64 ? 8 : 4;
+    const size_t csize = pl.key.mode == M_FUNC ? 8 : tsize;  // function parameters are FP64
+    auto al = [](const void *p, size_t a) { return ((uintptr_t)p % a) == 0; };
+    if (!al(coords, 8) || !al(out_K, tsize) || !al(out_F, tsize) ||
+        (reads_coeffs && !al(coeffs, csize)))
+        return fail(FE_ERR_UNSUPPORTED, "kind %d: pointers must be aligned to their element size",
+                    kind);
+    // V elements per lane read and write V-wide vectors: the rows must start
+    // on multiples of V and the pointers on the vector size; other requests
+    // are processed element by element
+    const int V = pl.key.vec;
+    const size_t ca = V > 1 ? 16 : 8, ta = V > 1 ? (tsize * V < 16 ? tsize * V : 16) : tsize;
+    *wide = !(ld_in % V || ld_out % V || !al(coords, ca) || !al(out_K, ta) || !al(out_F, ta) ||
+              (reads_coeffs && pl.key.mode != M_FUNC && !al(coeffs, ta)));
+    return FE_OK;
+}
+
+Chunk batch_chunk(int64_t c, int64_t chunk_elems, int64_t n_elem, const double *coords,
+                  const void *coeffs, int64_t ld_in, void *out_K, void *out_F, int64_t ld_out,
+                  bool wide)
+{
+    Chunk ch;
+    ch.coords = coords;
+    ch.coeffs = coeffs;
+    ch.out_K = out_K;
+    ch.out_F = out_F;
+    ch.ld_in = ld_in;
+    ch.ld_out = ld_out;
+    ch.e0 = c * chunk_elems;
+    ch.n = (n_elem - ch.e0) < chunk_elems ? (n_elem - ch.e0) : chunk_elems;
+    if (!wide)
+        ch.n = -ch.n;
+    return ch;
+}
+
+}  // namespace fe
+
 struct fe_batch {
     int n_kinds = 0;
     Kind kinds[MAX_BATCH_KINDS];
@@ -123,46 +210,14 @@ int fe_batch_create(const fe_batch_kind *kinds, int n_kinds, int max_chunks, int
     b->chunk_elems = chunk_elems;
     b->table_bytes = HEADER_BYTES + sizeof(Chunk) * (size_t)max_chunks;
     for (int k = 0; k < n_kinds; ++k) {
-        const fe_batch_kind &bk = kinds[k];
-        fe_quad_rule rule{bk.n_q, bk.xi, bk.w};
         Kind &K = b->kinds[k];
-        // Resolve the kernel for this kind (validation, tuned variant,
-        // reference tables) with an empty batch.
-        int st = plan(&bk.problem, bk.elem_type, 0, nullptr, nullptr, 0, &rule, nullptr, nullptr, 0,
-                      nullptr, K.plan);
+        const int st = batch_kind_plan(kinds[k], k, chunk_elems, blocks_per_kind, K.plan);
         if (st) {
             destroy_batch(b);
             return st;
         }
-        if (!K.plan.entry->batch) {
-            // The tuned variant has no batched form: keep its workgroup and
-            // width with streaming memory operations, else the base variant.
-            const fe_variant tuned = K.plan.variant;
-            const fe_variant alts[2] = {
-                {tuned.wg_size, tuned.elems_per_thread, tuned.ref_in_lds, 1, 0, tuned.row_split, 1},
-                {256, 1, 2, 1, 0, 1, 1}};
-            for (const fe_variant &v : alts) {
-                Plan alt;
-                if (plan(&bk.problem, bk.elem_type, 0, nullptr, nullptr, 0, &rule, nullptr, nullptr,
-                         0, &v, alt) == FE_OK && alt.entry->batch) {
-                    K.plan = alt;
-                    break;
-                }
-            }
-        }
-        if (!K.plan.entry->batch) {
-            destroy_batch(b);
-            return fail(FE_ERR_UNSUPPORTED, "kind %d has no batched kernel (elem=%d kind=%d mode=%d)",
-                        k, K.plan.key.elem, K.plan.key.kind, K.plan.key.mode);
-        }
         K.vec = K.plan.key.vec;
-        K.tsize = bk.problem.precision == FE_FP64 ? 8 : 4;
-        // 4096 workgroups per kind: most batches take one or two passes of the
-        // tile loop (a long grid-stride loop streams more slowly; measured on
-        // MI355X: resident served throughput +8% over 1024)
-        const unsigned per_kind = blocks_per_kind > 0 ? (unsigned)blocks_per_kind : 4096u;
-        K.plan.grid = per_kind;
-        K.plan.args.n_elem = chunk_elems;  // the kernel's tile count per chunk
+        K.tsize = kinds[k].problem.precision == FE_FP64 ? 8 : 4;
     }
     HIP_TRY(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
     for (int k = 0; k < n_kinds; ++k) {
@@ -189,8 +244,8 @@ int fe_batch_create(const fe_batch_kind *kinds, int n_kinds, int max_chunks, int
             cerr = hipStreamWaitEvent(b->branch[k], b->forked, 0);
             if (cerr != hipSuccess)
                 break;
-            K.plan.entry->batch(K.plan.args, hdr, chunks, k, K.plan.grid, K.plan.block, b->branch[k]);
-            cerr = hipGetLastError();
+            cerr = K.plan.entry->batch(K.plan.args, hdr, chunks, k, K.plan.grid, K.plan.block,
+                                       b->branch[k]);
             if (cerr == hipSuccess)
                 cerr = hipEventRecord(b->joined[k], b->branch[k]);
             if (cerr == hipSuccess)
@@ -219,39 +274,18 @@ int fe_batch_add(fe_batch *b, int kind, int64_t n_elem, const double *coords, co
         return fail(FE_ERR_INVALID_ARG, "n_elem is negative");
     if (n_elem == 0)
         return FE_OK;
-    const Kind &K = b->kinds[kind];
-    bool reads_coeffs = false;
-    for (int s = 0; s < 20; ++s)
-        reads_coeffs = reads_coeffs || K.plan.args.col[s] >= 0;
-    if (!coords || !out_K || !out_F || (reads_coeffs && !coeffs))
-        return fail(FE_ERR_INVALID_ARG, "NULL input or output pointer");
-    if (ld_in < n_elem || ld_out < n_elem)
-        return fail(FE_ERR_INVALID_ARG, "leading dimension smaller than n_elem");
-    const int V = K.vec;
-    const size_t ca = V > 1 ? 16 : 8, ta = V > 1 ? (K.tsize * V < 16 ? K.tsize * V : 16) : K.tsize;
-    auto al = [](const void *p, size_t a) { return ((uintptr_t)p % a) == 0; };
-    if (ld_in % V || ld_out % V || !al(coords, ca) || !al(out_K, ta) || !al(out_F, ta) ||
-        (reads_coeffs && !al(coeffs, ta)))
-        return fail(FE_ERR_UNSUPPORTED,
-                    "kind %d processes %d elements per lane: leading dimensions must be multiples "
-                    "of %d and pointers aligned to %zu bytes",
-                    kind, V, V, ta);
+    bool wide = true;
+    const int st = batch_check_request(b->kinds[kind].plan, kind, n_elem, coords, coeffs, ld_in,
+                                       out_K, out_F, ld_out, &wide);
+    if (st)
+        return st;
     const int64_t n_chunks = (n_elem + b->chunk_elems - 1) / b->chunk_elems;
     if (b->pending_total + n_chunks > b->max_chunks)
         return fail(FE_ERR_CAPACITY, "batch table full (%d of %d chunks pending, %lld more)",
                     b->pending_total, b->max_chunks, (long long)n_chunks);
-    for (int64_t c = 0; c < n_chunks; ++c) {
-        Chunk ch;
-        ch.coords = coords;
-        ch.coeffs = coeffs;
-        ch.out_K = out_K;
-        ch.out_F = out_F;
-        ch.ld_in = ld_in;
-        ch.ld_out = ld_out;
-        ch.e0 = c * b->chunk_elems;
-        ch.n = (n_elem - ch.e0) < b->chunk_elems ? (n_elem - ch.e0) : b->chunk_elems;
-        b->pending[kind].push_back(ch);
-    }
+    for (int64_t c = 0; c < n_chunks; ++c)
+        b->pending[kind].push_back(batch_chunk(c, b->chunk_elems, n_elem, coords, coeffs, ld_in,
+                                               out_K, out_F, ld_out, wide));
     b->pending_total += (int)n_chunks;
     return FE_OK;
 }

@@ -33,9 +33,9 @@ extern "C" int fe_stream_copy(void *dst, const void *src, int64_t n_bytes, hipSt
     int64_t grid = (n + 255) / 256;
     if (grid > 0x7fffffff)
         grid = 0x7fffffff;
-    hipLaunchKernelGGL(stream_copy_kernel, dim3((unsigned)grid), dim3(256), 0, stream,
-                       static_cast<d2_t *>(dst), static_cast<const d2_t *>(src), n);
-    const hipError_t err = hipGetLastError();
+    const hipError_t err =
+        fe::launch_kernel(&stream_copy_kernel, dim3((unsigned)grid), dim3(256), 0, stream,
+                          static_cast<d2_t *>(dst), static_cast<const d2_t *>(src), n);
     if (err != hipSuccess)
         return fe::fail(FE_ERR_HIP, "copy launch failed: %s", hipGetErrorString(err));
     return FE_OK;

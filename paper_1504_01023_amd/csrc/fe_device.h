@@ -2094,7 +2094,10 @@ __global__ __launch_bounds__(256) void fe_kernel(KArgs a)
 // Persistent batched form: the blocks of one launch walk the chunks of one
 // kind in the device table (chunk c by block c mod gridDim), so requests of
 // different sizes share one launch. Chunk starts are multiples of V, so every
-// element is processed by the same code path as in a plain launch.
+// element is processed by the same code path as in a plain launch. A chunk
+// whose rows or pointers do not suit V-wide accesses carries a negative
+// element count and is processed element by element (the code path of a
+// plain launch's last partial group, which rounds identically).
 template <class P, int V, int NT, int REF>
 __global__ __launch_bounds__(256) void fe_batch_kernel(KArgs a, const BatchHeader *__restrict__ hdr,
                                                        const Chunk *__restrict__ chunks, int kind)
@@ -2121,25 +2124,27 @@ __global__ __launch_bounds__(256) void fe_batch_kernel(KArgs a, const BatchHeade
     const int64_t n_tiles = (int64_t)(end - begin) * tiles_per_chunk;
     for (int64_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
         const Chunk ch = chunks[begin + (int)(t / tiles_per_chunk)];
+        const bool by_elem = ch.n < 0;
         const int64_t e0 = ch.e0 + (t % tiles_per_chunk) * tile + (int64_t)threadIdx.x * V;
-        const int64_t last = ch.e0 + ch.n;
+        const int64_t last = ch.e0 + (by_elem ? -ch.n : ch.n);
         if (e0 >= last)
             continue;
         const Streams st{ch.coords, ch.coeffs, ch.out_K, ch.out_F, ch.ld_in, ch.ld_out};
-        if (V == 1 || e0 + V <= last) {
+        if (V == 1 || (!by_elem && e0 + V <= last)) {
             P::template run<V, NT, REF>(a, st, ref, e0);
         } else {
-            for (int64_t e = e0; e < last; ++e)
+            const int64_t stop = e0 + V < last ? e0 + V : last;
+            for (int64_t e = e0; e < stop; ++e)
                 P::template run<1, NT, REF>(a, st, ref, e);
         }
     }
 }
 
 template <class P, int V, int NT, int REF>
-void launch_fe_batch_kernel(const KArgs &a, const BatchHeader *hdr, const Chunk *chunks, int kind,
+hipError_t launch_fe_batch_kernel(const KArgs &a, const BatchHeader *hdr, const Chunk *chunks, int kind,
                             unsigned grid, unsigned block, hipStream_t stream)
 {
-    hipLaunchKernelGGL((fe_batch_kernel<P, V, NT, REF>), dim3(grid), dim3(block), 0, stream, a, hdr,
+    return launch_kernel(&fe_batch_kernel<P, V, NT, REF>, dim3(grid), dim3(block), 0, stream, a, hdr,
                        chunks, kind);
 }
 
@@ -2550,44 +2555,42 @@ __global__ __launch_bounds__(256) void fe_csr_rows_kernel(KArgs a, IdxArgs gi, A
 }
 
 template <class P, int NV, int NC, typename T, int NT, int REF>
-void launch_fe_apply(const KArgs &a, const IdxArgs &gi, const ApplyArgs &ap, int atomic,
+hipError_t launch_fe_apply(const KArgs &a, const IdxArgs &gi, const ApplyArgs &ap, int atomic,
                      unsigned grid, unsigned block, hipStream_t stream)
 {
     if (ap.vals && ap.inc) {
         if (ap.b)
-            hipLaunchKernelGGL((fe_csr_rows_kernel<P, NV, NC, T, NT, REF, true>), dim3(grid),
+            return launch_kernel(&fe_csr_rows_kernel<P, NV, NC, T, NT, REF, true>, dim3(grid),
                                dim3(block), 0, stream, a, gi, ap);
         else
-            hipLaunchKernelGGL((fe_csr_rows_kernel<P, NV, NC, T, NT, REF, false>), dim3(grid),
+            return launch_kernel(&fe_csr_rows_kernel<P, NV, NC, T, NT, REF, false>, dim3(grid),
                                dim3(block), 0, stream, a, gi, ap);
-        return;
     }
     if (ap.vals) {
         if (atomic && ap.b)
-            hipLaunchKernelGGL((fe_csr_kernel<P, NV, NC, T, NT, REF, true, true>), dim3(grid),
+            return launch_kernel(&fe_csr_kernel<P, NV, NC, T, NT, REF, true, true>, dim3(grid),
                                dim3(block), 0, stream, a, gi, ap);
         else if (atomic)
-            hipLaunchKernelGGL((fe_csr_kernel<P, NV, NC, T, NT, REF, true, false>), dim3(grid),
+            return launch_kernel(&fe_csr_kernel<P, NV, NC, T, NT, REF, true, false>, dim3(grid),
                                dim3(block), 0, stream, a, gi, ap);
         else if (ap.b)
-            hipLaunchKernelGGL((fe_csr_kernel<P, NV, NC, T, NT, REF, false, true>), dim3(grid),
+            return launch_kernel(&fe_csr_kernel<P, NV, NC, T, NT, REF, false, true>, dim3(grid),
                                dim3(block), 0, stream, a, gi, ap);
         else
-            hipLaunchKernelGGL((fe_csr_kernel<P, NV, NC, T, NT, REF, false, false>), dim3(grid),
+            return launch_kernel(&fe_csr_kernel<P, NV, NC, T, NT, REF, false, false>, dim3(grid),
                                dim3(block), 0, stream, a, gi, ap);
-        return;
     }
     if (atomic && ap.b)
-        hipLaunchKernelGGL((fe_apply_kernel<P, NV, NC, T, NT, REF, true, true>), dim3(grid), dim3(block),
+        return launch_kernel(&fe_apply_kernel<P, NV, NC, T, NT, REF, true, true>, dim3(grid), dim3(block),
                            0, stream, a, gi, ap);
     else if (atomic)
-        hipLaunchKernelGGL((fe_apply_kernel<P, NV, NC, T, NT, REF, true, false>), dim3(grid),
+        return launch_kernel(&fe_apply_kernel<P, NV, NC, T, NT, REF, true, false>, dim3(grid),
                            dim3(block), 0, stream, a, gi, ap);
     else if (ap.b)
-        hipLaunchKernelGGL((fe_apply_kernel<P, NV, NC, T, NT, REF, false, true>), dim3(grid),
+        return launch_kernel(&fe_apply_kernel<P, NV, NC, T, NT, REF, false, true>, dim3(grid),
                            dim3(block), 0, stream, a, gi, ap);
     else
-        hipLaunchKernelGGL((fe_apply_kernel<P, NV, NC, T, NT, REF, false, false>), dim3(grid),
+        return launch_kernel(&fe_apply_kernel<P, NV, NC, T, NT, REF, false, false>, dim3(grid),
                            dim3(block), 0, stream, a, gi, ap);
 }
 
@@ -2627,9 +2630,9 @@ __global__ __launch_bounds__(256) void fe_kernel_lanes(KArgs a)
 }
 
 template <class P, int G, int NT, int REF>
-void launch_fe_kernel_lanes(const KArgs &a, unsigned grid, unsigned block, hipStream_t stream)
+hipError_t launch_fe_kernel_lanes(const KArgs &a, unsigned grid, unsigned block, hipStream_t stream)
 {
-    hipLaunchKernelGGL((fe_kernel_lanes<P, G, NT, REF>), dim3(grid), dim3(block), 0, stream, a);
+    return launch_kernel(&fe_kernel_lanes<P, G, NT, REF>, dim3(grid), dim3(block), 0, stream, a);
 }
 
 // Natural-order inputs and outputs (the element-contiguous organisation
@@ -2763,28 +2766,28 @@ __global__ __launch_bounds__(256) void fe_kernel_aos_direct(KArgs a, AosArgs ao)
 }
 
 template <class P, int NV, int NT, int REF>
-void launch_fe_kernel_aos(const KArgs &a, const AosArgs &ao, unsigned grid, size_t lds_bytes,
+hipError_t launch_fe_kernel_aos(const KArgs &a, const AosArgs &ao, unsigned grid, size_t lds_bytes,
                           hipStream_t stream)
 {
     if (ao.direct)
-        hipLaunchKernelGGL((fe_kernel_aos_direct<P, NV, NT, REF>), dim3(grid), dim3(256), 0, stream,
+        return launch_kernel(&fe_kernel_aos_direct<P, NV, NT, REF>, dim3(grid), dim3(256), 0, stream,
                            a, ao);
     else
-        hipLaunchKernelGGL((fe_kernel_aos<P, NV, NT, REF>), dim3(grid), dim3(AOS_TILE), lds_bytes,
+        return launch_kernel(&fe_kernel_aos<P, NV, NT, REF>, dim3(grid), dim3(AOS_TILE), lds_bytes,
                            stream, a, ao);
 }
 
 template <class P, int V, int NT, int REF>
-void launch_fe_kernel_idx(const KArgs &a, const IdxArgs &gi, unsigned grid, unsigned block,
+hipError_t launch_fe_kernel_idx(const KArgs &a, const IdxArgs &gi, unsigned grid, unsigned block,
                           hipStream_t stream)
 {
-    hipLaunchKernelGGL((fe_kernel_idx<P, V, NT, REF>), dim3(grid), dim3(block), 0, stream, a, gi);
+    return launch_kernel(&fe_kernel_idx<P, V, NT, REF>, dim3(grid), dim3(block), 0, stream, a, gi);
 }
 
 template <class P, int V, int NT, int REF>
-void launch_fe_kernel(const KArgs &a, unsigned grid, unsigned block, hipStream_t stream)
+hipError_t launch_fe_kernel(const KArgs &a, unsigned grid, unsigned block, hipStream_t stream)
 {
-    hipLaunchKernelGGL((fe_kernel<P, V, NT, REF>), dim3(grid), dim3(block), 0, stream, a);
+    return launch_kernel(&fe_kernel<P, V, NT, REF>, dim3(grid), dim3(block), 0, stream, a);
 }
 
 }  // namespace fe

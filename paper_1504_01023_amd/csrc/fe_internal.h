@@ -2,11 +2,32 @@
 // the kernel translation units. Not part of the public ABI.
 #pragma once
 
+#include <hip/hip_runtime.h>
+
 #include <cstdint>
+#include <tuple>
+#include <utility>
 
 #include "fe.h"
 
 namespace fe {
+
+// Launches the __global__ function k with the given arguments, converted to
+// its parameter types, and returns the launch's own status. (The thread's
+// last error is not consulted: it may hold a failure of the caller's earlier
+// work, which the library neither reports as its own nor clears.)
+template <typename... P, typename... A>
+inline hipError_t launch_kernel(void (*k)(P...), dim3 grid, dim3 block, size_t lds,
+                                hipStream_t stream, A &&...args)
+{
+    std::tuple<P...> vals(std::forward<A>(args)...);
+    void *ptrs[sizeof...(P) > 0 ? sizeof...(P) : 1];
+    std::apply([&ptrs](auto &...v) {
+        int i = 0;
+        ((ptrs[i++] = static_cast<void *>(&v)), ...);
+    }, vals);
+    return hipLaunchKernel(reinterpret_cast<const void *>(k), grid, block, ptrs, lds, stream);
+}
 
 // Term groups of the scalar weak form (Sec. 2.1, eq. "weak_form"); a kernel
 // is compiled for a set of groups and the code for absent groups is removed.
@@ -92,7 +113,7 @@ struct KernelKey {
     int lanes;     // lanes per element (1, or 2, 3, 6 for the prism point split)
 };
 
-typedef void (*LaunchFn)(const KArgs &, unsigned grid, unsigned block, hipStream_t);
+typedef hipError_t (*LaunchFn)(const KArgs &, unsigned grid, unsigned block, hipStream_t);
 
 // Persistent batched launches: a table of chunks (element ranges of many
 // requests), grouped by kind; kind k owns chunks [begin[k], end[k]).
@@ -105,14 +126,15 @@ struct Chunk {
     int64_t ld_in;
     int64_t ld_out;
     int64_t e0;  // first element of the chunk (offset into the arrays above)
-    int64_t n;   // elements in the chunk
+    int64_t n;   // elements in the chunk; negated when the rows or pointers do
+                 // not suit the kind's elements per lane (element by element)
 };
 static_assert(sizeof(Chunk) == 64, "chunk records are one 64-byte line");
 struct BatchHeader {
     int32_t begin[MAX_BATCH_KINDS];
     int32_t end[MAX_BATCH_KINDS];
 };
-typedef void (*BatchLaunchFn)(const KArgs &, const BatchHeader *, const Chunk *, int kind,
+typedef hipError_t (*BatchLaunchFn)(const KArgs &, const BatchHeader *, const Chunk *, int kind,
                               unsigned grid, unsigned block, hipStream_t);
 
 // Indexed geometry: coordinates gathered from a node array through
@@ -123,7 +145,7 @@ struct IdxArgs {
     int64_t ld_conn;
     uint32_t n_nodes;      // ids are clamped to [0, n_nodes)
 };
-typedef void (*IdxLaunchFn)(const KArgs &, const IdxArgs &, unsigned grid, unsigned block,
+typedef hipError_t (*IdxLaunchFn)(const KArgs &, const IdxArgs &, unsigned grid, unsigned block,
                             hipStream_t);
 
 // Matrix-free application: nodal vectors in the precision of the tier,
@@ -147,7 +169,7 @@ struct ApplyArgs {
     const int32_t *inc;
     int64_t n_own;  // nodes in this launch
 };
-typedef void (*ApplyLaunchFn)(const KArgs &, const IdxArgs &, const ApplyArgs &, int atomic,
+typedef hipError_t (*ApplyLaunchFn)(const KArgs &, const IdxArgs &, const ApplyArgs &, int atomic,
                               unsigned grid, unsigned block, hipStream_t);
 
 // Natural-order (element-contiguous) inputs and outputs: every element's
@@ -165,7 +187,7 @@ struct AosArgs {
     // dimension 1), grid over elements with 256 lanes per workgroup
     int32_t direct;
 };
-typedef void (*AosLaunchFn)(const KArgs &, const AosArgs &, unsigned grid, size_t lds_bytes,
+typedef hipError_t (*AosLaunchFn)(const KArgs &, const AosArgs &, unsigned grid, size_t lds_bytes,
                             hipStream_t);
 constexpr int AOS_TILE = 64;  // elements per workgroup tile (one wavefront)
 

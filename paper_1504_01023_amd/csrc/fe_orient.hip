@@ -90,11 +90,10 @@ extern "C" int fe_count_inverted(fe_elem_type elem_type, int64_t n_elem, const d
     if (grid > 4096)
         grid = 4096;
     unsigned long long *c = reinterpret_cast<unsigned long long *>(count);
-    if (elem_type == FE_TET4)
-        hipLaunchKernelGGL(count_inverted_kernel<4>, dim3((unsigned)grid), dim3(256), 0, stream, a, c);
-    else
-        hipLaunchKernelGGL(count_inverted_kernel<6>, dim3((unsigned)grid), dim3(256), 0, stream, a, c);
-    const hipError_t err = hipGetLastError();
+    const hipError_t err =
+        elem_type == FE_TET4
+            ? launch_kernel(&count_inverted_kernel<4>, dim3((unsigned)grid), dim3(256), 0, stream, a, c)
+            : launch_kernel(&count_inverted_kernel<6>, dim3((unsigned)grid), dim3(256), 0, stream, a, c);
     if (err != hipSuccess)
         return fail(FE_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(err));
     return FE_OK;

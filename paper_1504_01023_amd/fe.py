@@ -703,6 +703,17 @@ def _batch_sigs(L):
     L._batch_sigs = True
 
 
+def _batch_kinds(kinds):
+    arr = (BatchKind * len(kinds))()
+    for i, (p, elem, rule) in enumerate(kinds):
+        arr[i].problem = p
+        arr[i].elem_type = ELEM.get(elem, elem)
+        arr[i].n_q = rule.n_q
+        arr[i].xi = rule.c.xi
+        arr[i].w = rule.c.w
+    return arr
+
+
 class Batch:
     """Persistent batched launches over a fixed set of kinds
     (fe_batch_create / fe_batch_add / fe_batch_launch)."""
@@ -712,13 +723,7 @@ class Batch:
         L = lib()
         _batch_sigs(L)
         self._rules = [k[2] for k in kinds]
-        arr = (BatchKind * len(kinds))()
-        for i, (p, elem, rule) in enumerate(kinds):
-            arr[i].problem = p
-            arr[i].elem_type = ELEM.get(elem, elem)
-            arr[i].n_q = rule.n_q
-            arr[i].xi = rule.c.xi
-            arr[i].w = rule.c.w
+        arr = _batch_kinds(kinds)
         self.kinds = list(kinds)
         self._h = ctypes.c_void_p()
         _check(L.fe_batch_create(arr, len(kinds), max_chunks, chunk_elems, blocks_per_kind,

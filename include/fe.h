@@ -471,6 +471,54 @@ FE_API int fe_batch_launch(fe_batch *b, hipStream_t stream);
 FE_API int fe_batch_destroy(fe_batch *b);
 
 /* ---------------------------------------------------------------------
+ * Batched integration that allocates nothing, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc). One call integrates a list of requests
+ * of up to FE_MAX_BATCH_KINDS kinds with the persistent batched kernels of
+ * fe_batch_launch, and gives the same results bit for bit as fe_batch_create
+ * + fe_batch_add (each request, in order) + fe_batch_launch with the same
+ * kinds, chunk_elems and blocks_per_kind.
+ *
+ * Memory: the chunk table lives in a device array inside the library of
+ * 128 + 64 * FE_BATCH_STATIC_MAX_CHUNKS bytes (about 64 KiB), one per device,
+ * held until the process ends. The call writes the table there with small
+ * table-writing kernels whose arguments carry it, then launches one
+ * persistent kernel per kind present, all on `stream`; it calls no
+ * allocating routine and never waits. The caller owns every input and output
+ * and keeps them valid until the stream work completes; `kinds` (and their
+ * rules) and `requests` are host memory read during the call only.
+ *
+ * Every call on one device shares that device's table and overwrites it:
+ * calls on the same stream are ordered, but calls that overlap on one device
+ * (from two streams, or from two host threads) race and give wrong results.
+ * Serialise them.
+ *
+ * Errors: FE_ERR_CAPACITY when the requests need more than
+ * FE_BATCH_STATIC_MAX_CHUNKS chunks of chunk_elems elements (use larger
+ * chunks or split the list); the other codes as for fe_batch_create and
+ * fe_batch_add. Every check is made before anything is enqueued, so on error
+ * nothing runs and the outputs are untouched.
+ * ------------------------------------------------------------------- */
+#define FE_BATCH_STATIC_MAX_CHUNKS 1024
+
+typedef struct fe_batch_request {
+    int32_t kind;              /* index into `kinds` */
+    int32_t reserved;          /* must be 0 */
+    int64_t n_elem;
+    const double *coords;      /* layouts as for fe_integrate_ex */
+    const void *coeffs;
+    int64_t ld_in;
+    void *out_K;
+    void *out_F;
+    int64_t ld_out;
+} fe_batch_request;
+
+FE_API int fe_batch_integrate_static(const fe_batch_kind *kinds, int n_kinds,
+                                     const fe_batch_request *requests, int n_requests,
+                                     int64_t chunk_elems, int blocks_per_kind,
+                                     hipStream_t stream);
+
+/* ---------------------------------------------------------------------
  * Continuous-batching server. Requests (one mesh of one kind each) are
  * submitted at any time; a scheduler thread admits them in arrival order
  * while a slot is free and their device bytes (inputs + outputs) fit in the

@@ -690,10 +690,21 @@ class BatchKind(ctypes.Structure):
                 ("xi", ctypes.POINTER(ctypes.c_double)), ("w", ctypes.POINTER(ctypes.c_double))]
 
 
+class BatchRequest(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32), ("n_elem", ctypes.c_int64),
+                ("coords", ctypes.c_void_p), ("coeffs", ctypes.c_void_p), ("ld_in", ctypes.c_int64),
+                ("out_K", ctypes.c_void_p), ("out_F", ctypes.c_void_p), ("ld_out", ctypes.c_int64)]
+
+
+BATCH_STATIC_MAX_CHUNKS = 1024
+
+
 def _batch_sigs(L):
     if getattr(L, "_batch_sigs", False):
         return
     vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    L.fe_batch_integrate_static.argtypes = [ctypes.POINTER(BatchKind), i32,
+                                            ctypes.POINTER(BatchRequest), i32, i64, i32, vp]
     L.fe_batch_create.argtypes = [ctypes.POINTER(BatchKind), i32, i32, i64, i32,
                                   ctypes.POINTER(vp)]
     L.fe_batch_add.argtypes = [vp, i32, i64, vp, vp, i64, vp, vp, i64]
@@ -712,6 +723,31 @@ def _batch_kinds(kinds):
         arr[i].xi = rule.c.xi
         arr[i].w = rule.c.w
     return arr
+
+
+def batch_integrate_static(kinds, requests, chunk_elems=16384, blocks_per_kind=0,
+                           stream=None) -> None:
+    """fe_batch_integrate_static: integrate a list of requests with the
+    persistent batched kernels, allocating nothing (the chunk table lives in
+    the library's own device array). kinds: list of (Problem, elem, Rule);
+    requests: list of (kind, coords, coeffs, out_K, out_F[, n_elem]) with
+    (rows, ld) tensors."""
+    L = lib()
+    _batch_sigs(L)
+    arr = _batch_kinds(kinds)
+    reqs = (BatchRequest * max(1, len(requests)))()
+    for i, r in enumerate(requests):
+        kind, coords, coeffs, out_K, out_F = r[:5]
+        reqs[i].kind = kind
+        reqs[i].n_elem = coords.shape[1] if len(r) < 6 or r[5] is None else int(r[5])
+        reqs[i].coords = coords.data_ptr()
+        reqs[i].coeffs = coeffs.data_ptr() if coeffs is not None else None
+        reqs[i].ld_in = coords.shape[1]
+        reqs[i].out_K = out_K.data_ptr()
+        reqs[i].out_F = out_F.data_ptr()
+        reqs[i].ld_out = out_K.shape[1]
+    _check(L.fe_batch_integrate_static(arr, len(kinds), reqs, len(requests), chunk_elems,
+                                       blocks_per_kind, _stream_handle(stream)))
 
 
 class Batch:

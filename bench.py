@@ -5,18 +5,29 @@ Default workload (the headline one): scalar Poisson (c^{i;j} = identity,
 d^0 = 1) on the jittered unit cube with N = 119 cells per side split into
 6 Kuhn tetrahedra (10,110,954 elements, seed 1), 1-point rule, packed 4x4 K
 and 4-vector F, FP64. One "step" is one fe_integrate call over the whole
-mesh with inputs already resident in HBM.
+mesh with inputs already resident in HBM, in the library's default layout
+(rows of fe_ld_for(n) elements) and launch variant (its built-in table).
 
-Prints one JSON line (rank 0). Timing: W untimed warm-up steps, then K
-timed steps between device synchronisations; the kernel's own duration is
-taken with HIP events recorded on the launch stream around every step.
-The launch variant comes from the committed MI355X tuning table
-(paper_1504_01023_amd/tuning_mi355x.txt); --tune re-runs the exhaustive
-search of fe_autotune during warm-up instead.
+Timing: W untimed warm-up steps, then K timed steps back to back between
+device synchronisations. `value` (elements/s) and `ms_per_step` come from the
+host clock over that region; `roofline.achieved` divides the algorithmic
+bytes by the average kernel duration from one pair of HIP events on the
+launch stream around the same region; `wall_frac` is `value` x bytes over
+the peak. Per-launch durations (min / median) come from a separate pass.
+
+The default run then reports the rest of the metric in the same line:
+`fp32` (the same workload in the FP32 bulk tier, its speed-up over FP64
+against the byte-ratio bound, and its error against the FP64 oracle) and
+`served` (the mixed request stream of one jittered mesh per request through
+the continuous-batching server: saturation throughput with host and with
+resident inputs, the speed-ups over one-at-a-time fe_integrate, p50/p99 at
+offered load 0.7 with the queue / H2D / device split, and the alone-vs-mix
+bitwise check). --headline-only skips both.
 
 Extra workloads (--workload): tet_cdr (N=119, 4-point rule, per-element
 coefficients, full K), prism_cdr_qp (141x141x100 prisms with per-point
-coefficients), tet_elasticity (N=94, packed 12x12), prism_elasticity;
+coefficients), tet_elasticity (N=94, packed 12x12), prism_elasticity, and
+more; `served` runs the full served protocol (loads 0.5, 0.7, 0.9);
 --precision fp32 selects the FP32 bulk tier.
 """
 from __future__ import annotations
@@ -126,11 +137,55 @@ def stored_traffic(workload: str, precision: str, src_hash: str):
     return float(m_val.group(1))
 
 
+def host_threads() -> int:
+    """Threads for host-side work: the CPUs this process may run on (its
+    affinity), capped by OMP_NUM_THREADS where the machine sets one (a GPU
+    share of a larger host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    if omp.isdigit() and int(omp) > 0:
+        n = min(n, int(omp))
+    return max(1, n)
+
+
+def cpu_description() -> dict:
+    """The host CPU: lscpu's model name (else /proc/cpuinfo's), nproc (the
+    affinity) and the logical CPU count of the machine."""
+    import subprocess
+    model = ""
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.strip().startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except (OSError, subprocess.SubprocessError):
+        pass
+    if not model:
+        try:
+            with open("/proc/cpuinfo") as f:
+                for line in f:
+                    if line.startswith("model name"):
+                        model = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count() or 1
+    return {"cpu_model": model, "nproc": nproc, "cpu_count": os.cpu_count(),
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
 def cpu_baseline(wl, min_s: float = 10.0, max_s: float = 30.0):
     """The oracle as it stands, timed on the host cores on passes over the
     same workload (whole passes until about min_s seconds have elapsed)."""
     import oracle
-    threads = max(1, min(16, os.cpu_count() or 1))
+    threads = host_threads()
     done, passes = 0, 0
     t0 = time.perf_counter()
     chunk = min(wl.n_elem, 2_000_000)
@@ -151,20 +206,12 @@ def cpu_baseline(wl, min_s: float = 10.0, max_s: float = 30.0):
     t1 = time.perf_counter()
     oracle.integrate_workload(wl, threads=1, elements=np.arange(n1))
     single = n1 / (time.perf_counter() - t1)
-    model = ""
-    try:
-        with open("/proc/cpuinfo") as f:
-            for line in f:
-                if line.startswith("model name"):
-                    model = line.split(":", 1)[1].strip()
-                    break
-    except OSError:
-        pass
-    return {"value": done / el, "unit": "elements/s", "cores": threads, "kind": "oracle",
-            "sample": f"{done} elements ({passes} pass(es) over the {wl.n_elem}-element workload, "
-                      f"chunks of {chunk}), {el:.1f} s wall",
-            "single_thread_value": single, "single_thread_sample": f"first {n1} elements",
-            "cpu_model": model}
+    out = {"value": done / el, "unit": "elements/s", "cores": threads, "kind": "oracle",
+           "sample": f"{done} elements ({passes} pass(es) over the {wl.n_elem}-element workload, "
+                     f"chunks of {chunk}), {el:.1f} s wall, {threads} threads",
+           "single_thread_value": single, "single_thread_sample": f"first {n1} elements"}
+    out.update(cpu_description())
+    return out
 
 
 # ---------------------------------------------------------------- serving
@@ -192,112 +239,205 @@ def served_requests(n_req, seed=5):
     return out
 
 
-def served_pools(torch):
-    """One 2.06M-element pinned host mesh (+ coefficients in both tiers) per
-    element type and problem; a request integrates the first n elements of
-    its pool, which stands in for a mesh of n elements."""
+def served_workload(r):
+    """Request r's own mesh, built from its drawn seed: a jittered unit cube
+    of about r["n"] elements (tets: N = max(1, round((n/6)^(1/3))) cells per
+    side, 6 N^3 elements; prisms: n = L = max(1, round((n/2)^(1/3))),
+    2 n^2 L elements), with per-element coefficients drawn as for the tet
+    CDR (20 slots) or elasticity (E, nu, f) workloads."""
     from paper_1504_01023_amd import inputs
-    pools = {}
-    for elem, prob in SERVED_KINDS:
-        if elem == "tet4":
-            wl = inputs.tet_cdr(70, seed=51) if prob == "scalar" else inputs.tet_elasticity(70, seed=52)
-        else:
-            wl = (inputs.prism_cdr_element(101, 101, seed=53) if prob == "scalar"
-                  else inputs.prism_elasticity(101, 101, seed=54))
-        hc = torch.from_numpy(wl.mesh.coords).pin_memory()
-        h64 = torch.from_numpy(wl.coeffs).pin_memory()
-        h32 = torch.from_numpy(wl.coeffs.astype(np.float32)).pin_memory()
-        pools[(elem, prob)] = {"wl": wl, "coords": hc, "fp64": h64, "fp32": h32}
-    return pools
+    seed = r["seed"]
+    if r["elem"] == "tet4":
+        N = inputs.tet_n_for(r["n"])
+        return inputs.tet_cdr(N, seed) if r["prob"] == "scalar" else inputs.tet_elasticity(N, seed)
+    m = inputs.prism_n_for(r["n"])
+    return (inputs.prism_cdr_element(m, m, seed, sliver=False) if r["prob"] == "scalar"
+            else inputs.prism_elasticity(m, m, seed, sliver=False))
 
 
-def run_served(a, torch, fe, serve) -> dict:
-    dev = torch.device("cuda:0")
-    t0 = time.time()
-    pools = served_pools(torch)
-    log(f"[served] pools generated in {time.time() - t0:.1f}s")
+def served_count(r):
+    """Elements of request r's mesh (the formulas of served_workload)."""
+    from paper_1504_01023_amd import inputs
+    if r["elem"] == "tet4":
+        return 6 * inputs.tet_n_for(r["n"]) ** 3
+    return 2 * inputs.prism_n_for(r["n"]) ** 3
+
+
+SLAB_BYTES = 1 << 32
+
+
+class PinnedSlabs:
+    """Pinned host memory carved into 256-byte aligned pieces from 4 GiB
+    slabs (few large pinned allocations instead of one per request)."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.slabs = []
+        self.used = SLAB_BYTES
+
+    def take(self, nbytes, dtype, shape):
+        torch = self.torch
+        nb = (nbytes + 255) // 256 * 256
+        if nb > SLAB_BYTES:
+            raise ValueError("request larger than a slab")
+        if self.used + nb > SLAB_BYTES:
+            self.slabs.append(torch.empty(SLAB_BYTES, dtype=torch.uint8, pin_memory=True))
+            self.used = 0
+        v = self.slabs[-1][self.used:self.used + nbytes]
+        self.used += nb
+        return v.view(dtype).view(shape)
+
+
+def served_payloads(reqs, torch, threads):
+    """Every request's inputs in pinned host memory: SoA coordinates (FP64)
+    and per-element coefficients in the request's tier, each with leading
+    dimension n. Generated in parallel (numpy releases the interpreter lock
+    in its array work); each request's arrays depend on its seed only."""
+    import concurrent.futures as cf
+    slabs = PinnedSlabs(torch)
+    plan = []
+    for r in reqs:
+        n = served_count(r)
+        nv = 4 if r["elem"] == "tet4" else 6
+        rows_k = 20 if r["prob"] == "scalar" else 5
+        dt = torch.float64 if r["tier"] == "fp64" else torch.float32
+        c = slabs.take(8 * 3 * nv * n, torch.float64, (3 * nv, n))
+        k = slabs.take((8 if r["tier"] == "fp64" else 4) * rows_k * n, dt, (rows_k, n))
+        r["n_actual"] = n
+        plan.append((r, c, k))
+
+    def fill(item):
+        r, c, k = item
+        wl = served_workload(r)
+        assert wl.n_elem == r["n_actual"] and wl.coeffs.shape == tuple(k.shape)
+        c.copy_(torch.from_numpy(wl.mesh.coords))
+        k.copy_(torch.from_numpy(wl.coeffs).to(k.dtype))
+        return r["n_actual"]
+
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(fill, plan))
+    return [(c, k) for _, c, k in plan], slabs
+
+
+def served_kinds(fe):
+    """The eight served kinds: (tet, prism) x (CDR, elasticity) x (FP64, FP32),
+    with the rules of the tet CDR (4 points), tet elasticity (1) and prism
+    (6) workloads."""
+    from paper_1504_01023_amd import inputs
     kinds = []
     for tier in ("fp64", "fp32"):
         for elem, prob in SERVED_KINDS:
-            wl = pools[(elem, prob)]["wl"]
+            if elem == "tet4":
+                wl = inputs.tet_cdr(1, 1) if prob == "scalar" else inputs.tet_elasticity(1, 1)
+            else:
+                wl = (inputs.prism_cdr_element(1, 1, 1, sliver=False) if prob == "scalar"
+                      else inputs.prism_elasticity(1, 1, 1, sliver=False))
             kinds.append((fe.problem_for(wl, tier), elem, fe.builtin_rule(elem, wl.n_q)))
-    n_warm, n_meas = a.served_warmup, a.served_requests
+    return kinds
+
+
+def run_served(a, torch, fe, serve, n_meas, n_warm, rhos, sample=20) -> dict:
+    dev = torch.device("cuda:0")
+    kinds = served_kinds(fe)
     reqs = served_requests(n_warm + n_meas)
+    t0 = time.time()
+    threads = host_threads()
+    payloads, slabs = served_payloads(reqs, torch, threads)
     meas = reqs[n_warm:]
-    tot_elems = sum(r["n"] for r in meas)
+    mpay = payloads[n_warm:]
+    tot_elems = sum(r["n_actual"] for r in meas)
+    host_bytes = sum(c.numel() * c.element_size() + k.numel() * k.element_size()
+                     for c, k in payloads)
+    log(f"[served] {n_warm + n_meas} per-request meshes ({tot_elems} measured elements, "
+        f"{host_bytes / 1e9:.1f} GB pinned) generated in {time.time() - t0:.1f}s on {threads} threads")
 
-    def host_ptrs(r):
-        pool = pools[(r["elem"], r["prob"])]
-        return pool["coords"].data_ptr(), pool[r["tier"]].data_ptr(), pool["wl"].n_elem
-
-    # --- sequential plain service (capacity): H2D of the request's inputs,
-    # then fe_integrate, one request at a time
     stream = torch.cuda.current_stream()
-    dev_pool = {}
-    for key, pool in pools.items():
-        dev_pool[key] = {"coords": pool["coords"].to(dev), "fp64": pool["fp64"].to(dev),
-                         "fp32": pool["fp32"].to(dev)}
-    torch.cuda.synchronize()
-
     hip = ctypes.CDLL("libamdhip64.so")
     hip.hipMemcpy2DAsync.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                      ctypes.c_size_t, ctypes.c_size_t, ctypes.c_size_t,
                                      ctypes.c_int, ctypes.c_void_p]
 
-    def h2d_rows(dst, src, n):
-        """Copy the first n columns of a pinned (rows, ld) host array into a
-        device (rows, ld') array, as the server does (one pitched copy)."""
+    def dev_ld(n):
+        return (n + 3) // 4 * 4
+
+    def h2d_rows(dst, src):
+        """Copy a pinned (rows, n) host array into a device (rows, ld) array
+        as the server does (one pitched copy)."""
         es = src.element_size()
         st = hip.hipMemcpy2DAsync(ctypes.c_void_p(dst.data_ptr()), dst.shape[1] * es,
-                                  ctypes.c_void_p(src.data_ptr()), src.shape[1] * es, n * es,
-                                  src.shape[0], 1, ctypes.c_void_p(stream.cuda_stream))
+                                  ctypes.c_void_p(src.data_ptr()), src.shape[1] * es,
+                                  src.shape[1] * es, src.shape[0], 1,
+                                  ctypes.c_void_p(stream.cuda_stream))
         if st != 0:
             raise RuntimeError(f"hipMemcpy2DAsync failed: {st}")
 
-    def plain_one(r, resident):
-        pool = pools[(r["elem"], r["prob"])]
-        k = kinds[r["kind"]]
-        n = r["n"]
-        if resident:
-            dp = dev_pool[(r["elem"], r["prob"])]
-            c, cf = dp["coords"], dp[r["tier"]]
-            Kt, Ft = fe.integrate(k[0], k[1], c, cf, k[2], n_elem=n)
-        else:
-            ld = (n + 3) // 4 * 4
-            src_c, src_k = pool["coords"], pool[r["tier"]]
-            c = torch.empty((src_c.shape[0], ld), dtype=src_c.dtype, device=dev)
-            cf = torch.empty((src_k.shape[0], ld), dtype=src_k.dtype, device=dev)
-            h2d_rows(c, src_c, n)
-            h2d_rows(cf, src_k, n)
-            Kt, Ft = fe.integrate(k[0], k[1], c, cf, k[2], n_elem=n)
-        return Kt, Ft
+    # inputs staged on the device for the resident mode (rows padded to a
+    # multiple of 4 elements, as the server pads its own copies)
+    t0 = time.time()
+    resident = []
+    for (c, k), r in zip(mpay, meas):
+        ld = dev_ld(r["n_actual"])
+        dc = torch.empty((c.shape[0], ld), dtype=c.dtype, device=dev)
+        dk = torch.empty((k.shape[0], ld), dtype=k.dtype, device=dev)
+        h2d_rows(dc, c)
+        h2d_rows(dk, k)
+        resident.append((dc, dk))
+    torch.cuda.synchronize()
+    log(f"[served] resident copies staged in {time.time() - t0:.1f}s")
 
-    for r in reqs[:n_warm]:
-        plain_one(r, False)
+    def plain_one(i, r, pay, on_dev):
+        k = kinds[r["kind"]]
+        n = r["n_actual"]
+        if on_dev:
+            dc, dk = resident[i]
+        else:
+            c, kk = pay
+            ld = dev_ld(n)
+            dc = torch.empty((c.shape[0], ld), dtype=c.dtype, device=dev)
+            dk = torch.empty((kk.shape[0], ld), dtype=kk.dtype, device=dev)
+            h2d_rows(dc, c)
+            h2d_rows(dk, kk)
+        return fe.integrate(k[0], k[1], dc, dk, k[2], n_elem=n)
+
+    # sequential plain service (the capacity): one request at a time through
+    # fe_integrate, H2D of its inputs included or inputs resident
+    for r, pay in zip(reqs[:n_warm], payloads[:n_warm]):
+        plain_one(0, r, pay, False)
     torch.cuda.synchronize()
     seq = {}
-    for resident in (False, True):
+    for on_dev in (False, True):
         ts = []
-        for r in meas:
+        for i, (r, pay) in enumerate(zip(meas, mpay)):
             w0 = time.perf_counter()
-            plain_one(r, resident)
+            plain_one(i, r, pay, on_dev)
             torch.cuda.synchronize()
             ts.append(time.perf_counter() - w0)
-        seq["resident" if resident else "h2d"] = {
+        seq["resident" if on_dev else "h2d"] = {
             "mean_service_s": float(np.mean(ts)), "elements_per_s": tot_elems / float(np.sum(ts)),
             "p50_s": float(np.percentile(ts, 50)), "p99_s": float(np.percentile(ts, 99))}
     log(f"[served] sequential plain: {seq}")
 
-    def serve_run(srv, rate, resident, sample_ids=()):
-        """Submit the measured requests with the given arrival rate (None =
-        all at once), consume completions, return latencies and outputs'
-        checksums for sample_ids."""
+    def fetch(c, r):
+        k = kinds[r["kind"]]
+        dt_ = torch.float64 if r["tier"] == "fp64" else torch.float32
+        out = []
+        for ptr, rows in ((c.out_K, fe.k_entries(k[0], k[1])), (c.out_F, fe.f_entries(k[0], k[1]))):
+            buf = torch.empty((rows, c.ld_out), dtype=dt_, device=dev)
+            fe.lib().fe_stream_copy(ctypes.c_void_p(buf.data_ptr()), ctypes.c_void_p(ptr),
+                                    buf.numel() * buf.element_size(),
+                                    ctypes.c_void_p(stream.cuda_stream))
+            out.append(buf[:, :r["n_actual"]].contiguous().cpu().numpy())
+        return out
+
+    def serve_run(srv, rate, on_dev, sample_ids=()):
+        """Submit the measured requests at the given arrival rate (None: all
+        at t = 0), consume completions; latencies, and the outputs of
+        sample_ids."""
         import threading
         srv.reset_stats()
         gaps = [r["gap"] for r in meas]
         arrivals = np.cumsum(gaps) / rate if rate else np.zeros(len(meas))
-        ids = {}
-        sums = {}
+        outs = {}
         t_start = serve.now()
         done = []
 
@@ -309,15 +449,14 @@ def run_served(a, torch, fe, serve) -> dict:
                     if dt <= 0:
                         break
                     time.sleep(min(dt, 0.002))
-                if resident:
-                    dp = dev_pool[(r["elem"], r["prob"])]
-                    rid = srv.submit(r["kind"], r["n"], dp["coords"].data_ptr(),
-                                     dp[r["tier"]].data_ptr(), on_device=True,
-                                     ld_in=dp["coords"].shape[1], tag=i)
+                if on_dev:
+                    dc, dk = resident[i]
+                    srv.submit(r["kind"], r["n_actual"], dc.data_ptr(), dk.data_ptr(),
+                               on_device=True, ld_in=dc.shape[1], tag=i)
                 else:
-                    cp, kp, ld = host_ptrs(r)
-                    rid = srv.submit(r["kind"], r["n"], cp, kp, ld_in=ld, tag=i)
-                ids[rid] = i
+                    c, k = mpay[i]
+                    srv.submit(r["kind"], r["n_actual"], c.data_ptr(), k.data_ptr(),
+                               ld_in=c.shape[1], tag=i)
 
         th = threading.Thread(target=submitter)
         th.start()
@@ -325,18 +464,8 @@ def run_served(a, torch, fe, serve) -> dict:
             for c in srv.poll(256, 0.01):
                 if c.status != 0:
                     raise RuntimeError(f"served request failed with status {c.status}")
-                i = c.tag
-                if i in sample_ids:
-                    r = meas[i]
-                    k = kinds[r["kind"]]
-                    dt_ = torch.float64 if r["tier"] == "fp64" else torch.float32
-                    for name, ptr, rows in (("K", c.out_K, fe.k_entries(k[0], k[1])),
-                                            ("F", c.out_F, fe.f_entries(k[0], k[1]))):
-                        buf = torch.empty((rows, c.ld_out), dtype=dt_, device=dev)
-                        fe.lib().fe_stream_copy(ctypes.c_void_p(buf.data_ptr()), ctypes.c_void_p(ptr),
-                                                buf.numel() * buf.element_size(),
-                                                ctypes.c_void_p(stream.cuda_stream))
-                        sums[(i, name)] = buf[:, :r["n"]].contiguous().cpu().numpy().tobytes()
+                if c.tag in sample_ids:
+                    outs[c.tag] = fetch(c, meas[c.tag])
                 srv.release(c.id)
                 done.append(c)
         th.join()
@@ -349,25 +478,30 @@ def run_served(a, torch, fe, serve) -> dict:
                 "mean_s": float(lat.mean()),
                 "mean_queue_s": st["mean_queue_s"], "mean_h2d_s": st["mean_h2d_s"],
                 "mean_device_s": st["mean_device_s"], "ticks": st["ticks"],
-                "peak_bytes": st["bytes_peak"]}, sums
+                "peak_bytes": st["bytes_peak"]}, outs
 
     budget = 64 << 30
+    counts = {}
+    for r in meas:
+        key = f"{r['elem']}/{r['prob']}/{r['tier']}"
+        counts[key] = counts.get(key, 0) + 1
     out = {"n_requests": n_meas, "warmup_requests": n_warm, "total_elements": tot_elems,
+           "mean_elements_per_request": tot_elems / n_meas,
+           "requests_by_kind": counts,
+           "meshes": "one jittered cube mesh per request, built from the request's drawn seed",
            "hbm_budget_bytes": budget, "max_slots": a.served_slots, "sequential_plain": seq}
     rng = np.random.default_rng(55)
-    sample_ids = set(int(x) for x in rng.choice(n_meas, size=min(20, n_meas), replace=False))
+    sample_ids = set(int(x) for x in rng.choice(n_meas, size=min(sample, n_meas), replace=False))
     with serve.Server(kinds, max_slots=a.served_slots, hbm_budget_bytes=budget, max_chunks=2048,
                       chunk_elems=4096, blocks_per_kind=a.served_blocks_per_kind) as srv:
-        # warm-up
-        for r in reqs[:n_warm]:
-            cp, kp, ld = host_ptrs(r)
-            srv.submit(r["kind"], r["n"], cp, kp, ld_in=ld)
+        for r, (c, k) in zip(reqs[:n_warm], payloads[:n_warm]):
+            srv.submit(r["kind"], r["n_actual"], c.data_ptr(), k.data_ptr(), ld_in=c.shape[1])
         got = 0
         while got < n_warm:
             for c in srv.poll(64, 0.05):
                 srv.release(c.id)
                 got += 1
-        sat, sums_mix = serve_run(srv, None, False, sample_ids)
+        sat, mix_out = serve_run(srv, None, False, sample_ids)
         out["saturation"] = sat
         out["served_speedup"] = sat["elements_per_s"] / seq["h2d"]["elements_per_s"]
         log(f"[served] saturation: {sat}")
@@ -377,35 +511,29 @@ def run_served(a, torch, fe, serve) -> dict:
         cap = 1.0 / seq["h2d"]["mean_service_s"]
         cap_r = 1.0 / seq["resident"]["mean_service_s"]
         out["load"] = {}
-        for rho in a.served_rho:
+        for rho in rhos:
             res, _ = serve_run(srv, rho * cap, False)
             res_r, _ = serve_run(srv, rho * cap_r, True)
             out["load"][f"rho_{rho}"] = {"rate_per_s": rho * cap, "h2d": res,
                                          "rate_resident_per_s": rho * cap_r, "resident": res_r}
             log(f"[served] rho {rho}: p50 {res['p50_s']*1e3:.2f} ms p99 {res['p99_s']*1e3:.2f} ms; "
                 f"resident p50 {res_r['p50_s']*1e3:.2f} ms p99 {res_r['p99_s']*1e3:.2f} ms")
-        # the sampled requests again, one at a time through the server
+        # the sampled requests again, one at a time through the server: the
+        # same bits alone as in the mix
         same = 0
         for i in sorted(sample_ids):
             r = meas[i]
-            cp, kp, ld = host_ptrs(r)
-            rid = srv.submit(r["kind"], r["n"], cp, kp, ld_in=ld, tag=i)
-            c = []
-            while not c:
-                c = srv.poll(4, 0.05)
-            c = c[0]
-            k = kinds[r["kind"]]
-            dt_ = torch.float64 if r["tier"] == "fp64" else torch.float32
-            ok = True
-            for name, ptr, rows in (("K", c.out_K, fe.k_entries(k[0], k[1])),
-                                    ("F", c.out_F, fe.f_entries(k[0], k[1]))):
-                buf = torch.empty((rows, c.ld_out), dtype=dt_, device=dev)
-                fe.lib().fe_stream_copy(ctypes.c_void_p(buf.data_ptr()), ctypes.c_void_p(ptr),
-                                        buf.numel() * buf.element_size(), ctypes.c_void_p(stream.cuda_stream))
-                ok = ok and buf[:, :r["n"]].contiguous().cpu().numpy().tobytes() == sums_mix[(i, name)]
-            same += int(ok)
-            srv.release(c.id)
+            c, k = mpay[i]
+            srv.submit(r["kind"], r["n_actual"], c.data_ptr(), k.data_ptr(), ld_in=c.shape[1], tag=i)
+            got = []
+            while not got:
+                got = srv.poll(4, 0.05)
+            alone = fetch(got[0], r)
+            same += int(all(np.array_equal(x, y) for x, y in zip(alone, mix_out[i])))
+            srv.release(got[0].id)
         out["alone_vs_mix_bitwise_equal"] = f"{same}/{len(sample_ids)}"
+    del resident, payloads, mpay, slabs
+    torch.cuda.empty_cache()
     return out
 
 
@@ -504,7 +632,7 @@ def run_paper(a, torch, fe) -> dict:
             Ko, Fo = oracle.integrate(wl.elem, wl.kind, wl.mesh.coords[:, sample],
                                       oracle.quad_rule(wl.elem, wl.n_q), wl.coef_mode, wl.mask,
                                       wl.uniform, None if wl.coeffs is None else wl.coeffs[:, sample],
-                                      threads=max(1, min(16, os.cpu_count() or 1)))
+                                      threads=host_threads())
             N = oracle.n_dof(wl.elem, wl.kind)
             Kg = fe.unpack_full(Ks, N, False)
             ek = float(np.sqrt(((Kg - Ko) ** 2).sum(axis=(1, 2)) / (Ko ** 2).sum(axis=(1, 2))).max())
@@ -672,7 +800,7 @@ def run_apply(a, torch, fe, oracle, base: str, dev, csr: bool = False) -> dict:
         if a.precision == "fp32":
             cf = cf.astype(np.float32).astype(np.float64)
     K, _ = oracle.integrate(wl.elem, wl.kind, wl.mesh.coords[:, touch], oracle.quad_rule(wl.elem, wl.n_q),
-                            wl.coef_mode, wl.mask, wl.uniform, cf, threads=max(1, min(16, os.cpu_count() or 1)))
+                            wl.coef_mode, wl.mask, wl.uniform, cf, threads=host_threads())
     dof = (conn_np[touch][:, :, None] * nc + np.arange(nc)[None, None, :]).reshape(len(touch), nv * nc)
     sd = (snodes[:, None] * nc + np.arange(nc)[None, :]).ravel()
     tol = 1e-12 if a.precision == "fp64" else 2e-5
@@ -743,8 +871,9 @@ def main() -> int:
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--tune", action="store_true",
                     help="run the exhaustive variant search (fe_autotune) during warm-up")
-    ap.add_argument("--tuning-file", default=os.path.join(ROOT, "paper_1504_01023_amd", "tuning_mi355x.txt"),
-                    help="tuning table to load (the committed MI355X table by default)")
+    ap.add_argument("--tuning-file", default=None,
+                    help="tuning table to load over the library's built-in one (the committed "
+                         "MI355X table, compiled in)")
     ap.add_argument("--save-tuning", default=None, help="write the tuning table here after the run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--parity-sample", type=int, default=20000)
@@ -752,14 +881,19 @@ def main() -> int:
                     help="node and element order of the matrix-free runs: Z-order renumbering, "
                          "or the generator's lexicographic order")
     ap.add_argument("--ld-align", type=int, default=256,
-                    help="pad the output leading dimension to a multiple of this many elements "
-                         "(0: ld = n_elem)")
+                    help="leading dimension of inputs and outputs: a multiple of this many "
+                         "elements (256: the library's default, fe_ld_for; 0: ld = n_elem)")
     ap.add_argument("--served-requests", type=int, default=1000)
     ap.add_argument("--served-blocks-per-kind", type=int, default=0,
                     help="workgroups of each kind's persistent batched kernel (0: the library's default)")
     ap.add_argument("--served-warmup", type=int, default=50)
     ap.add_argument("--served-slots", type=int, default=64)
     ap.add_argument("--served-rho", type=float, nargs="*", default=[0.5, 0.7, 0.9])
+    ap.add_argument("--headline-only", action="store_true",
+                    help="default workload: only the FP64 line, without the FP32 tier and the "
+                         "served summary")
+    ap.add_argument("--summary-served-requests", type=int, default=1000,
+                    help="measured requests of the served summary in the default run")
     a = ap.parse_args()
 
     if a.gpus != 1:
@@ -831,52 +965,120 @@ def main() -> int:
 
     if a.workload == "served":
         from paper_1504_01023_amd import serve
-        if a.tuning_file and os.path.exists(a.tuning_file):
+        if a.tuning_file:
             fe.tuning_load(a.tuning_file)
-        res = run_served(a, torch, fe, serve)
+        res = run_served(a, torch, fe, serve, a.served_requests, a.served_warmup, a.served_rho)
         sat = res["saturation"]
         line = {"metric": "served elements/s (continuous batching, mixed stream, H2D included)",
                 "value": sat["elements_per_s"], "unit": "elements/s", "n_gpus": 1,
                 "steps": res["n_requests"], "warmup": res["warmup_requests"],
                 "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
                 "vs_baseline": None, "dtype": "f64/f32 mix", "data": "synthetic",
-                "config": {"workload": "served", "mix": "50/50 tet/prism, 70/30 CDR/elasticity, "
-                           "50/50 FP64/FP32, n log-uniform in [1e3, 2e6], Poisson arrivals, seed 5"},
-                "served": res}
+                "config": {"workload": "served", "mix": SERVED_MIX}, "served": res}
         print(json.dumps(line), flush=True)
         return 0
 
-    indexed = a.workload.endswith("_indexed")
-    natural = a.workload.endswith("_natural")
-    base = a.workload[: -len("_indexed")] if indexed else (
-        a.workload[: -len("_natural")] if natural else a.workload)
+    out = measure_plain(a, torch, fe, oracle, a.workload, a.precision, dev, a.parity_sample,
+                        with_cpu=not a.no_cpu)
+    if a.workload == "tet_poisson" and a.precision == "fp64" and not a.headline_only:
+        # the rest of the metric: the FP32 bulk tier of the same workload and
+        # the served mixed stream, against the plain FP64 form on this GPU
+        t0 = time.time()
+        f32 = measure_plain(a, torch, fe, oracle, "tet_poisson", "fp32", dev,
+                            min(a.parity_sample, 5000), with_cpu=False)
+        bpe64, bpe32 = out["config"]["bytes_per_element"], f32["config"]["bytes_per_element"]
+        out["fp32"] = {
+            "workload": "tet_poisson", "precision": "fp32 (FP64 Jacobian terms)",
+            "value": f32["value"], "unit": "elements/s", "ms_per_step": f32["ms_per_step"],
+            "kernel_ms_avg": f32["kernel_ms_avg"], "roofline": f32["roofline"],
+            "speedup_vs_fp64": f32["value"] / out["value"],
+            "speedup_vs_fp64_kernel": out["kernel_ms_avg"] / f32["kernel_ms_avg"],
+            "byte_bound_speedup": bpe64 / bpe32,
+            "max_rel_err_vs_fp64_oracle": {"K": f32["parity"]["max_rel_err_K"],
+                                           "F": f32["parity"]["max_rel_err_F"],
+                                           "sampled_elements": f32["parity"]["sampled_elements"],
+                                           "tol": f32["parity"]["tol"], "ok": f32["parity"]["ok"]},
+            "kernel_source_hash": f32["kernel_source_hash"]}
+        log(f"[bench] fp32 tier: {f32['value']:.3e} elements/s ({time.time() - t0:.1f}s)")
+        t0 = time.time()
+        from paper_1504_01023_amd import serve
+        res = run_served(a, torch, fe, serve, a.summary_served_requests,
+                         max(1, a.summary_served_requests // 20), [0.7])
+        rho = res["load"]["rho_0.7"]
+        out["served"] = {
+            "mix": SERVED_MIX, "n_requests": res["n_requests"],
+            "warmup_requests": res["warmup_requests"], "total_elements": res["total_elements"],
+            "requests_by_kind": res["requests_by_kind"], "meshes": res["meshes"],
+            "hbm_budget_bytes": res["hbm_budget_bytes"], "max_slots": res["max_slots"],
+            "saturation_elements_per_s": {"h2d": res["saturation"]["elements_per_s"],
+                                          "resident": res["saturation_resident"]["elements_per_s"]},
+            "sequential_plain_elements_per_s": {
+                "h2d": res["sequential_plain"]["h2d"]["elements_per_s"],
+                "resident": res["sequential_plain"]["resident"]["elements_per_s"]},
+            "served_speedup": {"h2d": res["served_speedup"],
+                               "resident": res["served_speedup_resident"]},
+            "rho_0.7": {mode: {"p50_ms": rho[mode]["p50_s"] * 1e3, "p99_ms": rho[mode]["p99_s"] * 1e3,
+                               "mean_ms": rho[mode]["mean_s"] * 1e3,
+                               "mean_queue_ms": rho[mode]["mean_queue_s"] * 1e3,
+                               "mean_h2d_ms": rho[mode]["mean_h2d_s"] * 1e3,
+                               "mean_device_ms": rho[mode]["mean_device_s"] * 1e3}
+                        for mode in ("h2d", "resident")},
+            "saturation_split_ms": {
+                "mean_queue_ms": res["saturation"]["mean_queue_s"] * 1e3,
+                "mean_h2d_ms": res["saturation"]["mean_h2d_s"] * 1e3,
+                "mean_device_ms": res["saturation"]["mean_device_s"] * 1e3},
+            "alone_vs_mix_bitwise_equal": res["alone_vs_mix_bitwise_equal"]}
+        log(f"[bench] served summary ({time.time() - t0:.1f}s)")
+    print(json.dumps(out), flush=True)
+    ok = out["parity"]["ok"] and (out.get("fp32") is None or out["fp32"]["max_rel_err_vs_fp64_oracle"]["ok"])
+    return 0 if ok else 3
+
+
+SERVED_MIX = ("50/50 tet/prism, 70/30 CDR/elasticity, 50/50 FP64/FP32, n log-uniform in "
+              "[1e3, 2e6], Poisson arrivals, seed 5")
+
+
+def measure_plain(a, torch, fe, oracle, workload, precision, dev, parity_sample, with_cpu):
+    """One workload through fe_integrate (or its indexed / natural forms):
+    warm-up, K timed steps, a sampled parity check against the oracle, and
+    the JSON record of the measurement."""
+    indexed = workload.endswith("_indexed")
+    natural = workload.endswith("_natural")
+    base = workload[: -len("_indexed")] if indexed else (
+        workload[: -len("_natural")] if natural else workload)
     t0 = time.time()
     wl = WORKLOADS[base][0]()
-    log(f"[bench] generated {a.workload}: {wl.n_elem} elements in {time.time() - t0:.1f}s")
-    dw = fe.to_device(wl, a.precision, device=dev)
+    log(f"[bench] generated {workload}: {wl.n_elem} elements in {time.time() - t0:.1f}s")
+    # The library's default layout: fe.to_device puts the input rows in
+    # buffers of fe_ld_for(n) columns (whole 2 KiB / 1 KiB lines of FP64 /
+    # FP32 elements per row) and the outputs take the same leading
+    # dimension, so every wavefront reads and writes whole cache lines of
+    # every row; rows that start mid-line leave partial lines at both ends of
+    # every wavefront's segment and cut the write rate. --ld-align 0 runs
+    # the unpadded layout (ld = n) for comparison.
+    dw = fe.to_device(wl, precision, device=dev)
     p, rule = dw.problem, dw.rule
-    if a.ld_align > 0 and not natural:
-        # input rows padded like the outputs, so wavefront segments of the
-        # input rows are whole cache lines too (no line fetched twice)
-        ld_in = (wl.n_elem + a.ld_align - 1) // a.ld_align * a.ld_align
+    n = wl.n_elem
+    if natural:
+        ld = n
+    elif a.ld_align == 256:
+        ld = fe.ld_for(n)
+    else:
+        ld = (n + a.ld_align - 1) // a.ld_align * a.ld_align if a.ld_align > 0 else n
 
-        def padded(t):
-            out = torch.zeros((t.shape[0], ld_in), dtype=t.dtype, device=dev)
-            out[:, : wl.n_elem] = t
-            return out
+        def relaid(t):
+            out = torch.zeros((t.shape[0], ld), dtype=t.dtype, device=dev)
+            out[:, :n] = t
+            return out[:, :n]
 
-        dw.coords = padded(dw.coords)
+        dw.coords = relaid(dw.coords)
         if dw.coeffs is not None and wl.coef_mode != "function":
-            dw.coeffs = padded(dw.coeffs)
+            dw.coeffs = relaid(dw.coeffs)
     nk, nf = fe.k_entries(p, wl.elem), fe.f_entries(p, wl.elem)
-    dt = torch.float64 if a.precision == "fp64" else torch.float32
-    # output rows padded to whole 2 KB (FP64) / 1 KB (FP32) lines of elements:
-    # every wavefront then writes whole cache lines of every row, which HBM
-    # takes at the copy rate; rows that start mid-line leave partial lines
-    # at both ends of every wavefront's segment and cut the write rate
-    ld_out = (wl.n_elem + a.ld_align - 1) // a.ld_align * a.ld_align if a.ld_align > 0 else wl.n_elem
-    K = torch.empty((nk, ld_out), dtype=dt, device=dev)
-    F = torch.empty((nf, ld_out), dtype=dt, device=dev)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    ld_out = ld
+    K = torch.empty((nk, ld_out), dtype=dt, device=dev)[:, :n]
+    F = torch.empty((nf, ld_out), dtype=dt, device=dev)[:, :n]
     bpe = fe.bytes_per_element(p, wl.elem, rule.n_q)
     stream = torch.cuda.current_stream()
     nv = 4 if wl.elem == "tet4" else 6
@@ -907,7 +1109,7 @@ def main() -> int:
         else:
             fe.integrate(p, wl.elem, dw.coords, dw.coeffs, rule, out_K=K, out_F=F, n_elem=wl.n_elem)
 
-    if a.tuning_file and os.path.exists(a.tuning_file):
+    if a.tuning_file:
         fe.tuning_load(a.tuning_file)
     if not natural and (a.tune or fe.tuning_get(p, wl.elem, rule.n_q) is None):
         tuned, tms = fe.autotune(p, wl.elem, dw.coords, dw.coeffs, rule, K, F, reps=5,
@@ -939,24 +1141,36 @@ def main() -> int:
     copy_gbps = 2 * nbytes * 10 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
     del src, dst
 
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps)]
+    # The timed region: K back-to-back steps between device synchronisations.
+    # The host clock gives `value`; one pair of HIP events on the launch
+    # stream brackets the same region and gives the average kernel duration
+    # of the roofline (both clocks see the same launches, gaps included).
+    ev_a, ev_b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     w0 = time.perf_counter()
+    ev_a.record(stream)
+    for _ in range(a.steps):
+        step()
+    ev_b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    avg_kern_s = ev_a.elapsed_time(ev_b) * 1e-3 / a.steps
+    ms_per_step = wall / a.steps * 1e3
+    value = wl.n_elem / (wall / a.steps)
+    # after the timed region, the same steps with an event pair around each
+    # one: the distribution of single-launch durations (not part of `value`)
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(a.steps)]
     for i in range(a.steps):
         starts[i].record(stream)
         step()
         ends[i].record(stream)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
     kern_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
-    avg_kern_s = float(np.mean(kern_ms)) * 1e-3
-    ms_per_step = wall / a.steps * 1e3
-    value = wl.n_elem / (wall / a.steps)
 
     # parity on a sample of the measured outputs
     rng = np.random.default_rng(12345)
-    sample = np.sort(rng.choice(wl.n_elem, size=min(a.parity_sample, wl.n_elem), replace=False))
+    sample = np.sort(rng.choice(wl.n_elem, size=min(parity_sample, wl.n_elem), replace=False))
     idx = torch.from_numpy(sample).to(dev)
     Ks = K.index_select(1, idx).cpu().numpy().astype(np.float64)
     Fs = F.index_select(1, idx).cpu().numpy().astype(np.float64)
@@ -965,22 +1179,22 @@ def main() -> int:
         coeffs = wl.coeffs
     elif wl.coeffs is not None:
         coeffs = wl.coeffs[:, sample]
-        if a.precision == "fp32":
+        if precision == "fp32":
             coeffs = coeffs.astype(np.float32).astype(np.float64)
     Ko, Fo = oracle.integrate(wl.elem, wl.kind, wl.mesh.coords[:, sample],
                               oracle.quad_rule(wl.elem, wl.n_q), wl.coef_mode, wl.mask, wl.uniform,
-                              coeffs, threads=max(1, min(16, os.cpu_count() or 1)))
+                              coeffs, threads=host_threads())
     N = oracle.n_dof(wl.elem, wl.kind)
     Kg = fe.unpack_full(Ks, N, wl.k_format == "packed")
     ek = np.sqrt(((Kg - Ko) ** 2).sum(axis=(1, 2)) / (Ko ** 2).sum(axis=(1, 2)))
     ef = np.sqrt(((Fs.T - Fo) ** 2).sum(axis=1) / np.maximum((Fo ** 2).sum(axis=1), 1e-300))
-    tol = 1e-12 if a.precision == "fp64" else 2e-5
+    tol = 1e-12 if precision == "fp64" else 2e-5
 
     achieved = bpe * wl.n_elem / avg_kern_s / 1e9
-    shash = source_hash(base, a.precision)
-    traffic = stored_traffic(a.workload, a.precision, shash)
+    shash = source_hash(base, precision)
+    traffic = stored_traffic(workload, precision, shash)
     cpu = None
-    if not a.no_cpu:
+    if with_cpu:
         log("[bench] timing the CPU oracle baseline")
         cpu = cpu_baseline(wl)
 
@@ -995,23 +1209,32 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if a.precision == "fp64" else "f32 (FP64 Jacobian)",
+        "dtype": "f64" if precision == "fp64" else "f32 (FP64 Jacobian)",
         "data": "synthetic",
-        "config": {"workload": a.workload,
+        "config": {"workload": workload,
                    "description": WORKLOADS[base][1] + (" (indexed geometry: node array + int32 "
                                                         "connectivity)" if indexed else "")
                    + (" (natural element-contiguous order, LDS-tiled)" if natural else ""),
-                   "n_elem": wl.n_elem, "precision": a.precision, "n_q": rule.n_q,
+                   "n_elem": wl.n_elem, "precision": precision, "n_q": rule.n_q,
                    "k_format": wl.k_format, "bytes_per_element": bpe,
-                   "ld_in": int(dw.coords.shape[1]), "ld_out": ld_out,
-                   "variant_wg_vec_ref_nt_blocks": variant_used, "parallelism": "single GPU"},
+                   "ld_in": int(dw.coords.stride(0)), "ld_out": ld_out,
+                   "variant_wg_vec_ref_nt_blocks": variant_used,
+                   "variant_source": ("natural-order form" if natural else
+                                      "tuned in this run" if a.tune else
+                                      "tuning file " + os.path.basename(a.tuning_file)
+                                      if a.tuning_file else
+                                      "the library's built-in table" if fe.tuning_builtin()[0]
+                                      else "the library's base variant"),
+                   "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": traffic},
         "cpu_baseline": cpu,
+        # the timed region by the host clock: value x bytes / peak
+        "wall_frac": value * bpe / 1e9 / HBM_PEAK_GBPS,
         "kernel_ms_avg": avg_kern_s * 1e3,
-        "kernel_ms_min": float(np.min(kern_ms)),
-        "kernel_ms_median": float(np.median(kern_ms)),
+        "kernel_ms_single_launch": {"avg": float(np.mean(kern_ms)), "min": float(np.min(kern_ms)),
+                                    "median": float(np.median(kern_ms))},
         "copy_ceiling_GBps": copy_gbps,
         "frac_of_copy_ceiling": achieved / copy_gbps,
         "parity": {"sampled_elements": int(len(sample)), "max_rel_err_K": float(ek.max()),
@@ -1019,8 +1242,9 @@ def main() -> int:
                    "ok": bool(ek.max() <= tol and ef.max() <= tol)},
         "kernel_source_hash": shash,
     }
-    print(json.dumps(out), flush=True)
-    return 0 if out["parity"]["ok"] else 3
+    del dw, K, F
+    torch.cuda.empty_cache()
+    return out
 
 
 if __name__ == "__main__":

@@ -394,6 +394,14 @@ FE_API int fe_quad_rule_builtin(fe_elem_type elem_type, int n_q, fe_quad_rule *o
 FE_API const char *fe_status_string(int status);
 FE_API const char *fe_last_error(void);
 
+/* The leading dimension to allocate for rows of n_elem elements: n_elem
+ * rounded up to a multiple of 256 elements, so that every row of the SoA
+ * inputs and outputs starts on a whole cache line (2 KiB of FP64, 1 KiB of
+ * FP32) and every wavefront reads and writes whole lines; rows that start
+ * mid-line cost the output stores up to a quarter of their rate (measured on
+ * MI355X). Any ld >= n_elem is valid. Returns -1 for negative n_elem. */
+FE_API int64_t fe_ld_for(int64_t n_elem);
+
 /* Library version as major*10000 + minor*100 + patch. */
 FE_API int fe_version(void);
 
@@ -410,16 +418,33 @@ FE_API int fe_autotune(const fe_problem *problem, fe_elem_type elem_type, int64_
                        const double *coords, const void *coeffs, int64_t ld_in,
                        const fe_quad_rule *quad_rule, void *out_K, void *out_F, int64_t ld_out,
                        int reps, fe_variant *best, double *best_ms, hipStream_t stream);
-/* Query / set the tuning table entry used by fe_integrate for a problem
- * shape. fe_tuning_get returns FE_ERR_INVALID_ARG when no entry exists. */
+/* The variant a call with variant = NULL uses comes from the caller's
+ * tuning table (fe_tuning_set, fe_tuning_load, fe_autotune) when it has an
+ * entry for the problem shape, else from the built-in table, else the
+ * library's base variant. The built-in table is the one measured on MI355X
+ * (gfx950) with ROCm 7.x, compiled into the library; it applies when the
+ * device the library first plans a launch on is a gfx950 and the HIP runtime
+ * has ROCm major version 7 (every variant gives the same results bit for bit;
+ * the tables only choose the fastest).
+ *
+ * fe_tuning_get returns the entry in effect (the caller's, else the
+ * built-in one) and FE_ERR_INVALID_ARG when neither exists; fe_tuning_set
+ * sets the caller's entry. */
 FE_API int fe_tuning_get(const fe_problem *problem, fe_elem_type elem_type, int n_q,
                          fe_variant *out);
 FE_API int fe_tuning_set(const fe_problem *problem, fe_elem_type elem_type, int n_q,
                          const fe_variant *v);
-/* Persist / restore the tuning table as text (one entry per line). */
+/* Persist / restore the caller's tuning table as text (one entry per line;
+ * the format of the built-in table). fe_tuning_clear empties the caller's
+ * table; the built-in entries stay in effect. */
 FE_API int fe_tuning_save(const char *path);
 FE_API int fe_tuning_load(const char *path);
 FE_API int fe_tuning_clear(void);
+/* Whether the built-in table is in effect (1) or not (0, e.g. another GPU
+ * architecture or no device); copies the table's architecture name into
+ * arch (arch_len bytes, NUL-terminated) and its entry count in effect into
+ * *n_entries, either may be NULL. */
+FE_API int fe_tuning_builtin(char *arch, int arch_len, int *n_entries);
 
 /* ---------------------------------------------------------------------
  * Persistent batched launches. Elements of the same type, problem and rule

@@ -366,36 +366,58 @@ int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coor
     k.order = order;
     k.lanes = lanes;
     k.nq = rule->n_q;
+    const KernelKey kv = k;  // the chosen variant, before any fallback
     auto usable = [&](const KernelEntry *x) {
         return x && (form == 0 || (form == 1 && x->idx != nullptr) || (form == 2 && x->apply != nullptr));
     };
     const int nq_rule = k.nq;
-    const KernelEntry *e = find_kernel(k);
-    if (!usable(e)) {
-        k.nq = 0;
-        e = find_kernel(k);
-    }
-    if (!usable(e) && k.packed == 2) {
-        // the symmetric accumulation is built for some variants only (QSS,
-        // one lane per element): the plain full-K kernel of this variant
-        k.packed = 0;
+    // the kernel of key k, compiled for the rule's point count or for any
+    auto find_nq = [&]() {
         k.nq = nq_rule;
-        e = find_kernel(k);
-        if (!usable(e)) {
+        const KernelEntry *x = find_kernel(k);
+        if (!usable(x)) {
             k.nq = 0;
-            e = find_kernel(k);
+            x = find_kernel(k);
         }
-    }
-    if (!usable(e) && !forced) {
-        // fall back to the always-built base variant
+        return x;
+    };
+    auto to_base = [&]() {
         k.vec = 1;
         k.nt = 1;
         k.ref = REF_KARG;
         k.split = 1;
         k.order = 1;
         k.lanes = 1;
-        k.nq = 0;
-        e = find_kernel(k);
+    };
+    const KernelEntry *e = find_nq();
+    // Fallbacks, keeping the accumulation (packed 2: the upper triangle of a
+    // symmetric K, mirrored) as long as some variant has it, so that every
+    // form of a problem (stored, indexed, consumers) rounds alike: the
+    // always-built base variant of the same accumulation, then the full-K
+    // accumulation in the chosen variant, then in the base variant.
+    if (!usable(e) && !forced && k.packed == 2) {
+        to_base();
+        e = find_nq();
+    }
+    if (!usable(e) && k.packed == 2) {
+        k.packed = 0;
+        if (!forced) {
+            k.vec = kv.vec;
+            k.nt = kv.nt;
+            k.ref = kv.ref;
+            k.split = kv.split;
+            k.order = kv.order;
+            k.lanes = kv.lanes;
+        }
+        e = find_nq();
+    }
+    if (!usable(e) && !forced) {
+        to_base();
+        e = find_nq();
+        if (!usable(e)) {
+            k.nq = 0;
+            e = find_kernel(k);
+        }
     }
     if (!usable(e))
         e = nullptr;
@@ -1009,6 +1031,13 @@ const char *fe_status_string(int status)
 
 const char *fe_last_error(void) { return g_last_error.c_str(); }
 
-int fe_version(void) { return 1 * 10000 + 0 * 100 + 0; }
+int fe_version(void) { return 1 * 10000 + 1 * 100 + 0; }
+
+int64_t fe_ld_for(int64_t n_elem)
+{
+    if (n_elem < 0)
+        return -1;
+    return (n_elem + 255) / 256 * 256;
+}
 
 }  // extern "C"

@@ -3,6 +3,12 @@
 // kept), extended with the GPU launch shape. The table maps a kernel family
 // (element, problem, precision, term set, coefficient mode, K format, point
 // count) to the variant fe_integrate uses.
+//
+// Two tables: the caller's (fe_tuning_set, fe_tuning_load, fe_autotune) and
+// the built-in one, the committed table measured on MI355X and compiled into
+// the library. The built-in entries apply, for families the caller has not
+// tuned, when the device the library first plans a launch on has the table's
+// GPU architecture and the HIP runtime has the table's ROCm major version.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,6 +27,8 @@ namespace fe {
 
 typedef std::tuple<int, int, int, int, int, int, int> FamilyKey;
 
+extern const char *const builtin_tuning_text;  // the committed table (build.py)
+
 static std::mutex g_tune_mu;
 static std::map<FamilyKey, fe_variant> &table()
 {
@@ -33,11 +41,109 @@ static FamilyKey family_of(const KernelKey &k, int n_q)
     return FamilyKey(k.elem, k.kind, k.prec, k.terms, k.mode, k.packed, n_q);
 }
 
+// One line of a table: 1 = an entry, 0 = blank or comment, -1 = malformed.
+static int parse_line(const char *line, FamilyKey &key, fe_variant &v)
+{
+    while (*line == ' ' || *line == '\t')
+        ++line;
+    if (*line == '#' || *line == '\n' || *line == '\r' || *line == 0)
+        return 0;
+    int a[7];
+    v = fe_variant{};
+    const int got = std::sscanf(line, "%d %d %d %d %d %d %d | %d %d %d %d %d %d %d %d", &a[0], &a[1],
+                                &a[2], &a[3], &a[4], &a[5], &a[6], &v.wg_size, &v.elems_per_thread,
+                                &v.ref_in_lds, &v.nontemporal, &v.blocks, &v.row_split,
+                                &v.loop_order, &v.lanes);
+    // tables written before the row-split / loop-order / lanes fields
+    if (got == 12)
+        v.row_split = 1;
+    if (got >= 12 && got <= 13)
+        v.loop_order = 1;
+    if (got >= 12 && got <= 14)
+        v.lanes = 1;
+    else if (got != 15)
+        return -1;
+    key = FamilyKey(a[0], a[1], a[2], a[3], a[4], a[5], a[6]);
+    return 1;
+}
+
+struct Builtin {
+    std::map<FamilyKey, fe_variant> entries;
+    char arch[64] = "";        // the table's architecture ("# arch gfx950")
+    int rocm_major = -1;       // the table's ROCm major version ("# rocm 7.2")
+    char device_arch[64] = ""; // the device's, when it could be queried
+    int runtime_major = -1;
+    bool active = false;
+};
+
+static Builtin &builtin()
+{
+    static Builtin b;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        // the table text: header fields, then entries
+        const char *p = builtin_tuning_text;
+        std::map<FamilyKey, fe_variant> entries;
+        while (p && *p) {
+            const char *eol = std::strchr(p, '\n');
+            const size_t len = eol ? (size_t)(eol - p) : std::strlen(p);
+            char line[512];
+            const size_t n = len < sizeof(line) - 1 ? len : sizeof(line) - 1;
+            std::memcpy(line, p, n);
+            line[n] = 0;
+            int maj = 0, min = 0;
+            char arch[64];
+            if (std::sscanf(line, "# arch %63s", arch) == 1)
+                std::snprintf(b.arch, sizeof(b.arch), "%s", arch);
+            else if (std::sscanf(line, "# rocm %d.%d", &maj, &min) >= 1)
+                b.rocm_major = maj;
+            FamilyKey k;
+            fe_variant v;
+            if (parse_line(line, k, v) == 1)
+                entries[k] = v;
+            p = eol ? eol + 1 : nullptr;
+        }
+        // the device the library is first used on (a failed query leaves no
+        // error behind for the caller; one pending before is kept)
+        const hipError_t pending = hipPeekAtLastError();
+        int dev = -1;
+        hipDeviceProp_t prop;
+        bool ok = hipGetDevice(&dev) == hipSuccess &&
+                  hipGetDeviceProperties(&prop, dev) == hipSuccess;
+        int rt = 0;
+        ok = ok && hipRuntimeGetVersion(&rt) == hipSuccess;
+        if (!ok) {
+            if (pending == hipSuccess)
+                (void)hipGetLastError();
+            return;
+        }
+        std::snprintf(b.device_arch, sizeof(b.device_arch), "%s", prop.gcnArchName);
+        char *colon = std::strchr(b.device_arch, ':');
+        if (colon)
+            *colon = 0;
+        b.runtime_major = rt / 10000000;  // major * 10^7 + minor * 10^5 + patch
+        if (std::strcmp(b.device_arch, b.arch) == 0 && b.runtime_major == b.rocm_major) {
+            b.entries = entries;
+            b.active = true;
+        }
+    });
+    return b;
+}
+
 int tuning_lookup(const KernelKey &family, int n_q, fe_variant &out)
 {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = table().find(family_of(family, n_q));
-    if (it == table().end())
+    const FamilyKey key = family_of(family, n_q);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = table().find(key);
+        if (it != table().end()) {
+            out = it->second;
+            return FE_OK;
+        }
+    }
+    const Builtin &b = builtin();
+    auto it = b.entries.find(key);
+    if (it == b.entries.end())
         return FE_ERR_INVALID_ARG;
     out = it->second;
     return FE_OK;
@@ -98,6 +204,16 @@ int fe_tuning_clear(void)
     return FE_OK;
 }
 
+int fe_tuning_builtin(char *arch, int arch_len, int *n_entries)
+{
+    const Builtin &b = builtin();
+    if (arch && arch_len > 0)
+        std::snprintf(arch, (size_t)arch_len, "%s", b.arch);
+    if (n_entries)
+        *n_entries = b.active ? (int)b.entries.size() : 0;
+    return b.active ? 1 : 0;
+}
+
 int fe_tuning_save(const char *path)
 {
     if (!path)
@@ -129,26 +245,15 @@ int fe_tuning_load(const char *path)
     char line[512];
     std::map<FamilyKey, fe_variant> loaded;
     while (std::fgets(line, sizeof(line), f)) {
-        if (line[0] == '#' || line[0] == '\n')
-            continue;
-        int a[7];
-        fe_variant v{};
-        const int got = std::sscanf(line, "%d %d %d %d %d %d %d | %d %d %d %d %d %d %d %d", &a[0],
-                                    &a[1], &a[2], &a[3], &a[4], &a[5], &a[6], &v.wg_size,
-                                    &v.elems_per_thread, &v.ref_in_lds, &v.nontemporal, &v.blocks,
-                                    &v.row_split, &v.loop_order, &v.lanes);
-        // tables written before the row-split / loop-order / lanes fields
-        if (got == 12)
-            v.row_split = 1;
-        if (got >= 12 && got <= 13)
-            v.loop_order = 1;
-        if (got >= 12 && got <= 14)
-            v.lanes = 1;
-        else if (got != 15) {
+        FamilyKey k;
+        fe_variant v;
+        const int r = parse_line(line, k, v);
+        if (r < 0) {
             std::fclose(f);
             return fail(FE_ERR_INVALID_ARG, "malformed tuning line: %s", line);
         }
-        loaded[FamilyKey(a[0], a[1], a[2], a[3], a[4], a[5], a[6])] = v;
+        if (r == 1)
+            loaded[k] = v;
     }
     std::fclose(f);
     std::lock_guard<std::mutex> lk(g_tune_mu);

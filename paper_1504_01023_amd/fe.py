@@ -116,6 +116,9 @@ def lib():
         L.fe_node_incidence.restype = i64
         L.fe_assemble_csr_rows.argtypes = [P, i32, i64, vp, i64, vp, i64, vp, i64, R, vp, vp, i64,
                                            vp, vp, vp, vp, vp]
+        L.fe_ld_for.argtypes = [i64]
+        L.fe_ld_for.restype = i64
+        L.fe_tuning_builtin.argtypes = [ctypes.c_char_p, i32, ctypes.POINTER(ctypes.c_int)]
         _lib = L
     return _lib
 
@@ -207,6 +210,20 @@ def _stream_handle(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def ld_for(n_elem: int) -> int:
+    """fe_ld_for: the leading dimension to allocate for rows of n_elem
+    elements (n_elem rounded up to whole cache lines of every row)."""
+    return int(lib().fe_ld_for(int(n_elem)))
+
+
+def _ld(t, name="tensor"):
+    """Leading dimension of a row-major (rows, n) tensor: its row stride, so
+    a view t[:, :n] of a padded (rows, ld) buffer passes ld."""
+    if t.dim() != 2 or (t.shape[1] > 1 and t.stride(1) != 1):
+        raise ValueError(f"{name} must be a 2-D tensor with unit column stride")
+    return t.stride(0) if t.shape[0] > 1 else max(t.stride(0), t.shape[1])
+
+
 def _check_tensor(t, name, dtype, rows, ld):
     if t is None:
         return
@@ -214,9 +231,15 @@ def _check_tensor(t, name, dtype, rows, ld):
         raise ValueError(f"{name} must be a GPU tensor")
     if t.dtype != dtype:
         raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
-    if not t.is_contiguous() or t.dim() != 2 or t.shape[1] != ld or t.shape[0] < rows:
-        raise ValueError(f"{name} must be a contiguous ({rows}, {ld}) tensor, got "
-                         f"{tuple(t.shape)}")
+    if t.dim() != 2 or _ld(t, name) != ld or t.shape[0] < rows:
+        raise ValueError(f"{name} must be a ({rows}, n) tensor with leading dimension {ld}, got "
+                         f"shape {tuple(t.shape)} and strides {tuple(t.stride())}")
+
+
+def _padded_out(rows, n, dt, device):
+    """A (rows, n) view of a (rows, ld_for(n)) buffer: line-aligned rows."""
+    import torch
+    return torch.empty((rows, max(1, ld_for(n))), dtype=dt, device=device)[:, :n]
 
 
 def _check_coeffs(p: Problem, coeffs, dt, nc, ld_in):
@@ -232,19 +255,22 @@ def _check_coeffs(p: Problem, coeffs, dt, nc, ld_in):
 def integrate(p: Problem, elem, coords, coeffs, rule: Rule, out_K=None, out_F=None,
               n_elem: int | None = None, variant: Variant | None = None, stream=None):
     """Enqueue the integration of n_elem elements (default: all columns of
-    coords) and return (out_K, out_F) device tensors of shape
-    (k_entries, ld_out) and (f_entries, ld_out)."""
+    coords) and return (out_K, out_F). Arrays are (rows, n) tensors whose
+    row stride is the leading dimension (views of padded buffers pass their
+    padding). Outputs not given are allocated with line-aligned rows
+    (ld_for(n)) and returned as (k_entries, n) and (f_entries, n) views."""
     import torch
     e = ELEM.get(elem, elem)
-    ld_in = coords.shape[1]
-    n = ld_in if n_elem is None else int(n_elem)
+    ld_in = _ld(coords, "coords")
+    n = coords.shape[1] if n_elem is None else int(n_elem)
     dt = _dtype(p)
     nk, nf = k_entries(p, e), f_entries(p, e)
-    if out_K is None:
-        out_K = torch.empty((nk, n), dtype=dt, device=coords.device)
-    if out_F is None:
-        out_F = torch.empty((nf, out_K.shape[1]), dtype=dt, device=coords.device)
-    ld_out = out_K.shape[1]
+    if out_K is None and out_F is None:
+        out_K = _padded_out(nk, n, dt, coords.device)
+        out_F = _padded_out(nf, n, dt, coords.device)
+    elif out_K is None or out_F is None:
+        raise ValueError("give both out_K and out_F, or neither")
+    ld_out = _ld(out_K, "out_K")
     _check_tensor(coords, "coords", torch.float64, 3 * (4 if e == TET4 else 6), ld_in)
     nc = coeff_entries(p, e, rule.n_q)
     if nc > 0:
@@ -269,23 +295,24 @@ def integrate_indexed(p: Problem, elem, nodes, conn, coeffs, rule: Rule, out_K=N
     import torch
     e = ELEM.get(elem, elem)
     nv = 4 if e == TET4 else 6
-    ld_conn = conn.shape[1]
-    n = ld_conn if n_elem is None else int(n_elem)
+    ld_conn = _ld(conn, "conn")
+    n = conn.shape[1] if n_elem is None else int(n_elem)
     dt = _dtype(p)
     nk, nf = k_entries(p, e), f_entries(p, e)
-    if out_K is None:
-        out_K = torch.empty((nk, n), dtype=dt, device=conn.device)
-    if out_F is None:
-        out_F = torch.empty((nf, out_K.shape[1]), dtype=dt, device=conn.device)
+    if out_K is None and out_F is None:
+        out_K = _padded_out(nk, n, dt, conn.device)
+        out_F = _padded_out(nf, n, dt, conn.device)
+    elif out_K is None or out_F is None:
+        raise ValueError("give both out_K and out_F, or neither")
     if not (nodes.is_cuda and nodes.dtype == torch.float64 and nodes.is_contiguous()
             and nodes.dim() == 2 and nodes.shape[1] == 3):
         raise ValueError("nodes must be a contiguous (n_nodes, 3) float64 GPU tensor")
     _check_tensor(conn, "conn", torch.int32, nv, ld_conn)
     nc = coeff_entries(p, e, rule.n_q)
-    ld_in = coeffs.shape[1] if (coeffs is not None and nc > 0 and coeffs.dim() == 2) else n
+    ld_in = _ld(coeffs, "coeffs") if (coeffs is not None and nc > 0 and coeffs.dim() == 2) else n
     if nc > 0:
         _check_coeffs(p, coeffs, dt, nc, ld_in)
-    ld_out = out_K.shape[1]
+    ld_out = _ld(out_K, "out_K")
     _check_tensor(out_K, "out_K", dt, nk, ld_out)
     _check_tensor(out_F, "out_F", dt, nf, ld_out)
     cptr = ctypes.c_void_p(coeffs.data_ptr()) if (coeffs is not None and nc > 0) else None
@@ -363,8 +390,8 @@ def apply_indexed(p: Problem, elem, nodes, conn, coeffs, rule: Rule, x, y=None, 
     import torch
     e = ELEM.get(elem, elem)
     nv = 4 if e == TET4 else 6
-    ld_conn = conn.shape[1]
-    n = ld_conn if n_elem is None else int(n_elem)
+    ld_conn = _ld(conn, "conn")
+    n = conn.shape[1] if n_elem is None else int(n_elem)
     dt = _dtype(p)
     ncomp = 1 if p.kind == SCALAR_CDR else 3
     ndof = nodes.shape[0] * ncomp
@@ -379,7 +406,7 @@ def apply_indexed(p: Problem, elem, nodes, conn, coeffs, rule: Rule, x, y=None, 
     if y is None:
         y = torch.zeros(ndof, dtype=dt, device=nodes.device)
     nc = coeff_entries(p, e, rule.n_q)
-    ld_in = coeffs.shape[1] if (coeffs is not None and nc > 0 and coeffs.dim() == 2) else n
+    ld_in = _ld(coeffs, "coeffs") if (coeffs is not None and nc > 0 and coeffs.dim() == 2) else n
     if nc > 0:
         _check_coeffs(p, coeffs, dt, nc, ld_in)
     cptr = ctypes.c_void_p(coeffs.data_ptr()) if (coeffs is not None and nc > 0) else None
@@ -440,8 +467,8 @@ def _csr_args(p: Problem, elem, nodes, conn, coeffs, rule: Rule, row_ptr, col_id
     import torch
     e = ELEM.get(elem, elem)
     nv = 4 if e == TET4 else 6
-    ld_conn = conn.shape[1]
-    n = ld_conn if n_elem is None else int(n_elem)
+    ld_conn = _ld(conn, "conn")
+    n = conn.shape[1] if n_elem is None else int(n_elem)
     dt = _dtype(p)
     ncomp = 1 if p.kind == SCALAR_CDR else 3
     ndof = nodes.shape[0] * ncomp
@@ -464,7 +491,7 @@ def _csr_args(p: Problem, elem, nodes, conn, coeffs, rule: Rule, row_ptr, col_id
                                   and t.numel() == size):
             raise ValueError(f"{name} must be a contiguous {dt} GPU vector of {size} values")
     nc = coeff_entries(p, e, rule.n_q)
-    ld_in = coeffs.shape[1] if (coeffs is not None and nc > 0 and coeffs.dim() == 2) else n
+    ld_in = _ld(coeffs, "coeffs") if (coeffs is not None and nc > 0 and coeffs.dim() == 2) else n
     if nc > 0:
         _check_coeffs(p, coeffs, dt, nc, ld_in)
     cptr = ctypes.c_void_p(coeffs.data_ptr()) if (coeffs is not None and nc > 0) else None
@@ -527,8 +554,8 @@ def assemble_csr_stored(p: Problem, elem, conn, n_nodes: int, K, F, row_ptr, col
     import torch
     e = ELEM.get(elem, elem)
     nv = 4 if e == TET4 else 6
-    ld_conn = conn.shape[1]
-    n = ld_conn if n_elem is None else int(n_elem)
+    ld_conn = _ld(conn, "conn")
+    n = conn.shape[1] if n_elem is None else int(n_elem)
     dt = _dtype(p)
     ncomp = 1 if p.kind == SCALAR_CDR else 3
     ndof = int(n_nodes) * ncomp
@@ -539,7 +566,7 @@ def assemble_csr_stored(p: Problem, elem, conn, n_nodes: int, K, F, row_ptr, col
         if F is not None:
             _check_tensor(F, "F", dt, n, f_entries(p, e))
     else:
-        ld = K.shape[1]
+        ld = _ld(K, "K")
         _check_tensor(K, "K", dt, k_entries(p, e), ld)
         if F is not None:
             _check_tensor(F, "F", dt, f_entries(p, e), ld)
@@ -576,8 +603,8 @@ def count_inverted(elem, coords, rule: Rule, n_elem: int | None = None, count=No
     it."""
     import torch
     e = ELEM.get(elem, elem)
-    ld_in = coords.shape[1]
-    n = ld_in if n_elem is None else int(n_elem)
+    ld_in = _ld(coords, "coords")
+    n = coords.shape[1] if n_elem is None else int(n_elem)
     _check_tensor(coords, "coords", torch.float64, 3 * (4 if e == TET4 else 6), ld_in)
     if count is None:
         count = torch.zeros(1, dtype=torch.int64, device=coords.device)
@@ -597,12 +624,12 @@ def autotune(p: Problem, elem, coords, coeffs, rule: Rule, out_K, out_F, reps: i
     e = ELEM.get(elem, elem)
     best = Variant()
     ms = ctypes.c_double(0.0)
-    ld_in = coords.shape[1]
-    n = ld_in if n_elem is None else int(n_elem)
+    ld_in = _ld(coords, "coords")
+    n = coords.shape[1] if n_elem is None else int(n_elem)
     cptr = ctypes.c_void_p(coeffs.data_ptr()) if coeffs is not None else None
     _check(lib().fe_autotune(ctypes.byref(p), e, n, ctypes.c_void_p(coords.data_ptr()), cptr, ld_in,
                              ctypes.byref(rule.c), ctypes.c_void_p(out_K.data_ptr()),
-                             ctypes.c_void_p(out_F.data_ptr()), out_K.shape[1], reps,
+                             ctypes.c_void_p(out_F.data_ptr()), _ld(out_K, "out_K"), reps,
                              ctypes.byref(best), ctypes.byref(ms), _stream_handle(stream)))
     return best.as_tuple(), ms.value
 
@@ -626,7 +653,17 @@ def tuning_load(path: str) -> None:
 
 
 def tuning_clear() -> None:
+    """Empty the caller's tuning table (the built-in entries stay in effect)."""
     lib().fe_tuning_clear()
+
+
+def tuning_builtin():
+    """(in effect, table architecture, entries in effect) of the built-in
+    tuning table."""
+    arch = ctypes.create_string_buffer(64)
+    n = ctypes.c_int(0)
+    on = lib().fe_tuning_builtin(arch, 64, ctypes.byref(n))
+    return bool(on), arch.value.decode(), n.value
 
 
 def stream_copy(dst, src, stream=None) -> None:
@@ -655,17 +692,25 @@ class DeviceWorkload:
 
 def to_device(wl, precision="fp64", device="cuda", rule: Rule | None = None) -> DeviceWorkload:
     """Upload a generated workload (coordinates FP64; coefficients in the
-    precision of the tier)."""
+    precision of the tier) into buffers with line-aligned rows (ld_for(n));
+    the arrays are (rows, n) views of them."""
     import torch
     p = problem_for(wl, precision)
     r = rule if rule is not None else builtin_rule(wl.elem, wl.n_q)
-    coords = torch.from_numpy(wl.mesh.coords).to(device)
+    n = wl.n_elem
+
+    def upload(a, dt):
+        # rows padded to ld_for(n): the (rows, n) view keeps line-aligned rows
+        buf = torch.zeros((a.shape[0], max(1, ld_for(n))), dtype=dt, device=device)
+        buf[:, :n] = torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dt)
+        return buf[:, :n]
+
+    coords = upload(wl.mesh.coords, torch.float64)
     coeffs = None
     if wl.coeffs is not None and wl.coef_mode == "function":
         coeffs = torch.from_numpy(np.ascontiguousarray(wl.coeffs, dtype=np.float64)).to(device)
     elif wl.coeffs is not None and wl.coef_mode != "uniform":
-        dt = torch.float64 if precision == "fp64" else torch.float32
-        coeffs = torch.from_numpy(np.ascontiguousarray(wl.coeffs)).to(device=device, dtype=dt)
+        coeffs = upload(wl.coeffs, torch.float64 if precision == "fp64" else torch.float32)
     return DeviceWorkload(wl, precision, p, r, coords, coeffs)
 
 
@@ -742,10 +787,10 @@ def batch_integrate_static(kinds, requests, chunk_elems=16384, blocks_per_kind=0
         reqs[i].n_elem = coords.shape[1] if len(r) < 6 or r[5] is None else int(r[5])
         reqs[i].coords = coords.data_ptr()
         reqs[i].coeffs = coeffs.data_ptr() if coeffs is not None else None
-        reqs[i].ld_in = coords.shape[1]
+        reqs[i].ld_in = _ld(coords, "coords")
         reqs[i].out_K = out_K.data_ptr()
         reqs[i].out_F = out_F.data_ptr()
-        reqs[i].ld_out = out_K.shape[1]
+        reqs[i].ld_out = _ld(out_K, "out_K")
     _check(L.fe_batch_integrate_static(arr, len(kinds), reqs, len(requests), chunk_elems,
                                        blocks_per_kind, _stream_handle(stream)))
 
@@ -769,8 +814,8 @@ class Batch:
         n = coords.shape[1] if n_elem is None else int(n_elem)
         _check(lib().fe_batch_add(self._h, kind, n, ctypes.c_void_p(coords.data_ptr()),
                                   ctypes.c_void_p(coeffs.data_ptr()) if coeffs is not None else None,
-                                  coords.shape[1], ctypes.c_void_p(out_K.data_ptr()),
-                                  ctypes.c_void_p(out_F.data_ptr()), out_K.shape[1]))
+                                  _ld(coords, "coords"), ctypes.c_void_p(out_K.data_ptr()),
+                                  ctypes.c_void_p(out_F.data_ptr()), _ld(out_K, "out_K")))
 
     def pending(self) -> int:
         return int(lib().fe_batch_pending(self._h))

@@ -188,15 +188,16 @@ def test_empty_batch_enqueues_nothing():
 def test_tuning_table_roundtrip(tmp_path):
     fe.tuning_clear()
     p = fe.problem("scalar", "fp64", "uniform", 0, None, "packed")
-    assert fe.tuning_get(p, "tet4", 1) is None
-    fe.tuning_set(p, "tet4", 1, fe.variant(128, 2, 2, 1, 0, 1, 1, 3))
-    assert fe.tuning_get(p, "tet4", 1) == (128, 2, 2, 1, 0, 1, 1, 3)
+    # a 2-point rule: a family the built-in table has no entry for
+    assert fe.tuning_get(p, "tet4", 2) is None
+    fe.tuning_set(p, "tet4", 2, fe.variant(128, 2, 2, 1, 0, 1, 1, 3))
+    assert fe.tuning_get(p, "tet4", 2) == (128, 2, 2, 1, 0, 1, 1, 3)
     path = str(tmp_path / "tune.txt")
     fe.tuning_save(path)
     fe.tuning_clear()
-    assert fe.tuning_get(p, "tet4", 1) is None
+    assert fe.tuning_get(p, "tet4", 2) is None
     fe.tuning_load(path)
-    assert fe.tuning_get(p, "tet4", 1) == (128, 2, 2, 1, 0, 1, 1, 3)
+    assert fe.tuning_get(p, "tet4", 2) == (128, 2, 2, 1, 0, 1, 1, 3)
     fe.tuning_clear()
     # tables written before the lanes field (and before split / order) still load
     old = tmp_path / "old.txt"
@@ -454,3 +455,28 @@ def test_product_path_fails_loudly_without_the_library(tmp_path):
                          timeout=120)
     assert "raised True" in out.stdout, out.stdout + out.stderr
     assert "oracle imported False" in out.stdout, out.stdout
+
+
+def test_ld_for_rounds_to_whole_lines():
+    assert fe.ld_for(0) == 0
+    assert fe.ld_for(1) == 256
+    assert fe.ld_for(256) == 256
+    assert fe.ld_for(257) == 512
+    assert fe.ld_for(10_110_954) == 10_110_976
+    assert fe.lib().fe_ld_for(-1) == -1
+
+
+def test_builtin_tuning_table_is_the_committed_one():
+    """The table compiled into the library is tuning_mi355x.txt; it is in
+    effect only on its own architecture (never without a device)."""
+    import re
+    path = os.path.join(ROOT, "paper_1504_01023_amd", "tuning_mi355x.txt")
+    text = open(path).read()
+    arch = re.search(r"^# arch (\S+)", text, re.M).group(1)
+    assert re.search(r"^# rocm (\d+)\.(\d+)", text, re.M)
+    on, tab_arch, n = fe.tuning_builtin()
+    assert tab_arch == arch == "gfx950"
+    if not on:
+        assert n == 0
+    else:
+        assert n == sum(1 for line in text.splitlines() if line and not line.startswith("#"))

@@ -118,8 +118,9 @@ def test_strided_slice_in_place():
     e0, m = 130, 517
     import ctypes
     L = fe.lib()
+    ld_in = dw.coords.stride(0)
     st = L.fe_integrate_ex(ctypes.byref(p), 0, m, ctypes.c_void_p(dw.coords.data_ptr() + 8 * e0),
-                           ctypes.c_void_p(dw.coeffs.data_ptr() + 8 * e0), n,
+                           ctypes.c_void_p(dw.coeffs.data_ptr() + 8 * e0), ld_in,
                            ctypes.byref(dw.rule.c), ctypes.c_void_p(K.data_ptr() + 8 * e0),
                            ctypes.c_void_p(F.data_ptr() + 8 * e0), n, None,
                            ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))

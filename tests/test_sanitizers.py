@@ -48,8 +48,13 @@ def test_server_under_sanitizer(tmp_path, san):
               "-I", os.path.join(ROOT, "include"), "-I", CSRC]
     objs = []
     procs = []
-    for src in SERVER_SRCS + ("server_stress.cpp",):
-        path = os.path.join(HERE, "csrc", src) if src == "server_stress.cpp" else os.path.join(CSRC, src)
+    from paper_1504_01023_amd import build as fe_build
+    os.makedirs(fe_build.BUILD, exist_ok=True)
+    table = fe_build._tuning_source()  # the built-in tuning table's unit
+    for src in SERVER_SRCS + ("server_stress.cpp", table):
+        path = (os.path.join(HERE, "csrc", src) if src == "server_stress.cpp" else
+                src if os.path.isabs(src) else os.path.join(CSRC, src))
+        src = os.path.basename(src)
         obj = str(tmp_path / (src + ".o"))
         objs.append(obj)
         procs.append(subprocess.Popen([HIPCC, *common, "-fPIC", "-c", path, "-o", obj],
@@ -58,7 +63,8 @@ def test_server_under_sanitizer(tmp_path, san):
         out, err = p.communicate(timeout=600)
         assert p.returncode == 0, err[-4000:]
     exe = str(tmp_path / "server_stress")
-    _run([HIPCC, *host, "--offload-arch=gfx950", *objs, "-o", exe])
+    _run([HIPCC, *host, "--offload-arch=gfx950", *objs, "-o", exe, "-L/opt/rocm/lib",
+          "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"])
     env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1", ASAN_OPTIONS="detect_leaks=0")
     env.pop("LD_PRELOAD", None)
     out = _run([exe], env=env, timeout=300)

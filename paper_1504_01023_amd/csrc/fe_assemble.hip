@@ -43,18 +43,6 @@ __device__ __forceinline__ int k_row(int N, bool packed, int r, int s)
     return lo * N - lo * (lo - 1) / 2 + (hi - lo);
 }
 
-// Workgroups are handed to the chip's 8 XCDs in turn (workgroup b to XCD
-// b mod 8), and each XCD has its own L2. The logical workgroup index gives
-// every XCD one contiguous range of nodes, so neighbouring nodes, which share
-// elements and vertex data, are read through the same L2. A bijection of
-// [0, G): XCD x takes q + 1 consecutive indices if x < G mod 8, else q
-// (q = G / 8).
-__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t G)
-{
-    const int64_t x = b % 8, k = b / 8, q = G / 8, r = G % 8;
-    return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
-}
-
 template <int NV, int NC, typename T, bool PACKED, bool WITH_B>
 __global__ __launch_bounds__(256) void assemble_stored_kernel(AsmArgs g)
 {

@@ -654,6 +654,16 @@ __device__ __forceinline__ void to_edge_vectors(double (&X)[NS * 3])
             X[3 * r + i] -= X[i];
 }
 
+// Reference derivatives of the linear prism that vanish at every point, for
+// any rule: d/dxi of shape functions 2 and 5 and d/deta of 1 and 4 (the
+// triangle functions eta and xi do not depend on the other coordinate).
+// Their terms are left out of the sums below (adding a zero product leaves
+// a finite sum unchanged).
+__device__ __forceinline__ constexpr bool prism_zero_derivative(int r, int k)
+{
+    return (k == 0 && (r == 2 || r == 5)) || (k == 1 && (r == 1 || r == 4));
+}
+
 // Element given by tables (prism): Jacobian terms at one point from the
 // edge vectors E (E_r = X_r - X_0, r >= 1): J[i][k] = sum_r E_r,i dphi_r/dxi_k;
 // g_r = J^{-T} grad_ref phi_r.
@@ -669,7 +679,8 @@ __device__ __forceinline__ void point_geometry(const double (&E)[NS * 3], const 
             double s = 0.0;
 #pragma unroll
             for (int r = 1; r < NS; ++r)
-                s += E[3 * r + i] * ref.dphi(q, r, k);
+                if (!(NS == 6 && prism_zero_derivative(r, k)))
+                    s += E[3 * r + i] * ref.dphi(q, r, k);
             J[i][k] = s;
         }
     const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
@@ -691,8 +702,14 @@ __device__ __forceinline__ void point_geometry(const double (&E)[NS * 3], const 
     for (int r = 0; r < NS; ++r) {
         const double d0 = ref.dphi(q, r, 0), d1 = ref.dphi(q, r, 1), d2 = ref.dphi(q, r, 2);
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
-            g[r][i] = (T)(d0 * Ji[0][i] + d1 * Ji[1][i] + d2 * Ji[2][i]);
+        for (int i = 0; i < 3; ++i) {
+            if (NS == 6 && prism_zero_derivative(r, 0))
+                g[r][i] = (T)(d1 * Ji[1][i] + d2 * Ji[2][i]);
+            else if (NS == 6 && prism_zero_derivative(r, 1))
+                g[r][i] = (T)(d0 * Ji[0][i] + d2 * Ji[2][i]);
+            else
+                g[r][i] = (T)(d0 * Ji[0][i] + d1 * Ji[1][i] + d2 * Ji[2][i]);
+        }
     }
     vol_t = (T)(det * ref.w(q));
 }
@@ -1372,6 +1389,56 @@ struct PrismScalar {
         }
     }
 
+    // One point's contribution to K (and to F when wf) from its gradients g,
+    // vol and the shape-function values phi. The trial function is the outer
+    // loop: its column of the integrand (the coefficients applied to Phi_s),
+    // scaled by vol, meets every test function's Phi_r, so only one column is
+    // live at a time.
+    template <int NK>
+    __device__ __forceinline__ static void contract(const Coefs &c, const T (&g)[6][3], T vol,
+                                                    const T (&phi)[6], T (&K)[NK], T (&F)[6],
+                                                    bool wf)
+    {
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+            T ts[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                T x = T(0);
+                if constexpr (DIFF)
+                    x = c.C[i][0] * g[s][0] + c.C[i][1] * g[s][1] + c.C[i][2] * g[s][2];
+                if constexpr (CA)
+                    x += phi[s] * c.ca[i];
+                ts[i] = vol * x;
+            }
+            T y = T(0);
+            if constexpr (CB)
+                y = c.cb[0] * g[s][0] + c.cb[1] * g[s][1] + c.cb[2] * g[s][2];
+            if constexpr (MASS)
+                y += c.c00 * phi[s];
+            const T sgs = vol * y;
+#pragma unroll
+            for (int r = 0; r < (PACKED ? s + 1 : 6); ++r) {
+                const int k = PACKED ? pidx(6, r, s) : 6 * r + s;
+                T x = K[k];
+                if constexpr (DIFF || CA)
+                    x += g[r][0] * ts[0] + g[r][1] * ts[1] + g[r][2] * ts[2];
+                if constexpr (CB || MASS)
+                    x += phi[r] * sgs;
+                K[k] = x;
+            }
+        }
+        if (wf) {
+#pragma unroll
+            for (int r = 0; r < 6; ++r) {
+                if constexpr (DG)
+                    F[r] += vol * (g[r][0] * c.d[0] + g[r][1] * c.d[1] + g[r][2] * c.d[2]);
+                if constexpr (D0)
+                    F[r] += (vol * phi[r]) * c.d0;
+            }
+        }
+    }
+
     // The points q0, q0 + qstep, ... of one element, summed into K and F.
     template <int NT, class R, class B2, int NK>
     __device__ __forceinline__ static void accumulate(const KArgs &a, const Streams &st, const R &ref,
@@ -1388,6 +1455,7 @@ struct PrismScalar {
         Coefs c;
         if constexpr (!PER_QP)
             load_coefs<NT>(a, st, ref, 0, e, X0, X, c, bl);
+        const bool wf = bl.with_f();
         const int nq = NQ > 0 ? NQ : a.n_q;
 #pragma unroll(NQ > 0 ? NQ : 1)
         for (int q = q0; q < nq; q += qstep) {
@@ -1396,51 +1464,54 @@ struct PrismScalar {
             T g[6][3], vol;
             point_geometry<6, T>(X, ref, q, g, vol);
             T phi[6];
-            if constexpr (NEED_PHI) {
 #pragma unroll
-                for (int r = 0; r < 6; ++r)
-                    phi[r] = (T)ref.phi(q, r);
+            for (int r = 0; r < 6; ++r)
+                phi[r] = NEED_PHI ? (T)ref.phi(q, r) : T(0);
+            contract(c, g, vol, phi, K, F, wf);
+        }
+    }
+
+    // The three blocks (A, 0), (A, 1), (A, 2) of the 3-component problem in
+    // one pass over the points: the Jacobian terms are formed once per point
+    // for the three, and each block's sums are those of `accumulate` for it.
+    template <int NT, class R>
+    __device__ __forceinline__ static void accumulate_row3(const KArgs &a, const Streams &st,
+                                                           const R &ref, int64_t e,
+                                                           const double (&X0)[3],
+                                                           const double (&X)[18], int A,
+                                                           T (&K)[3][36], T (&F)[6])
+    {
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int k = 0; k < 36; ++k)
+                K[b][k] = T(0);
+#pragma unroll
+        for (int r = 0; r < 6; ++r)
+            F[r] = T(0);
+        Coefs c[3];
+        if constexpr (!PER_QP) {
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                load_coefs<NT>(a, st, ref, 0, e, X0, X, c[b], VecBlock{A, b});
+        }
+        const int nq = NQ > 0 ? NQ : a.n_q;
+#pragma unroll(NQ > 0 ? NQ : 1)
+        for (int q = 0; q < nq; ++q) {
+            if constexpr (PER_QP) {
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+                    load_coefs<NT>(a, st, ref, q, e, X0, X, c[b], VecBlock{A, b});
             }
-            T t[6][3], sg[6];
+            T g[6][3], vol;
+            point_geometry<6, T>(X, ref, q, g, vol);
+            T phi[6];
 #pragma unroll
-            for (int s = 0; s < 6; ++s) {
+            for (int r = 0; r < 6; ++r)
+                phi[r] = NEED_PHI ? (T)ref.phi(q, r) : T(0);
 #pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    T x = T(0);
-                    if constexpr (DIFF)
-                        x = c.C[i][0] * g[s][0] + c.C[i][1] * g[s][1] + c.C[i][2] * g[s][2];
-                    if constexpr (CA)
-                        x += phi[s] * c.ca[i];
-                    t[s][i] = x;
-                }
-                T y = T(0);
-                if constexpr (CB)
-                    y = c.cb[0] * g[s][0] + c.cb[1] * g[s][1] + c.cb[2] * g[s][2];
-                if constexpr (MASS)
-                    y += c.c00 * phi[s];
-                sg[s] = y;
-            }
-#pragma unroll
-            for (int r = 0; r < 6; ++r) {
-                const T u0 = vol * g[r][0], u1 = vol * g[r][1], u2 = vol * g[r][2];
-                T p = T(0);
-                if constexpr (NEED_PHI)
-                    p = vol * phi[r];
-#pragma unroll
-                for (int s = (PACKED ? r : 0); s < 6; ++s) {
-                    const int k = PACKED ? pidx(6, r, s) : 6 * r + s;
-                    T x = K[k];
-                    if constexpr (DIFF || CA)
-                        x += u0 * t[s][0] + u1 * t[s][1] + u2 * t[s][2];
-                    if constexpr (CB || MASS)
-                        x += p * sg[s];
-                    K[k] = x;
-                }
-                if constexpr (DG)
-                    F[r] += u0 * c.d[0] + u1 * c.d[1] + u2 * c.d[2];
-                if constexpr (D0)
-                    F[r] += p * c.d0;
-            }
+            for (int b = 0; b < 3; ++b)
+                contract(c[b], g, vol, phi, K[b], F, b == 0);
         }
     }
 
@@ -1494,8 +1565,9 @@ struct PrismScalar {
 // ================================================= prism, 3-component CDR
 // Block by block as for tetrahedra: the (alpha, beta) block runs the scalar
 // point loop with the block's coefficients, so a lane holds one 6x6 block of
-// accumulators at a time instead of the whole 18x18 matrix (the per-point
-// Jacobian terms are recomputed for each block).
+// accumulators (FP64) or one row of three blocks (FP32) at a time instead of
+// the whole 18x18 matrix; the per-point Jacobian terms are recomputed for
+// each pass.
 template <typename T, int MODE, int NQ>
 struct PrismVector {
     // each block's coefficients are read after earlier blocks are stored
@@ -1513,10 +1585,40 @@ struct PrismVector {
             X[s] = Xg[0][s];
         const double X0[3] = {X[0], X[1], X[2]};
         to_edge_vectors<6>(X);
+        typedef PrismScalar<T, TS_FULL, MODE, 0, NQ, VecBlock> PS;
+        if constexpr (sizeof(T) == 4) {
+            // FP32 tier: a row of three blocks per pass over the points, so
+            // the FP64 Jacobian terms are formed three times instead of nine
+            // (the three blocks' FP32 sums fit the registers)
 #pragma unroll 1
-        for (int b = 0; b < 9; ++b)
-            PrismScalar<T, TS_FULL, MODE, 0, NQ, VecBlock>::template body<NT>(a, st, ref, e, X0, X,
-                                                                               VecBlock{b / 3, b % 3});
+            for (int A = 0; A < 3; ++A) {
+                T K[3][36], F[6];
+                PS::template accumulate_row3<NT>(a, st, ref, e, X0, X, A, K, F);
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    const VecBlock bl{A, b};
+#pragma unroll
+                    for (int r = 0; r < 6; ++r)
+#pragma unroll
+                        for (int s2 = 0; s2 < 6; ++s2) {
+                            const T v[1] = {K[b][6 * r + s2]};
+                            bl.template put_k<1, NT>(st, 6, 0, r, s2, e, v);
+                        }
+                }
+                const VecBlock b0{A, 0};
+#pragma unroll
+                for (int r = 0; r < 6; ++r) {
+                    const T v[1] = {F[r]};
+                    b0.template put_f<1, NT>(st, r, e, v);
+                }
+            }
+        } else {
+            // FP64: one block per pass (three blocks' FP64 sums would not
+            // fit the registers)
+#pragma unroll 1
+            for (int b = 0; b < 9; ++b)
+                PS::template body<NT>(a, st, ref, e, X0, X, VecBlock{b / 3, b % 3});
+        }
     }
 
     // Matrix-free and assembly consumers: the nine blocks handed to bl.
@@ -2218,18 +2320,6 @@ __device__ __forceinline__ void stage_reference(const KArgs &a, RefLds &lds)
             (&lds.dphi[0][0][0])[i] = (&a.dphi[0][0][0])[i];
         __syncthreads();
     }
-}
-
-// Workgroups are handed to the chip's 8 XCDs in turn (workgroup b to XCD
-// b mod 8), and each XCD has its own L2. The logical workgroup index gives
-// every XCD one contiguous range of the work (nodes, or elements in mesh
-// order), so neighbours, which share elements and vertex data, are read
-// through the same L2. A bijection of [0, G): XCD x takes q + 1 consecutive
-// indices if x < G mod 8, else q (q = G / 8).
-__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t G)
-{
-    const int64_t x = b % 8, k = b / 8, q = G / 8, r = G % 8;
-    return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
 }
 
 // Matrix-free application of the assembled operator (indexed geometry, one

@@ -29,6 +29,18 @@ inline hipError_t launch_kernel(void (*k)(P...), dim3 grid, dim3 block, size_t l
     return hipLaunchKernel(reinterpret_cast<const void *>(k), grid, block, ptrs, lds, stream);
 }
 
+// Workgroups are handed to the chip's 8 XCDs in turn (workgroup b to XCD
+// b mod 8), and each XCD has its own L2. The logical workgroup index
+// xcd_block(b, G) gives every XCD one contiguous range of the work (nodes,
+// or elements in mesh order), so neighbours, which share elements and
+// vertex data, are read through the same L2. A bijection of [0, G): XCD x
+// takes q + 1 consecutive indices if x < G mod 8, else q (q = G / 8).
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t G)
+{
+    const int64_t x = b % 8, k = b / 8, q = G / 8, r = G % 8;
+    return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
 // Term groups of the scalar weak form (Sec. 2.1, eq. "weak_form"); a kernel
 // is compiled for a set of groups and the code for absent groups is removed.
 enum TermBits : int {

@@ -40,12 +40,22 @@
 #include <unordered_set>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "fe.h"
 #include "fe_api_internal.h"
 
 using namespace fe;
 
 namespace {
+
+// A roctx range over a scope (visible in rocprofv3 --marker-trace; a no-op
+// when no tool is attached).
+struct TraceRange {
+    explicit TraceRange(const char *name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+};
+
 
 double now_s()
 {
@@ -329,6 +339,7 @@ bool admit_one(fe_server *s)
         r.fake_ready = s->fake_copy_free;
         return true;
     }
+    const TraceRange trace("fe_server admit: H2D");
     hipError_t err = hipMemcpy2DAsync(const_cast<double *>(r.coords), 8 * r.ld_in, r.h_coords,
                                       8 * r.ld_host, 8 * r.n, 3 * ki.nv, hipMemcpyHostToDevice,
                                       s->copy);
@@ -360,6 +371,7 @@ bool inputs_ready(fe_server *s, Req &r, double t)
 // chunk), and capacity a request cannot use goes to the others in admission
 // order, so a large request never holds back requests that arrive while it
 // runs.
+
 void launch_tick(fe_server *s)
 {
     const int64_t ce = s->cfg.chunk_elems;
@@ -371,6 +383,7 @@ void launch_tick(fe_server *s)
     }
     if (ready.empty())
         return;
+    const TraceRange trace("fe_server tick");
     std::vector<int64_t> want(ready.size()), give(ready.size(), 0);
     int64_t cap = s->cfg.max_chunks;
     for (size_t i = 0; i < ready.size(); ++i)

@@ -889,6 +889,9 @@ def main() -> int:
     ap.add_argument("--served-warmup", type=int, default=50)
     ap.add_argument("--served-slots", type=int, default=64)
     ap.add_argument("--served-rho", type=float, nargs="*", default=[0.5, 0.7, 0.9])
+    ap.add_argument("--workloads", default=None,
+                    help="several workloads in one process, e.g. tet_cdr:fp64,prism_cdr:fp32 "
+                         "(one JSON line each; for profiling runs that cover many kernels)")
     ap.add_argument("--headline-only", action="store_true",
                     help="default workload: only the FP64 line, without the FP32 tier and the "
                          "served summary")
@@ -977,6 +980,16 @@ def main() -> int:
                 "config": {"workload": "served", "mix": SERVED_MIX}, "served": res}
         print(json.dumps(line), flush=True)
         return 0
+
+    if a.workloads:
+        ok = True
+        for item in a.workloads.split(","):
+            w, _, prec = item.partition(":")
+            r = measure_plain(a, torch, fe, oracle, w, prec or "fp64", dev, a.parity_sample,
+                              with_cpu=False)
+            print(json.dumps(r), flush=True)
+            ok = ok and r["parity"]["ok"]
+        return 0 if ok else 3
 
     out = measure_plain(a, torch, fe, oracle, a.workload, a.precision, dev, a.parity_sample,
                         with_cpu=not a.no_cpu)

@@ -665,11 +665,11 @@ __device__ __forceinline__ constexpr bool prism_zero_derivative(int r, int k)
 }
 
 // Element given by tables (prism): Jacobian terms at one point from the
-// edge vectors E (E_r = X_r - X_0, r >= 1): J[i][k] = sum_r E_r,i dphi_r/dxi_k;
-// g_r = J^{-T} grad_ref phi_r.
-template <int NS, typename T, class R>
-__device__ __forceinline__ void point_geometry(const double (&E)[NS * 3], const R &ref, int q,
-                                               T (&g)[NS][3], T &vol_t)
+// edge vectors E (E_r = X_r - X_0, r >= 1): J[i][k] = sum_r E_r,i dphi_r/dxi_k,
+// Ji[k][i] = (J^{-1})_{k i} and det J.
+template <int NS, class R>
+__device__ __forceinline__ void point_jacobian(const double (&E)[NS * 3], const R &ref, int q,
+                                               double (&Ji)[3][3], double &det)
 {
     double J[3][3];
 #pragma unroll
@@ -686,9 +686,8 @@ __device__ __forceinline__ void point_geometry(const double (&E)[NS * 3], const 
     const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
     const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
     const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-    const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+    det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
     const double inv = 1.0 / det;
-    double Ji[3][3];  // Ji[k][i] = (J^{-1})_{k i}
     Ji[0][0] = c00 * inv;
     Ji[1][0] = c01 * inv;
     Ji[2][0] = c02 * inv;
@@ -698,6 +697,16 @@ __device__ __forceinline__ void point_geometry(const double (&E)[NS * 3], const 
     Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * inv;
     Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * inv;
     Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * inv;
+}
+
+// Global derivatives at one point: g_r = J^{-T} grad_ref phi_r, and
+// vol = det J w_q.
+template <int NS, typename T, class R>
+__device__ __forceinline__ void point_geometry(const double (&E)[NS * 3], const R &ref, int q,
+                                               T (&g)[NS][3], T &vol_t)
+{
+    double Ji[3][3], det;
+    point_jacobian<NS>(E, ref, q, Ji, det);
 #pragma unroll
     for (int r = 0; r < NS; ++r) {
         const double d0 = ref.dphi(q, r, 0), d1 = ref.dphi(q, r, 1), d2 = ref.dphi(q, r, 2);
@@ -1245,6 +1254,11 @@ struct PrismScalar {
                           MASS = TERMS & T_MASS, DG = TERMS & T_DGRAD, D0 = TERMS & T_D0;
     static constexpr bool PER_QP = (MODE == M_QP || MODE == M_QP_MIXED || MODE == M_FUNC);
     static constexpr bool NEED_PHI = CA || CB || MASS || D0;
+    // FP64 with coefficients that are uniform, per element, or per point
+    // slot by slot: the contraction runs in reference coordinates
+    // (contract_ref); with every slot per point or coefficient functions the
+    // per-point form through the global derivatives measured faster.
+    static constexpr bool REF_SPACE = sizeof(T) == 8 && MODE != M_QP && MODE != M_FUNC;
 
     struct Coefs {
         T C[3][3], ca[3], cb[3], c00, d[3], d0;
@@ -1439,6 +1453,115 @@ struct PrismScalar {
         }
     }
 
+    // One point's contribution in reference coordinates (FP64): with
+    // Jv = vol J^{-1}, the global derivatives never appear, since
+    //   vol g_r . C g_s = dphi_r . B dphi_s,     B = Jv C J^{-T}
+    //   vol (c^{.;0} . g_r) phi_s = (dphi_r . a) phi_s,   a = Jv c^{.;0}
+    //   vol phi_r (c^{0;.} . g_s) = phi_r (b . dphi_s),   b = Jv c^{0;.}
+    //   vol g_r . d = dphi_r . f,   f = Jv d,
+    // so K_rs += dphi_r . (B dphi_s + a phi_s) + phi_r (b . dphi_s + m phi_s)
+    // with m = vol c^{0;0}, and F_r += dphi_r . f + phi_r (vol d^0). The
+    // reference derivatives are wave-uniform table values, and the ones that
+    // vanish for the prism are skipped.
+    template <class R, int NK>
+    __device__ __forceinline__ static void contract_ref(const Coefs &c, const R &ref, int q,
+                                                        const double (&Ji)[3][3], double vol,
+                                                        T (&K)[NK], T (&F)[6], bool wf)
+    {
+        double Jv[3][3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                Jv[k][i] = vol * Ji[k][i];
+        double B[3][3], av[3], bv[3];
+        if constexpr (DIFF) {
+            double M[3][3];  // Jv C
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+                    M[k][j] = Jv[k][0] * c.C[0][j] + Jv[k][1] * c.C[1][j] + Jv[k][2] * c.C[2][j];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int l = 0; l < 3; ++l)
+                    B[k][l] = M[k][0] * Ji[l][0] + M[k][1] * Ji[l][1] + M[k][2] * Ji[l][2];
+        }
+        if constexpr (CA) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                av[k] = Jv[k][0] * c.ca[0] + Jv[k][1] * c.ca[1] + Jv[k][2] * c.ca[2];
+        }
+        if constexpr (CB) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                bv[k] = Jv[k][0] * c.cb[0] + Jv[k][1] * c.cb[1] + Jv[k][2] * c.cb[2];
+        }
+        const double m = MASS ? vol * c.c00 : 0.0;
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+            const double ps = NEED_PHI ? ref.phi(q, s) : 0.0;
+            double u[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                double x = 0.0;
+                if constexpr (DIFF) {
+#pragma unroll
+                    for (int l = 0; l < 3; ++l)
+                        if (!prism_zero_derivative(s, l))
+                            x += B[k][l] * ref.dphi(q, s, l);
+                }
+                if constexpr (CA)
+                    x += av[k] * ps;
+                u[k] = x;
+            }
+            double sg = 0.0;
+            if constexpr (CB) {
+#pragma unroll
+                for (int l = 0; l < 3; ++l)
+                    if (!prism_zero_derivative(s, l))
+                        sg += bv[l] * ref.dphi(q, s, l);
+            }
+            if constexpr (MASS)
+                sg += m * ps;
+#pragma unroll
+            for (int r = 0; r < (PACKED ? s + 1 : 6); ++r) {
+                const int kk = PACKED ? pidx(6, r, s) : 6 * r + s;
+                T x = K[kk];
+                if constexpr (DIFF || CA) {
+#pragma unroll
+                    for (int k = 0; k < 3; ++k)
+                        if (!prism_zero_derivative(r, k))
+                            x += ref.dphi(q, r, k) * u[k];
+                }
+                if constexpr (CB || MASS)
+                    x += ref.phi(q, r) * sg;
+                K[kk] = x;
+            }
+        }
+        if (wf) {
+            double fv[3] = {0.0, 0.0, 0.0};
+            if constexpr (DG) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    fv[k] = Jv[k][0] * c.d[0] + Jv[k][1] * c.d[1] + Jv[k][2] * c.d[2];
+            }
+            const double f0 = D0 ? vol * c.d0 : 0.0;
+#pragma unroll
+            for (int r = 0; r < 6; ++r) {
+                if constexpr (DG) {
+#pragma unroll
+                    for (int k = 0; k < 3; ++k)
+                        if (!prism_zero_derivative(r, k))
+                            F[r] += ref.dphi(q, r, k) * fv[k];
+                }
+                if constexpr (D0)
+                    F[r] += ref.phi(q, r) * f0;
+            }
+        }
+    }
+
     // The points q0, q0 + qstep, ... of one element, summed into K and F.
     template <int NT, class R, class B2, int NK>
     __device__ __forceinline__ static void accumulate(const KArgs &a, const Streams &st, const R &ref,
@@ -1461,6 +1584,12 @@ struct PrismScalar {
         for (int q = q0; q < nq; q += qstep) {
             if constexpr (PER_QP)
                 load_coefs<NT>(a, st, ref, q, e, X0, X, c, bl);
+            if constexpr (REF_SPACE) {
+                double Ji[3][3], det;
+                point_jacobian<6>(X, ref, q, Ji, det);
+                contract_ref(c, ref, q, Ji, det * ref.w(q), K, F, wf);
+                continue;
+            }
             T g[6][3], vol;
             point_geometry<6, T>(X, ref, q, g, vol);
             T phi[6];

@@ -102,6 +102,8 @@ void fill_reference(int elem, const fe_quad_rule &rule, KArgs &a)
     std::memset(a.w, 0, sizeof(a.w));
     std::memset(a.phi, 0, sizeof(a.phi));
     std::memset(a.dphi, 0, sizeof(a.dphi));
+    std::memset(a.phi_f, 0, sizeof(a.phi_f));
+    std::memset(a.dphi_f, 0, sizeof(a.dphi_f));
     std::memset(a.m, 0, sizeof(a.m));
     std::memset(a.M, 0, sizeof(a.M));
     a.Wsum = 0.0;
@@ -113,8 +115,11 @@ void fill_reference(int elem, const fe_quad_rule &rule, KArgs &a)
         a.Wsum += rule.w[q];
         for (int r = 0; r < ns; ++r) {
             a.phi[q][r] = phi[r];
-            for (int k = 0; k < 3; ++k)
+            a.phi_f[q][r] = (float)phi[r];
+            for (int k = 0; k < 3; ++k) {
                 a.dphi[q][r][k] = dphi[r][k];
+                a.dphi_f[q][r][k] = (float)dphi[r][k];
+            }
             a.m[r] += rule.w[q] * phi[r];
             for (int s = 0; s < ns; ++s)
                 a.M[r][s] += rule.w[q] * phi[r] * phi[s];

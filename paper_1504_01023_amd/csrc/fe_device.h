@@ -600,6 +600,22 @@ struct Ref {
     {
         return REF == REF_LDS ? s->dphi[q][r][k] : a.dphi[q][r][k];
     }
+    // The tables in the arithmetic type U: FP32 reads the rounded copies in
+    // the kernel arguments; otherwise the FP64 value is converted.
+    template <typename U>
+    __device__ __forceinline__ U dphi_t(int q, int r, int k) const
+    {
+        if constexpr (sizeof(U) == 4 && REF == REF_KARG)
+            return a.dphi_f[q][r][k];
+        return (U)dphi(q, r, k);
+    }
+    template <typename U>
+    __device__ __forceinline__ U phi_t(int q, int r) const
+    {
+        if constexpr (sizeof(U) == 4 && REF == REF_KARG)
+            return a.phi_f[q][r];
+        return (U)phi(q, r);
+    }
 };
 
 // ------------------------------------------------- tetrahedron geometry
@@ -1254,11 +1270,11 @@ struct PrismScalar {
                           MASS = TERMS & T_MASS, DG = TERMS & T_DGRAD, D0 = TERMS & T_D0;
     static constexpr bool PER_QP = (MODE == M_QP || MODE == M_QP_MIXED || MODE == M_FUNC);
     static constexpr bool NEED_PHI = CA || CB || MASS || D0;
-    // FP64 with coefficients that are uniform, per element, or per point
-    // slot by slot: the contraction runs in reference coordinates
-    // (contract_ref); with every slot per point or coefficient functions the
-    // per-point form through the global derivatives measured faster.
-    static constexpr bool REF_SPACE = sizeof(T) == 8 && MODE != M_QP && MODE != M_FUNC;
+    // Coefficients that are uniform, per element, or per point slot by slot:
+    // the contraction runs in reference coordinates (contract_ref); with
+    // every slot per point or coefficient functions the per-point form
+    // through the global derivatives measured faster.
+    static constexpr bool REF_SPACE = MODE != M_QP && MODE != M_FUNC;
 
     struct Coefs {
         T C[3][3], ca[3], cb[3], c00, d[3], d0;
@@ -1453,7 +1469,8 @@ struct PrismScalar {
         }
     }
 
-    // One point's contribution in reference coordinates (FP64): with
+    // One point's contribution in reference coordinates, in the tier's
+    // arithmetic type U (FP32 starts from the FP64 Jacobian terms): with
     // Jv = vol J^{-1}, the global derivatives never appear, since
     //   vol g_r . C g_s = dphi_r . B dphi_s,     B = Jv C J^{-T}
     //   vol (c^{.;0} . g_r) phi_s = (dphi_r . a) phi_s,   a = Jv c^{.;0}
@@ -1463,20 +1480,25 @@ struct PrismScalar {
     // with m = vol c^{0;0}, and F_r += dphi_r . f + phi_r (vol d^0). The
     // reference derivatives are wave-uniform table values, and the ones that
     // vanish for the prism are skipped.
-    template <class R, int NK>
+    template <typename U, class R, int NK>
     __device__ __forceinline__ static void contract_ref(const Coefs &c, const R &ref, int q,
-                                                        const double (&Ji)[3][3], double vol,
+                                                        const double (&Jd)[3][3], double vol,
                                                         T (&K)[NK], T (&F)[6], bool wf)
     {
-        double Jv[3][3];
+        U Ji[3][3], Jv[3][3];
 #pragma unroll
         for (int k = 0; k < 3; ++k)
 #pragma unroll
             for (int i = 0; i < 3; ++i)
-                Jv[k][i] = vol * Ji[k][i];
-        double B[3][3], av[3], bv[3];
+                Ji[k][i] = (U)Jd[k][i];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                Jv[k][i] = (U)vol * Ji[k][i];
+        U B[3][3], av[3], bv[3];
         if constexpr (DIFF) {
-            double M[3][3];  // Jv C
+            U M[3][3];  // Jv C
 #pragma unroll
             for (int k = 0; k < 3; ++k)
 #pragma unroll
@@ -1498,30 +1520,30 @@ struct PrismScalar {
             for (int k = 0; k < 3; ++k)
                 bv[k] = Jv[k][0] * c.cb[0] + Jv[k][1] * c.cb[1] + Jv[k][2] * c.cb[2];
         }
-        const double m = MASS ? vol * c.c00 : 0.0;
+        const U m = MASS ? (U)vol * c.c00 : U(0);
 #pragma unroll
         for (int s = 0; s < 6; ++s) {
-            const double ps = NEED_PHI ? ref.phi(q, s) : 0.0;
-            double u[3];
+            const U ps = NEED_PHI ? ref.template phi_t<U>(q, s) : U(0);
+            U u[3];
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                double x = 0.0;
+                U x = U(0);
                 if constexpr (DIFF) {
 #pragma unroll
                     for (int l = 0; l < 3; ++l)
                         if (!prism_zero_derivative(s, l))
-                            x += B[k][l] * ref.dphi(q, s, l);
+                            x += B[k][l] * ref.template dphi_t<U>(q, s, l);
                 }
                 if constexpr (CA)
                     x += av[k] * ps;
                 u[k] = x;
             }
-            double sg = 0.0;
+            U sg = U(0);
             if constexpr (CB) {
 #pragma unroll
                 for (int l = 0; l < 3; ++l)
                     if (!prism_zero_derivative(s, l))
-                        sg += bv[l] * ref.dphi(q, s, l);
+                        sg += bv[l] * ref.template dphi_t<U>(q, s, l);
             }
             if constexpr (MASS)
                 sg += m * ps;
@@ -1533,31 +1555,31 @@ struct PrismScalar {
 #pragma unroll
                     for (int k = 0; k < 3; ++k)
                         if (!prism_zero_derivative(r, k))
-                            x += ref.dphi(q, r, k) * u[k];
+                            x += ref.template dphi_t<U>(q, r, k) * u[k];
                 }
                 if constexpr (CB || MASS)
-                    x += ref.phi(q, r) * sg;
+                    x += ref.template phi_t<U>(q, r) * sg;
                 K[kk] = x;
             }
         }
         if (wf) {
-            double fv[3] = {0.0, 0.0, 0.0};
+            U fv[3] = {U(0), U(0), U(0)};
             if constexpr (DG) {
 #pragma unroll
                 for (int k = 0; k < 3; ++k)
                     fv[k] = Jv[k][0] * c.d[0] + Jv[k][1] * c.d[1] + Jv[k][2] * c.d[2];
             }
-            const double f0 = D0 ? vol * c.d0 : 0.0;
+            const U f0 = D0 ? (U)vol * c.d0 : U(0);
 #pragma unroll
             for (int r = 0; r < 6; ++r) {
                 if constexpr (DG) {
 #pragma unroll
                     for (int k = 0; k < 3; ++k)
                         if (!prism_zero_derivative(r, k))
-                            F[r] += ref.dphi(q, r, k) * fv[k];
+                            F[r] += ref.template dphi_t<U>(q, r, k) * fv[k];
                 }
                 if constexpr (D0)
-                    F[r] += ref.phi(q, r) * f0;
+                    F[r] += ref.template phi_t<U>(q, r) * f0;
             }
         }
     }
@@ -1587,7 +1609,7 @@ struct PrismScalar {
             if constexpr (REF_SPACE) {
                 double Ji[3][3], det;
                 point_jacobian<6>(X, ref, q, Ji, det);
-                contract_ref(c, ref, q, Ji, det * ref.w(q), K, F, wf);
+                contract_ref<T>(c, ref, q, Ji, det * ref.w(q), K, F, wf);
                 continue;
             }
             T g[6][3], vol;
@@ -1631,6 +1653,15 @@ struct PrismScalar {
 #pragma unroll
                 for (int b = 0; b < 3; ++b)
                     load_coefs<NT>(a, st, ref, q, e, X0, X, c[b], VecBlock{A, b});
+            }
+            if constexpr (REF_SPACE) {
+                // each block's sums are exactly those `accumulate` forms
+                double Ji[3][3], det;
+                point_jacobian<6>(X, ref, q, Ji, det);
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+                    contract_ref<T>(c[b], ref, q, Ji, det * ref.w(q), K[b], F, b == 0);
+                continue;
             }
             T g[6][3], vol;
             point_geometry<6, T>(X, ref, q, g, vol);

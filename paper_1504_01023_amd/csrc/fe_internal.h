@@ -102,6 +102,8 @@ struct KArgs {
     double w[FE_MAX_QP];
     double phi[FE_MAX_QP][6];
     double dphi[FE_MAX_QP][6][3];
+    float phi_f[FE_MAX_QP][6];  // the same tables rounded to FP32 (FP32 tier)
+    float dphi_f[FE_MAX_QP][6][3];
     double Wsum;
     double m[6];
     double M[6][6];

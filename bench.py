@@ -703,6 +703,14 @@ def run_apply(a, torch, fe, oracle, base: str, dev, csr: bool = False) -> dict:
         ip, inc = fe.node_incidence(wl.elem, conn_np[perm], n_nodes)
         ipd = torch.from_numpy(ip).to(dev)
         incd = torch.from_numpy(inc).to(dev)
+        # node blocks for the LDS-staged row ownership (scalar tets)
+        bld = None
+        if wl.elem == "tet4" and wl.kind == "scalar":
+            t0 = time.time()
+            blocks = fe.csr_blocks(wl.elem, conn_np[perm], n_nodes, ip, inc)
+            bld = blocks.to(dev)
+            log(f"[bench] node blocks: {blocks.n_blocks}, element slots "
+                f"{len(blocks.elems) / n:.2f} per element ({time.time() - t0:.1f}s)")
 
     def step(cp=ptr):
         if csr:
@@ -714,6 +722,9 @@ def run_apply(a, torch, fe, oracle, base: str, dev, csr: bool = False) -> dict:
     def step_rows():
         fe.assemble_csr_rows(p, wl.elem, nodes, conn, coeffs, rule, rpd, cid, ipd, incd,
                              values=vals)
+
+    def step_blocks():
+        fe.assemble_csr_blocks(p, wl.elem, nodes, coeffs, rule, rpd, cid, ipd, bld, values=vals)
 
     if csr:
         # element-contiguous inputs and outputs for the stored schedule
@@ -757,22 +768,29 @@ def run_apply(a, torch, fe, oracle, base: str, dev, csr: bool = False) -> dict:
         e1.record(stream)
     torch.cuda.synchronize()
     ms_at = np.array([e0.elapsed_time(e1) for e0, e1 in ev_at])
-    ms_rows = None
-    if csr:
-        # by row ownership (one lane per node, no colours, no atomics)
-        ev_r = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                for _ in range(a.steps)]
+    ms_rows = ms_blocks = None
+
+    def timed(fn):
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(a.steps)]
         for _ in range(a.warmup):
-            step_rows()
+            fn()
         torch.cuda.synchronize()
         w0 = time.perf_counter()
-        for e0, e1 in ev_r:
+        for e0, e1 in evs:
             e0.record(stream)
-            step_rows()
+            fn()
             e1.record(stream)
         torch.cuda.synchronize()
-        wall = time.perf_counter() - w0
-        ms_rows = np.array([e0.elapsed_time(e1) for e0, e1 in ev_r])
+        return np.array([e0.elapsed_time(e1) for e0, e1 in evs]), time.perf_counter() - w0
+
+    if csr:
+        # by row ownership (one lane per node, no colours, no atomics), plain
+        # and over node blocks staged in LDS
+        ms_rows, wall_rows = timed(step_rows)
+        wall = wall_rows
+        if bld is not None:
+            ms_blocks, wall = timed(step_blocks)
         ev_s = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                 for _ in range(a.steps)]
         for _ in range(a.warmup):
@@ -817,11 +835,19 @@ def run_apply(a, torch, fe, oracle, base: str, dev, csr: bool = False) -> dict:
         Ra = sp.csr_matrix((np.abs(K).ravel(), (rows, cols)), shape=(nd, nd))[sd]
         den = np.maximum(Ra.max(axis=1).toarray().ravel(), 1e-300)
         err = 0.0
-        for mode in ("coloured", "rows"):
-            if mode == "rows":
+        rows_vals = None
+        blocks_equal = None
+        for mode in ("coloured", "rows", "blocks"):
+            if mode == "blocks" and bld is None:
+                continue
+            if mode != "coloured":
                 vals.zero_()
-                step_rows()
+                (step_rows if mode == "rows" else step_blocks)()
                 torch.cuda.synchronize()
+            if mode == "rows":
+                rows_vals = vals.clone()
+            if mode == "blocks":
+                blocks_equal = bool(torch.equal(rows_vals, vals))
             G = sp.csr_matrix((vals.double().cpu().numpy(), ci, rp), shape=(nd, nd))[sd]
             D = abs(G - R)
             err = max(err, float((D.max(axis=1).toarray().ravel() / den).max()))
@@ -838,8 +864,9 @@ def run_apply(a, torch, fe, oracle, base: str, dev, csr: bool = False) -> dict:
         err = float((np.abs(yg[sd] - yr[sd]) / np.maximum(ya[sd], 1e-300)).max())
         bpe = 4 * nv + tsz * ncoef + (24 + 3 * tsz * nc) * n_nodes / n
     if csr:
-        # the value is the row-ownership assembly; the coloured one beside it
-        ms, ms_col = ms_rows, ms
+        # the value is the row-ownership assembly (over node blocks where they
+        # are built); the coloured one beside it
+        ms, ms_col = (ms_blocks if ms_blocks is not None else ms_rows), ms
     avg = float(ms.mean()) * 1e-3
     return {"wl": wl, "n_elem": n, "n_nodes": n_nodes, "colours": int(len(ptr) - 1),
             "ms_avg": float(ms.mean()), "ms_min": float(ms.min()), "ms_median": float(np.median(ms)),
@@ -852,9 +879,16 @@ def run_apply(a, torch, fe, oracle, base: str, dev, csr: bool = False) -> dict:
             "elements_per_s": n / avg, "bytes_per_element": bpe,
             "achieved_GBps": bpe * n / avg / 1e9,
             "nnz": int(len(ci)) if csr else None,
+            "rows_ms_avg": float(ms_rows.mean()) if csr else None,
+            "rows_elements_per_s": n / (float(ms_rows.mean()) * 1e-3) if csr else None,
+            "blocks": ({"n_blocks": int(bld.n_blocks),
+                        "element_slots_per_element": float(bld.elems.numel() / n),
+                        "vertex_slots_per_node": float(bld.verts.numel() / n_nodes)}
+                       if csr and bld is not None else None),
             "parity": {"sampled_nodes": int(len(snodes)),
                        ("max_rel_err_rows" if csr else "max_rel_err_y"): err, "tol": tol,
-                       "ok": bool(err <= tol)}}
+                       "ok": bool(err <= tol and (not csr or blocks_equal is not False)),
+                       **({"blocks_equal_rows_bitwise": blocks_equal} if csr else {})}}
 
 
 def main() -> int:
@@ -943,8 +977,10 @@ def main() -> int:
                 "dtype": "f64" if a.precision == "fp64" else "f32 (FP64 Jacobian)",
                 "data": "synthetic",
                 "config": {"workload": a.workload,
-                           "description": WORKLOADS[base][1] + ("; values += A, one lane per node (row ownership)"
-                                                                if csr else "; y += A x, coloured launches"),
+                           "description": WORKLOADS[base][1] + (
+                               ("; values += A, one lane per node (row ownership"
+                                + (", node blocks staged in LDS)" if r["blocks"] else ")"))
+                               if csr else "; y += A x, coloured launches"),
                            "n_elem": r["n_elem"], "n_nodes": r["n_nodes"], "colours": r["colours"],
                            "nnz": r["nnz"],
                            "node_element_order": a.apply_order,
@@ -958,6 +994,10 @@ def main() -> int:
                 "atomic": {"ms_avg": r["atomic_ms_avg"], "elements_per_s": r["atomic_elements_per_s"]},
                 "coloured": ({"ms_avg": r["coloured_ms_avg"],
                               "elements_per_s": r["coloured_elements_per_s"]} if csr else None),
+                "row_ownership_plain": ({"ms_avg": r["rows_ms_avg"],
+                                         "elements_per_s": r["rows_elements_per_s"]}
+                                        if csr else None),
+                "node_blocks": r["blocks"],
                 "stored": ({"ms_avg": r["stored_ms_avg"], "elements_per_s": r["stored_elements_per_s"],
                             "what": "fe_integrate_natural (K, F stored element by element) + "
                                     "fe_assemble_csr_stored"}

@@ -271,10 +271,12 @@ int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coor
     if (form >= 1)
         coords = nullptr;  // indexed geometry: no per-element coordinates
     if (n_elem > 0) {
-        // form 0: per-element coordinates; 1: indexed; 2: indexed, matrix-free (no K, F)
-        if ((form == 0 && !coords) || (form >= 1 && !conn) || (form < 2 && (!out_K || !out_F)))
+        // form 0: per-element coordinates; 1: indexed; 2: indexed, matrix-free
+        // (no K, F); 3: as 2 over node blocks (block-local connectivity)
+        const bool by_conn = form == 1 || form == 2;
+        if ((form == 0 && !coords) || (by_conn && !conn) || (form < 2 && (!out_K || !out_F)))
             return fail(FE_ERR_INVALID_ARG, "NULL coordinates, connectivity or output pointer");
-        if (form >= 1 && ld_conn < n_elem)
+        if (by_conn && ld_conn < n_elem)
             return fail(FE_ERR_INVALID_ARG, "connectivity leading dimension smaller than n_elem");
         if (mask && !coeffs)
             return fail(FE_ERR_INVALID_ARG, "coeffs is NULL but coef_mask reads %u slots",
@@ -354,7 +356,7 @@ int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coor
             return false;
         const size_t ca = std::min<size_t>(16, 8 * V), ta = std::min<size_t>(16, tsz * V);
         const size_t ia = std::min<size_t>(16, 4 * V);
-        if (form >= 1 && (ld_conn % V || !aligned(conn, ia)))
+        if ((form == 1 || form == 2) && (ld_conn % V || !aligned(conn, ia)))
             return false;
         return aligned(coords, ca) && aligned(out_K, ta) && aligned(out_F, ta) &&
                (!mask || fn || aligned(coeffs, ta));
@@ -373,7 +375,7 @@ int plan(const fe_problem *problem, int elem, int64_t n_elem, const double *coor
     k.nq = rule->n_q;
     const KernelKey kv = k;  // the chosen variant, before any fallback
     auto usable = [&](const KernelEntry *x) {
-        return x && (form == 0 || (form == 1 && x->idx != nullptr) || (form == 2 && x->apply != nullptr));
+        return x && (form == 0 || (form == 1 && x->idx != nullptr) || (form >= 2 && x->apply != nullptr));
     };
     const int nq_rule = k.nq;
     // the kernel of key k, compiled for the rule's point count or for any
@@ -689,6 +691,66 @@ int fe_assemble_csr_rows(const fe_problem *problem, fe_elem_type elem_type, int6
     return FE_OK;
 }
 
+int fe_assemble_csr_blocks(const fe_problem *problem, fe_elem_type elem_type, int64_t n_elem,
+                           const double *nodes, int64_t n_nodes, const void *coeffs,
+                           int64_t ld_in, const fe_quad_rule *quad_rule, const int64_t *row_ptr,
+                           const int32_t *col_idx, int64_t nnz, void *values, void *b,
+                           const int64_t *inc_ptr, int64_t n_blocks, const int64_t *blk,
+                           const int32_t *elems, const int32_t *verts, const uint16_t *lconn,
+                           const uint16_t *linc, hipStream_t stream)
+{
+    if (elem_type != FE_TET4 || !problem || problem->kind != FE_SCALAR_CDR)
+        return fail(FE_ERR_UNSUPPORTED, "node blocks are built for scalar problems on tetrahedra");
+    if (n_elem > 0 && (!nodes || n_nodes < 1 || n_nodes > 0x7fffffffLL))
+        return fail(FE_ERR_INVALID_ARG, "need a node array with 1 .. 2^31-1 nodes");
+    if (n_elem > 0x7fffffffLL / 4)
+        return fail(FE_ERR_INVALID_ARG, "element * vertex codes must fit in int32");
+    if (n_blocks < 0 || n_blocks > 0x7fffffffLL || (n_elem > 0 && n_blocks < 1))
+        return fail(FE_ERR_INVALID_ARG, "n_blocks out of range");
+    if (n_elem > 0 && (!row_ptr || !col_idx || !values || !inc_ptr || !blk || !elems || !verts ||
+                       !lconn || !linc))
+        return fail(FE_ERR_INVALID_ARG,
+                    "row_ptr, col_idx, values, inc_ptr and the node block arrays must not be NULL");
+    if (nnz < 0 || nnz > 0x7fffffffffffLL)
+        return fail(FE_ERR_INVALID_ARG, "nnz out of range");
+    if (!aligned(nodes, 8) || !aligned(row_ptr, 8) || !aligned(col_idx, 4) ||
+        !aligned(inc_ptr, 8) || !aligned(blk, 8) || !aligned(elems, 4) || !aligned(verts, 4) ||
+        !aligned(lconn, 2) || !aligned(linc, 2))
+        return fail(FE_ERR_UNSUPPORTED, "pointers must be aligned to their element size");
+    const fe_variant base{256, 1, 2, 1, 0, 1, 1};
+    Plan pl;
+    int st = plan(problem, elem_type, n_elem, nullptr, coeffs, ld_in, quad_rule, nullptr, nullptr,
+                  n_elem, &base, pl, 3, nullptr, 0);
+    if (st)
+        return st;
+    if (!pl.entry->apply)
+        return fail(FE_ERR_UNSUPPORTED, "no assembly form for this problem");
+    const size_t tsz = problem->precision == FE_FP64 ? 8 : 4;
+    if (!aligned(values, tsz) || !aligned(b, tsz))
+        return fail(FE_ERR_UNSUPPORTED, "values and b must be aligned to their element size");
+    if (n_elem == 0)
+        return FE_OK;
+    ApplyArgs ap{};
+    ap.b = b;
+    ap.row_ptr = row_ptr;
+    ap.col_idx = col_idx;
+    ap.nnz = nnz;
+    ap.vals = values;
+    ap.inc_ptr = inc_ptr;
+    ap.n_own = n_nodes;
+    ap.blk = blk;
+    ap.blk_elems = elems;
+    ap.blk_verts = verts;
+    ap.blk_conn = lconn;
+    ap.linc = linc;
+    const IdxArgs gi{nodes, nullptr, 0, (uint32_t)n_nodes};
+    const hipError_t err =
+        pl.entry->apply(pl.args, gi, ap, 0, (unsigned)n_blocks, FE_CSR_BLOCK_NODES, stream);
+    if (err != hipSuccess)
+        return fail(FE_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(err));
+    return FE_OK;
+}
+
 int fe_integrate_natural(const fe_problem *problem, fe_elem_type elem_type, int64_t n_elem,
                          const double *coords, const void *coeffs, const fe_quad_rule *quad_rule,
                          void *out_K, void *out_F, hipStream_t stream)
@@ -836,6 +898,150 @@ int64_t fe_node_incidence(fe_elem_type elem_type, int64_t n_elem, const int32_t 
                 inc[fill[conn[v * ld_conn + e]]++] = (int32_t)(e * nv + v);
     }
     return inc_ptr[n_nodes];
+}
+
+int64_t fe_csr_blocks(fe_elem_type elem_type, int64_t n_elem, const int32_t *conn, int64_t ld_conn,
+                      int64_t n_nodes, const int64_t *inc_ptr, const int32_t *inc, int64_t *sizes,
+                      int64_t *blk, int32_t *elems, int32_t *verts, uint16_t *lconn,
+                      uint16_t *linc)
+{
+    if (elem_type != FE_TET4 && elem_type != FE_PRISM6)
+        return -fail(FE_ERR_INVALID_ARG, "bad element type %d", elem_type);
+    const int nv = n_shape(elem_type);
+    if (n_elem < 0 || n_elem > 0x7fffffffLL / nv || n_nodes < 1 || n_nodes > 0x7fffffffLL ||
+        (n_elem > 0 && (!conn || ld_conn < n_elem)) || !inc_ptr || !inc || !sizes)
+        return -fail(FE_ERR_INVALID_ARG, "bad node block arguments");
+    if (inc_ptr[0] != 0 || inc_ptr[n_nodes] != n_elem * nv)
+        return -fail(FE_ERR_INVALID_ARG, "inc_ptr does not cover n_elem * n_vert incidences");
+    for (int64_t i = 0; i < n_nodes; ++i)
+        if (inc_ptr[i + 1] < inc_ptr[i])
+            return -fail(FE_ERR_INVALID_ARG, "inc_ptr decreases at node %lld", (long long)i);
+    for (int64_t k = 0; k < n_elem * nv; ++k)
+        if (inc[k] < 0 || inc[k] >= n_elem * nv)
+            return -fail(FE_ERR_INVALID_ARG, "incidence %lld codes no element", (long long)k);
+    for (int v = 0; v < nv; ++v)
+        for (int64_t e = 0; e < n_elem; ++e)
+            if (conn[v * ld_conn + e] < 0 || conn[v * ld_conn + e] >= n_nodes)
+                return -fail(FE_ERR_INVALID_ARG, "element %lld has node id %d outside [0, %lld)",
+                             (long long)e, conn[v * ld_conn + e], (long long)n_nodes);
+    // greedy partition of the node order: a block grows node by node while
+    // its nodes, their elements and those elements' vertices fit
+    std::vector<int64_t> e_mark((size_t)n_elem, -1), v_mark((size_t)n_nodes, -1);
+    std::vector<int64_t> bounds{0};
+    int64_t n_in = 0, e_in = 0, v_in = 0, e_tot = 0, v_tot = 0, trial = 0;
+    const int64_t block_id_base = n_nodes + 1;  // marks of committed blocks
+    int64_t cur = block_id_base;
+    auto count_new = [&](int64_t i, int64_t &ne, int64_t &nvx) {
+        // elements and vertices node i adds to the current block
+        ++trial;
+        ne = nvx = 0;
+        for (int64_t k = inc_ptr[i]; k < inc_ptr[i + 1]; ++k) {
+            const int64_t e = inc[k] / nv;
+            if (e_mark[e] == cur || e_mark[e] == -2 - trial)
+                continue;
+            e_mark[e] = -2 - trial;
+            ++ne;
+            for (int v = 0; v < nv; ++v) {
+                const int32_t g = conn[v * ld_conn + e];
+                if (v_mark[g] == cur || v_mark[g] == -2 - trial)
+                    continue;
+                v_mark[g] = -2 - trial;
+                ++nvx;
+            }
+        }
+    };
+    auto commit = [&](int64_t i) {
+        for (int64_t k = inc_ptr[i]; k < inc_ptr[i + 1]; ++k) {
+            const int64_t e = inc[k] / nv;
+            e_mark[e] = cur;
+            for (int v = 0; v < nv; ++v)
+                v_mark[conn[v * ld_conn + e]] = cur;
+        }
+    };
+    for (int64_t i = 0; i < n_nodes; ++i) {
+        int64_t ne, nvx;
+        count_new(i, ne, nvx);
+        if (n_in > 0 && (n_in + 1 > FE_CSR_BLOCK_NODES || e_in + ne > FE_CSR_BLOCK_ELEMS ||
+                         v_in + nvx > FE_CSR_BLOCK_VERTS)) {
+            bounds.push_back(i);
+            e_tot += e_in;
+            v_tot += v_in;
+            n_in = e_in = v_in = 0;
+            ++cur;
+            count_new(i, ne, nvx);
+        }
+        if (ne > FE_CSR_BLOCK_ELEMS || nvx > FE_CSR_BLOCK_VERTS)
+            return -fail(FE_ERR_CAPACITY, "node %lld alone has %lld elements and %lld vertices "
+                         "(a block holds %d and %d)", (long long)i, (long long)ne, (long long)nvx,
+                         FE_CSR_BLOCK_ELEMS, FE_CSR_BLOCK_VERTS);
+        commit(i);
+        ++n_in;
+        e_in += ne;
+        v_in += nvx;
+    }
+    bounds.push_back(n_nodes);
+    e_tot += e_in;
+    v_tot += v_in;
+    const int64_t nb = (int64_t)bounds.size() - 1;
+    sizes[0] = nb;
+    sizes[1] = e_tot;
+    sizes[2] = v_tot;
+    if (!blk)
+        return nb;
+    if (!elems || !verts || !lconn || !linc)
+        return -fail(FE_ERR_INVALID_ARG, "NULL node block output");
+    // fill: per block, its elements in the order of first appearance along
+    // the nodes' incidence lists, its vertices ascending
+    std::vector<int32_t> e_loc((size_t)n_elem, -1), v_loc((size_t)n_nodes, -1);
+    std::vector<int32_t> el, vl;
+    int64_t es = 0, vs = 0;
+    for (int64_t bb = 0; bb < nb; ++bb) {
+        const int64_t n0 = bounds[bb], n1 = bounds[bb + 1];
+        el.clear();
+        vl.clear();
+        for (int64_t i = n0; i < n1; ++i)
+            for (int64_t k = inc_ptr[i]; k < inc_ptr[i + 1]; ++k) {
+                const int64_t e = inc[k] / nv;
+                if (e_loc[e] >= 0 && e_loc[e] < (int32_t)el.size() && el[e_loc[e]] == e)
+                    continue;
+                e_loc[e] = (int32_t)el.size();
+                el.push_back((int32_t)e);
+            }
+        for (int32_t e : el)
+            for (int v = 0; v < nv; ++v) {
+                const int32_t g = conn[v * ld_conn + e];
+                if (v_loc[g] == (int32_t)bb)
+                    continue;
+                v_loc[g] = (int32_t)bb;
+                vl.push_back(g);
+            }
+        std::sort(vl.begin(), vl.end());
+        for (size_t j = 0; j < vl.size(); ++j)
+            v_loc[vl[j]] = (int32_t)j;
+        blk[3 * bb + 0] = n0;
+        blk[3 * bb + 1] = es;
+        blk[3 * bb + 2] = vs;
+        for (size_t j = 0; j < el.size(); ++j) {
+            elems[es + j] = el[j];
+            for (int v = 0; v < nv; ++v)
+                lconn[(es + (int64_t)j) * nv + v] = (uint16_t)v_loc[conn[v * ld_conn + el[j]]];
+        }
+        for (size_t j = 0; j < vl.size(); ++j)
+            verts[vs + j] = vl[j];
+        for (int64_t i = n0; i < n1; ++i)
+            for (int64_t k = inc_ptr[i]; k < inc_ptr[i + 1]; ++k)
+                linc[k] = (uint16_t)(e_loc[inc[k] / nv] * nv + inc[k] % nv);
+        // vertex marks of the next block must not match this block's
+        // local indices: reset the ones used here
+        for (int32_t g : vl)
+            v_loc[g] = -1;
+        es += (int64_t)el.size();
+        vs += (int64_t)vl.size();
+    }
+    blk[3 * nb + 0] = n_nodes;
+    blk[3 * nb + 1] = es;
+    blk[3 * nb + 2] = vs;
+    return nb;
 }
 
 int64_t fe_csr_pattern(fe_elem_type elem_type, int64_t n_elem, const int32_t *conn,

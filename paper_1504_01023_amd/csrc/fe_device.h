@@ -2597,6 +2597,13 @@ __global__ __launch_bounds__(256) void fe_csr_kernel(KArgs a, IdxArgs gi, ApplyA
     }
 }
 
+// A vertex staged in LDS for row ownership over node blocks: coordinates
+// and global id, 32 bytes (two 16-byte reads).
+struct LdsVertex {
+    double x, y, z;
+    int32_t gid, pad;
+};
+
 // Assembly into a CSR matrix by row ownership (one node per lane, no
 // colours and no atomics): node i's lane loads the node columns of its
 // rows (the first RC in registers), then for each element at the node
@@ -2610,8 +2617,11 @@ __global__ __launch_bounds__(256) void fe_csr_kernel(KArgs a, IdxArgs gi, ApplyA
 // (x + (-0) is x for every x), the same additions in the same order as a
 // read-add-write. Entries beyond the first RC, and the rows of prisms
 // (whose element arithmetic already fills the registers), are added
-// through memory.
-template <class P, int NV, int NC, typename T, int NT, int REF, bool WITH_B>
+// through memory. BLK (scalar tets): one workgroup per node block, whose
+// elements and their vertices are read from HBM once into LDS; the lanes
+// then walk the same incidence lists in the same order against LDS, so the
+// values are those of the plain form bit for bit.
+template <class P, int NV, int NC, typename T, int NT, int REF, bool WITH_B, bool BLK = false>
 __global__ __launch_bounds__(256) void fe_csr_rows_kernel(KArgs a, IdxArgs gi, ApplyArgs ap)
 {
     __shared__ RefLds lds_ref[1];
@@ -2621,14 +2631,56 @@ __global__ __launch_bounds__(256) void fe_csr_rows_kernel(KArgs a, IdxArgs gi, A
     constexpr int N = NV * NC;
     constexpr int RC = 32;  // node columns of a row held in registers
     constexpr bool REG_ROW = NC == 1 && NV == 4;
+    static_assert(!BLK || REG_ROW, "node blocks are built for scalar tetrahedra");
     const int64_t nnz = ap.nnz;
     T *vals = static_cast<T *>(ap.vals);
     T *b = static_cast<T *>(ap.b);
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    // scalar tets: workgroup b takes the nodes of logical workgroup
-    // xcd_block(b) (one contiguous range of nodes per XCD, see xcd_block)
-    const int64_t blk = REG_ROW ? xcd_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
-    for (int64_t i = blk * blockDim.x + threadIdx.x; i < ap.n_own; i += stride) {
+    // BLK: the workgroup's node block; its elements (block-local vertex
+    // indices, global id) and their vertices (coordinates, global id) are
+    // staged in LDS once, and every element at a node is read from there
+    constexpr int BV = BLK ? FE_CSR_BLOCK_VERTS : 1;
+    constexpr int BE = BLK ? FE_CSR_BLOCK_ELEMS : 1;
+    __shared__ LdsVertex lvx[BV];
+    __shared__ uint16_t lcn[BE * NV];
+    __shared__ int32_t lel[BE];
+    int32_t n_ve = 0, n_el = 0;
+    int64_t first, last, step;
+    if constexpr (BLK) {
+        // workgroup b takes block xcd_block(b): one contiguous range of
+        // blocks per XCD
+        const int64_t *bp = ap.blk + 3 * xcd_block(blockIdx.x, gridDim.x);
+        const int64_t n0 = bp[0], n1 = bp[3];
+        const int64_t es = bp[1], ve = bp[2];
+        // counts clamped to the LDS arrays: never a fault
+        const int64_t ne = bp[4] - es, nvx = bp[5] - ve;
+        n_el = (int32_t)(ne < 0 ? 0 : (ne > BE ? BE : ne));
+        n_ve = (int32_t)(nvx < 0 ? 0 : (nvx > BV ? BV : nvx));
+        for (int j = threadIdx.x; j < n_ve; j += blockDim.x) {
+            uint32_t g = (uint32_t)ap.blk_verts[ve + j];
+            g = g < gi.n_nodes ? g : gi.n_nodes - 1;
+            const double *pn = gi.nodes + 3 * (int64_t)g;
+            lvx[j] = LdsVertex{pn[0], pn[1], pn[2], (int32_t)g, 0};
+        }
+        for (int j = threadIdx.x; j < n_el * NV; j += blockDim.x) {
+            const uint16_t l = ap.blk_conn[es * NV + j];
+            lcn[j] = l < n_ve ? l : 0;
+        }
+        for (int j = threadIdx.x; j < n_el; j += blockDim.x)
+            lel[j] = ap.blk_elems[es + j];
+        __syncthreads();
+        first = n0 + threadIdx.x;
+        last = n1 < n0 + (int64_t)blockDim.x ? n1 : n0 + (int64_t)blockDim.x;
+        last = last < ap.n_own ? last : ap.n_own;
+        step = blockDim.x;  // one node per lane
+    } else {
+        // scalar tets: workgroup b takes the nodes of logical workgroup
+        // xcd_block(b) (one contiguous range of nodes per XCD, see xcd_block)
+        const int64_t blk = REG_ROW ? xcd_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+        first = blk * blockDim.x + threadIdx.x;
+        last = ap.n_own;
+        step = (int64_t)gridDim.x * blockDim.x;
+    }
+    for (int64_t i = first; i < last; i += step) {
         // row bounds clamped into [0, nnz]: never a fault
         int64_t r0 = ap.row_ptr[NC * i], r1 = ap.row_ptr[NC * i + 1];
         r0 = r0 < 0 ? 0 : (r0 > nnz ? nnz : r0);
@@ -2653,31 +2705,56 @@ __global__ __launch_bounds__(256) void fe_csr_rows_kernel(KArgs a, IdxArgs gi, A
         // k + 2 and the vertex ids of element k + 1 are loaded while
         // element k is processed
         auto code_at = [&](int64_t k) -> uint32_t {
+            if constexpr (BLK)
+                return k < k1 ? (uint32_t)ap.linc[k] : 0u;
             return k < k1 ? (uint32_t)ap.inc[k] : 0u;
         };
-        auto ids_of = [&](uint32_t code, uint32_t (&id)[NV]) {
-            const int64_t e = code / NV < a.n_elem ? code / NV : 0;
+        // global ids (for the columns) and, over blocks, block-local indices
+        // (for the staged coordinates) of the element's vertices
+        auto ids_of = [&](uint32_t code, uint32_t (&id)[NV], uint32_t (&lid)[NV]) {
+            if constexpr (BLK) {
+                const uint32_t sl = code / NV < (uint32_t)n_el ? code / NV : 0;
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                const uint32_t u = (uint32_t)ld1<NT>(gi.conn + v * gi.ld_conn + e);
-                id[v] = u < gi.n_nodes ? u : gi.n_nodes - 1;  // clamped: never a fault
+                for (int v = 0; v < NV; ++v) {
+                    lid[v] = lcn[sl * NV + v];
+                    id[v] = (uint32_t)lvx[lid[v]].gid;
+                }
+            } else {
+                const int64_t e = code / NV < a.n_elem ? code / NV : 0;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    const uint32_t u = (uint32_t)ld1<NT>(gi.conn + v * gi.ld_conn + e);
+                    id[v] = u < gi.n_nodes ? u : gi.n_nodes - 1;  // clamped: never a fault
+                    lid[v] = 0;
+                }
             }
         };
         uint32_t c_cur = code_at(k0), c_next = code_at(k0 + 1);
-        uint32_t id_cur[NV];
-        ids_of(c_cur, id_cur);
+        uint32_t id_cur[NV], lid_cur[NV];
+        ids_of(c_cur, id_cur, lid_cur);
         for (int64_t k = k0; k < k1; ++k) {
             const uint32_t code = c_cur;
-            uint32_t id[NV];
+            uint32_t id[NV], lid[NV];
 #pragma unroll
-            for (int v = 0; v < NV; ++v)
+            for (int v = 0; v < NV; ++v) {
                 id[v] = id_cur[v];
+                lid[v] = lid_cur[v];
+            }
             const uint32_t c_after = code_at(k + 2);
             if (k + 1 < k1)
-                ids_of(c_next, id_cur);
+                ids_of(c_next, id_cur, lid_cur);
             c_cur = c_next;
             c_next = c_after;
-            const int64_t e = code / NV;
+            int64_t e;
+            if constexpr (BLK) {
+                if (code / NV >= (uint32_t)n_el)
+                    continue;
+                e = lel[code / NV];
+                if (e < 0)
+                    continue;
+            } else {
+                e = code / NV;
+            }
             if (e >= a.n_elem)
                 continue;
             RowBlock<T, NV, NC> bl;
@@ -2694,10 +2771,17 @@ __global__ __launch_bounds__(256) void fe_csr_rows_kernel(KArgs a, IdxArgs gi, A
             double X[3 * NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                const double *pn = gi.nodes + 3 * (int64_t)id[v];
-                X[3 * v + 0] = pn[0];
-                X[3 * v + 1] = pn[1];
-                X[3 * v + 2] = pn[2];
+                if constexpr (BLK) {
+                    const LdsVertex &w = lvx[lid[v]];
+                    X[3 * v + 0] = w.x;
+                    X[3 * v + 1] = w.y;
+                    X[3 * v + 2] = w.z;
+                } else {
+                    const double *pn = gi.nodes + 3 * (int64_t)id[v];
+                    X[3 * v + 0] = pn[0];
+                    X[3 * v + 1] = pn[1];
+                    X[3 * v + 2] = pn[2];
+                }
             }
             if constexpr (REG_ROW) {
                 P::template apply_x<NT, REF>(a, st, ref, X, e, bl);
@@ -2808,6 +2892,17 @@ template <class P, int NV, int NC, typename T, int NT, int REF>
 hipError_t launch_fe_apply(const KArgs &a, const IdxArgs &gi, const ApplyArgs &ap, int atomic,
                      unsigned grid, unsigned block, hipStream_t stream)
 {
+    if (ap.vals && ap.blk) {
+        if constexpr (NV == 4 && NC == 1) {
+            if (ap.b)
+                return launch_kernel(&fe_csr_rows_kernel<P, NV, NC, T, NT, REF, true, true>,
+                                     dim3(grid), dim3(block), 0, stream, a, gi, ap);
+            else
+                return launch_kernel(&fe_csr_rows_kernel<P, NV, NC, T, NT, REF, false, true>,
+                                     dim3(grid), dim3(block), 0, stream, a, gi, ap);
+        }
+        return hipErrorInvalidValue;
+    }
     if (ap.vals && ap.inc) {
         if (ap.b)
             return launch_kernel(&fe_csr_rows_kernel<P, NV, NC, T, NT, REF, true>, dim3(grid),

@@ -116,6 +116,10 @@ def lib():
         L.fe_node_incidence.restype = i64
         L.fe_assemble_csr_rows.argtypes = [P, i32, i64, vp, i64, vp, i64, vp, i64, R, vp, vp, i64,
                                            vp, vp, vp, vp, vp]
+        L.fe_csr_blocks.argtypes = [i32, i64, vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.fe_csr_blocks.restype = i64
+        L.fe_assemble_csr_blocks.argtypes = [P, i32, i64, vp, i64, vp, i64, R, vp, vp, i64, vp,
+                                             vp, vp, i64, vp, vp, vp, vp, vp, vp]
         L.fe_ld_for.argtypes = [i64]
         L.fe_ld_for.restype = i64
         L.fe_tuning_builtin.argtypes = [ctypes.c_char_p, i32, ctypes.POINTER(ctypes.c_int)]
@@ -539,6 +543,117 @@ def assemble_csr_rows(p: Problem, elem, nodes, conn, coeffs, rule: Rule, row_ptr
         raise ValueError("inc must be a contiguous int32 GPU vector")
     _check(lib().fe_assemble_csr_rows(*head, ctypes.c_void_p(inc_ptr.data_ptr()),
                                       ctypes.c_void_p(inc.data_ptr()), _stream_handle(stream)))
+    return values, b
+
+
+@dataclass
+class CsrBlocks:
+    """Node blocks for assemble_csr_blocks (fe_csr_blocks): numpy arrays on
+    the host, or device tensors after .to(device) (lconn and linc then hold
+    their uint16 codes as int16 bits)."""
+    n_blocks: int
+    blk: object     # int64, 3 * (n_blocks + 1)
+    elems: object   # int32, element slots
+    verts: object   # int32, vertex slots
+    lconn: object   # uint16, element slots * n_vert
+    linc: object    # uint16, n_elem * n_vert
+
+    def to(self, device):
+        import torch
+
+        def dev(a):
+            a = np.ascontiguousarray(a)
+            if a.dtype == np.uint16:
+                a = a.view(np.int16)
+            return torch.from_numpy(a).to(device)
+        return CsrBlocks(self.n_blocks, dev(self.blk), dev(self.elems), dev(self.verts),
+                         dev(self.lconn), dev(self.linc))
+
+
+def csr_blocks(elem, conn, n_nodes: int, inc_ptr, inc) -> CsrBlocks:
+    """Node blocks built on the host from conn ((n_elem, n_vert) node ids)
+    and node_incidence's (inc_ptr, inc): consecutive nodes whose elements
+    and vertices fit one workgroup's LDS (FE_CSR_BLOCK_* limits)."""
+    e = ELEM.get(elem, elem)
+    c = np.ascontiguousarray(np.asarray(conn).T.astype(np.int32))
+    nv, n = c.shape
+    ip = np.ascontiguousarray(inc_ptr, dtype=np.int64)
+    ic = np.ascontiguousarray(inc, dtype=np.int32)
+    if ip.shape[0] != int(n_nodes) + 1 or ic.shape[0] != n * nv:
+        raise ValueError("inc_ptr / inc do not match conn and n_nodes")
+    vp = ctypes.c_void_p
+    sizes = np.zeros(3, dtype=np.int64)
+    args = (e, n, c.ctypes.data_as(vp), n, int(n_nodes), ip.ctypes.data_as(vp),
+            ic.ctypes.data_as(vp), sizes.ctypes.data_as(vp))
+    got = lib().fe_csr_blocks(*args, None, None, None, None, None)
+    if got < 0:
+        _check(-got)
+    nb, ne, nvx = (int(x) for x in sizes)
+    blk = np.empty(3 * (nb + 1), dtype=np.int64)
+    elems = np.empty(max(ne, 1), dtype=np.int32)
+    verts = np.empty(max(nvx, 1), dtype=np.int32)
+    lconn = np.empty(max(ne * nv, 1), dtype=np.uint16)
+    linc = np.empty(max(n * nv, 1), dtype=np.uint16)
+    got = lib().fe_csr_blocks(*args, blk.ctypes.data_as(vp), elems.ctypes.data_as(vp),
+                              verts.ctypes.data_as(vp), lconn.ctypes.data_as(vp),
+                              linc.ctypes.data_as(vp))
+    if got < 0:
+        _check(-got)
+    return CsrBlocks(nb, blk, elems[:ne], verts[:nvx], lconn[:ne * nv], linc[:n * nv])
+
+
+def assemble_csr_blocks(p: Problem, elem, nodes, coeffs, rule: Rule, row_ptr, col_idx, inc_ptr,
+                        blocks: CsrBlocks, values=None, b=None, stream=None,
+                        with_b: bool = False):
+    """The row-ownership assembly over node blocks (blocks: device
+    CsrBlocks, inc_ptr the device copy of node_incidence's inc_ptr): each
+    workgroup stages its block's elements and vertices in LDS once. Values
+    and b equal assemble_csr_rows' bit for bit. Returns (values, b)."""
+    import torch
+    e = ELEM.get(elem, elem)
+    nv = 4 if e == TET4 else 6
+    dt = _dtype(p)
+    n = blocks.linc.numel() // nv
+    ndof = nodes.shape[0]
+    if not (nodes.is_cuda and nodes.dtype == torch.float64 and nodes.is_contiguous()
+            and nodes.dim() == 2 and nodes.shape[1] == 3):
+        raise ValueError("nodes must be a contiguous (n_nodes, 3) float64 GPU tensor")
+    if not (row_ptr.is_cuda and row_ptr.dtype == torch.int64 and row_ptr.is_contiguous()
+            and row_ptr.numel() == ndof + 1):
+        raise ValueError(f"row_ptr must be a contiguous int64 GPU vector of {ndof + 1} values")
+    if not (col_idx.is_cuda and col_idx.dtype == torch.int32 and col_idx.is_contiguous()):
+        raise ValueError("col_idx must be a contiguous int32 GPU vector")
+    if not (inc_ptr.is_cuda and inc_ptr.dtype == torch.int64 and inc_ptr.is_contiguous()
+            and inc_ptr.numel() == ndof + 1):
+        raise ValueError("inc_ptr must be a contiguous int64 GPU vector of n_nodes + 1 values")
+    for name, t, want in (("blk", blocks.blk, torch.int64), ("elems", blocks.elems, torch.int32),
+                          ("verts", blocks.verts, torch.int32), ("lconn", blocks.lconn, torch.int16),
+                          ("linc", blocks.linc, torch.int16)):
+        if not (t.is_cuda and t.dtype == want and t.is_contiguous()):
+            raise ValueError(f"blocks.{name} must be a contiguous {want} GPU tensor")
+    if blocks.blk.numel() != 3 * (blocks.n_blocks + 1):
+        raise ValueError("blocks.blk must hold 3 * (n_blocks + 1) values")
+    nnz = col_idx.numel()
+    if values is None:
+        values = torch.zeros(nnz, dtype=dt, device=nodes.device)
+    if b is None and with_b:
+        b = torch.zeros(ndof, dtype=dt, device=nodes.device)
+    for name, t, size in (("values", values, nnz), ("b", b, ndof)):
+        if t is not None and not (t.is_cuda and t.dtype == dt and t.is_contiguous()
+                                  and t.numel() == size):
+            raise ValueError(f"{name} must be a contiguous {dt} GPU vector of {size} values")
+    nc = coeff_entries(p, e, rule.n_q)
+    ld_in = _ld(coeffs, "coeffs") if (coeffs is not None and nc > 0 and coeffs.dim() == 2) else n
+    if nc > 0:
+        _check_coeffs(p, coeffs, dt, nc, ld_in)
+    cptr = ctypes.c_void_p(coeffs.data_ptr()) if (coeffs is not None and nc > 0) else None
+    vp = ctypes.c_void_p
+    _check(lib().fe_assemble_csr_blocks(
+        ctypes.byref(p), e, n, vp(nodes.data_ptr()), ndof, cptr, ld_in, ctypes.byref(rule.c),
+        vp(row_ptr.data_ptr()), vp(col_idx.data_ptr()), nnz, vp(values.data_ptr()),
+        vp(b.data_ptr()) if b is not None else None, vp(inc_ptr.data_ptr()), blocks.n_blocks,
+        vp(blocks.blk.data_ptr()), vp(blocks.elems.data_ptr()), vp(blocks.verts.data_ptr()),
+        vp(blocks.lconn.data_ptr()), vp(blocks.linc.data_ptr()), _stream_handle(stream)))
     return values, b
 
 

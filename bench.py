@@ -707,7 +707,7 @@ def run_apply(a, torch, fe, oracle, base: str, dev, csr: bool = False) -> dict:
         bld = None
         if wl.elem == "tet4" and wl.kind == "scalar":
             t0 = time.time()
-            blocks = fe.csr_blocks(wl.elem, conn_np[perm], n_nodes, ip, inc)
+            blocks = fe.csr_blocks(wl.elem, conn_np[perm], n_nodes, ip, inc, rp, ci)
             bld = blocks.to(dev)
             log(f"[bench] node blocks: {blocks.n_blocks}, element slots "
                 f"{len(blocks.elems) / n:.2f} per element ({time.time() - t0:.1f}s)")

@@ -150,8 +150,8 @@ typedef struct fe_problem {
  * nodes, elements at them and vertices of those elements per block (the
  * elements and vertices of a block are staged in one workgroup's LDS). */
 #define FE_CSR_BLOCK_NODES 256
-#define FE_CSR_BLOCK_ELEMS 3072
-#define FE_CSR_BLOCK_VERTS 1024
+#define FE_CSR_BLOCK_ELEMS 2432
+#define FE_CSR_BLOCK_VERTS 768
 typedef struct fe_quad_rule {
     int32_t n_q;
     const double *xi;
@@ -328,14 +328,16 @@ FE_API int64_t fe_node_incidence(fe_elem_type elem_type, int64_t n_elem, const i
 
 /* Node blocks for fe_assemble_csr_blocks, built on the host (Sec. 3.2
  * assembles at the nodes; here consecutive nodes share one workgroup, which
- * reads the elements at them once). conn is host memory as for
- * fe_color_elements; inc_ptr and inc (host) as fe_node_incidence writes them.
- * Consecutive nodes form a block while the block's nodes (at most
- * FE_CSR_BLOCK_NODES), the elements at them (at most FE_CSR_BLOCK_ELEMS) and
- * those elements' vertices (at most FE_CSR_BLOCK_VERTS) fit; a node order
- * with neighbours close together (a space-filling curve) keeps the blocks
- * full. Writes sizes[0] = n_blocks, sizes[1] = element slots, sizes[2] =
- * vertex slots (host, 3 values); when blk is not NULL also (host):
+ * reads the elements at them once). Tetrahedra, scalar patterns. conn is
+ * host memory as for fe_color_elements; inc_ptr and inc (host) as
+ * fe_node_incidence writes them; row_ptr and col_idx (host) as
+ * fe_csr_pattern writes them with n_comp = 1. Consecutive nodes form a
+ * block while the block's nodes (at most FE_CSR_BLOCK_NODES), the elements
+ * at them (at most FE_CSR_BLOCK_ELEMS) and those elements' vertices (at most
+ * FE_CSR_BLOCK_VERTS) fit; a node order with neighbours close together (a
+ * space-filling curve) keeps the blocks full. Writes sizes[0] = n_blocks,
+ * sizes[1] = element slots, sizes[2] = vertex slots (host, 3 values); when
+ * blk is not NULL also (host):
  *   blk[3 b + 0, 1, 2]  first node, first element slot, first vertex slot of
  *                       block b, for b = 0 .. n_blocks (the last triple
  *                       holds n_nodes and the two totals);
@@ -344,27 +346,37 @@ FE_API int64_t fe_node_incidence(fe_elem_type elem_type, int64_t n_elem, const i
  *                       nodes' incidence lists);
  *   verts[slot]         the global node id of a vertex slot (ascending
  *                       within a block);
- *   lconn[slot * n_vert + v]  the block-local index of vertex v of the
- *                       element in that slot;
- *   linc[k]             inc[k] recoded as block-local element slot * n_vert
- *                       + local vertex (n_elem * n_vert values).
+ *   lconn[slot * 4 + v] the block-local index of vertex v of the element in
+ *                       that slot;
+ *   linc[k]             inc[k] recoded for the node i whose list holds it:
+ *                       bits 0-13 block-local element slot * 4 + local vertex,
+ *                       bits 14-19, 20-25, 26-31 the positions in row i
+ *                       (offsets from row_ptr[i]) of the element's other
+ *                       three vertices in increasing local order, 62 where
+ *                       the pattern has no such entry, 63 past offset 61
+ *                       (n_elem * 4 values).
  * Returns n_blocks, or minus a status: FE_ERR_CAPACITY when one node's
- * elements or their vertices alone exceed a block, FE_ERR_INVALID_ARG for
- * bad arguments. Call once with blk = NULL to learn the sizes. */
+ * elements or their vertices alone exceed a block, FE_ERR_UNSUPPORTED for
+ * prisms, FE_ERR_INVALID_ARG for bad arguments. Call once with blk = NULL to
+ * learn the sizes. */
 FE_API int64_t fe_csr_blocks(fe_elem_type elem_type, int64_t n_elem, const int32_t *conn,
                              int64_t ld_conn, int64_t n_nodes, const int64_t *inc_ptr,
-                             const int32_t *inc, int64_t *sizes, int64_t *blk, int32_t *elems,
-                             int32_t *verts, uint16_t *lconn, uint16_t *linc);
+                             const int32_t *inc, const int64_t *row_ptr, const int32_t *col_idx,
+                             int64_t *sizes, int64_t *blk, int32_t *elems, int32_t *verts,
+                             uint16_t *lconn, uint32_t *linc);
 
 /* The assembly of fe_assemble_csr_rows over node blocks: one workgroup per
  * block (fe_csr_blocks; device copies of blk, elems, verts, lconn, linc and
  * of inc_ptr) first reads the block's vertices (coordinates from nodes) and
- * elements into LDS, once, then each lane adds one node's row, walking the
- * node's incidence list in the same order against LDS and computing each
- * element as fe_assemble_csr_rows does: the values and b equal that entry
- * point's bit for bit. Other arguments as for fe_assemble_csr_rows (no conn:
- * the blocks carry the connectivity). Scalar problems on tetrahedra; others
- * return FE_ERR_UNSUPPORTED. Enqueued on `stream`; no allocation. */
+ * elements into LDS, once; then each lane adds one node's row, walking the
+ * node's incidence list in the same order against LDS, computing each
+ * element as fe_assemble_csr_rows does and adding its values at the
+ * positions linc carries (the row's first entries accumulate in LDS): the
+ * values and b equal that entry point's bit for bit. row_ptr and col_idx
+ * must be the pattern the blocks were built from. Other arguments as for
+ * fe_assemble_csr_rows (no conn: the blocks carry the connectivity). Scalar
+ * problems on tetrahedra; others return FE_ERR_UNSUPPORTED. Enqueued on
+ * `stream`; no allocation. */
 FE_API int fe_assemble_csr_blocks(const fe_problem *problem, fe_elem_type elem_type,
                                   int64_t n_elem, const double *nodes, int64_t n_nodes,
                                   const void *coeffs, int64_t ld_in,
@@ -372,7 +384,7 @@ FE_API int fe_assemble_csr_blocks(const fe_problem *problem, fe_elem_type elem_t
                                   const int32_t *col_idx, int64_t nnz, void *values, void *b,
                                   const int64_t *inc_ptr, int64_t n_blocks, const int64_t *blk,
                                   const int32_t *elems, const int32_t *verts,
-                                  const uint16_t *lconn, const uint16_t *linc,
+                                  const uint16_t *lconn, const uint32_t *linc,
                                   hipStream_t stream);
 
 /* The same assembly as fe_assemble_csr by row ownership: one lane per node

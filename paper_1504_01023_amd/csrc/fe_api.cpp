@@ -697,7 +697,7 @@ int fe_assemble_csr_blocks(const fe_problem *problem, fe_elem_type elem_type, in
                            const int32_t *col_idx, int64_t nnz, void *values, void *b,
                            const int64_t *inc_ptr, int64_t n_blocks, const int64_t *blk,
                            const int32_t *elems, const int32_t *verts, const uint16_t *lconn,
-                           const uint16_t *linc, hipStream_t stream)
+                           const uint32_t *linc, hipStream_t stream)
 {
     if (elem_type != FE_TET4 || !problem || problem->kind != FE_SCALAR_CDR)
         return fail(FE_ERR_UNSUPPORTED, "node blocks are built for scalar problems on tetrahedra");
@@ -715,7 +715,7 @@ int fe_assemble_csr_blocks(const fe_problem *problem, fe_elem_type elem_type, in
         return fail(FE_ERR_INVALID_ARG, "nnz out of range");
     if (!aligned(nodes, 8) || !aligned(row_ptr, 8) || !aligned(col_idx, 4) ||
         !aligned(inc_ptr, 8) || !aligned(blk, 8) || !aligned(elems, 4) || !aligned(verts, 4) ||
-        !aligned(lconn, 2) || !aligned(linc, 2))
+        !aligned(lconn, 2) || !aligned(linc, 4))
         return fail(FE_ERR_UNSUPPORTED, "pointers must be aligned to their element size");
     const fe_variant base{256, 1, 2, 1, 0, 1, 1};
     Plan pl;
@@ -900,17 +900,26 @@ int64_t fe_node_incidence(fe_elem_type elem_type, int64_t n_elem, const int32_t 
     return inc_ptr[n_nodes];
 }
 
+static_assert(FE_CSR_BLOCK_ELEMS * 4 <= 0x4000, "element slot and vertex fit 14 bits of a code");
+
 int64_t fe_csr_blocks(fe_elem_type elem_type, int64_t n_elem, const int32_t *conn, int64_t ld_conn,
-                      int64_t n_nodes, const int64_t *inc_ptr, const int32_t *inc, int64_t *sizes,
+                      int64_t n_nodes, const int64_t *inc_ptr, const int32_t *inc,
+                      const int64_t *row_ptr, const int32_t *col_idx, int64_t *sizes,
                       int64_t *blk, int32_t *elems, int32_t *verts, uint16_t *lconn,
-                      uint16_t *linc)
+                      uint32_t *linc)
 {
-    if (elem_type != FE_TET4 && elem_type != FE_PRISM6)
+    if (elem_type == FE_PRISM6)
+        return -fail(FE_ERR_UNSUPPORTED, "node blocks are built for tetrahedra");
+    if (elem_type != FE_TET4)
         return -fail(FE_ERR_INVALID_ARG, "bad element type %d", elem_type);
-    const int nv = n_shape(elem_type);
+    const int nv = 4;
     if (n_elem < 0 || n_elem > 0x7fffffffLL / nv || n_nodes < 1 || n_nodes > 0x7fffffffLL ||
-        (n_elem > 0 && (!conn || ld_conn < n_elem)) || !inc_ptr || !inc || !sizes)
+        (n_elem > 0 && (!conn || ld_conn < n_elem)) || !inc_ptr || !inc || !row_ptr ||
+        !col_idx || !sizes)
         return -fail(FE_ERR_INVALID_ARG, "bad node block arguments");
+    for (int64_t i = 0; i < n_nodes; ++i)
+        if (row_ptr[i + 1] < row_ptr[i] || row_ptr[i] < 0)
+            return -fail(FE_ERR_INVALID_ARG, "row_ptr decreases at row %lld", (long long)i);
     if (inc_ptr[0] != 0 || inc_ptr[n_nodes] != n_elem * nv)
         return -fail(FE_ERR_INVALID_ARG, "inc_ptr does not cover n_elem * n_vert incidences");
     for (int64_t i = 0; i < n_nodes; ++i)
@@ -1028,9 +1037,28 @@ int64_t fe_csr_blocks(fe_elem_type elem_type, int64_t n_elem, const int32_t *con
         }
         for (size_t j = 0; j < vl.size(); ++j)
             verts[vs + j] = vl[j];
-        for (int64_t i = n0; i < n1; ++i)
-            for (int64_t k = inc_ptr[i]; k < inc_ptr[i + 1]; ++k)
-                linc[k] = (uint16_t)(e_loc[inc[k] / nv] * nv + inc[k] % nv);
+        for (int64_t i = n0; i < n1; ++i) {
+            const int32_t *cb = col_idx + row_ptr[i], *ce = col_idx + row_ptr[i + 1];
+            for (int64_t k = inc_ptr[i]; k < inc_ptr[i + 1]; ++k) {
+                const int64_t e = inc[k] / nv;
+                const int lv = (int)(inc[k] % nv);
+                uint32_t code = (uint32_t)(e_loc[e] * nv + lv);
+                int f = 0;
+                for (int u = 0; u < nv; ++u) {
+                    if (u == lv)
+                        continue;
+                    // position of vertex u's column in row i (ascending
+                    // columns): 62 absent, 63 past offset 61
+                    const int32_t g = conn[u * ld_conn + e];
+                    const int32_t *at = std::lower_bound(cb, ce, g);
+                    const int64_t pos = at - cb;
+                    const uint32_t field = (at == ce || *at != g) ? 62u : (pos < 62 ? (uint32_t)pos : 63u);
+                    code |= field << (14 + 6 * f);
+                    ++f;
+                }
+                linc[k] = code;
+            }
+        }
         // vertex marks of the next block must not match this block's
         // local indices: reset the ones used here
         for (int32_t g : vl)

@@ -754,6 +754,8 @@ struct TetScalar {
     static constexpr bool DIFF = TERMS & T_DIFF, CA = TERMS & T_CONVA, CB = TERMS & T_CONVB,
                           MASS = TERMS & T_MASS, DG = TERMS & T_DGRAD, D0 = TERMS & T_D0;
     static constexpr bool PER_QP = (MODE == M_QP || MODE == M_QP_MIXED || MODE == M_FUNC);
+    // coefficients read from memory by element id
+    static constexpr bool ELEM_COEFS = MODE != M_UNIFORM && MODE != M_FUNC;
 
     template <int V, int NT, int REF, class S>
     __device__ __forceinline__ static void run(const KArgs &a, const S &st, const Ref<REF> &ref,
@@ -2597,13 +2599,6 @@ __global__ __launch_bounds__(256) void fe_csr_kernel(KArgs a, IdxArgs gi, ApplyA
     }
 }
 
-// A vertex staged in LDS for row ownership over node blocks: coordinates
-// and global id, 32 bytes (two 16-byte reads).
-struct LdsVertex {
-    double x, y, z;
-    int32_t gid, pad;
-};
-
 // Assembly into a CSR matrix by row ownership (one node per lane, no
 // colours and no atomics): node i's lane loads the node columns of its
 // rows (the first RC in registers), then for each element at the node
@@ -2617,11 +2612,8 @@ struct LdsVertex {
 // (x + (-0) is x for every x), the same additions in the same order as a
 // read-add-write. Entries beyond the first RC, and the rows of prisms
 // (whose element arithmetic already fills the registers), are added
-// through memory. BLK (scalar tets): one workgroup per node block, whose
-// elements and their vertices are read from HBM once into LDS; the lanes
-// then walk the same incidence lists in the same order against LDS, so the
-// values are those of the plain form bit for bit.
-template <class P, int NV, int NC, typename T, int NT, int REF, bool WITH_B, bool BLK = false>
+// through memory.
+template <class P, int NV, int NC, typename T, int NT, int REF, bool WITH_B>
 __global__ __launch_bounds__(256) void fe_csr_rows_kernel(KArgs a, IdxArgs gi, ApplyArgs ap)
 {
     __shared__ RefLds lds_ref[1];
@@ -2631,56 +2623,14 @@ __global__ __launch_bounds__(256) void fe_csr_rows_kernel(KArgs a, IdxArgs gi, A
     constexpr int N = NV * NC;
     constexpr int RC = 32;  // node columns of a row held in registers
     constexpr bool REG_ROW = NC == 1 && NV == 4;
-    static_assert(!BLK || REG_ROW, "node blocks are built for scalar tetrahedra");
     const int64_t nnz = ap.nnz;
     T *vals = static_cast<T *>(ap.vals);
     T *b = static_cast<T *>(ap.b);
-    // BLK: the workgroup's node block; its elements (block-local vertex
-    // indices, global id) and their vertices (coordinates, global id) are
-    // staged in LDS once, and every element at a node is read from there
-    constexpr int BV = BLK ? FE_CSR_BLOCK_VERTS : 1;
-    constexpr int BE = BLK ? FE_CSR_BLOCK_ELEMS : 1;
-    __shared__ LdsVertex lvx[BV];
-    __shared__ uint16_t lcn[BE * NV];
-    __shared__ int32_t lel[BE];
-    int32_t n_ve = 0, n_el = 0;
-    int64_t first, last, step;
-    if constexpr (BLK) {
-        // workgroup b takes block xcd_block(b): one contiguous range of
-        // blocks per XCD
-        const int64_t *bp = ap.blk + 3 * xcd_block(blockIdx.x, gridDim.x);
-        const int64_t n0 = bp[0], n1 = bp[3];
-        const int64_t es = bp[1], ve = bp[2];
-        // counts clamped to the LDS arrays: never a fault
-        const int64_t ne = bp[4] - es, nvx = bp[5] - ve;
-        n_el = (int32_t)(ne < 0 ? 0 : (ne > BE ? BE : ne));
-        n_ve = (int32_t)(nvx < 0 ? 0 : (nvx > BV ? BV : nvx));
-        for (int j = threadIdx.x; j < n_ve; j += blockDim.x) {
-            uint32_t g = (uint32_t)ap.blk_verts[ve + j];
-            g = g < gi.n_nodes ? g : gi.n_nodes - 1;
-            const double *pn = gi.nodes + 3 * (int64_t)g;
-            lvx[j] = LdsVertex{pn[0], pn[1], pn[2], (int32_t)g, 0};
-        }
-        for (int j = threadIdx.x; j < n_el * NV; j += blockDim.x) {
-            const uint16_t l = ap.blk_conn[es * NV + j];
-            lcn[j] = l < n_ve ? l : 0;
-        }
-        for (int j = threadIdx.x; j < n_el; j += blockDim.x)
-            lel[j] = ap.blk_elems[es + j];
-        __syncthreads();
-        first = n0 + threadIdx.x;
-        last = n1 < n0 + (int64_t)blockDim.x ? n1 : n0 + (int64_t)blockDim.x;
-        last = last < ap.n_own ? last : ap.n_own;
-        step = blockDim.x;  // one node per lane
-    } else {
-        // scalar tets: workgroup b takes the nodes of logical workgroup
-        // xcd_block(b) (one contiguous range of nodes per XCD, see xcd_block)
-        const int64_t blk = REG_ROW ? xcd_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
-        first = blk * blockDim.x + threadIdx.x;
-        last = ap.n_own;
-        step = (int64_t)gridDim.x * blockDim.x;
-    }
-    for (int64_t i = first; i < last; i += step) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // scalar tets: workgroup b takes the nodes of logical workgroup
+    // xcd_block(b) (one contiguous range of nodes per XCD, see xcd_block)
+    const int64_t blk = REG_ROW ? xcd_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+    for (int64_t i = blk * blockDim.x + threadIdx.x; i < ap.n_own; i += stride) {
         // row bounds clamped into [0, nnz]: never a fault
         int64_t r0 = ap.row_ptr[NC * i], r1 = ap.row_ptr[NC * i + 1];
         r0 = r0 < 0 ? 0 : (r0 > nnz ? nnz : r0);
@@ -2705,56 +2655,31 @@ __global__ __launch_bounds__(256) void fe_csr_rows_kernel(KArgs a, IdxArgs gi, A
         // k + 2 and the vertex ids of element k + 1 are loaded while
         // element k is processed
         auto code_at = [&](int64_t k) -> uint32_t {
-            if constexpr (BLK)
-                return k < k1 ? (uint32_t)ap.linc[k] : 0u;
             return k < k1 ? (uint32_t)ap.inc[k] : 0u;
         };
-        // global ids (for the columns) and, over blocks, block-local indices
-        // (for the staged coordinates) of the element's vertices
-        auto ids_of = [&](uint32_t code, uint32_t (&id)[NV], uint32_t (&lid)[NV]) {
-            if constexpr (BLK) {
-                const uint32_t sl = code / NV < (uint32_t)n_el ? code / NV : 0;
+        auto ids_of = [&](uint32_t code, uint32_t (&id)[NV]) {
+            const int64_t e = code / NV < a.n_elem ? code / NV : 0;
 #pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    lid[v] = lcn[sl * NV + v];
-                    id[v] = (uint32_t)lvx[lid[v]].gid;
-                }
-            } else {
-                const int64_t e = code / NV < a.n_elem ? code / NV : 0;
-#pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    const uint32_t u = (uint32_t)ld1<NT>(gi.conn + v * gi.ld_conn + e);
-                    id[v] = u < gi.n_nodes ? u : gi.n_nodes - 1;  // clamped: never a fault
-                    lid[v] = 0;
-                }
+            for (int v = 0; v < NV; ++v) {
+                const uint32_t u = (uint32_t)ld1<NT>(gi.conn + v * gi.ld_conn + e);
+                id[v] = u < gi.n_nodes ? u : gi.n_nodes - 1;  // clamped: never a fault
             }
         };
         uint32_t c_cur = code_at(k0), c_next = code_at(k0 + 1);
-        uint32_t id_cur[NV], lid_cur[NV];
-        ids_of(c_cur, id_cur, lid_cur);
+        uint32_t id_cur[NV];
+        ids_of(c_cur, id_cur);
         for (int64_t k = k0; k < k1; ++k) {
             const uint32_t code = c_cur;
-            uint32_t id[NV], lid[NV];
+            uint32_t id[NV];
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
+            for (int v = 0; v < NV; ++v)
                 id[v] = id_cur[v];
-                lid[v] = lid_cur[v];
-            }
             const uint32_t c_after = code_at(k + 2);
             if (k + 1 < k1)
-                ids_of(c_next, id_cur, lid_cur);
+                ids_of(c_next, id_cur);
             c_cur = c_next;
             c_next = c_after;
-            int64_t e;
-            if constexpr (BLK) {
-                if (code / NV >= (uint32_t)n_el)
-                    continue;
-                e = lel[code / NV];
-                if (e < 0)
-                    continue;
-            } else {
-                e = code / NV;
-            }
+            const int64_t e = code / NV;
             if (e >= a.n_elem)
                 continue;
             RowBlock<T, NV, NC> bl;
@@ -2771,17 +2696,10 @@ __global__ __launch_bounds__(256) void fe_csr_rows_kernel(KArgs a, IdxArgs gi, A
             double X[3 * NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                if constexpr (BLK) {
-                    const LdsVertex &w = lvx[lid[v]];
-                    X[3 * v + 0] = w.x;
-                    X[3 * v + 1] = w.y;
-                    X[3 * v + 2] = w.z;
-                } else {
-                    const double *pn = gi.nodes + 3 * (int64_t)id[v];
-                    X[3 * v + 0] = pn[0];
-                    X[3 * v + 1] = pn[1];
-                    X[3 * v + 2] = pn[2];
-                }
+                const double *pn = gi.nodes + 3 * (int64_t)id[v];
+                X[3 * v + 0] = pn[0];
+                X[3 * v + 1] = pn[1];
+                X[3 * v + 2] = pn[2];
             }
             if constexpr (REG_ROW) {
                 P::template apply_x<NT, REF>(a, st, ref, X, e, bl);
@@ -2888,18 +2806,174 @@ __global__ __launch_bounds__(256) void fe_csr_rows_kernel(KArgs a, IdxArgs gi, A
     }
 }
 
+// Row ownership over node blocks (scalar tetrahedra): one workgroup per
+// block of consecutive nodes. The block's elements (block-local vertex
+// indices and, where coefficients are read per element, global ids) and
+// their vertices' coordinates are read from HBM into LDS once; then each
+// lane walks its node's incidence list in
+// the order fe_csr_rows_kernel walks it, computes the element's row for the
+// node (RowBlock) and adds its four values where the host-built incidence
+// codes place them: the first RL entries of the node's row accumulate in
+// LDS (starting from their stored values, written back once), entries past
+// them through memory. Every entry receives the same additions in the same
+// order as in fe_csr_rows_kernel, so the values are the same bit for bit;
+// and no lane compares columns, which is most of that kernel's arithmetic.
+// Incidence code: bits 0-13 element slot * 4 + local vertex; bits 14-19,
+// 20-25, 26-31 the row positions of the element's other three vertices in
+// increasing local order (62: no such entry in the pattern; 63: position
+// past 61, found by its column).
+template <class P, typename T, int NT, int REF, bool WITH_B>
+__global__ __launch_bounds__(FE_CSR_BLOCK_NODES) void fe_csr_blocks_kernel(KArgs a, IdxArgs gi,
+                                                                          ApplyArgs ap)
+{
+    constexpr int NV = 4;
+    constexpr int BN = FE_CSR_BLOCK_NODES, BV = FE_CSR_BLOCK_VERTS, BE = FE_CSR_BLOCK_ELEMS;
+    constexpr int RL = 16;  // row entries per node accumulated in LDS
+    constexpr bool EID = P::ELEM_COEFS;
+    __shared__ RefLds lds_ref[1];
+    __shared__ double lx[BV], ly[BV], lz[BV];
+    __shared__ uint16_t lcn[BE * NV];
+    __shared__ int32_t lel[EID ? BE : 1];
+    __shared__ T lrow[RL * BN];  // entry c of lane t's row at [c * BN + t]
+    stage_reference<REF>(a, lds_ref[0]);
+    const Ref<REF> ref{a, &lds_ref[0]};
+    const Streams st{nullptr, a.coeffs, nullptr, nullptr, a.ld_in, a.ld_out};
+    const int64_t nnz = ap.nnz;
+    T *vals = static_cast<T *>(ap.vals);
+    T *b = static_cast<T *>(ap.b);
+    // workgroup b takes block xcd_block(b): one contiguous range of blocks
+    // per XCD
+    const int64_t *bp = ap.blk + 3 * xcd_block(blockIdx.x, gridDim.x);
+    const int64_t n0 = bp[0], n1 = bp[3], es = bp[1], ve = bp[2];
+    // counts clamped to the LDS arrays: never a fault
+    const int64_t ne = bp[4] - es, nvx = bp[5] - ve;
+    const int32_t n_el = (int32_t)(ne < 0 ? 0 : (ne > BE ? BE : ne));
+    const int32_t n_ve = (int32_t)(nvx < 0 ? 0 : (nvx > BV ? BV : nvx));
+    for (int j = threadIdx.x; j < n_ve; j += blockDim.x) {
+        uint32_t g = (uint32_t)ap.blk_verts[ve + j];
+        g = g < gi.n_nodes ? g : gi.n_nodes - 1;
+        const double *pn = gi.nodes + 3 * (int64_t)g;
+        lx[j] = pn[0];
+        ly[j] = pn[1];
+        lz[j] = pn[2];
+    }
+    for (int j = threadIdx.x; j < n_el * NV; j += blockDim.x) {
+        const uint16_t l = ap.blk_conn[es * NV + j];
+        lcn[j] = l < n_ve ? l : 0;
+    }
+    if constexpr (EID) {
+        for (int j = threadIdx.x; j < n_el; j += blockDim.x)
+            lel[j] = ap.blk_elems[es + j];
+    }
+    const int t = threadIdx.x;
+    const int64_t i = n0 + t;
+    const bool own = t < BN && i < n1 && i < ap.n_own;
+    int64_t r0 = 0, len = 0;
+    int pos_self = 62;
+    if (own) {
+        // row bounds clamped into [0, nnz]: never a fault
+        r0 = ap.row_ptr[i];
+        int64_t r1 = ap.row_ptr[i + 1];
+        r0 = r0 < 0 ? 0 : (r0 > nnz ? nnz : r0);
+        r1 = r1 < r0 ? r0 : (r1 > nnz ? nnz : r1);
+        len = r1 - r0;
+        for (int64_t j = 0; j < len; ++j)
+            if (ap.col_idx[r0 + j] == (int32_t)i) {
+                pos_self = j < 62 ? (int)j : 63;
+                break;
+            }
+#pragma unroll
+        for (int c = 0; c < RL; ++c)
+            lrow[c * BN + t] = c < len ? vals[r0 + c] : T(0);
+    }
+    __syncthreads();
+    if (!own)
+        return;
+    T fb = T(0);
+    const int64_t k0 = ap.inc_ptr[i], k1 = ap.inc_ptr[i + 1];
+    auto code_at = [&](int64_t k) -> uint32_t { return k < k1 ? ap.linc[k] : 0u; };
+    // adds x to the row entry at position p (62: none; 63: found by the
+    // column of block vertex l)
+    auto add_at = [&](int p, uint32_t l, T x) {
+        if (p < RL) {
+            lrow[p * BN + t] += x;
+        } else if (p < 62) {
+            if (p < len)
+                vals[r0 + p] = vals[r0 + p] + x;
+        } else if (p == 63) {
+            const int32_t g = ap.blk_verts[ve + l];
+            for (int64_t j = 0; j < len; ++j)
+                if (ap.col_idx[r0 + j] == g)
+                    vals[r0 + j] = vals[r0 + j] + x;
+        }
+    };
+    uint32_t c_next = code_at(k0);
+    for (int64_t k = k0; k < k1; ++k) {
+        const uint32_t code = c_next;
+        c_next = code_at(k + 1);
+        const uint32_t sl = (code & 0x3fffu) / NV;
+        if (sl >= (uint32_t)n_el)
+            continue;
+        int64_t e = 0;
+        if constexpr (EID) {
+            e = lel[sl];
+            if (e < 0 || e >= a.n_elem)
+                continue;
+        }
+        const int lv = (int)(code & 3u);
+        uint32_t lid[NV];
+        double X[3 * NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            lid[v] = lcn[sl * NV + v];
+            X[3 * v + 0] = lx[lid[v]];
+            X[3 * v + 1] = ly[lid[v]];
+            X[3 * v + 2] = lz[lid[v]];
+        }
+        RowBlock<T, NV, 1> bl;
+        bl.lv = lv;
+        T kr[NV], fr[1];
+#pragma unroll
+        for (int j = 0; j < NV; ++j)
+            kr[j] = T(0);
+        fr[0] = T(0);
+        bl.kr = kr;
+        bl.fr = fr;
+        P::template apply_x<NT, REF>(a, st, ref, X, e, bl);
+        // positions of the element's vertices in the row: the node's own
+        // for lv, the code's fields for the others in increasing order
+        const int f0 = (int)((code >> 14) & 63u), f1 = (int)((code >> 20) & 63u),
+                  f2 = (int)((code >> 26) & 63u);
+#pragma unroll
+        for (int u = 0; u < NV; ++u) {
+            const int p = u == lv ? pos_self : (u < lv ? (u == 0 ? f0 : (u == 1 ? f1 : f2))
+                                                       : (u == 1 ? f0 : (u == 2 ? f1 : f2)));
+            add_at(p, lid[u], kr[u]);
+        }
+        fb += fr[0];
+    }
+#pragma unroll
+    for (int c = 0; c < RL; ++c)
+        if (c < len)
+            vals[r0 + c] = lrow[c * BN + t];
+    if constexpr (WITH_B)
+        b[i] += fb;
+}
+
 template <class P, int NV, int NC, typename T, int NT, int REF>
 hipError_t launch_fe_apply(const KArgs &a, const IdxArgs &gi, const ApplyArgs &ap, int atomic,
                      unsigned grid, unsigned block, hipStream_t stream)
 {
     if (ap.vals && ap.blk) {
         if constexpr (NV == 4 && NC == 1) {
+            if (block != FE_CSR_BLOCK_NODES)
+                return hipErrorInvalidValue;
             if (ap.b)
-                return launch_kernel(&fe_csr_rows_kernel<P, NV, NC, T, NT, REF, true, true>,
-                                     dim3(grid), dim3(block), 0, stream, a, gi, ap);
+                return launch_kernel(&fe_csr_blocks_kernel<P, T, NT, REF, true>, dim3(grid),
+                                     dim3(block), 0, stream, a, gi, ap);
             else
-                return launch_kernel(&fe_csr_rows_kernel<P, NV, NC, T, NT, REF, false, true>,
-                                     dim3(grid), dim3(block), 0, stream, a, gi, ap);
+                return launch_kernel(&fe_csr_blocks_kernel<P, T, NT, REF, false>, dim3(grid),
+                                     dim3(block), 0, stream, a, gi, ap);
         }
         return hipErrorInvalidValue;
     }

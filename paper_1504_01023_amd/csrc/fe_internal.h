@@ -186,14 +186,15 @@ struct ApplyArgs {
     // block, tetrahedra): block b owns nodes [blk[3b], blk[3b + 3]), its
     // element slots are [blk[3b + 1], blk[3b + 4]) and its vertex slots
     // [blk[3b + 2], blk[3b + 5]). blk_elems / blk_verts give a slot's global
-    // element / node id, blk_conn[slot * n_vert + v] the block-local index of
-    // the element's vertex v, and linc[k] (aligned with inc) codes the
-    // incidence inc[k] as block-local element slot * n_vert + local vertex.
+    // element / node id, blk_conn[slot * 4 + v] the block-local index of the
+    // element's vertex v, and linc[k] (aligned with inc) codes the incidence
+    // inc[k] with the row positions of the element's vertices (the code of
+    // fe_csr_blocks_kernel).
     const int64_t *blk;
     const int32_t *blk_elems;
     const int32_t *blk_verts;
     const uint16_t *blk_conn;
-    const uint16_t *linc;
+    const uint32_t *linc;
 };
 typedef hipError_t (*ApplyLaunchFn)(const KArgs &, const IdxArgs &, const ApplyArgs &, int atomic,
                               unsigned grid, unsigned block, hipStream_t);

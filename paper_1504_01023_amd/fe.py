@@ -116,7 +116,8 @@ def lib():
         L.fe_node_incidence.restype = i64
         L.fe_assemble_csr_rows.argtypes = [P, i32, i64, vp, i64, vp, i64, vp, i64, R, vp, vp, i64,
                                            vp, vp, vp, vp, vp]
-        L.fe_csr_blocks.argtypes = [i32, i64, vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.fe_csr_blocks.argtypes = [i32, i64, vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                                    vp]
         L.fe_csr_blocks.restype = i64
         L.fe_assemble_csr_blocks.argtypes = [P, i32, i64, vp, i64, vp, i64, R, vp, vp, i64, vp,
                                              vp, vp, i64, vp, vp, vp, vp, vp, vp]
@@ -550,13 +551,13 @@ def assemble_csr_rows(p: Problem, elem, nodes, conn, coeffs, rule: Rule, row_ptr
 class CsrBlocks:
     """Node blocks for assemble_csr_blocks (fe_csr_blocks): numpy arrays on
     the host, or device tensors after .to(device) (lconn and linc then hold
-    their uint16 codes as int16 bits)."""
+    their unsigned codes as int16 / int32 bits)."""
     n_blocks: int
     blk: object     # int64, 3 * (n_blocks + 1)
     elems: object   # int32, element slots
     verts: object   # int32, vertex slots
-    lconn: object   # uint16, element slots * n_vert
-    linc: object    # uint16, n_elem * n_vert
+    lconn: object   # uint16, element slots * 4
+    linc: object    # uint32, n_elem * 4: slot, local vertex and row positions
 
     def to(self, device):
         import torch
@@ -565,26 +566,35 @@ class CsrBlocks:
             a = np.ascontiguousarray(a)
             if a.dtype == np.uint16:
                 a = a.view(np.int16)
+            elif a.dtype == np.uint32:
+                a = a.view(np.int32)
             return torch.from_numpy(a).to(device)
         return CsrBlocks(self.n_blocks, dev(self.blk), dev(self.elems), dev(self.verts),
                          dev(self.lconn), dev(self.linc))
 
 
-def csr_blocks(elem, conn, n_nodes: int, inc_ptr, inc) -> CsrBlocks:
-    """Node blocks built on the host from conn ((n_elem, n_vert) node ids)
-    and node_incidence's (inc_ptr, inc): consecutive nodes whose elements
-    and vertices fit one workgroup's LDS (FE_CSR_BLOCK_* limits)."""
+def csr_blocks(elem, conn, n_nodes: int, inc_ptr, inc, row_ptr, col_idx) -> CsrBlocks:
+    """Node blocks built on the host from conn ((n_elem, 4) node ids),
+    node_incidence's (inc_ptr, inc) and csr_pattern's scalar (row_ptr,
+    col_idx): consecutive nodes whose elements and vertices fit one
+    workgroup's LDS (FE_CSR_BLOCK_* limits), with every incidence coded with
+    the row positions of its element's vertices."""
     e = ELEM.get(elem, elem)
     c = np.ascontiguousarray(np.asarray(conn).T.astype(np.int32))
     nv, n = c.shape
     ip = np.ascontiguousarray(inc_ptr, dtype=np.int64)
     ic = np.ascontiguousarray(inc, dtype=np.int32)
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
     if ip.shape[0] != int(n_nodes) + 1 or ic.shape[0] != n * nv:
         raise ValueError("inc_ptr / inc do not match conn and n_nodes")
+    if rp.shape[0] != int(n_nodes) + 1 or ci.shape[0] != rp[-1]:
+        raise ValueError("row_ptr / col_idx are not a scalar pattern of n_nodes rows")
     vp = ctypes.c_void_p
     sizes = np.zeros(3, dtype=np.int64)
     args = (e, n, c.ctypes.data_as(vp), n, int(n_nodes), ip.ctypes.data_as(vp),
-            ic.ctypes.data_as(vp), sizes.ctypes.data_as(vp))
+            ic.ctypes.data_as(vp), rp.ctypes.data_as(vp), ci.ctypes.data_as(vp),
+            sizes.ctypes.data_as(vp))
     got = lib().fe_csr_blocks(*args, None, None, None, None, None)
     if got < 0:
         _check(-got)
@@ -593,7 +603,7 @@ def csr_blocks(elem, conn, n_nodes: int, inc_ptr, inc) -> CsrBlocks:
     elems = np.empty(max(ne, 1), dtype=np.int32)
     verts = np.empty(max(nvx, 1), dtype=np.int32)
     lconn = np.empty(max(ne * nv, 1), dtype=np.uint16)
-    linc = np.empty(max(n * nv, 1), dtype=np.uint16)
+    linc = np.empty(max(n * nv, 1), dtype=np.uint32)
     got = lib().fe_csr_blocks(*args, blk.ctypes.data_as(vp), elems.ctypes.data_as(vp),
                               verts.ctypes.data_as(vp), lconn.ctypes.data_as(vp),
                               linc.ctypes.data_as(vp))
@@ -628,7 +638,7 @@ def assemble_csr_blocks(p: Problem, elem, nodes, coeffs, rule: Rule, row_ptr, co
         raise ValueError("inc_ptr must be a contiguous int64 GPU vector of n_nodes + 1 values")
     for name, t, want in (("blk", blocks.blk, torch.int64), ("elems", blocks.elems, torch.int32),
                           ("verts", blocks.verts, torch.int32), ("lconn", blocks.lconn, torch.int16),
-                          ("linc", blocks.linc, torch.int16)):
+                          ("linc", blocks.linc, torch.int32)):
         if not (t.is_cuda and t.dtype == want and t.is_contiguous()):
             raise ValueError(f"blocks.{name} must be a contiguous {want} GPU tensor")
     if blocks.blk.numel() != 3 * (blocks.n_blocks + 1):

@@ -42,7 +42,7 @@ def _both(wl, precision, init=None):
     nodes = torch.from_numpy(wl.mesh.nodes).cuda().contiguous()
     rp, ci = fe.csr_pattern(wl.elem, wl.mesh.conn, nn, 1)
     ip, inc = fe.node_incidence(wl.elem, wl.mesh.conn, nn)
-    bl = fe.csr_blocks(wl.elem, wl.mesh.conn, nn, ip, inc)
+    bl = fe.csr_blocks(wl.elem, wl.mesh.conn, nn, ip, inc, rp, ci)
     rpd, cid = torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda()
     ipd, incd = torch.from_numpy(ip).cuda(), torch.from_numpy(inc).cuda()
     dt = torch.float64 if precision == "fp64" else torch.float32
@@ -121,13 +121,14 @@ def test_blocks_match_oracle():
 
 
 def test_blocks_unsupported_problem():
-    wl = P.small("prism_cdr")
+    # blocks of a tetrahedral mesh handed to an elasticity problem
+    wl = P.small("tet_elasticity")
     nn = wl.mesh.nodes.shape[0]
     dw = fe.to_device(wl, "fp64")
     nodes = torch.from_numpy(wl.mesh.nodes).cuda().contiguous()
     rp, ci = fe.csr_pattern(wl.elem, wl.mesh.conn, nn, 1)
     ip, inc = fe.node_incidence(wl.elem, wl.mesh.conn, nn)
-    bl = fe.csr_blocks(wl.elem, wl.mesh.conn, nn, ip, inc)
+    bl = fe.csr_blocks(wl.elem, wl.mesh.conn, nn, ip, inc, rp, ci)
     with pytest.raises(fe.FeError) as ex:
         fe.assemble_csr_blocks(dw.problem, wl.elem, nodes, dw.coeffs, dw.rule,
                                torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda(),

@@ -1051,6 +1051,7 @@ def main() -> int:
                                            "F": f32["parity"]["max_rel_err_F"],
                                            "sampled_elements": f32["parity"]["sampled_elements"],
                                            "tol": f32["parity"]["tol"], "ok": f32["parity"]["ok"]},
+            "access_pattern": f32["access_pattern"],
             "kernel_source_hash": f32["kernel_source_hash"]}
         log(f"[bench] fp32 tier: {f32['value']:.3e} elements/s ({time.time() - t0:.1f}s)")
         t0 = time.time()
@@ -1194,6 +1195,30 @@ def measure_plain(a, torch, fe, oracle, workload, precision, dev, parity_sample,
     copy_gbps = 2 * nbytes * 10 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
     del src, dst
 
+    # the kernel's own access pattern with the arithmetic removed: the same
+    # rows read (coordinates, coefficient rows as FP64-row equivalents) and
+    # written (K and F in the tier's type), one element per lane
+    pattern = None
+    if not (indexed or natural):
+        ncoef = fe.coeff_entries(p, wl.elem, rule.n_q) if wl.coef_mode != "function" else 0
+        tsz = 8 if precision == "fp64" else 4
+        rows_in = 3 * nv + (ncoef * tsz + 7) // 8
+        rows_out = nk + nf
+        pin = torch.zeros((rows_in, ld), dtype=torch.float64, device=dev)
+        pout = torch.empty((rows_out, ld), dtype=dt, device=dev)
+        for _ in range(3):
+            fe.stream_pattern(pin, pout, wl.n_elem)
+        ev0.record(stream)
+        for _ in range(10):
+            fe.stream_pattern(pin, pout, wl.n_elem)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        pt = ev0.elapsed_time(ev1) * 1e-3 / 10
+        pbytes = wl.n_elem * (8 * rows_in + tsz * rows_out)
+        pattern = {"rows_in_fp64": rows_in, "rows_out": rows_out, "ms": pt * 1e3,
+                   "GBps": pbytes / pt / 1e9}
+        del pin, pout
+
     # The timed region: K back-to-back steps between device synchronisations.
     # The host clock gives `value`; one pair of HIP events on the launch
     # stream brackets the same region and gives the average kernel duration
@@ -1290,6 +1315,8 @@ def measure_plain(a, torch, fe, oracle, workload, precision, dev, parity_sample,
                                     "median": float(np.median(kern_ms))},
         "copy_ceiling_GBps": copy_gbps,
         "frac_of_copy_ceiling": achieved / copy_gbps,
+        "access_pattern": (dict(pattern, kernel_vs_pattern=pattern["ms"] / (avg_kern_s * 1e3))
+                           if pattern else None),
         "parity": {"sampled_elements": int(len(sample)), "max_rel_err_K": float(ek.max()),
                    "max_rel_err_F": float(ef.max()), "tol": tol,
                    "ok": bool(ek.max() <= tol and ef.max() <= tol)},

@@ -700,6 +700,18 @@ FE_API double fe_server_now(void);
  * ------------------------------------------------------------------- */
 FE_API int fe_stream_copy(void *dst, const void *src, int64_t n_bytes, hipStream_t stream);
 
+/* Measurement helper: the bare access pattern of an integration kernel,
+ * with its arithmetic removed. For each element e < n, reads rows_in FP64
+ * rows in[r * ld + e] and writes rows_out rows out[w * ld + e] of out_bytes
+ * (8: FP64, 4: FP32) with the value sum_r in[r][e] + w, one element per
+ * lane, streaming loads and stores (device memory, rows of ld >= n
+ * elements). Its rate is the memory system's rate for that pattern: the
+ * ceiling of an integration kernel that moves the same rows. Returns
+ * FE_ERR_INVALID_ARG for bad sizes or misaligned pointers. Enqueued on
+ * `stream`. */
+FE_API int fe_stream_pattern(const double *in, int32_t rows_in, void *out, int32_t rows_out,
+                             int32_t out_bytes, int64_t n, int64_t ld, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

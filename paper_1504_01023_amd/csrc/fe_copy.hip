@@ -1,5 +1,7 @@
 // fe_copy.hip -- a plain streaming copy used to calibrate HBM byte counters
-// and to measure the achieved copy ceiling next to the integration kernels.
+// and to measure the achieved copy ceiling next to the integration kernels,
+// and the bare access pattern of an integration kernel (its rows read and
+// written, no arithmetic) for the memory-side ceiling of that pattern.
 #include <hip/hip_runtime.h>
 
 #include "fe.h"
@@ -17,7 +19,51 @@ __global__ __launch_bounds__(256) void stream_copy_kernel(d2_t *__restrict__ dst
         __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
+// rows_in FP64 rows read and rows_out rows of TO written per element, one
+// element per lane, streaming loads and stores: out[w][e] = sum_r in[r][e] + w.
+template <typename TO>
+__global__ __launch_bounds__(256) void stream_pattern_kernel(const double *__restrict__ in,
+                                                             int rows_in, TO *__restrict__ out,
+                                                             int rows_out, int64_t n, int64_t ld)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n)
+        return;
+    double s = 0.0;
+#pragma unroll 8
+    for (int r = 0; r < rows_in; ++r)
+        s += __builtin_nontemporal_load(in + r * ld + e);
+#pragma unroll 8
+    for (int w = 0; w < rows_out; ++w)
+        __builtin_nontemporal_store((TO)(s + (double)w), out + w * ld + e);
+}
+
 }  // namespace
+
+extern "C" int fe_stream_pattern(const double *in, int32_t rows_in, void *out, int32_t rows_out,
+                                 int32_t out_bytes, int64_t n, int64_t ld, hipStream_t stream)
+{
+    if (rows_in < 0 || rows_out < 1 || n < 0 || ld < n || (out_bytes != 8 && out_bytes != 4))
+        return fe::fail(FE_ERR_INVALID_ARG, "bad pattern arguments");
+    if (n == 0)
+        return FE_OK;
+    if (!out || (rows_in > 0 && !in) || ((uintptr_t)in % 8) || ((uintptr_t)out % out_bytes))
+        return fe::fail(FE_ERR_INVALID_ARG, "pointers must be non-NULL and aligned");
+    int64_t grid = (n + 255) / 256;
+    if (grid > 0x7fffffff)
+        return fe::fail(FE_ERR_INVALID_ARG, "n too large");
+    const hipError_t err =
+        out_bytes == 8
+            ? fe::launch_kernel(&stream_pattern_kernel<double>, dim3((unsigned)grid), dim3(256), 0,
+                                stream, in, (int)rows_in, static_cast<double *>(out),
+                                (int)rows_out, n, ld)
+            : fe::launch_kernel(&stream_pattern_kernel<float>, dim3((unsigned)grid), dim3(256), 0,
+                                stream, in, (int)rows_in, static_cast<float *>(out),
+                                (int)rows_out, n, ld);
+    if (err != hipSuccess)
+        return fe::fail(FE_ERR_HIP, "pattern launch failed: %s", hipGetErrorString(err));
+    return FE_OK;
+}
 
 extern "C" int fe_stream_copy(void *dst, const void *src, int64_t n_bytes, hipStream_t stream)
 {

@@ -121,6 +121,7 @@ def lib():
         L.fe_csr_blocks.restype = i64
         L.fe_assemble_csr_blocks.argtypes = [P, i32, i64, vp, i64, vp, i64, R, vp, vp, i64, vp,
                                              vp, vp, i64, vp, vp, vp, vp, vp, vp]
+        L.fe_stream_pattern.argtypes = [vp, i32, vp, i32, i32, i64, i64, vp]
         L.fe_ld_for.argtypes = [i64]
         L.fe_ld_for.restype = i64
         L.fe_tuning_builtin.argtypes = [ctypes.c_char_p, i32, ctypes.POINTER(ctypes.c_int)]
@@ -789,6 +790,24 @@ def tuning_builtin():
     n = ctypes.c_int(0)
     on = lib().fe_tuning_builtin(arch, 64, ctypes.byref(n))
     return bool(on), arch.value.decode(), n.value
+
+
+def stream_pattern(inp, out, n: int, stream=None) -> None:
+    """The bare access pattern of an integration kernel: inp (rows_in, ld)
+    float64 and out (rows_out, ld) float64 or float32 device tensors (row
+    views of ld >= n columns); reads the first n columns of every input row
+    and writes those of every output row."""
+    import torch
+    ld = inp.stride(0) if inp.dim() == 2 and inp.shape[0] > 0 else out.stride(0)
+    if not (out.is_cuda and out.dim() == 2 and out.stride(1) == 1 and out.stride(0) == ld
+            and out.dtype in (torch.float64, torch.float32)):
+        raise ValueError("out must be a (rows_out, ld) float64 / float32 GPU row view")
+    if not (inp.is_cuda and inp.dim() == 2 and inp.dtype == torch.float64
+            and (inp.shape[0] == 0 or (inp.stride(1) == 1 and inp.stride(0) == ld))):
+        raise ValueError("inp must be a (rows_in, ld) float64 GPU row view with out's ld")
+    _check(lib().fe_stream_pattern(ctypes.c_void_p(inp.data_ptr()) if inp.shape[0] else None,
+                                   inp.shape[0], ctypes.c_void_p(out.data_ptr()), out.shape[0],
+                                   out.element_size(), int(n), int(ld), _stream_handle(stream)))
 
 
 def stream_copy(dst, src, stream=None) -> None:

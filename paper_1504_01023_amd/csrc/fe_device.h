@@ -2867,7 +2867,7 @@ __global__ __launch_bounds__(FE_CSR_BLOCK_NODES) void fe_csr_blocks_kernel(KArgs
     }
     const int t = threadIdx.x;
     const int64_t i = n0 + t;
-    const bool own = t < BN && i < n1 && i < ap.n_own;
+    const bool own = t < BN && i >= 0 && i < n1 && i < ap.n_own;
     int64_t r0 = 0, len = 0;
     int pos_self = 62;
     if (own) {

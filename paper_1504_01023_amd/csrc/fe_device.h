@@ -2810,14 +2810,14 @@ __global__ __launch_bounds__(256) void fe_csr_rows_kernel(KArgs a, IdxArgs gi, A
 // block of consecutive nodes. The block's elements (block-local vertex
 // indices and, where coefficients are read per element, global ids) and
 // their vertices' coordinates are read from HBM into LDS once; then each
-// lane walks its node's incidence list in
-// the order fe_csr_rows_kernel walks it, computes the element's row for the
-// node (RowBlock) and adds its four values where the host-built incidence
-// codes place them: the first RL entries of the node's row accumulate in
-// LDS (starting from their stored values, written back once), entries past
-// them through memory. Every entry receives the same additions in the same
-// order as in fe_csr_rows_kernel, so the values are the same bit for bit;
-// and no lane compares columns, which is most of that kernel's arithmetic.
+// lane walks its node's incidence list in the order fe_csr_rows_kernel
+// walks it, computes the element's row for the node (RowBlock) and adds its
+// four values where the host-built incidence codes place them: the first RL
+// entries of the node's row accumulate in LDS (starting from their stored
+// values, written back once), entries past them through memory. Every
+// entry receives the same additions in the same order as in
+// fe_csr_rows_kernel, so the values are the same bit for bit; and no lane
+// compares columns, which is most of that kernel's arithmetic.
 // Incidence code: bits 0-13 element slot * 4 + local vertex; bits 14-19,
 // 20-25, 26-31 the row positions of the element's other three vertices in
 // increasing local order (62: no such entry in the pattern; 63: position

@@ -435,6 +435,43 @@ def test_assemble_csr_stored_validation_before_launch():
     assert call(n=0, K=0, F=0, inc=0) == 0
 
 
+def test_assemble_csr_blocks_validation_before_launch():
+    L = fe.lib()
+    p = fe.problem("scalar", "fp64", "uniform", 0, inputs.identity_diffusion_uniform(), "packed")
+    rule = fe.builtin_rule("tet4", 1)
+    v = lambda a: ctypes.c_void_p(a) if a else None
+    call = lambda elem=0, n=10, nb=2, blk=0x2000, linc=0x3000, vals=0x7000, prob=p: \
+        L.fe_assemble_csr_blocks(ctypes.byref(prob), elem, n, v(0x8000), 10, None, 10,
+                                 ctypes.byref(rule.c), v(0x5000), v(0x6000), 100, v(vals), None,
+                                 v(0xa000), nb, v(blk), v(0x4000), v(0x4800), v(0x5800),
+                                 v(linc), None)
+    assert call(elem=1) == 2           # prisms: not built
+    pe = fe.problem("elasticity", "fp64", "element", (1 << 5) - 1, np.zeros(20), "packed")
+    assert call(prob=pe) == 2          # vector problems: not built
+    assert call(blk=0) == 1
+    assert call(linc=0) == 1
+    assert call(vals=0) == 1
+    assert call(nb=0) == 1
+    assert call(nb=-1) == 1
+    assert call(linc=0x3002) == 2      # misaligned codes
+    assert call(n=0, nb=0, blk=0, linc=0, vals=0) == 0
+
+
+def test_stream_pattern_validation():
+    L = fe.lib()
+    v = lambda a: ctypes.c_void_p(a) if a else None
+    call = lambda rin=2, rout=3, ob=8, n=10, ld=10, inp=0x1000, out=0x2000: L.fe_stream_pattern(
+        v(inp), rin, v(out), rout, ob, n, ld, None)
+    assert call(rin=-1) == 1
+    assert call(rout=0) == 1
+    assert call(ob=2) == 1
+    assert call(ld=9) == 1
+    assert call(out=0) == 1
+    assert call(inp=0) == 1            # rows to read but no input
+    assert call(out=0x2004) == 1       # misaligned for FP64 output
+    assert call(n=0) == 0
+
+
 def test_product_path_fails_loudly_without_the_library(tmp_path):
     # with libfe.so absent the binding raises; nothing falls back to the oracle
     import subprocess

@@ -561,7 +561,7 @@ static int indexed_consumer(const fe_problem *problem, fe_elem_type elem_type, i
                 return fail(FE_ERR_INVALID_ARG, "color_ptr must not decrease");
     }
     // the matrix-free form exists for the base variant: one element per lane
-    const fe_variant base{256, 1, 2, 1, 0, 1, 1};
+    const fe_variant base{256, 1, 2, 1, 0, 1, 1, 1};
     Plan pl;
     int st = plan(problem, elem_type, n_elem, nullptr, coeffs, ld_in, quad_rule, nullptr, nullptr,
                   n_elem, &base, pl, 2, conn, ld_conn);
@@ -659,7 +659,7 @@ int fe_assemble_csr_rows(const fe_problem *problem, fe_elem_type elem_type, int6
         !aligned(inc_ptr, 8) || !aligned(inc, 4))
         return fail(FE_ERR_UNSUPPORTED, "pointers must be aligned to their element size");
     // the assembly form exists for the base variant: one element per lane
-    const fe_variant base{256, 1, 2, 1, 0, 1, 1};
+    const fe_variant base{256, 1, 2, 1, 0, 1, 1, 1};
     Plan pl;
     int st = plan(problem, elem_type, n_elem, nullptr, coeffs, ld_in, quad_rule, nullptr, nullptr,
                   n_elem, &base, pl, 2, conn, ld_conn);
@@ -717,7 +717,7 @@ int fe_assemble_csr_blocks(const fe_problem *problem, fe_elem_type elem_type, in
         !aligned(inc_ptr, 8) || !aligned(blk, 8) || !aligned(elems, 4) || !aligned(verts, 4) ||
         !aligned(lconn, 2) || !aligned(linc, 4))
         return fail(FE_ERR_UNSUPPORTED, "pointers must be aligned to their element size");
-    const fe_variant base{256, 1, 2, 1, 0, 1, 1};
+    const fe_variant base{256, 1, 2, 1, 0, 1, 1, 1};
     Plan pl;
     int st = plan(problem, elem_type, n_elem, nullptr, coeffs, ld_in, quad_rule, nullptr, nullptr,
                   n_elem, &base, pl, 3, nullptr, 0);
